@@ -1,0 +1,166 @@
+"""Seeded synthetic systems shaped like the paper's FD-mode workloads.
+
+Recipe (one system):
+  * orthorhombic periodic cell of n = (N0, N1, N2) points, spacing h (bohr),
+    grid points at r = (i h0, j h1, k h2);
+  * Bloch vector k in reduced units (k = 0 gives a real problem);
+  * atom sites: fractional U[0,1)^3 times the cell lengths;
+  * one Gaussian well per atom for the local potential,
+    v(r) = depth * sum_a sum_R exp(-|r - R_a - R|^2 / (2 width^2)),
+    periodic images truncated at 8 widths;
+  * per atom 13 projectors: channels (l, sigma) = (0, rc/3), (0, rc/5),
+    (1, rc/3), (1, rc/5), (2, rc/3), each a Gaussian times r^l with a smooth
+    cut-off at rc (the functions themselves are evaluated by the consumers);
+  * Delta H^a = (A + A^T)/2 and Delta S^a = s (B + B^T)/2 with A, B drawn
+    U[-1,1]^{13x13} per atom (s = 0.1);
+  * the block of wave functions: U[-1,1] per grid value (real), or
+    independent U[-1,1] real and imaginary parts (complex).
+
+Draw order from numpy.random.default_rng(seed): positions, Delta H,
+Delta S, wave functions.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+
+def standard_channels(rc: float):
+    """The 13-projector channel set: (l, sigma, rc) triples, channel-major."""
+    return [(0, rc / 3.0, rc), (0, rc / 5.0, rc), (1, rc / 3.0, rc),
+            (1, rc / 5.0, rc), (2, rc / 3.0, rc)]
+
+
+@dataclass
+class System:
+    n: tuple            # grid points per axis (N0, N1, N2); axis 2 is contiguous
+    h: tuple            # grid spacing per axis (bohr)
+    k: tuple            # Bloch vector, reduced units
+    pos: np.ndarray     # [natoms][3] cartesian bohr
+    channels: list      # [(l, sigma, rc)]
+    dH: np.ndarray      # [natoms][ni][ni] real symmetric
+    dS: np.ndarray      # [natoms][ni][ni] real symmetric
+    v: np.ndarray       # [N0][N1][N2] float64
+    psi: np.ndarray     # [nb][N0][N1][N2] float64 or complex128
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def natoms(self):
+        return self.pos.shape[0]
+
+    @property
+    def nb(self):
+        return self.psi.shape[0]
+
+    @property
+    def ni(self):
+        return sum(2 * l + 1 for (l, _, _) in self.channels)
+
+    @property
+    def ng(self):
+        return int(np.prod(self.n))
+
+    @property
+    def cell(self):
+        return tuple(self.n[c] * self.h[c] for c in range(3))
+
+    @property
+    def is_complex(self):
+        return np.iscomplexobj(self.psi)
+
+
+def gaussian_potential(n, h, pos, depth=-2.0, width=1.0):
+    """Sum of periodic Gaussian wells, one per atom (an input field)."""
+    L = [n[c] * h[c] for c in range(3)]
+    axes = [np.arange(n[c]) * h[c] for c in range(3)]
+    v = np.zeros(n)
+    reach = 8.0 * width
+    for a in range(pos.shape[0]):
+        parts = []
+        for c in range(3):
+            m = int(math.ceil(reach / L[c])) + 1
+            d = axes[c][:, None] - pos[a, c] - L[c] * np.arange(-m, m + 1)[None, :]
+            g = np.exp(-d * d / (2.0 * width * width))
+            g[np.abs(d) > reach] = 0.0
+            parts.append(g.sum(axis=1))
+        # the Gaussian factorises over axes, and so does its image sum
+        v += parts[0][:, None, None] * parts[1][None, :, None] * parts[2][None, None, :]
+    return depth * v
+
+
+def make_system(n, h, nb, natoms, rc, seed, k=(0.0, 0.0, 0.0), complex_psi=None,
+                ds_scale=0.1, depth=-2.0, width=1.0, name=""):
+    n = tuple(int(x) for x in n)
+    h = (float(h),) * 3 if np.isscalar(h) else tuple(float(x) for x in h)
+    k = tuple(float(x) for x in k)
+    if complex_psi is None:
+        complex_psi = any(x != 0.0 for x in k)
+    rng = np.random.default_rng(seed)
+    L = np.array([n[c] * h[c] for c in range(3)])
+    pos = rng.random((natoms, 3)) * L[None, :]
+    channels = standard_channels(rc)
+    ni = sum(2 * l + 1 for (l, _, _) in channels)
+    A = rng.uniform(-1.0, 1.0, (natoms, ni, ni))
+    dH = 0.5 * (A + A.transpose(0, 2, 1))
+    B = rng.uniform(-1.0, 1.0, (natoms, ni, ni))
+    dS = ds_scale * 0.5 * (B + B.transpose(0, 2, 1))
+    shape = (nb,) + n
+    if complex_psi:
+        psi = rng.uniform(-1.0, 1.0, shape) + 1j * rng.uniform(-1.0, 1.0, shape)
+    else:
+        psi = rng.uniform(-1.0, 1.0, shape)
+    v = gaussian_potential(n, h, pos, depth, width)
+    return System(n=n, h=h, k=k, pos=pos, channels=channels, dH=dH, dS=dS, v=v,
+                  psi=psi, name=name,
+                  meta=dict(seed=seed, rc=rc, ds_scale=ds_scale, depth=depth, width=width))
+
+
+# The five workloads: small real case, the single-GPU FP64 case, the precision
+# form, the complex Bloch case and the batched form (grid spacing 0.2 bohr and
+# rc = 2.0 bohr where the workload does not state them).
+CONFIGS = {
+    "A": dict(n=(24, 24, 24), h=0.2, nb=16, natoms=4, rc=2.0, seed=0),
+    "B": dict(n=(48, 48, 48), h=0.18, nb=128, natoms=16, rc=2.2, seed=1),
+    "C": dict(n=(96, 96, 96), h=0.2, nb=512, natoms=64, rc=2.0, seed=2),
+    "D": dict(n=(120, 120, 160), h=0.2, nb=1024, natoms=128, rc=2.0, seed=3,
+              k=(0.25, 0.0, 0.5)),
+}
+
+
+def config_system(name, nb=None):
+    """The named workload; nb overrides the band count (for bounded samples)."""
+    cfg = dict(CONFIGS[name])
+    if nb is not None:
+        cfg["nb"] = nb
+    return make_system(name=name, **cfg)
+
+
+def batched_systems(count=64, seed=4):
+    """Uneven independent systems: grids 16..48 per axis, 8..96 bands,
+    2..16 atoms, half of them complex with k ~ U[0, 0.5)^3."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(count):
+        n = tuple(int(x) for x in rng.integers(16, 49, 3))
+        nb = int(rng.integers(8, 97))
+        natoms = int(rng.integers(2, 17))
+        cplx = bool(s % 2)
+        k = tuple(rng.uniform(0.0, 0.5, 3)) if cplx else (0.0, 0.0, 0.0)
+        sub_seed = int(rng.integers(0, 2**31 - 1))
+        out.append(dict(n=n, h=0.2, nb=nb, natoms=natoms, rc=2.0, seed=sub_seed,
+                        k=k, complex_psi=cplx))
+    return out
+
+
+def ragged_cases():
+    """Small shapes that exercise tile tails, odd sizes, self-overlapping
+    spheres, no atoms and a single band."""
+    return [
+        dict(n=(13, 17, 11), h=(0.21, 0.19, 0.23), nb=5, natoms=3, rc=1.6, seed=11),
+        dict(n=(16, 16, 16), h=0.2, nb=1, natoms=2, rc=2.0, seed=12),
+        dict(n=(10, 9, 12), h=0.2, nb=7, natoms=0, rc=2.0, seed=13),
+        dict(n=(20, 18, 66), h=0.2, nb=33, natoms=5, rc=2.0, seed=14),
+    ]
