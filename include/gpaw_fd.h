@@ -1,0 +1,175 @@
+/*
+ * gpaw_fd.h -- C ABI of the MI355X (gfx950) library for one block step of the
+ * real-space (finite-difference) PAW eigensolver.
+ *
+ * Method (GPAW review, arXiv:2310.14776):
+ *   H~ = -1/2 nabla^2 + v~(r) + sum_a sum_ii' |p~^a_i> Delta H^a_ii' <p~^a_i'|
+ *   S~ = 1 + sum_a sum_ii' |p~^a_i> Delta S^a_ii' <p~^a_i'|
+ * (Sec. "Projector augmented-wave method", Eq. (dh) and the overlap operator
+ * beside it), the kinetic operator represented on a uniform Cartesian grid
+ * (Sec. "Wave-function representations"), and the subspace diagonalisation
+ * that opens every SCF step (Sec. "Solving the Kohn-Sham equation", step 1),
+ * with Cholesky decomposition and diagonalisation as dense linear algebra
+ * (Sec. "Parallelization"). Arrays cross the boundary as plain pointers to
+ * contiguous memory, as GPAW's C hot spots receive NumPy buffers
+ * (Sec. "Developer's perspective").
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Grid: orthorhombic cell of n[0] x n[1] x n[2] points with spacing h[c]
+ *   (bohr); point (i,j,l) sits at (i h0, j h1, l h2); axis 2 is contiguous.
+ *   Ng = n0*n1*n2, dV = h0*h1*h2; integrals are dV times grid sums.
+ * Boundary: Bloch, psi(r + L_c e_c) = exp(2 pi i k_c) psi(r), k in reduced
+ *   units; k = 0 is the periodic (real) case.
+ * Kinetic operator: per axis the 6th-order central second difference,
+ *   weights (1/90, -3/20, 3/2, -49/18, 3/2, -3/20, 1/90)/h_c^2 (19-point star).
+ * Projectors: every atom carries the same channel list; channel (l, sigma, rc)
+ *   gives 2l+1 functions N r^l exp(-r^2/2sigma^2) (1-(r/rc)^2)^2 Y_lm(r^) for
+ *   r < rc, N = [Gamma(l+3/2) sigma^(2l+3)/2]^(-1/2), m = -l..l, real
+ *   harmonics ordered (y,z,x) for l=1 and (xy,yz,3z^2-r^2,xz,x^2-y^2) for l=2.
+ *   ni = sum(2l+1) projectors per atom, Np = natoms*ni, index a*ni + i.
+ *   Grid values sum all periodic images R with exp(i k.R).
+ * Layouts (row-major, C order):
+ *   psi, Hpsi, Spsi, psi_out : [nb][n0][n1][n2]  of the system dtype
+ *   P, P_out                 : [nb][Np]          of the system dtype
+ *   H_nn, S_nn, C_nn         : [nb][nb]          double (real systems) or
+ *                                                interleaved complex double
+ *   eps                      : [nb]              double
+ * Complex data are interleaved (re, im).
+ * Memory: pointers named *_dev, and every array argument of the compute calls,
+ *   are device pointers owned by the caller; the library never frees them.
+ *   The library owns the gpaw_sys object: its projector tables, potential,
+ *   correction matrices and workspace (sized by max_bands at creation).
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *   Compute calls only enqueue work and return; gpaw_subspace_diag with a
+ *   NULL info pointer is the one call that waits for its stream.
+ * Concurrency: calls on one gpaw_sys share its workspace; calls that overlap
+ *   in time on one system (two streams, two host threads) race.
+ * Errors: every int-returning call returns GPAW_OK (0) or a negative code;
+ *   gpaw_last_error() gives a message for the calling host thread's last
+ *   failure. A rejected call has enqueued nothing.
+ */
+#ifndef GPAW_FD_H
+#define GPAW_FD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GPAW_FD_VERSION 1
+
+#if defined(__GNUC__)
+#define GPAW_API __attribute__((visibility("default")))
+#else
+#define GPAW_API
+#endif
+
+enum gpaw_status {
+  GPAW_OK = 0,
+  GPAW_EINVAL = -1,       /* NULL pointer, bad size, bad channel, bad k  */
+  GPAW_EDTYPE = -2,       /* dtype not supported by this call            */
+  GPAW_ESHAPE = -3,       /* nb outside [1, max_bands] or above a limit  */
+  GPAW_EALIAS = -4,       /* output overlaps an input that it must not   */
+  GPAW_EHIP = -5,         /* HIP runtime or launch failure               */
+  GPAW_ENOTPD = -6,       /* S_nm is not positive definite               */
+  GPAW_ENOMEM = -7,       /* device or host allocation failed            */
+  GPAW_ENOCONV = -8       /* eigenvector orthogonalisation did not settle */
+};
+
+typedef enum { GPAW_F64 = 0, GPAW_C128 = 1 } gpaw_dtype;
+
+typedef struct {
+  int32_t l;       /* 0, 1 or 2 */
+  double sigma;    /* Gaussian width (bohr), > 0 */
+  double rc;       /* cut-off radius (bohr), > 0 */
+} gpaw_channel;
+
+typedef struct {
+  int32_t n[3];             /* grid points per axis, each >= 1 */
+  double h[3];              /* grid spacing per axis (bohr), > 0 */
+  double k[3];              /* Bloch vector, reduced units */
+  int32_t dtype;            /* gpaw_dtype of psi; GPAW_F64 needs k = 0 */
+  int32_t natoms;           /* >= 0 */
+  const double *pos;        /* host [natoms][3] cartesian positions (bohr) */
+  int32_t nchan;            /* >= 1 when natoms > 0 */
+  const gpaw_channel *chan; /* host [nchan], same for every atom */
+  const double *dH;         /* host [natoms][ni][ni], Delta H^a (real symmetric) */
+  const double *dS;         /* host [natoms][ni][ni], Delta S^a (real symmetric) */
+  const double *v;          /* host [n0][n1][n2], local potential v~ (Ha) */
+  int32_t max_bands;        /* largest nb any call will pass, >= 1 */
+} gpaw_sys_desc;
+
+typedef struct gpaw_sys gpaw_sys;
+
+/* Build one system on the current HIP device: evaluates the projector
+ * functions on the grid spheres (host), uploads tables, potential and
+ * corrections, and allocates workspace. Synchronous. On success *out owns
+ * the object; release it with gpaw_sys_destroy. */
+GPAW_API int gpaw_sys_create(const gpaw_sys_desc *desc, gpaw_sys **out);
+
+/* Free everything the system owns (waits for the device first). NULL is a
+ * no-op. */
+GPAW_API void gpaw_sys_destroy(gpaw_sys *sys);
+
+/* Sizes of a built system, written to host info[0..7]:
+ * Ng, Np, ni, natoms, sphere entries, covered grid points, max_bands, dtype. */
+GPAW_API int gpaw_sys_info(const gpaw_sys *sys, int64_t *info);
+
+/* Projections P[n][a*ni+i] = <p~^a_i | psi_n> = dV sum_r conj(q^a_i(r)) psi_n(r)
+ * (the projector overlaps of Eq. (dh); the same quantity the paper's GPU
+ * section stores beside psi~_n). psi [nb][Ng] -> P [nb][Np]. */
+GPAW_API int gpaw_project(gpaw_sys *sys, const void *psi, int32_t nb, void *P, void *stream);
+
+/* Hpsi = H~ psi for each band (Eq. (dh)): kinetic stencil, local potential
+ * and non-local add-back sum_a q^a (Delta H^a P^a). P is the projection of
+ * this psi block ([nb][Np]) or NULL, in which case the call computes it into
+ * workspace. Hpsi must not overlap psi (the stencil reads neighbours). */
+GPAW_API int gpaw_fd_apply_H(gpaw_sys *sys, const void *psi, int32_t nb, const void *P,
+                    void *Hpsi, void *stream);
+
+/* Spsi = S~ psi = psi + sum_a q^a (Delta S^a P^a) (overlap operator beside
+ * Eq. (dh)). P as for gpaw_fd_apply_H. Spsi must not overlap psi. */
+GPAW_API int gpaw_fd_apply_S(gpaw_sys *sys, const void *psi, int32_t nb, const void *P,
+                    void *Spsi, void *stream);
+
+/* Subspace matrices of SCF step (1) (Sec. "Solving the Kohn-Sham equation"):
+ * H_nm = dV sum_r conj(psi_n(r)) Hpsi_m(r), S_nm likewise with Spsi, both
+ * [nb][nb], full (not symmetrised), summed in a fixed order (bitwise
+ * reproducible). Spsi may be NULL: then only H_nn is formed and S_nn is
+ * ignored. */
+GPAW_API int gpaw_subspace_matrices(gpaw_sys *sys, const void *psi, const void *Hpsi,
+                           const void *Spsi, int32_t nb, void *H_nn, void *S_nn,
+                           void *stream);
+
+/* Generalised Hermitian eigenproblem of the subspace (Cholesky of S_nm and
+ * diagonalisation, Sec. "Parallelization"), all in double precision on the
+ * device: symmetrise X <- (X + X^H)/2, S = L L^H, eigen-decompose
+ * L^-1 H L^-H, C = L^-H U. Output: eps ascending [nb], C_nn [nb][nb] with
+ * column j the j-th eigenvector (C^H S C = I, C^H H C = diag eps).
+ * H_nn and S_nn are not modified. nb <= 128.
+ * info: device int32 or NULL. Non-NULL: the call is asynchronous and the
+ * device writes 0 on success, j > 0 when the leading j x j minor of S_nm is
+ * not positive definite, or -1 when orthogonalisation did not settle.
+ * NULL: the call waits for the stream and returns GPAW_ENOTPD / GPAW_ENOCONV. */
+GPAW_API int gpaw_subspace_diag(gpaw_sys *sys, const void *H_nn, const void *S_nn, int32_t nb,
+                       double *eps, void *C_nn, int32_t *info, void *stream);
+
+/* Rotation of SCF step (1): psi_out_n = sum_m C_mn psi_m (psi_out = C^T psi),
+ * and, when P and P_out are both non-NULL, P_out = C^T P (the projections of
+ * the rotated block). psi_out must not overlap psi, nor P_out P. */
+GPAW_API int gpaw_rotate(gpaw_sys *sys, const void *psi, const void *C_nn, int32_t nb,
+                void *psi_out, const void *P, void *P_out, void *stream);
+
+/* Message for the calling host thread's last non-zero return ("" if none). */
+GPAW_API const char *gpaw_last_error(void);
+
+/* GPAW_FD_VERSION of the built library. */
+GPAW_API int gpaw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPAW_FD_H */

@@ -1,0 +1,227 @@
+"""ctypes binding of libgpawfd.so: argument marshalling only.
+
+Tensors must be contiguous torch tensors on the GPU. Every call forwards
+data pointers, sizes and the current HIP stream to the C ABI declared in
+include/gpaw_fd.h; all arithmetic runs in the library's kernels. There is
+no fallback: a missing library or a non-zero status raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libgpawfd.so")
+
+GPAW_F64, GPAW_C128 = 0, 1
+
+STATUS = {0: "GPAW_OK", -1: "GPAW_EINVAL", -2: "GPAW_EDTYPE", -3: "GPAW_ESHAPE",
+          -4: "GPAW_EALIAS", -5: "GPAW_EHIP", -6: "GPAW_ENOTPD", -7: "GPAW_ENOMEM",
+          -8: "GPAW_ENOCONV"}
+
+
+class GpawError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class Channel(ctypes.Structure):
+    _fields_ = [("l", ctypes.c_int32), ("sigma", ctypes.c_double), ("rc", ctypes.c_double)]
+
+
+class SysDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3), ("k", ctypes.c_double * 3),
+                ("dtype", ctypes.c_int32), ("natoms", ctypes.c_int32),
+                ("pos", ctypes.POINTER(ctypes.c_double)), ("nchan", ctypes.c_int32),
+                ("chan", ctypes.POINTER(Channel)), ("dH", ctypes.POINTER(ctypes.c_double)),
+                ("dS", ctypes.POINTER(ctypes.c_double)), ("v", ctypes.POINTER(ctypes.c_double)),
+                ("max_bands", ctypes.c_int32)]
+
+
+_lib = None
+
+ENTRY_POINTS = ["gpaw_sys_create", "gpaw_sys_destroy", "gpaw_sys_info", "gpaw_project",
+                "gpaw_fd_apply_H", "gpaw_fd_apply_S", "gpaw_subspace_matrices",
+                "gpaw_subspace_diag", "gpaw_rotate", "gpaw_last_error", "gpaw_version"]
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def load():
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
+    lib.gpaw_sys_create.argtypes = [ctypes.POINTER(SysDesc), ctypes.POINTER(vp)]
+    lib.gpaw_sys_destroy.argtypes = [vp]
+    lib.gpaw_sys_destroy.restype = None
+    lib.gpaw_sys_info.argtypes = [vp, i64p]
+    lib.gpaw_project.argtypes = [vp, vp, i32, vp, vp]
+    lib.gpaw_fd_apply_H.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.gpaw_fd_apply_S.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.gpaw_subspace_matrices.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
+    lib.gpaw_subspace_diag.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+    lib.gpaw_rotate.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+    lib.gpaw_last_error.restype = ctypes.c_char_p
+    lib.gpaw_last_error.argtypes = []
+    lib.gpaw_version.argtypes = []
+    for name in ENTRY_POINTS:
+        if name not in ("gpaw_sys_destroy", "gpaw_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise GpawError(rc, load().gpaw_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to the library must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _host(a, dtype=np.float64):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+class System:
+    """One FD-PAW system on the current GPU (owns the library's gpaw_sys)."""
+
+    def __init__(self, n, h, k, pos, channels, dH, dS, v, max_bands, complex_=None):
+        lib = load()
+        k = tuple(float(x) for x in k)
+        if complex_ is None:
+            complex_ = any(x != 0.0 for x in k)
+        self.dtype = torch.complex128 if complex_ else torch.float64
+        self.n = tuple(int(x) for x in n)
+        self.ng = int(np.prod(self.n))
+        pos = _host(pos).reshape(-1, 3)
+        self._keep = [pos, _host(dH), _host(dS), _host(v).ravel()]
+        chans = (Channel * max(1, len(channels)))(*[Channel(int(l), float(s), float(r))
+                                                    for (l, s, r) in channels])
+        self._keep.append(chans)
+        d = SysDesc()
+        d.n[:] = self.n
+        d.h[:] = [float(x) for x in (h if np.ndim(h) else (h, h, h))]
+        d.k[:] = k
+        d.dtype = GPAW_C128 if complex_ else GPAW_F64
+        d.natoms = pos.shape[0]
+        dp = ctypes.POINTER(ctypes.c_double)
+        d.pos = self._keep[0].ctypes.data_as(dp)
+        d.nchan = len(channels)
+        d.chan = chans
+        d.dH = self._keep[1].ctypes.data_as(dp)
+        d.dS = self._keep[2].ctypes.data_as(dp)
+        d.v = self._keep[3].ctypes.data_as(dp)
+        d.max_bands = int(max_bands)
+        handle = ctypes.c_void_p()
+        _check(lib.gpaw_sys_create(ctypes.byref(d), ctypes.byref(handle)))
+        self._h = handle
+        info = (ctypes.c_int64 * 8)()
+        _check(lib.gpaw_sys_info(self._h, info))
+        self.info = dict(ng=info[0], np=info[1], ni=info[2], natoms=info[3], entries=info[4],
+                         covered=info[5], max_bands=info[6], dtype=info[7])
+        self.np = int(info[1])
+        self.max_bands = int(max_bands)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    @classmethod
+    def from_synth(cls, s, max_bands=None):
+        return cls(s.n, s.h, s.k, s.pos, s.channels, s.dH, s.dS, s.v,
+                   max_bands or s.nb, complex_=s.is_complex)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gpaw_sys_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ helpers
+    def _new(self, *shape, dtype=None):
+        return torch.empty(shape, dtype=dtype or self.dtype, device=self.device)
+
+    def _nb(self, psi):
+        if psi.dtype != self.dtype:
+            raise TypeError(f"expected {self.dtype}, got {psi.dtype}")
+        if psi.numel() % self.ng:
+            raise ValueError("psi does not hold whole grids")
+        return psi.numel() // self.ng
+
+    # ------------------------------------------------------------ calls
+    def project(self, psi, out=None, stream=None):
+        nb = self._nb(psi)
+        out = self._new(nb, self.np) if out is None else out
+        _check(load().gpaw_project(self._h, _ptr(psi), nb, _ptr(out), _stream(stream)))
+        return out
+
+    def apply_H(self, psi, P=None, out=None, stream=None):
+        nb = self._nb(psi)
+        out = torch.empty_like(psi) if out is None else out
+        _check(load().gpaw_fd_apply_H(self._h, _ptr(psi), nb, _ptr(P), _ptr(out), _stream(stream)))
+        return out
+
+    def apply_S(self, psi, P=None, out=None, stream=None):
+        nb = self._nb(psi)
+        out = torch.empty_like(psi) if out is None else out
+        _check(load().gpaw_fd_apply_S(self._h, _ptr(psi), nb, _ptr(P), _ptr(out), _stream(stream)))
+        return out
+
+    def subspace_matrices(self, psi, Hpsi, Spsi=None, H=None, S=None, stream=None):
+        nb = self._nb(psi)
+        H = self._new(nb, nb) if H is None else H
+        if Spsi is not None and S is None:
+            S = self._new(nb, nb)
+        _check(load().gpaw_subspace_matrices(self._h, _ptr(psi), _ptr(Hpsi), _ptr(Spsi), nb,
+                                             _ptr(H), _ptr(S), _stream(stream)))
+        return H, S
+
+    def subspace_diag(self, H, S, eps=None, C=None, info=None, stream=None):
+        nb = H.shape[0]
+        eps = self._new(nb, dtype=torch.float64) if eps is None else eps
+        C = self._new(nb, nb) if C is None else C
+        _check(load().gpaw_subspace_diag(self._h, _ptr(H), _ptr(S), nb, _ptr(eps), _ptr(C),
+                                         _ptr(info), _stream(stream)))
+        return eps, C
+
+    def rotate(self, psi, C, out=None, P=None, P_out=None, stream=None):
+        nb = self._nb(psi)
+        out = torch.empty_like(psi) if out is None else out
+        if P is not None and P_out is None:
+            P_out = torch.empty_like(P)
+        _check(load().gpaw_rotate(self._h, _ptr(psi), _ptr(C), nb, _ptr(out), _ptr(P),
+                                  _ptr(P_out), _stream(stream)))
+        return out, P_out
+
+    def step(self, psi, stream=None):
+        """One block step: P, H~psi, S~psi, H_nm, S_nm, eigensolve, rotation."""
+        P = self.project(psi, stream=stream)
+        Hpsi = self.apply_H(psi, P, stream=stream)
+        Spsi = self.apply_S(psi, P, stream=stream)
+        H, S = self.subspace_matrices(psi, Hpsi, Spsi, stream=stream)
+        eps, C = self.subspace_diag(H, S, stream=stream)
+        psi_rot, P_rot = self.rotate(psi, C, P=P, stream=stream)
+        return dict(P=P, Hpsi=Hpsi, Spsi=Spsi, H=H, S=S, eps=eps, C=C,
+                    psi_rot=psi_rot, P_rot=P_rot)

@@ -1,0 +1,314 @@
+// C ABI entry points: argument checks, system construction and dispatch of
+// the device kernels. No arithmetic of the method happens here.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+
+namespace gfd {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t err, const char *what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(err);
+  return err == hipErrorOutOfMemory ? GPAW_ENOMEM : GPAW_EHIP;
+}
+
+size_t elem_size(int32_t dtype) { return dtype == GPAW_C128 ? 16 : 8; }
+
+namespace {
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+  const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+int check_sys(const gpaw_sys *s) {
+  if (!s) return fail(GPAW_EINVAL, "system is NULL");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != s->device)
+    return fail(GPAW_EINVAL, "current HIP device differs from the system's device");
+  return GPAW_OK;
+}
+
+int check_nb(const gpaw_sys *s, int32_t nb) {
+  if (nb < 1 || nb > s->max_bands)
+    return fail(GPAW_ESHAPE, "nb=" + std::to_string(nb) + " outside [1, max_bands=" +
+                                 std::to_string(s->max_bands) + "]");
+  return GPAW_OK;
+}
+
+int after_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, what);
+  return GPAW_OK;
+}
+
+void free_sys(gpaw_sys *s) {
+  if (!s) return;
+  void *bufs[] = {s->tab.a_start, s->tab.e_g,  s->tab.e_q, s->tab.g2u, s->tab.u_start,
+                  s->tab.pm_atom, s->tab.pm_q, s->dH,      s->dS,      s->v,
+                  s->ws.P,        s->ws.X,     s->ws.part, s->ws.eig,  s->ws.info};
+  for (void *p : bufs)
+    if (p) (void)hipFree(p);
+  delete s;
+}
+
+template <typename T>
+int dev_alloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return GPAW_OK;
+  GFD_HIP(hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T)));
+  return GPAW_OK;
+}
+
+}  // namespace
+}  // namespace gfd
+
+using namespace gfd;
+
+extern "C" {
+
+const char *gpaw_last_error(void) { return g_last_error.c_str(); }
+
+int gpaw_version(void) { return GPAW_FD_VERSION; }
+
+int gpaw_sys_create(const gpaw_sys_desc *d, gpaw_sys **out) {
+  if (!d || !out) return fail(GPAW_EINVAL, "desc and out must not be NULL");
+  *out = nullptr;
+  int64_t ng = 1;
+  for (int c = 0; c < 3; ++c) {
+    if (d->n[c] < 1) return fail(GPAW_EINVAL, "grid sizes must be >= 1");
+    if (!(d->h[c] > 0.0) || !std::isfinite(d->h[c]))
+      return fail(GPAW_EINVAL, "grid spacings must be finite and > 0");
+    if (!std::isfinite(d->k[c])) return fail(GPAW_EINVAL, "k must be finite");
+    ng *= d->n[c];
+  }
+  if (ng > (int64_t(1) << 31) - 1) return fail(GPAW_EINVAL, "grid has more than 2^31-1 points");
+  if (d->dtype != GPAW_F64 && d->dtype != GPAW_C128) return fail(GPAW_EDTYPE, "unknown dtype");
+  if (d->dtype == GPAW_F64 && (d->k[0] != 0.0 || d->k[1] != 0.0 || d->k[2] != 0.0))
+    return fail(GPAW_EDTYPE, "a real (GPAW_F64) system needs k = 0; use GPAW_C128");
+  if (d->natoms < 0) return fail(GPAW_EINVAL, "natoms must be >= 0");
+  if (!d->v) return fail(GPAW_EINVAL, "v must not be NULL");
+  if (d->max_bands < 1) return fail(GPAW_EINVAL, "max_bands must be >= 1");
+  int ni = 0;
+  if (d->natoms > 0) {
+    if (!d->pos || !d->dH || !d->dS || !d->chan || d->nchan < 1)
+      return fail(GPAW_EINVAL, "atoms need pos, dH, dS and at least one channel");
+    for (int c = 0; c < d->nchan; ++c) {
+      const gpaw_channel &ch = d->chan[c];
+      if (ch.l < 0 || ch.l > 2) return fail(GPAW_EINVAL, "channel l must be 0, 1 or 2");
+      if (!(ch.sigma > 0.0) || !(ch.rc > 0.0) || !std::isfinite(ch.sigma) || !std::isfinite(ch.rc))
+        return fail(GPAW_EINVAL, "channel sigma and rc must be finite and > 0");
+      ni += 2 * ch.l + 1;
+    }
+    if (ni > 32) return fail(GPAW_EINVAL, "at most 32 projectors per atom");
+    for (int a = 0; a < 3 * d->natoms; ++a)
+      if (!std::isfinite(d->pos[a])) return fail(GPAW_EINVAL, "atom positions must be finite");
+  }
+  int dev = 0;
+  GFD_HIP(hipGetDevice(&dev));
+
+  gpaw_sys *s = new gpaw_sys();
+  s->device = dev;
+  for (int c = 0; c < 3; ++c) {
+    s->n[c] = d->n[c];
+    s->h[c] = d->h[c];
+    s->k[c] = d->k[c];
+    const double arg = 2.0 * 3.14159265358979323846 * d->k[c];
+    s->phase[c] = zmake(std::cos(arg), std::sin(arg));
+  }
+  s->dV = d->h[0] * d->h[1] * d->h[2];
+  s->dtype = d->dtype;
+  s->natoms = d->natoms;
+  s->ni = d->natoms > 0 ? ni : 0;
+  s->np = s->natoms * s->ni;
+  s->ng = ng;
+  s->max_bands = d->max_bands;
+
+  int rc = GPAW_OK;
+  const size_t es = elem_size(s->dtype);
+  do {
+    if (s->natoms > 0) {
+      if ((rc = build_tables(d, s)) != GPAW_OK) break;
+      const size_t nd = static_cast<size_t>(s->natoms) * s->ni * s->ni;
+      if ((rc = dev_alloc(&s->dH, nd)) != GPAW_OK) break;
+      if ((rc = dev_alloc(&s->dS, nd)) != GPAW_OK) break;
+      if (hipMemcpy(s->dH, d->dH, nd * 8, hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(s->dS, d->dS, nd * 8, hipMemcpyHostToDevice) != hipSuccess) {
+        rc = fail(GPAW_EHIP, "upload of Delta H / Delta S failed");
+        break;
+      }
+      const size_t pbytes = static_cast<size_t>(s->max_bands) * s->np * es;
+      if ((rc = dev_alloc(reinterpret_cast<char **>(&s->ws.P), pbytes)) != GPAW_OK) break;
+      if ((rc = dev_alloc(reinterpret_cast<char **>(&s->ws.X), pbytes)) != GPAW_OK) break;
+    }
+    if ((rc = dev_alloc(&s->v, static_cast<size_t>(ng))) != GPAW_OK) break;
+    if (hipMemcpy(s->v, d->v, ng * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      rc = fail(GPAW_EHIP, "upload of v failed");
+      break;
+    }
+    s->ws.part_elems = subspace_part_elems(s, s->max_bands);
+    if ((rc = dev_alloc(&s->ws.part, s->ws.part_elems)) != GPAW_OK) break;
+    s->ws.eig_elems = eig_ws_elems(s->max_bands, s->dtype == GPAW_C128);
+    if ((rc = dev_alloc(&s->ws.eig, s->ws.eig_elems)) != GPAW_OK) break;
+    if ((rc = dev_alloc(&s->ws.info, 1)) != GPAW_OK) break;
+  } while (false);
+  if (rc != GPAW_OK) {
+    free_sys(s);
+    return rc;
+  }
+  *out = s;
+  return GPAW_OK;
+}
+
+void gpaw_sys_destroy(gpaw_sys *s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  free_sys(s);
+}
+
+int gpaw_sys_info(const gpaw_sys *s, int64_t *info) {
+  if (!s || !info) return fail(GPAW_EINVAL, "system and info must not be NULL");
+  info[0] = s->ng;
+  info[1] = s->np;
+  info[2] = s->ni;
+  info[3] = s->natoms;
+  info[4] = s->tab.nent;
+  info[5] = s->tab.nu;
+  info[6] = s->max_bands;
+  info[7] = s->dtype;
+  return GPAW_OK;
+}
+
+int gpaw_project(gpaw_sys *s, const void *psi, int32_t nb, void *P, void *stream) {
+  int rc;
+  if ((rc = check_sys(s)) != GPAW_OK) return rc;
+  if ((rc = check_nb(s, nb)) != GPAW_OK) return rc;
+  if (!psi) return fail(GPAW_EINVAL, "psi must not be NULL");
+  if (s->np == 0) return GPAW_OK;
+  if (!P) return fail(GPAW_EINVAL, "P must not be NULL");
+  const size_t es = elem_size(s->dtype);
+  if (overlaps(P, nb * s->np * es, psi, nb * s->ng * es))
+    return fail(GPAW_EALIAS, "P overlaps psi");
+  if ((rc = launch_project(s, psi, nb, P, static_cast<hipStream_t>(stream))) != GPAW_OK) return rc;
+  return after_launch("gpaw_project");
+}
+
+namespace {
+
+int apply(gpaw_sys *s, const void *psi, int32_t nb, const void *P, void *out, void *stream,
+          bool hamiltonian) {
+  int rc;
+  if ((rc = check_sys(s)) != GPAW_OK) return rc;
+  if ((rc = check_nb(s, nb)) != GPAW_OK) return rc;
+  if (!psi || !out) return fail(GPAW_EINVAL, "psi and output must not be NULL");
+  const size_t es = elem_size(s->dtype);
+  const size_t bytes = static_cast<size_t>(nb) * s->ng * es;
+  if (overlaps(out, bytes, psi, bytes)) return fail(GPAW_EALIAS, "output overlaps psi");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const void *X = nullptr;
+  if (s->np > 0) {
+    const size_t pbytes = static_cast<size_t>(nb) * s->np * es;
+    if (P && overlaps(out, bytes, P, pbytes)) return fail(GPAW_EALIAS, "output overlaps P");
+    if (!P) {
+      if ((rc = launch_project(s, psi, nb, s->ws.P, st)) != GPAW_OK) return rc;
+      P = s->ws.P;
+    }
+    if ((rc = launch_dmat(s, hamiltonian ? s->dH : s->dS, P, nb, s->ws.X, st)) != GPAW_OK)
+      return rc;
+    X = s->ws.X;
+  }
+  rc = hamiltonian ? launch_stencil(s, psi, nb, X, out, st) : launch_apply_S(s, psi, nb, X, out, st);
+  if (rc != GPAW_OK) return rc;
+  return after_launch(hamiltonian ? "gpaw_fd_apply_H" : "gpaw_fd_apply_S");
+}
+
+}  // namespace
+
+int gpaw_fd_apply_H(gpaw_sys *s, const void *psi, int32_t nb, const void *P, void *Hpsi,
+                    void *stream) {
+  return apply(s, psi, nb, P, Hpsi, stream, true);
+}
+
+int gpaw_fd_apply_S(gpaw_sys *s, const void *psi, int32_t nb, const void *P, void *Spsi,
+                    void *stream) {
+  return apply(s, psi, nb, P, Spsi, stream, false);
+}
+
+int gpaw_subspace_matrices(gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
+                           int32_t nb, void *H, void *S, void *stream) {
+  int rc;
+  if ((rc = check_sys(s)) != GPAW_OK) return rc;
+  if ((rc = check_nb(s, nb)) != GPAW_OK) return rc;
+  if (!psi || !Hpsi || !H) return fail(GPAW_EINVAL, "psi, Hpsi and H_nn must not be NULL");
+  if (Spsi && !S) return fail(GPAW_EINVAL, "S_nn must not be NULL when Spsi is given");
+  const size_t mbytes = static_cast<size_t>(nb) * nb * elem_size(s->dtype);
+  if (Spsi && overlaps(H, mbytes, S, mbytes)) return fail(GPAW_EALIAS, "H_nn overlaps S_nn");
+  if ((rc = launch_subspace(s, psi, Hpsi, Spsi, nb, H, Spsi ? S : nullptr,
+                            static_cast<hipStream_t>(stream))) != GPAW_OK)
+    return rc;
+  return after_launch("gpaw_subspace_matrices");
+}
+
+int gpaw_subspace_diag(gpaw_sys *s, const void *H, const void *S, int32_t nb, double *eps,
+                       void *C, int32_t *info, void *stream) {
+  int rc;
+  if ((rc = check_sys(s)) != GPAW_OK) return rc;
+  if ((rc = check_nb(s, nb)) != GPAW_OK) return rc;
+  if (nb > 128) return fail(GPAW_ESHAPE, "gpaw_subspace_diag supports nb <= 128");
+  if (!H || !S || !eps || !C) return fail(GPAW_EINVAL, "H_nn, S_nn, eps and C_nn must not be NULL");
+  const size_t mbytes = static_cast<size_t>(nb) * nb * elem_size(s->dtype);
+  if (overlaps(C, mbytes, H, mbytes) || overlaps(C, mbytes, S, mbytes) ||
+      overlaps(eps, nb * 8, C, mbytes) || overlaps(eps, nb * 8, H, mbytes) ||
+      overlaps(eps, nb * 8, S, mbytes))
+    return fail(GPAW_EALIAS, "outputs of gpaw_subspace_diag overlap its inputs");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int32_t *dinfo = info ? info : s->ws.info;
+  if ((rc = launch_eigh(s, H, S, nb, eps, C, dinfo, st)) != GPAW_OK) return rc;
+  if ((rc = after_launch("gpaw_subspace_diag")) != GPAW_OK) return rc;
+  if (info) return GPAW_OK;
+  int32_t h_info = 0;
+  GFD_HIP(hipMemcpyAsync(&h_info, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  GFD_HIP(hipStreamSynchronize(st));
+  if (h_info > 0)
+    return fail(GPAW_ENOTPD, "S_nm is not positive definite (leading minor " +
+                                 std::to_string(h_info) + ")");
+  if (h_info < 0) return fail(GPAW_ENOCONV, "eigenvector orthogonalisation did not settle");
+  return GPAW_OK;
+}
+
+int gpaw_rotate(gpaw_sys *s, const void *psi, const void *C, int32_t nb, void *psi_out,
+                const void *P, void *P_out, void *stream) {
+  int rc;
+  if ((rc = check_sys(s)) != GPAW_OK) return rc;
+  if ((rc = check_nb(s, nb)) != GPAW_OK) return rc;
+  if (!psi || !C || !psi_out) return fail(GPAW_EINVAL, "psi, C_nn and psi_out must not be NULL");
+  if ((P == nullptr) != (P_out == nullptr))
+    return fail(GPAW_EINVAL, "P and P_out must be both NULL or both set");
+  const size_t es = elem_size(s->dtype);
+  const size_t bytes = static_cast<size_t>(nb) * s->ng * es;
+  const size_t pbytes = static_cast<size_t>(nb) * s->np * es;
+  if (overlaps(psi_out, bytes, psi, bytes)) return fail(GPAW_EALIAS, "psi_out overlaps psi");
+  if (overlaps(psi_out, bytes, C, static_cast<size_t>(nb) * nb * es))
+    return fail(GPAW_EALIAS, "psi_out overlaps C_nn");
+  if (P && s->np > 0 && (overlaps(P_out, pbytes, P, pbytes) || overlaps(P_out, pbytes, psi_out, bytes)))
+    return fail(GPAW_EALIAS, "P_out overlaps P or psi_out");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = launch_rotate(s, C, psi, nb, s->ng, psi_out, st)) != GPAW_OK) return rc;
+  if (P && s->np > 0)
+    if ((rc = launch_rotate(s, C, P, nb, s->np, P_out, st)) != GPAW_OK) return rc;
+  return after_launch("gpaw_rotate");
+}
+
+}  // extern "C"

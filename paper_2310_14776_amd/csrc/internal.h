@@ -1,0 +1,132 @@
+// Internal declarations of the gfx950 FD-PAW library: the system object,
+// error plumbing, complex helpers and the kernel launchers each .hip file
+// provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "gpaw_fd.h"
+
+namespace gfd {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t err, const char *what);
+
+#define GFD_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return ::gfd::hip_fail(e_, #call); \
+  } while (0)
+
+// ---------------------------------------------------------------- complex
+struct z64 {
+  double x, y;
+};
+
+__host__ __device__ inline z64 zmake(double a, double b) { return z64{a, b}; }
+__host__ __device__ inline z64 operator+(z64 a, z64 b) { return z64{a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline z64 operator-(z64 a, z64 b) { return z64{a.x - b.x, a.y - b.y}; }
+__host__ __device__ inline z64 operator*(z64 a, z64 b) {
+  return z64{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__host__ __device__ inline z64 operator*(double s, z64 a) { return z64{s * a.x, s * a.y}; }
+__host__ __device__ inline z64 zconj(z64 a) { return z64{a.x, -a.y}; }
+
+// Scalar traits: one kernel body serves real and complex grids.
+template <typename T> struct St;
+template <> struct St<double> {
+  static constexpr bool cplx = false;
+  __host__ __device__ static double zero() { return 0.0; }
+  __host__ __device__ static double conj(double a) { return a; }
+  // a * b where b is a Bloch phase (identity for real systems)
+  __host__ __device__ static double phase(double a, z64) { return a; }
+  __host__ __device__ static double mul(double a, double b) { return a * b; }
+  __host__ __device__ static double scale(double s, double a) { return s * a; }
+};
+template <> struct St<z64> {
+  static constexpr bool cplx = true;
+  __host__ __device__ static z64 zero() { return z64{0.0, 0.0}; }
+  __host__ __device__ static z64 conj(z64 a) { return zconj(a); }
+  __host__ __device__ static z64 phase(z64 a, z64 p) { return a * p; }
+  __host__ __device__ static z64 mul(z64 a, z64 b) { return a * b; }
+  __host__ __device__ static z64 scale(double s, z64 a) { return s * a; }
+};
+
+// ---------------------------------------------------------------- system
+// Projector tables: entries are (atom, grid point) pairs with at least one
+// image of the atom's sphere covering the point. Two orders of the same
+// entries: atom-major (for the projection gather) and point-major (for the
+// add-back, where each covered point sums over the atoms that reach it).
+struct Tables {
+  int64_t nent = 0;      // entries
+  int64_t nu = 0;        // distinct covered grid points
+  int32_t *a_start = nullptr;   // [natoms+1] atom-major entry ranges
+  int32_t *e_g = nullptr;       // [nent] grid index (atom-major)
+  void *e_q = nullptr;          // [ni][nent] projector values (atom-major)
+  int32_t *g2u = nullptr;       // [Ng] covered-point index or -1
+  int32_t *u_start = nullptr;   // [nu+1] point-major entry ranges
+  int32_t *pm_atom = nullptr;   // [nent] atom of each point-major entry
+  void *pm_q = nullptr;         // [ni][nent] projector values (point-major)
+};
+
+struct Workspace {
+  void *P = nullptr;       // [max_bands][Np] projections when the caller gives none
+  void *X = nullptr;       // [max_bands][Np] Delta.P
+  double *part = nullptr;  // subspace split-K partial sums
+  size_t part_elems = 0;
+  double *eig = nullptr;   // dense eigensolver scratch
+  size_t eig_elems = 0;
+  int32_t *info = nullptr; // device status word for synchronous diag
+};
+
+}  // namespace gfd
+
+struct gpaw_sys {
+  int device = 0;
+  int32_t n[3] = {0, 0, 0};
+  double h[3] = {0, 0, 0};
+  double k[3] = {0, 0, 0};
+  double dV = 0;
+  int32_t dtype = GPAW_F64;
+  gfd::z64 phase[3];       // exp(2 pi i k_c)
+  int32_t natoms = 0, ni = 0, np = 0;
+  int64_t ng = 0;
+  int32_t max_bands = 0;
+  gfd::Tables tab;
+  double *dH = nullptr, *dS = nullptr;  // device [natoms][ni][ni]
+  double *v = nullptr;                  // device [Ng]
+  gfd::Workspace ws;
+};
+
+namespace gfd {
+
+size_t elem_size(int32_t dtype);
+
+// Host construction of the projector tables (tables.hip).
+struct HostTables;
+int build_tables(const gpaw_sys_desc *d, gpaw_sys *s);
+
+// ---------------------------------------------------------------- launchers
+// Each returns GPAW_OK or an error code with the message set.
+int launch_project(const gpaw_sys *s, const void *psi, int nb, void *P, hipStream_t st);
+int launch_dmat(const gpaw_sys *s, const double *D, const void *P, int nb, void *X,
+                hipStream_t st);
+int launch_stencil(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,
+                   hipStream_t st);
+int launch_apply_S(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,
+                   hipStream_t st);
+int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
+                    int nb, void *H, void *S, hipStream_t st);
+size_t subspace_part_elems(const gpaw_sys *s, int nb);
+int launch_rotate(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
+                  void *dst, hipStream_t st);
+size_t eig_ws_elems(int nmax, bool cplx);
+int launch_eigh(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps, void *C,
+                int32_t *info, hipStream_t st);
+
+}  // namespace gfd
