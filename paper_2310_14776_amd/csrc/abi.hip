@@ -56,9 +56,9 @@ int after_launch(const char *what) {
 
 void free_sys(gpaw_sys *s) {
   if (!s) return;
-  void *bufs[] = {s->tab.a_start, s->tab.e_g,  s->tab.e_q, s->tab.g2u, s->tab.u_start,
-                  s->tab.pm_atom, s->tab.pm_q, s->dH,      s->dS,      s->v,
-                  s->ws.P,        s->ws.X,     s->ws.part, s->ws.eig,  s->ws.info};
+  void *bufs[] = {s->tab.a_start, s->tab.e_g, s->tab.e_xyz, s->tab.estart, s->tab.pm_code,
+                  s->tab.pos,     s->dH,      s->dS,        s->v,          s->ws.P,
+                  s->ws.X,        s->ws.part, s->ws.eig,    s->ws.info,    s->tab.proj};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   delete s;
@@ -185,7 +185,7 @@ int gpaw_sys_info(const gpaw_sys *s, int64_t *info) {
   info[2] = s->ni;
   info[3] = s->natoms;
   info[4] = s->tab.nent;
-  info[5] = s->tab.nu;
+  info[5] = s->tab.ncov;
   info[6] = s->max_bands;
   info[7] = s->dtype;
   return GPAW_OK;

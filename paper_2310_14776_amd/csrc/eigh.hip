@@ -3,25 +3,26 @@
 // matrices, Sec. "Parallelization"; SCF step (1), Sec. "Solving the
 // Kohn-Sham equation").
 //
-// Pipeline (real symmetric, nb <= 128):
-//   k_eig_reduce  (1 workgroup, 1024 lanes, matrix in LDS)
-//       S <- (S+S^T)/2;  S = L L^T (right-looking, one barrier per column);
-//       Linv = L^-1 (column-parallel forward substitution, 8 lanes per column);
-//       A = Linv ((H+H^T)/2) Linv^T;  A <- (A+A^T)/2;
-//       Householder tridiagonalisation A = Q T Q^T (reflectors kept for later).
-//   k_eig_values  (one wavefront per eigenvalue)
-//       T splits where |e_i| <= eps (|d_i| + |d_i+1|); each eigenvalue is found
-//       in its unreduced block by 65-way multisection on Sturm counts.
-//   k_eig_vectors (one lane per eigenvalue, LDS scratch)
-//       inverse iteration on the block with a pivoted tridiagonal LU; shifts of
-//       eigenvalues closer than 10 eps ||T|| are pulled apart by that amount.
-//   k_eig_finish  (1 workgroup)
-//       Newton-Schulz steps Z <- Z (3I - Z^T Z)/2 until Z^T Z = I to 1e-8
-//       (each step squares the defect); back-transform U = Q Z; eigen-order by
-//       value; C = Linv^T U.
+// Pipeline (real symmetric, nb <= 128), all on one stream:
+//   k_eig_chol     (1 workgroup, matrix in LDS) S <- (S+S^T)/2 = L L^T,
+//                  Linv = L^-1 by column-parallel forward substitution;
+//   k_small_gemm   A = Linv ((H+H^T)/2) Linv^T on FP64 MFMA (two products);
+//   k_eig_tridiag  (1 workgroup, A in LDS) Householder A = Q T Q^T;
+//   k_eig_values   (one wavefront per eigenvalue) T splits where
+//                  |e_i| <= eps (|d_i| + |d_i+1|); each eigenvalue is found in
+//                  its unreduced block by 65-way multisection on Sturm counts;
+//   k_eig_vectors  (one lane per eigenvalue) inverse iteration with a pivoted
+//                  tridiagonal LU; shifts closer than 10 eps ||T|| are pulled
+//                  apart by that amount;
+//   Newton-Schulz  two steps Z <- Z (3I - Z^T Z)/2 (each squares the
+//                  orthogonality defect; the second Gram matrix must be
+//                  within 1e-7 of I);
+//   k_eig_back     (8 lanes per column, reflectors in LDS) U = Q Z written
+//                  in eigen-order; then C = Linv^T U on MFMA.
 #include <algorithm>
 #include <cfloat>
 #include <mutex>
+#include <string>
 
 #include "internal.h"
 
@@ -31,26 +32,35 @@ namespace {
 
 constexpr int EIG_T = 1024;
 constexpr int EIG_NMAX = 128;
-constexpr int VEC_T = 16;  // lanes (eigenvectors) per inverse-iteration workgroup
+constexpr int VEC_T = 8;  // lanes (eigenvectors) per inverse-iteration workgroup
+constexpr int SG_T = 256;  // small-GEMM workgroup: four 16x16 output tiles
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Matrices Linv, T1, A, V and tau hold the system's scalar (double or
+// complex); Z, Z2, G, d, e, lam are real. Pointers are to doubles.
 struct EigWs {
-  double *Linv, *T1, *V, *Z, *Z2, *tau, *d, *e, *lam;
+  double *Linv, *T1, *A, *V, *Z, *Z2, *G, *tau, *d, *e, *lam;
 };
 
-EigWs eig_layout(double *base, int n) {
+EigWs eig_layout(double *base, int n, int sz) {
   const size_t nn = static_cast<size_t>(n) * n;
   EigWs w;
   w.Linv = base;
-  w.T1 = w.Linv + nn;
-  w.V = w.T1 + nn;
-  w.Z = w.V + nn;
+  w.T1 = w.Linv + sz * nn;
+  w.A = w.T1 + sz * nn;
+  w.V = w.A + sz * nn;
+  w.Z = w.V + sz * nn;
   w.Z2 = w.Z + nn;
-  w.tau = w.Z2 + nn;
-  w.d = w.tau + n;
+  w.G = w.Z2 + nn;
+  w.tau = w.G + nn;
+  w.d = w.tau + sz * n;
   w.e = w.d + n;
   w.lam = w.e + n;
   return w;
 }
+
+template <typename T> __device__ inline T *as(double *p) { return reinterpret_cast<T *>(p); }
 
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
@@ -65,50 +75,87 @@ __device__ inline double wave_min(double v) {
   return v;
 }
 
+__device__ inline z64 wave_sum(z64 v) { return z64{wave_sum(v.x), wave_sum(v.y)}; }
+
+// 8-lane group reductions (lanes 8q..8q+7)
+__device__ inline double group8_sum(double v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 4);
+  return v;
+}
+__device__ inline z64 group8_sum(z64 v) { return z64{group8_sum(v.x), group8_sum(v.y)}; }
+
+// real / complex helpers
+__device__ inline double re_of(double a) { return a; }
+__device__ inline double re_of(z64 a) { return a.x; }
+__device__ inline double abs2(double a) { return a * a; }
+__device__ inline double abs2(z64 a) { return a.x * a.x + a.y * a.y; }
+__device__ inline double cj(double a) { return a; }
+__device__ inline z64 cj(z64 a) { return zconj(a); }
+__device__ inline z64 operator*(z64 a, double s) { return z64{a.x * s, a.y * s}; }
+
+template <typename T> __device__ inline T realv(double r);
+template <> __device__ inline double realv<double>(double r) { return r; }
+template <> __device__ inline z64 realv<z64>(double r) { return z64{r, 0.0}; }
+
+template <typename T> struct EigMax;
+template <> struct EigMax<double> { static constexpr int n = 128; };
+template <> struct EigMax<z64> { static constexpr int n = 96; };
+
 __device__ inline bool split_at(const double *d, const double *e, int i) {
   return fabs(e[i]) <= DBL_EPSILON * (fabs(d[i]) + fabs(d[i + 1]));
 }
 
-// ------------------------------------------------------------------ reduce
-__global__ __launch_bounds__(EIG_T) void k_eig_reduce(const double *__restrict__ H,
-                                                      const double *__restrict__ S, int n,
-                                                      EigWs w, int32_t *info) {
+// ------------------------------------------------------------------ Cholesky
+// S <- (S+S^H)/2 = L L^H in LDS, then Linv = L^-1 to global memory.
+// Thread (ty, tx) = (tid/32, tid%32) owns rows ty+32a and columns tx+32b.
+template <typename T>
+__global__ __launch_bounds__(EIG_T) void k_eig_chol(const T *__restrict__ S, int n, EigWs w,
+                                                    int32_t *info) {
   extern __shared__ double sm[];
+  constexpr int NMAX = EigMax<T>::n;
   const int lda = n + 1;
-  double *A = sm;              // [n][lda]
-  double *vv = A + n * lda;    // Householder vector
-  double *pp = vv + n;         // tau * A v
-  double *dinv = pp + n;       // 1 / L_jj
-  double *red = dinv + n;      // 16 wavefront partials
-  double *scal = red + 16;     // tau of the current step
+  T *A = reinterpret_cast<T *>(sm);
+  double *dinv = reinterpret_cast<double *>(A + n * lda);
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int ty = tid >> 5, tx = tid & 31;
 
-  for (int idx = tid; idx < n * n; idx += EIG_T) {
-    const int i = idx / n, j = idx - i * n;
-    A[i * lda + j] = 0.5 * (S[i * n + j] + S[j * n + i]);
-  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int r = ty + 32 * a, c = tx + 32 * b;
+      if (r < n && c < n) A[r * lda + c] = St<T>::scale(0.5, S[r * n + c] + cj(S[c * n + r]));
+    }
   __syncthreads();
 
-  // Cholesky, lower. Column j is scaled one step late so that the trailing
-  // update of step j and the scaling of column j-1 touch disjoint entries.
+  // right-looking, lower; column j-1 is scaled while step j updates j+1..n-1
   int failed = 0;
   double prev_rs = 0.0;
   for (int j = 0; j < n; ++j) {
-    const double djj = A[j * lda + j];
+    const double djj = re_of(A[j * lda + j]);
     if (!(djj > 0.0)) {
       failed = j + 1;
       break;
     }
-    if (j > 0)
-      for (int i = j + tid; i < n; i += EIG_T) A[i * lda + j - 1] *= prev_rs;
-    const int m = n - j - 1;
+    if (j > 0 && tid < n && tid >= j) A[tid * lda + j - 1] = A[tid * lda + j - 1] * prev_rs;
     const double inv = 1.0 / djj;
-    for (int idx = tid; idx < m * m; idx += EIG_T) {
-      const int ii = idx / m, cc = idx - ii * m;
-      if (cc <= ii) {
-        const int i = j + 1 + ii, c = j + 1 + cc;
-        A[i * lda + c] -= A[i * lda + j] * A[c * lda + j] * inv;
+    T lc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int c = tx + 32 * b;
+      lc[b] = (c > j && c < n) ? cj(A[c * lda + j]) * inv : T{};
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int r = ty + 32 * a;
+      if (r <= j || r >= n) continue;
+      const T lr = A[r * lda + j];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int c = tx + 32 * b;
+        if (c > j && c <= r) A[r * lda + c] = A[r * lda + c] - lr * lc[b];
       }
     }
     prev_rs = 1.0 / sqrt(djj);
@@ -118,191 +165,245 @@ __global__ __launch_bounds__(EIG_T) void k_eig_reduce(const double *__restrict__
     if (tid == 0) *info = failed;
     return;
   }
-  for (int j = tid; j < n; j += EIG_T) {
-    const double r = sqrt(A[j * lda + j]);
-    A[j * lda + j] = r;
-    dinv[j] = 1.0 / r;
+  if (tid < n) {
+    const double r = sqrt(re_of(A[tid * lda + tid]));
+    A[tid * lda + tid] = realv<T>(r);
+    dinv[tid] = 1.0 / r;
   }
   __syncthreads();
 
-  // Linv: column col by 8 lanes; lane s keeps x_{8t+s} in xr[t]
-  {
-    const int col = tid >> 3, s = tid & 7;
-    double xr[EIG_NMAX / 8];
+  // Linv column col by 8 lanes; lane s keeps rows 8t+s in xr[t]
+  T *Linv = as<T>(w.Linv);
+  const int col = tid >> 3, s = tid & 7;
+  T xr[NMAX / 8];
 #pragma unroll
-    for (int t = 0; t < EIG_NMAX / 8; ++t) xr[t] = 0.0;
-    if (col < n) {
-      for (int i = col; i < n; ++i) {
-        double part = 0.0;
+  for (int t = 0; t < NMAX / 8; ++t) xr[t] = T{};
+  if (col < n) {
+    for (int i = col; i < n; ++i) {
+      T part = T{};
+      const T *Li = A + i * lda;
 #pragma unroll
-        for (int t = 0; t < EIG_NMAX / 8; ++t) {
-          const int kk = 8 * t + s;
-          if (kk >= col && kk < i) part += A[i * lda + kk] * xr[t];
-        }
-        part += __shfl_xor(part, 1);
-        part += __shfl_xor(part, 2);
-        part += __shfl_xor(part, 4);
-        const double xi = (i == col) ? dinv[i] : -part * dinv[i];
-#pragma unroll
-        for (int t = 0; t < EIG_NMAX / 8; ++t)
-          if (8 * t + s == i) xr[t] = xi;
+      for (int t = 0; t < NMAX / 8; ++t) {
+        const int kk = 8 * t + s;
+        if (kk >= col && kk < i) part = part + Li[kk] * xr[t];
       }
+      part = group8_sum(part);
+      const T xi = (i == col) ? realv<T>(dinv[i]) : part * (-dinv[i]);
 #pragma unroll
-      for (int t = 0; t < EIG_NMAX / 8; ++t) {
-        const int row = 8 * t + s;
-        if (row < n) w.Linv[row * n + col] = xr[t];
+      for (int t = 0; t < NMAX / 8; ++t)
+        if (8 * t + s == i) xr[t] = xi;
+    }
+#pragma unroll
+    for (int t = 0; t < NMAX / 8; ++t) {
+      const int row = 8 * t + s;
+      if (row < n) Linv[row * n + col] = xr[t];
+    }
+  }
+  if (tid == 0) *info = 0;
+}
+
+// ------------------------------------------------------------------ small GEMM
+// C = op(A) op(B) for n x n row-major matrices on FP64 MFMA, one 16x16 tile
+// per wavefront. Operand modes:
+//   A: 0 = A, 1 = A^H, 2 = (A + A^H)/2
+//   B: 0 = B, 1 = B^H, 3 = 1.5 I - 0.5 B
+template <typename T>
+__device__ inline T opval(const T *M, int mode, int r, int c, int n) {
+  switch (mode) {
+    case 0: return M[r * n + c];
+    case 1: return cj(M[c * n + r]);
+    case 2: return St<T>::scale(0.5, M[r * n + c] + cj(M[c * n + r]));
+    default: return realv<T>(r == c ? 1.5 : 0.0) - St<T>::scale(0.5, M[r * n + c]);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(SG_T) void k_small_gemm(const T *__restrict__ A, int amode,
+                                                     const T *__restrict__ B, int bmode,
+                                                     T *__restrict__ C, int n,
+                                                     const int32_t *info) {
+  if (*info != 0) return;
+  constexpr bool CX = St<T>::cplx;
+  const int lane = threadIdx.x & 63;
+  const int tiles_n = (n + 15) / 16;
+  const int tile = blockIdx.x * (SG_T / 64) + (threadIdx.x >> 6);
+  if (tile >= tiles_n * tiles_n) return;
+  const int i0 = (tile / tiles_n) * 16, j0 = (tile % tiles_n) * 16;
+  const int li = lane & 15, lk = lane >> 4;
+  d4 accr = {0.0, 0.0, 0.0, 0.0}, acci = {0.0, 0.0, 0.0, 0.0};
+  const int r = i0 + li, c = j0 + li;
+  for (int k0 = 0; k0 < n; k0 += 32) {
+    T a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + 4 * u + lk;
+      a[u] = (r < n && k < n) ? opval(A, amode, r, k, n) : T{};
+      b[u] = (c < n && k < n) ? opval(B, bmode, k, c, n) : T{};
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if constexpr (CX) {
+        const z64 au = a[u], bu = b[u];
+        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(au.x, bu.x, accr, 0, 0, 0);
+        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-au.y, bu.y, accr, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(au.x, bu.y, acci, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(au.y, bu.x, acci, 0, 0, 0);
+      } else {
+        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(re_of(a[u]), re_of(b[u]), accr, 0, 0, 0);
       }
     }
   }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int rr = i0 + lk + 4 * e, cc = j0 + li;
+    if (rr < n && cc < n) {
+      if constexpr (CX) C[rr * n + cc] = T{accr[e], acci[e]};
+      else C[rr * n + cc] = accr[e];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ tridiagonal
+// A (global, made Hermitian on load) -> LDS; Householder A = Q T Q^H with
+// H_k = I - tau_k v_k v_k^H chosen so that T is real symmetric (the
+// sub-diagonal beta_k is real). Reflector k is kept in column k of A below
+// the diagonal (that column is not read again), so the loop issues no
+// global stores; V, tau, d, e go out at the end.
+template <typename T>
+__global__ __launch_bounds__(EIG_T) void k_eig_tridiag(int n, EigWs w, const int32_t *info) {
+  if (*info != 0) return;
+  extern __shared__ double sm[];
+  const int lda = n + 1;
+  T *A = reinterpret_cast<T *>(sm);
+  T *vv = A + n * lda;
+  T *pp = vv + n;
+  T *taus = pp + n;
+  double *dd = reinterpret_cast<double *>(taus + n);
+  double *ee = dd + n;
+  T *red = reinterpret_cast<T *>(ee + n);  // 16 wavefront partials
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int ty = tid >> 5, tx = tid & 31;
+  const T *Ag = as<T>(w.A);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int r = ty + 32 * a, c = tx + 32 * b;
+      if (r < n && c < n) A[r * lda + c] = St<T>::scale(0.5, Ag[r * n + c] + cj(Ag[c * n + r]));
+    }
   __syncthreads();
 
-  // Hs in LDS; T1 = Hs Linv^T (global); A = Linv T1 (LDS)
-  for (int idx = tid; idx < n * n; idx += EIG_T) {
-    const int i = idx / n, j = idx - i * n;
-    A[i * lda + j] = 0.5 * (H[i * n + j] + H[j * n + i]);
-  }
-  __syncthreads();
-  {
-    const int i0 = (tid >> 5) * 4, j0 = (tid & 31) * 4;
-    if (i0 < n && j0 < n) {
-      double acc[4][4] = {};
-      const int kmax = min(n, j0 + 4);
-      for (int kk = 0; kk < kmax; ++kk) {
-        double a[4], b[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = (i0 + r < n) ? A[(i0 + r) * lda + kk] : 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = (j0 + c < n) ? w.Linv[(j0 + c) * n + kk] : 0.0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          if (i0 + r < n && j0 + c < n) w.T1[(i0 + r) * n + j0 + c] = acc[r][c];
-    }
-  }
-  __syncthreads();
-  {
-    const int i0 = (tid >> 5) * 4, j0 = (tid & 31) * 4;
-    if (i0 < n && j0 < n) {
-      double acc[4][4] = {};
-      const int kmax = min(n, i0 + 4);
-      for (int kk = 0; kk < kmax; ++kk) {
-        double a[4], b[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = (i0 + r < n) ? w.Linv[(i0 + r) * n + kk] : 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = (j0 + c < n) ? w.T1[kk * n + j0 + c] : 0.0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          if (i0 + r < n && j0 + c < n) A[(i0 + r) * lda + j0 + c] = acc[r][c];
-    }
-  }
-  __syncthreads();
-  for (int idx = tid; idx < n * n; idx += EIG_T) {
-    const int i = idx / n, j = idx - i * n;
-    if (i < j) {
-      const double avg = 0.5 * (A[i * lda + j] + A[j * lda + i]);
-      A[i * lda + j] = avg;
-      A[j * lda + i] = avg;
-    }
-  }
-  __syncthreads();
-
-  // Householder tridiagonalisation, reflector k acts on rows/columns k+1..n-1
-  for (int k = 0; k + 2 < n; ++k) {
-    const int m = n - k - 1;
+  for (int k = 0; k + 1 < n; ++k) {
     if (wave == 0) {
       double xn2 = 0.0;
-      for (int r = k + 2 + lane; r < n; r += 64) {
-        const double x = A[r * lda + k];
-        xn2 += x * x;
-      }
+      for (int r = k + 2 + lane; r < n; r += 64) xn2 += abs2(A[r * lda + k]);
       xn2 = wave_sum(xn2);
-      const double alpha = A[(k + 1) * lda + k];
-      double beta, tau, scl;
-      if (xn2 == 0.0) {
-        beta = alpha;
-        tau = 0.0;
-        scl = 0.0;
+      const T alpha = A[(k + 1) * lda + k];
+      const double ar = re_of(alpha);
+      double beta;
+      T tau, scl;
+      if (xn2 == 0.0 && abs2(alpha) == ar * ar) {
+        beta = ar;
+        tau = T{};
+        scl = T{};
       } else {
-        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-        tau = (beta - alpha) / beta;
-        scl = 1.0 / (alpha - beta);
+        beta = -copysign(sqrt(abs2(alpha) + xn2), ar);
+        // tau = (beta - alpha)/beta, scl = 1/(alpha - beta)
+        const T amb = alpha - realv<T>(beta);
+        tau = St<T>::scale(-1.0 / beta, amb);
+        scl = cj(amb) * (1.0 / abs2(amb));
       }
       for (int r = k + 1 + lane; r < n; r += 64) {
-        const double vr = (r == k + 1) ? 1.0 : A[r * lda + k] * scl;
+        const T vr = (r == k + 1) ? realv<T>(1.0) : A[r * lda + k] * scl;
         vv[r] = vr;
-        w.V[k * n + r] = vr;
+        A[r * lda + k] = vr;
       }
       if (lane == 0) {
-        scal[0] = tau;
-        w.tau[k] = tau;
-        w.d[k] = A[k * lda + k];
-        w.e[k] = beta;
+        taus[k] = tau;
+        dd[k] = re_of(A[k * lda + k]);
+        ee[k] = beta;
       }
     }
     __syncthreads();
-    const double tau = scal[0];
+    const T tau = taus[k];
     {
       const int r = k + 1 + (tid >> 3), s = tid & 7;
-      double part = 0.0;
-      if (r < n)
-        for (int c = k + 1 + s; c < n; c += 8) part += A[r * lda + c] * vv[c];
-      part += __shfl_xor(part, 1);
-      part += __shfl_xor(part, 2);
-      part += __shfl_xor(part, 4);
-      double contrib = 0.0;
+      T part = T{};
+      if (r < n) {
+        const T *Ar = A + r * lda;
+        for (int c = k + 1 + s; c < n; c += 8) part = part + Ar[c] * vv[c];
+      }
+      part = group8_sum(part);
+      T contrib = T{};
       if (r < n && s == 0) {
-        const double p = tau * part;
+        const T p = tau * part;
         pp[r] = p;
-        contrib = p * vv[r];
+        contrib = cj(p) * vv[r];
       }
       contrib = wave_sum(contrib);
       if (lane == 0) red[wave] = contrib;
     }
     __syncthreads();
     {
-      double pv = 0.0;
-      for (int q = 0; q < EIG_T / 64; ++q) pv += red[q];
-      const double K = -0.5 * tau * pv;
-      for (int idx = tid; idx < m * m; idx += EIG_T) {
-        const int ii = idx / m, cc = idx - ii * m;
-        const int r = k + 1 + ii, c = k + 1 + cc;
-        const double wr = pp[r] + K * vv[r], wc = pp[c] + K * vv[c];
-        A[r * lda + c] -= vv[r] * wc + wr * vv[c];
+      T pv = T{};
+#pragma unroll
+      for (int q = 0; q < EIG_T / 64; ++q) pv = pv + red[q];
+      const T K = St<T>::scale(-0.5, tau * pv);
+      T vc[4], wc[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int c = tx + 32 * b;
+        const bool in = c > k && c < n;
+        vc[b] = in ? cj(vv[c]) : T{};
+        wc[b] = in ? cj(pp[c] + K * vv[c]) : T{};
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int r = ty + 32 * a;
+        if (r <= k || r >= n) continue;
+        const T vr = vv[r], wr = pp[r] + K * vv[r];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int c = tx + 32 * b;
+          if (c > k && c < n) A[r * lda + c] = A[r * lda + c] - (vr * wc[b] + wr * vc[b]);
+        }
       }
     }
     __syncthreads();
   }
-  if (tid == 0) {
-    if (n >= 2) {
-      w.d[n - 2] = A[(n - 2) * lda + n - 2];
-      w.e[n - 2] = A[(n - 1) * lda + n - 2];
-    }
-    w.d[n - 1] = A[(n - 1) * lda + n - 1];
-    *info = 0;
+  if (tid == 0) dd[n - 1] = re_of(A[(n - 1) * lda + n - 1]);
+  __syncthreads();
+  T *tg = as<T>(w.tau);
+  for (int i = tid; i < n; i += EIG_T) {
+    w.d[i] = dd[i];
+    w.e[i] = (i + 1 < n) ? ee[i] : 0.0;
+    tg[i] = (i + 1 < n) ? taus[i] : T{};
   }
+  // V[k][r] = reflector k at row r (rows k+1.., zero elsewhere)
+  T *V = as<T>(w.V);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int k = ty + 32 * a, r = tx + 32 * b;
+      if (k < n && r < n) V[k * n + r] = (k + 1 < n && r > k) ? A[r * lda + k] : T{};
+    }
 }
 
 // ------------------------------------------------------------------ values
 __global__ __launch_bounds__(256) void k_eig_values(int n, EigWs w, const int32_t *info) {
   if (*info != 0) return;
+  __shared__ double d[EIG_NMAX], e[EIG_NMAX], e2[EIG_NMAX];
+  for (int i = threadIdx.x; i < n; i += 256) {
+    d[i] = w.d[i];
+    e[i] = (i + 1 < n) ? w.e[i] : 0.0;
+    e2[i] = e[i] * e[i];
+  }
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= n) return;
-  const double *d = w.d, *e = w.e;
   int lo = j, hi = j;
   while (lo > 0 && !split_at(d, e, lo - 1)) --lo;
   while (hi < n - 1 && !split_at(d, e, hi)) ++hi;
@@ -312,7 +413,7 @@ __global__ __launch_bounds__(256) void k_eig_values(int n, EigWs w, const int32_
     const double off = (i > lo ? fabs(e[i - 1]) : 0.0) + (i < hi ? fabs(e[i]) : 0.0);
     gl = fmin(gl, d[i] - off);
     gu = fmax(gu, d[i] + off);
-    if (i < hi) emax2 = fmax(emax2, e[i] * e[i]);
+    if (i < hi) emax2 = fmax(emax2, e2[i]);
   }
   gl = wave_min(gl);
   gu = wave_max(gu);
@@ -325,20 +426,28 @@ __global__ __launch_bounds__(256) void k_eig_values(int n, EigWs w, const int32_
     const double width = b - a;
     if (width <= 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + pivmin) break;
     const double x = a + width * ((lane + 1) / 65.0);
+    // number of eigenvalues below x = sign changes along the leading minors
+    // P_i = (d_i - x) P_{i-1} - e_{i-1}^2 P_{i-2}; an exact zero takes the sign
+    // opposite to its predecessor; power-of-two rescaling keeps P in range
     int cnt = 0;
-    double q = 1.0;
-    for (int i = lo; i <= hi; ++i) {
-      double t = d[i] - x;
-      if (i > lo) t -= e[i - 1] * e[i - 1] / q;
-      if (fabs(t) < pivmin) t = -pivmin;
-      cnt += (t < 0.0);
-      q = t;
+    double pm = 1.0, pc = d[lo] - x;
+    bool neg = pc < 0.0 || pc == 0.0;
+    cnt += neg;
+    for (int i = lo + 1; i <= hi; ++i) {
+      const double pn = (d[i] - x) * pc - e2[i - 1] * pm;
+      const bool nn = pn < 0.0 || (pn == 0.0 && !neg);
+      cnt += (nn != neg);
+      neg = nn;
+      const double mag = fmax(fabs(pn), fabs(pc));
+      const double sc = mag > 0x1p+400 ? 0x1p-400 : (mag < 0x1p-400 ? 0x1p+400 : 1.0);
+      pm = pc * sc;
+      pc = pn * sc;
     }
-    // eigenvalue li lies at or above x exactly when fewer than li+1 lie below x
+    // eigenvalue li lies at or above x exactly when at most li lie below x
     const double na = wave_max(cnt <= li ? x : -DBL_MAX);
-    const double nb = wave_min(cnt > li ? x : DBL_MAX);
+    const double nbnd = wave_min(cnt > li ? x : DBL_MAX);
     a = fmax(a, na);
-    b = fmin(b, nb);
+    b = fmin(b, nbnd);
   }
   if (lane == 0) w.lam[j] = 0.5 * (a + b);
 }
@@ -355,16 +464,22 @@ __device__ inline double start_value(int j, int i) {
 __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int32_t *info) {
   if (*info != 0) return;
   extern __shared__ double sv[];
+  double *d = sv, *e = sv + n, *lam = sv + 2 * n;
+  double *scratch = sv + 3 * n;
   const int t = threadIdx.x;
+  for (int i = t; i < n; i += VEC_T) {
+    d[i] = w.d[i];
+    e[i] = (i + 1 < n) ? w.e[i] : 0.0;
+    lam[i] = w.lam[i];
+  }
+  __syncthreads();
   const int j = blockIdx.x * VEC_T + t;
   if (j >= n) return;
-  // per-lane scratch, lane-interleaved: u0, u1, u2, y
-  double *u0 = sv + 0 * n * VEC_T + t;
-  double *u1 = sv + 1 * n * VEC_T + t;
-  double *u2 = sv + 2 * n * VEC_T + t;
-  double *y = sv + 3 * n * VEC_T + t;
+  double *u0 = scratch + 0 * n * VEC_T + t;
+  double *u1 = scratch + 1 * n * VEC_T + t;
+  double *u2 = scratch + 2 * n * VEC_T + t;
+  double *y = scratch + 3 * n * VEC_T + t;
 #define AT(p, i) (p)[(i) * VEC_T]
-  const double *d = w.d, *e = w.e;
   int lo = j, hi = j;
   while (lo > 0 && !split_at(d, e, lo - 1)) --lo;
   while (hi < n - 1 && !split_at(d, e, hi)) ++hi;
@@ -374,12 +489,12 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
     tn = fmax(tn, fabs(d[i]) + (i > lo ? fabs(e[i - 1]) : 0.0) + (i < hi ? fabs(e[i]) : 0.0));
   const double pert = 10.0 * DBL_EPSILON * fmax(tn, DBL_MIN);
   int ties = 0;
-  for (int i = j; i > lo && w.lam[i] - w.lam[i - 1] < pert; --i) ++ties;
-  const double x = w.lam[j - ties] + ties * pert;
+  for (int i = j; i > lo && lam[i] - lam[i - 1] < pert; --i) ++ties;
+  const double x = lam[j - ties] + ties * pert;
   const double tiny = DBL_EPSILON * fmax(tn, DBL_MIN);
 
   for (int i = 0; i < m; ++i) AT(y, i) = start_value(j, i);
-  for (int iter = 0; iter < 3; ++iter) {
+  for (int iter = 0; iter < 2; ++iter) {
     // LU with partial pivoting of (T_block - x I), forward-eliminating y
     double c0 = d[lo] - x, c1 = (m > 1) ? e[lo] : 0.0;
     for (int i = 0; i + 1 < m; ++i) {
@@ -406,15 +521,15 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
       }
     }
     AT(u0, m - 1) = c0;
-    // back substitution with tiny pivots replaced by +-eps ||T||
+    // back substitution, tiny pivots replaced by +-eps ||T||
     double y1 = 0.0, y2 = 0.0, ymax = 0.0;
     for (int i = m - 1; i >= 0; --i) {
       double p = AT(u0, i);
       if (fabs(p) < tiny) p = (p < 0.0) ? -tiny : tiny;
-      double s = AT(y, i);
-      if (i + 1 < m) s -= AT(u1, i) * y1;
-      if (i + 2 < m) s -= AT(u2, i) * y2;
-      const double yi = s / p;
+      double sacc = AT(y, i);
+      if (i + 1 < m) sacc -= AT(u1, i) * y1;
+      if (i + 2 < m) sacc -= AT(u2, i) * y2;
+      const double yi = sacc / p;
       AT(y, i) = yi;
       y2 = y1;
       y1 = yi;
@@ -439,196 +554,147 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
 #undef AT
 }
 
-// ------------------------------------------------------------------ finish
-// out = In * M with M = 1.5 I - 0.5 G, all n x n row-major in global memory
-__device__ void ns_step(const double *In, const double *G, double *Out, int n, int tid) {
-  const int i0 = (tid >> 5) * 4, j0 = (tid & 31) * 4;
-  if (i0 >= n || j0 >= n) return;
-  double acc[4][4] = {};
-  for (int kk = 0; kk < n; ++kk) {
-    double a[4], b[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) a[r] = (i0 + r < n) ? In[(i0 + r) * n + kk] : 0.0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-      b[c] = (j0 + c < n) ? ((kk == j0 + c ? 1.5 : 0.0) - 0.5 * G[kk * n + j0 + c]) : 0.0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-      if (i0 + r < n && j0 + c < n) Out[(i0 + r) * n + j0 + c] = acc[r][c];
-}
-
-// G = Z^T Z; returns max |G - I| over the workgroup (all lanes)
-__device__ double gram(const double *Z, double *G, int n, int tid, double *red) {
-  const int i0 = (tid >> 5) * 4, j0 = (tid & 31) * 4;
+// ------------------------------------------------------------------ orthogonality
+// dev[slot] = max |G - I| (one workgroup); info = -1 when above the limit
+__global__ __launch_bounds__(256) void k_gram_check(const double *__restrict__ G, int n,
+                                                    double limit, int32_t *info) {
+  if (*info != 0) return;
+  __shared__ double red[4];
   double dev = 0.0;
-  if (i0 < n && j0 < n) {
-    double acc[4][4] = {};
-    for (int r = 0; r < n; ++r) {
-      double a[4], b[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = (i0 + q < n) ? Z[r * n + i0 + q] : 0.0;
-        b[q] = (j0 + q < n) ? Z[r * n + j0 + q] : 0.0;
-      }
-#pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
-    }
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (i0 + p < n && j0 + q < n) {
-          G[(i0 + p) * n + j0 + q] = acc[p][q];
-          dev = fmax(dev, fabs(acc[p][q] - ((i0 + p == j0 + q) ? 1.0 : 0.0)));
-        }
+  for (int idx = threadIdx.x; idx < n * n; idx += 256) {
+    const int r = idx / n, c = idx - r * n;
+    dev = fmax(dev, fabs(G[idx] - (r == c ? 1.0 : 0.0)));
   }
   dev = wave_max(dev);
-  if ((tid & 63) == 0) red[tid >> 6] = dev;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dev;
   __syncthreads();
-  double all = 0.0;
-  for (int q = 0; q < EIG_T / 64; ++q) all = fmax(all, red[q]);
-  __syncthreads();
-  return all;
+  if (threadIdx.x == 0) {
+    const double all = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (!(all <= limit)) *info = -1;
+  }
 }
 
-__global__ __launch_bounds__(EIG_T) void k_eig_finish(int n, EigWs w, double *__restrict__ eps,
-                                                      double *__restrict__ C,
-                                                      int32_t *__restrict__ info) {
+// ------------------------------------------------------------------ back-transform
+// Column j of Z (real): U = Q Z with the reflectors applied last to first
+// from LDS (8 lanes per column, rows 8t+s in registers):
+// u <- u - tau_k v_k (v_k^H u). U lands in column rank(j) of Uo, where rank
+// orders the eigenvalues by (value, slot).
+template <typename T>
+__global__ __launch_bounds__(128) void k_eig_back(int n, EigWs w, const double *__restrict__ Z,
+                                                  T *__restrict__ Uo, double *__restrict__ eps,
+                                                  const int32_t *info) {
   if (*info != 0) return;
-  __shared__ double red[EIG_T / 64];
-  __shared__ int rank[EIG_NMAX];
-  const int tid = threadIdx.x;
-  double *Z = w.Z, *Z2 = w.Z2;
-  double *G = w.T1;  // T1 is free after the reduction
-  bool ok = false;
-  for (int it = 0; it < 8; ++it) {
-    const double dev = gram(Z, G, n, tid, red);
-    if (!(dev < 0.3)) break;
-    ns_step(Z, G, Z2, n, tid);
-    __syncthreads();
-    double *tmp = Z;
-    Z = Z2;
-    Z2 = tmp;
-    if (dev <= 1e-8) {
-      ok = true;
-      break;
-    }
-  }
-  if (!ok) {
-    if (tid == 0) *info = -1;
-    return;
-  }
-  // eigen-order: rank of each slot by (value, slot)
-  for (int j = tid; j < n; j += EIG_T) {
-    const double lj = w.lam[j];
-    int r = 0;
-    for (int i = 0; i < n; ++i) {
-      const double li = w.lam[i];
-      r += (li < lj) || (li == lj && i < j);
-    }
-    rank[j] = r;
-  }
-  // back-transform each column of Z: 8 lanes per column, rows 8t+s in registers
-  {
-    const int col = tid >> 3, s = tid & 7;
-    double zr[EIG_NMAX / 8];
-#pragma unroll
-    for (int t = 0; t < EIG_NMAX / 8; ++t) {
-      const int row = 8 * t + s;
-      zr[t] = (col < n && row < n) ? Z[row * n + col] : 0.0;
-    }
-    if (col < n) {
-      for (int k = n - 3; k >= 0; --k) {
-        const double tk = w.tau[k];
-        const double *vk = w.V + static_cast<int64_t>(k) * n;
-        double part = 0.0;
-#pragma unroll
-        for (int t = 0; t < EIG_NMAX / 8; ++t) {
-          const int row = 8 * t + s;
-          if (row > k && row < n) part += vk[row] * zr[t];
-        }
-        part += __shfl_xor(part, 1);
-        part += __shfl_xor(part, 2);
-        part += __shfl_xor(part, 4);
-        const double f = tk * part;
-#pragma unroll
-        for (int t = 0; t < EIG_NMAX / 8; ++t) {
-          const int row = 8 * t + s;
-          if (row > k && row < n) zr[t] -= f * vk[row];
-        }
-      }
-    }
-    __syncthreads();  // every read of Z2/Z done before it is reused for U
-#pragma unroll
-    for (int t = 0; t < EIG_NMAX / 8; ++t) {
-      const int row = 8 * t + s;
-      if (col < n && row < n) Z2[row * n + col] = zr[t];
-    }
-  }
+  constexpr int NMAX = EigMax<T>::n;
+  extern __shared__ double sv[];
+  T *V = reinterpret_cast<T *>(sv);  // [n][n]
+  T *tau = V + n * n;                // [n]
+  const T *Vg = as<T>(w.V);
+  const T *tg = as<T>(w.tau);
+  for (int idx = threadIdx.x; idx < n * n; idx += 128) V[idx] = Vg[idx];
+  for (int idx = threadIdx.x; idx < n; idx += 128) tau[idx] = tg[idx];
   __syncthreads();
-  // C[m][rank j] = sum_{k >= m} Linv[k][m] U[k][j]
-  {
-    const double *U = Z2;
-    const int i0 = (tid >> 5) * 4, j0 = (tid & 31) * 4;
-    if (i0 < n && j0 < n) {
-      double acc[4][4] = {};
-      for (int kk = i0; kk < n; ++kk) {
-        double a[4], b[4];
+  const int col = blockIdx.x * 16 + (threadIdx.x >> 3), s = threadIdx.x & 7;
+  if (col >= n) return;
+  T zr[NMAX / 8];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = (i0 + r < n && kk >= i0 + r) ? w.Linv[kk * n + i0 + r] : 0.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = (j0 + c < n) ? U[kk * n + j0 + c] : 0.0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          if (i0 + r < n && j0 + c < n) C[(i0 + r) * n + rank[j0 + c]] = acc[r][c];
-    }
+  for (int t = 0; t < NMAX / 8; ++t) {
+    const int row = 8 * t + s;
+    zr[t] = realv<T>((row < n) ? Z[row * n + col] : 0.0);
   }
-  for (int j = tid; j < n; j += EIG_T) eps[rank[j]] = w.lam[j];
+  for (int k = n - 2; k >= 0; --k) {
+    const T *vk = V + k * n;
+    T vr[NMAX / 8];
+    T part = T{};
+#pragma unroll
+    for (int t = 0; t < NMAX / 8; ++t) {
+      const int row = 8 * t + s;
+      vr[t] = (row > k && row < n) ? vk[row] : T{};
+      part = part + cj(vr[t]) * zr[t];
+    }
+    part = group8_sum(part);
+    const T f = tau[k] * part;
+#pragma unroll
+    for (int t = 0; t < NMAX / 8; ++t) zr[t] = zr[t] - f * vr[t];
+  }
+  const double lj = w.lam[col];
+  int rank = 0;
+  for (int i = 0; i < n; ++i) {
+    const double li = w.lam[i];
+    rank += (li < lj) || (li == lj && i < col);
+  }
+#pragma unroll
+  for (int t = 0; t < NMAX / 8; ++t) {
+    const int row = 8 * t + s;
+    if (row < n) Uo[row * n + rank] = zr[t];
+  }
+  if (s == 0) eps[rank] = lj;
+}
+
+template <typename T>
+int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps, void *C,
+           int32_t *info, hipStream_t st) {
+  constexpr int NMAX = EigMax<T>::n;
+  if (nb > NMAX)
+    return fail(GPAW_ESHAPE, "subspace eigensolver supports nb <= " + std::to_string(NMAX) +
+                                 (St<T>::cplx ? " for complex systems" : ""));
+  static std::once_flag once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(once, [] {
+    const void *fns[] = {reinterpret_cast<const void *>(&k_eig_chol<T>),
+                         reinterpret_cast<const void *>(&k_eig_tridiag<T>),
+                         reinterpret_cast<const void *>(&k_eig_back<T>)};
+    for (const void *f : fns)
+      if (attr_err == hipSuccess)
+        attr_err = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  });
+  if (attr_err != hipSuccess) return hip_fail(attr_err, "hipFuncSetAttribute(eigensolver)");
+  const int n = nb;
+  const int sz = St<T>::cplx ? 2 : 1;
+  const EigWs w = eig_layout(s->ws.eig, n, sz);
+  const T *Hd = static_cast<const T *>(H);
+  const T *Sd = static_cast<const T *>(S);
+  const size_t lda_bytes = (static_cast<size_t>(n) * (n + 1)) * sizeof(T);
+  const int tiles = ((n + 15) / 16) * ((n + 15) / 16);
+  const unsigned sg_blocks = static_cast<unsigned>((tiles + 3) / 4);
+  T *Linv = reinterpret_cast<T *>(w.Linv), *T1 = reinterpret_cast<T *>(w.T1);
+  T *Am = reinterpret_cast<T *>(w.A), *U = reinterpret_cast<T *>(w.T1);
+
+  k_eig_chol<T><<<1, EIG_T, lda_bytes + n * sizeof(double), st>>>(Sd, n, w, info);
+  // A = Linv ((H + H^H)/2) Linv^H
+  k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Hd, 2, Linv, 1, T1, n, info);
+  k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Linv, 0, T1, 0, Am, n, info);
+  k_eig_tridiag<T><<<1, EIG_T, lda_bytes + 3 * n * sizeof(T) + 2 * n * sizeof(double) + 16 * sizeof(T),
+                     st>>>(n, w, info);
+  k_eig_values<<<(n + 3) / 4, 256, 0, st>>>(n, w, info);
+  k_eig_vectors<<<(n + VEC_T - 1) / VEC_T, VEC_T, (3 * n + 4 * n * VEC_T) * sizeof(double), st>>>(
+      n, w, info);
+  // two Newton-Schulz steps Z <- Z (3I - Z^T Z)/2 on the real tridiagonal
+  // eigenvectors; the second Gram matrix must be within 1e-7 of I, so the
+  // result is orthonormal to ~1e-14
+  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z, 1, w.Z, 0, w.G, n, info);
+  k_gram_check<<<1, 256, 0, st>>>(w.G, n, 0.5, info);
+  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z, 0, w.G, 3, w.Z2, n, info);
+  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z2, 1, w.Z2, 0, w.G, n, info);
+  k_gram_check<<<1, 256, 0, st>>>(w.G, n, 1e-7, info);
+  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z2, 0, w.G, 3, w.Z, n, info);
+  // U = Q Z in eigen-order, then C = Linv^H U
+  k_eig_back<T><<<(n + 15) / 16, 128, (static_cast<size_t>(n) * n + n) * sizeof(T), st>>>(
+      n, w, w.Z, U, eps, info);
+  k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Linv, 1, U, 0, static_cast<T *>(C), n, info);
+  return GPAW_OK;
 }
 
 }  // namespace
 
 size_t eig_ws_elems(int nmax, bool cplx) {
-  const size_t n = static_cast<size_t>(std::min(nmax, EIG_NMAX));
-  return (5 * n * n + 4 * n + 64) * (cplx ? 2 : 1);
+  const size_t n = static_cast<size_t>(std::min(nmax, cplx ? EigMax<z64>::n : EigMax<double>::n));
+  return (7 * n * n + 6 * n + 64) * (cplx ? 2 : 1);
 }
 
 int launch_eigh(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps, void *C,
                 int32_t *info, hipStream_t st) {
-  if (s->dtype != GPAW_F64) return fail(GPAW_EDTYPE, "subspace eigensolver: complex not built yet");
-  if (nb > EIG_NMAX) return fail(GPAW_ESHAPE, "subspace eigensolver supports nb <= 128");
-  static std::once_flag once;
-  static hipError_t attr_err = hipSuccess;
-  std::call_once(once, [] {
-    attr_err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_eig_reduce),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  });
-  if (attr_err != hipSuccess) return hip_fail(attr_err, "hipFuncSetAttribute(k_eig_reduce)");
-  const EigWs w = eig_layout(s->ws.eig, nb);
-  const size_t lds1 = (static_cast<size_t>(nb) * (nb + 1) + 3 * nb + 17) * sizeof(double);
-  k_eig_reduce<<<1, EIG_T, lds1, st>>>(static_cast<const double *>(H),
-                                       static_cast<const double *>(S), nb, w, info);
-  k_eig_values<<<(nb + 3) / 4, 256, 0, st>>>(nb, w, info);
-  const size_t lds3 = static_cast<size_t>(4) * nb * VEC_T * sizeof(double);
-  k_eig_vectors<<<(nb + VEC_T - 1) / VEC_T, VEC_T, lds3, st>>>(nb, w, info);
-  k_eig_finish<<<1, EIG_T, 0, st>>>(nb, w, eps, static_cast<double *>(C), info);
-  return GPAW_OK;
+  if (s->dtype == GPAW_C128) return eigh_t<z64>(s, H, S, nb, eps, C, info, st);
+  return eigh_t<double>(s, H, S, nb, eps, C, info, st);
 }
 
 }  // namespace gfd

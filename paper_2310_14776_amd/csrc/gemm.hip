@@ -36,118 +36,145 @@ __device__ inline d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// part[(split*nmat + mat)][nb][nb] = sum_{k in range} A[n][k] B_mat[m][k]
-__global__ __launch_bounds__(256) void k_subspace_f64(const double *__restrict__ A,
-                                                      const double *__restrict__ B0,
-                                                      const double *__restrict__ B1,
-                                                      double *__restrict__ part, int nb,
-                                                      int64_t ng, int64_t kchunk, int tiles_n,
-                                                      int nmat) {
-  __shared__ d4 red[2][4][4][64];  // 2 wavefronts x 4x4 blocks x 64 lanes = 64 KB
+// Complex operands: conj(a) b = (ax bx + ay by) + i (ax by - ay bx) and
+// a b = (ax bx - ay by) + i (ax by + ay bx), four real MFMAs each.
+template <typename T> struct Cx;
+template <> struct Cx<double> {
+  static constexpr int parts = 1;
+  __device__ static double re(double a) { return a; }
+  __device__ static double im(double) { return 0.0; }
+  __device__ static double make(double r, double) { return r; }
+};
+template <> struct Cx<z64> {
+  static constexpr int parts = 2;
+  __device__ static double re(z64 a) { return a.x; }
+  __device__ static double im(z64 a) { return a.y; }
+  __device__ static z64 make(double r, double i) { return z64{r, i}; }
+};
+
+// part[(split*nmat + mat)][nb][nb] = sum_{k in range} conj(A[n][k]) B_mat[m][k]
+// BM x BM blocks of 16x16 per wavefront (a TILE x TILE output tile).
+template <typename T, int BM>
+__global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const T *__restrict__ B0,
+                                                  const T *__restrict__ B1, T *__restrict__ part,
+                                                  int nb, int64_t ng, int64_t kchunk, int tiles_n,
+                                                  int nmat) {
+  constexpr int TILE = 16 * BM;
+  constexpr int NP = Cx<T>::parts;
+  __shared__ d4 red[2][NP][BM][BM][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tm = blockIdx.x / tiles_n, tn = blockIdx.x - tm * tiles_n;
   const int mat = blockIdx.y;
-  const double *B = mat ? B1 : B0;
+  const T *B = mat ? B1 : B0;
   const int64_t kb = static_cast<int64_t>(blockIdx.z) * kchunk;
   const int64_t ke = std::min(ng, kb + kchunk);
   const int r = lane & 15, kq = lane >> 4;
 
-  const double *ap[4];
-  const double *bp[4];
-  bool av[4], bv[4];
+  const T *ap[BM];
+  const T *bp[BM];
+  bool av[BM], bv[BM];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int ra = tm * SUB_TILE + q * 16 + r;
-    const int rb = tn * SUB_TILE + q * 16 + r;
+  for (int q = 0; q < BM; ++q) {
+    const int ra = tm * TILE + q * 16 + r;
+    const int rb = tn * TILE + q * 16 + r;
     av[q] = ra < nb;
     bv[q] = rb < nb;
     ap[q] = A + static_cast<int64_t>(av[q] ? ra : 0) * ng;
     bp[q] = B + static_cast<int64_t>(bv[q] ? rb : 0) * ng;
   }
 
-  d4 acc[4][4];
+  d4 acc[NP][BM][BM];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int c = 0; c < NP; ++c)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int j = 0; j < BM; ++j) acc[c][i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
   for (int64_t kg = kb + wave * 16; kg < ke; kg += 64) {
     const int64_t k = kg + 4 * kq;
-    double a[4][4], b[4][4];
-    if (kg + 16 <= ke) {
+    T a[BM][4], b[BM][4];
+    const bool full = kg + 16 <= ke;
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < BM; ++q)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          a[q][s] = av[q] ? ap[q][k + s] : 0.0;
-          b[q][s] = bv[q] ? bp[q][k + s] : 0.0;
-        }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const bool in = k + s < ke;
-          a[q][s] = (av[q] && in) ? ap[q][k + s] : 0.0;
-          b[q][s] = (bv[q] && in) ? bp[q][k + s] : 0.0;
-        }
-    }
+      for (int s = 0; s < 4; ++s) {
+        const bool in = full || k + s < ke;
+        a[q][s] = (av[q] && in) ? ap[q][k + s] : T{};
+        b[q][s] = (bv[q] && in) ? bp[q][k + s] : T{};
+      }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < BM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = mfma(a[i][s], b[j][s], acc[i][j]);
+        for (int j = 0; j < BM; ++j) {
+          const double ax = Cx<T>::re(a[i][s]), bx = Cx<T>::re(b[j][s]);
+          acc[0][i][j] = mfma(ax, bx, acc[0][i][j]);
+          if constexpr (NP == 2) {
+            const double ay = Cx<T>::im(a[i][s]), by = Cx<T>::im(b[j][s]);
+            acc[0][i][j] = mfma(ay, by, acc[0][i][j]);
+            acc[NP - 1][i][j] = mfma(ax, by, acc[NP - 1][i][j]);
+            acc[NP - 1][i][j] = mfma(-ay, bx, acc[NP - 1][i][j]);
+          }
+        }
   }
 
   // fixed-order sum of the four wavefronts' tiles: (w0 + w2) + (w1 + w3)
   if (wave >= 2)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int c = 0; c < NP; ++c)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) red[wave - 2][i][j][lane] = acc[i][j];
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BM; ++j) red[wave - 2][c][i][j][lane] = acc[c][i][j];
   __syncthreads();
   if (wave < 2)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int c = 0; c < NP; ++c)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] += red[wave][i][j][lane];
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BM; ++j) acc[c][i][j] += red[wave][c][i][j][lane];
   __syncthreads();
   if (wave == 1)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int c = 0; c < NP; ++c)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) red[0][i][j][lane] = acc[i][j];
+      for (int i = 0; i < BM; ++i)
+#pragma unroll
+        for (int j = 0; j < BM; ++j) red[0][c][i][j][lane] = acc[c][i][j];
   __syncthreads();
   if (wave == 0) {
-    double *out = part + (static_cast<int64_t>(blockIdx.z) * nmat + mat) * nb * nb;
+    T *out = part + (static_cast<int64_t>(blockIdx.z) * nmat + mat) * nb * nb;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < BM; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const d4 v = acc[i][j] + red[0][i][j][lane];
-        const int col = tn * SUB_TILE + j * 16 + (lane & 15);
+      for (int j = 0; j < BM; ++j) {
+        const d4 vr = acc[0][i][j] + red[0][0][i][j][lane];
+        const d4 vi = acc[NP - 1][i][j] + red[0][NP - 1][i][j][lane];
+        const int col = tn * TILE + j * 16 + (lane & 15);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int row = tm * SUB_TILE + i * 16 + (lane >> 4) + 4 * e;
-          if (row < nb && col < nb) out[static_cast<int64_t>(row) * nb + col] = v[e];
+          const int row = tm * TILE + i * 16 + (lane >> 4) + 4 * e;
+          if (row < nb && col < nb) out[static_cast<int64_t>(row) * nb + col] = Cx<T>::make(vr[e], vi[e]);
         }
       }
   }
 }
 
-__global__ __launch_bounds__(256) void k_subspace_reduce(const double *__restrict__ part,
-                                                         double *__restrict__ H,
-                                                         double *__restrict__ S, int nb,
-                                                         int nsplit, int nmat, double dV) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_subspace_reduce(const T *__restrict__ part,
+                                                         T *__restrict__ H, T *__restrict__ S,
+                                                         int nb, int nsplit, int nmat, double dV) {
   const int64_t nn = static_cast<int64_t>(nb) * nb;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (idx >= nn * nmat) return;
   const int mat = static_cast<int>(idx / nn);
   const int64_t e = idx - mat * nn;
-  double acc = 0.0;
-  for (int s = 0; s < nsplit; ++s) acc += part[(static_cast<int64_t>(s) * nmat + mat) * nn + e];
-  (mat ? S : H)[e] = dV * acc;
+  T acc{};
+  for (int s = 0; s < nsplit; ++s) acc = acc + part[(static_cast<int64_t>(s) * nmat + mat) * nn + e];
+  (mat ? S : H)[e] = St<T>::scale(dV, acc);
 }
 
 struct SplitPlan {
@@ -156,9 +183,9 @@ struct SplitPlan {
   int64_t kchunk;
 };
 
-SplitPlan plan_subspace(int nb, int64_t ng, int nmat) {
+SplitPlan plan_subspace(int nb, int64_t ng, int nmat, int tile) {
   SplitPlan p;
-  p.tiles_n = (nb + SUB_TILE - 1) / SUB_TILE;
+  p.tiles_n = (nb + tile - 1) / tile;
   p.tiles = p.tiles_n * p.tiles_n;
   // aim at ~512 workgroups (two per CU) with at least 1024 K per workgroup
   const int64_t want = std::max<int64_t>(1, 512 / (p.tiles * nmat));
@@ -171,15 +198,16 @@ SplitPlan plan_subspace(int nb, int64_t ng, int nmat) {
   return p;
 }
 
-// out[n][g] = sum_m C[m][n] src[m][g], rows n in the 128-row group blockIdx.y
-__global__ __launch_bounds__(256) void k_rotate_f64(const double *__restrict__ C,
-                                                    const double *__restrict__ src,
-                                                    double *__restrict__ dst, int nb,
-                                                    int64_t cols) {
+// out[n][g] = sum_m C[m][n] src[m][g]; each wavefront owns RB*16 rows (the
+// row group blockIdx.y) by 32 columns; no conjugation (psi' = C^T psi).
+template <typename T, int RB>
+__global__ __launch_bounds__(256) void k_rotate(const T *__restrict__ C, const T *__restrict__ src,
+                                                T *__restrict__ dst, int nb, int64_t cols) {
+  constexpr int NP = Cx<T>::parts;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = lane & 15, kq = lane >> 4;
   const int64_t g0 = static_cast<int64_t>(blockIdx.x) * 128 + wave * 32;
-  const int n0 = blockIdx.y * 128;
+  const int n0 = blockIdx.y * RB * 16;
   int64_t gc[2];
   bool gv[2];
 #pragma unroll
@@ -187,78 +215,104 @@ __global__ __launch_bounds__(256) void k_rotate_f64(const double *__restrict__ C
     gc[cb] = g0 + cb * 16 + j;
     gv[cb] = gc[cb] < cols;
   }
-  d4 acc[8][2];
+  d4 acc[NP][RB][2];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int c = 0; c < NP; ++c)
 #pragma unroll
-    for (int c = 0; c < 2; ++c) acc[i][c] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) acc[c][i][q] = d4{0.0, 0.0, 0.0, 0.0};
 
   for (int m0 = 0; m0 < nb; m0 += 4) {
     const int m = m0 + kq;
     const bool mv = m < nb;
-    double a[8], b[2];
+    T a[RB], b[2];
 #pragma unroll
-    for (int rb = 0; rb < 8; ++rb) {
+    for (int rb = 0; rb < RB; ++rb) {
       const int n = n0 + rb * 16 + j;
-      a[rb] = (mv && n < nb) ? C[static_cast<int64_t>(m) * nb + n] : 0.0;
+      a[rb] = (mv && n < nb) ? C[static_cast<int64_t>(m) * nb + n] : T{};
     }
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
-      b[cb] = (mv && gv[cb]) ? src[static_cast<int64_t>(m) * cols + gc[cb]] : 0.0;
+      b[cb] = (mv && gv[cb]) ? src[static_cast<int64_t>(m) * cols + gc[cb]] : T{};
 #pragma unroll
-    for (int rb = 0; rb < 8; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma(a[rb], b[cb], acc[rb][cb]);
+      for (int cb = 0; cb < 2; ++cb) {
+        const double ax = Cx<T>::re(a[rb]), bx = Cx<T>::re(b[cb]);
+        acc[0][rb][cb] = mfma(ax, bx, acc[0][rb][cb]);
+        if constexpr (NP == 2) {
+          const double ay = Cx<T>::im(a[rb]), by = Cx<T>::im(b[cb]);
+          acc[0][rb][cb] = mfma(-ay, by, acc[0][rb][cb]);
+          acc[NP - 1][rb][cb] = mfma(ax, by, acc[NP - 1][rb][cb]);
+          acc[NP - 1][rb][cb] = mfma(ay, bx, acc[NP - 1][rb][cb]);
+        }
+      }
   }
 #pragma unroll
-  for (int rb = 0; rb < 8; ++rb)
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
       if (!gv[cb]) continue;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int n = n0 + rb * 16 + kq + 4 * e;
-        if (n < nb) dst[static_cast<int64_t>(n) * cols + gc[cb]] = acc[rb][cb][e];
+        if (n < nb)
+          dst[static_cast<int64_t>(n) * cols + gc[cb]] =
+              Cx<T>::make(acc[0][rb][cb][e], acc[NP - 1][rb][cb][e]);
       }
     }
+}
+
+template <typename T, int BM>
+int subspace_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi, int nb,
+               void *H, void *S, hipStream_t st) {
+  const int nmat = Spsi ? 2 : 1;
+  const SplitPlan p = plan_subspace(nb, s->ng, nmat, 16 * BM);
+  const int64_t need = static_cast<int64_t>(p.nsplit) * nmat * nb * nb * Cx<T>::parts;
+  if (need > static_cast<int64_t>(s->ws.part_elems))
+    return fail(GPAW_EINVAL, "subspace workspace too small");
+  T *part = reinterpret_cast<T *>(s->ws.part);
+  dim3 grid(p.tiles, nmat, p.nsplit);
+  k_subspace<T, BM><<<grid, 256, 0, st>>>(static_cast<const T *>(psi), static_cast<const T *>(Hpsi),
+                                          static_cast<const T *>(Spsi ? Spsi : Hpsi), part, nb,
+                                          s->ng, p.kchunk, p.tiles_n, nmat);
+  const int64_t tot = static_cast<int64_t>(nb) * nb * nmat;
+  k_subspace_reduce<T><<<static_cast<unsigned>((tot + 255) / 256), 256, 0, st>>>(
+      part, static_cast<T *>(H), static_cast<T *>(S), nb, p.nsplit, nmat, s->dV);
+  return GPAW_OK;
+}
+
+template <typename T, int RB>
+int rotate_t(const void *C, const void *src, int nb, int64_t cols, void *dst, hipStream_t st) {
+  dim3 grid(static_cast<unsigned>((cols + 127) / 128), (nb + RB * 16 - 1) / (RB * 16));
+  k_rotate<T, RB><<<grid, 256, 0, st>>>(static_cast<const T *>(C), static_cast<const T *>(src),
+                                        static_cast<T *>(dst), nb, cols);
+  return GPAW_OK;
 }
 
 }  // namespace
 
 size_t subspace_part_elems(const gpaw_sys *s, int nb) {
-  // nsplit * tiles * nmat <= 512 whenever want >= 1, else nsplit = 1
-  const int64_t bound = std::max<int64_t>(512 * SUB_TILE * SUB_TILE, 2 * int64_t(nb) * nb);
-  return static_cast<size_t>(bound) * (s->dtype == GPAW_C128 ? 2 : 1);
+  // nsplit * tiles * nmat <= 512 whenever that allows one split, else nsplit = 1;
+  // complex tiles are 32 x 32 (a quarter of the real 64 x 64)
+  const bool cplx = s->dtype == GPAW_C128;
+  const int64_t tile = cplx ? 32 : SUB_TILE;
+  const int64_t bound = std::max<int64_t>(512 * tile * tile, 2 * int64_t(nb) * nb);
+  return static_cast<size_t>(bound) * (cplx ? 2 : 1);
 }
 
 int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
                     int nb, void *H, void *S, hipStream_t st) {
-  if (s->dtype != GPAW_F64) return fail(GPAW_EDTYPE, "subspace matrices: complex not built yet");
-  const int nmat = Spsi ? 2 : 1;
-  const SplitPlan p = plan_subspace(nb, s->ng, nmat);
-  const int64_t need = static_cast<int64_t>(p.nsplit) * nmat * nb * nb;
-  if (need > static_cast<int64_t>(s->ws.part_elems))
-    return fail(GPAW_EINVAL, "subspace workspace too small");
-  dim3 grid(p.tiles, nmat, p.nsplit);
-  k_subspace_f64<<<grid, 256, 0, st>>>(static_cast<const double *>(psi),
-                                       static_cast<const double *>(Hpsi),
-                                       static_cast<const double *>(Spsi ? Spsi : Hpsi),
-                                       s->ws.part, nb, s->ng, p.kchunk, p.tiles_n, nmat);
-  const int64_t tot = static_cast<int64_t>(nb) * nb * nmat;
-  k_subspace_reduce<<<static_cast<unsigned>((tot + 255) / 256), 256, 0, st>>>(
-      s->ws.part, static_cast<double *>(H), static_cast<double *>(S), nb, p.nsplit, nmat, s->dV);
-  return GPAW_OK;
+  if (s->dtype == GPAW_C128) return subspace_t<z64, 2>(s, psi, Hpsi, Spsi, nb, H, S, st);
+  return subspace_t<double, 4>(s, psi, Hpsi, Spsi, nb, H, S, st);
 }
 
 int launch_rotate(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
                   void *dst, hipStream_t st) {
-  if (s->dtype != GPAW_F64) return fail(GPAW_EDTYPE, "rotation: complex not built yet");
   if (cols == 0) return GPAW_OK;
-  dim3 grid(static_cast<unsigned>((cols + 127) / 128), (nb + 127) / 128);
-  k_rotate_f64<<<grid, 256, 0, st>>>(static_cast<const double *>(C),
-                                     static_cast<const double *>(src),
-                                     static_cast<double *>(dst), nb, cols);
-  return GPAW_OK;
+  if (s->dtype == GPAW_C128) return rotate_t<z64, 4>(C, src, nb, cols, dst, st);
+  return rotate_t<double, 8>(C, src, nb, cols, dst, st);
 }
 
 }  // namespace gfd

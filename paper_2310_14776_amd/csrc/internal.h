@@ -57,21 +57,42 @@ template <> struct St<z64> {
   __host__ __device__ static z64 scale(double s, z64 a) { return s * a; }
 };
 
+// ---------------------------------------------------------------- projectors
+// Parameters of the projector functions, passed by value to the kernels
+// (device evaluation in proj.h).
+constexpr int PROJ_MAX_CHAN = 8;
+constexpr int PROJ_MAX_NI = 32;
+
+struct ProjDev {
+  int nchan, ni;
+  int std13;                       // channel l sequence is (0, 0, 1, 1, 2)
+  int l[PROJ_MAX_CHAN];
+  double norm[PROJ_MAX_CHAN];
+  double rc2inv[PROJ_MAX_CHAN];    // 1 / rc^2
+  double a2[PROJ_MAX_CHAN];        // 1 / (2 sigma^2)
+  signed char ch[PROJ_MAX_NI];     // channel of projector i
+  signed char ym[PROJ_MAX_NI];     // harmonic slot (0..8) of projector i
+  int n[3];
+  double h[3];
+  z64 ph[3][16];                   // exp(-2 pi i k_c w), w = -8..7
+};
+
 // ---------------------------------------------------------------- system
-// Projector tables: entries are (atom, grid point) pairs with at least one
-// image of the atom's sphere covering the point. Two orders of the same
-// entries: atom-major (for the projection gather) and point-major (for the
-// add-back, where each covered point sums over the atoms that reach it).
+// Projector geometry. An entry is one (grid point, atom, periodic image)
+// triple with the image's sphere covering the point; projector values are
+// recomputed from it on the device. Two orders of the same entries:
+// atom-major (projection gather) and point-major (add-back, where each grid
+// point sums over the entries that reach it).
 struct Tables {
-  int64_t nent = 0;      // entries
-  int64_t nu = 0;        // distinct covered grid points
-  int32_t *a_start = nullptr;   // [natoms+1] atom-major entry ranges
-  int32_t *e_g = nullptr;       // [nent] grid index (atom-major)
-  void *e_q = nullptr;          // [ni][nent] projector values (atom-major)
-  int32_t *g2u = nullptr;       // [Ng] covered-point index or -1
-  int32_t *u_start = nullptr;   // [nu+1] point-major entry ranges
-  int32_t *pm_atom = nullptr;   // [nent] atom of each point-major entry
-  void *pm_q = nullptr;         // [ni][nent] projector values (point-major)
+  int64_t nent = 0;            // entries
+  int64_t ncov = 0;            // distinct covered grid points
+  int32_t *a_start = nullptr;  // [natoms+1] atom-major entry ranges
+  int32_t *e_g = nullptr;      // [nent] folded grid index (atom-major)
+  short4 *e_xyz = nullptr;     // [nent] unwrapped grid indices + image code (atom-major)
+  int32_t *estart = nullptr;   // [Ng+1] point-major entry range of every grid point
+  int32_t *pm_code = nullptr;  // [nent] atom << 12 | image code (point-major)
+  double *pos = nullptr;       // [natoms][3] atom positions
+  ProjDev *proj = nullptr;     // device copy of the projector parameters
 };
 
 struct Workspace {
@@ -98,6 +119,7 @@ struct gpaw_sys {
   int64_t ng = 0;
   int32_t max_bands = 0;
   gfd::Tables tab;
+  gfd::ProjDev proj;                    // projector parameters (host copy)
   double *dH = nullptr, *dS = nullptr;  // device [natoms][ni][ni]
   double *v = nullptr;                  // device [Ng]
   gfd::Workspace ws;
@@ -107,8 +129,7 @@ namespace gfd {
 
 size_t elem_size(int32_t dtype);
 
-// Host construction of the projector tables (tables.hip).
-struct HostTables;
+// Host construction of the projector geometry (tables.hip).
 int build_tables(const gpaw_sys_desc *d, gpaw_sys *s);
 
 // ---------------------------------------------------------------- launchers

@@ -3,12 +3,13 @@
 //
 // Projection: one workgroup per (atom, group of bands). Lanes stride over the
 // atom's sphere entries (sorted by grid index, so neighbouring lanes gather
-// neighbouring z points), keep the ni x NBG partial sums in registers, and
-// reduce them across the wavefront with cross-lane shuffles and across the
-// four wavefronts through LDS in a fixed order (bitwise reproducible).
+// neighbouring z points), evaluate the projector values of their entry once
+// for all bands of the group, keep the ni x NBG partial sums in registers,
+// and reduce them across the wavefront with cross-lane shuffles and across
+// the four wavefronts through LDS in a fixed order (bitwise reproducible).
 #include <algorithm>
 
-#include "internal.h"
+#include "proj.h"
 
 namespace gfd {
 
@@ -35,11 +36,15 @@ template <typename T, int NI, int NBG>
 __global__ __launch_bounds__(256) void k_project(const T *__restrict__ psi, T *__restrict__ P,
                                                  const int32_t *__restrict__ a_start,
                                                  const int32_t *__restrict__ e_g,
-                                                 const T *__restrict__ e_q, int64_t nent,
-                                                 int64_t ng, int nb, int ni, int np, double dV) {
+                                                 const short4 *__restrict__ e_xyz,
+                                                 const double *__restrict__ pos,
+                                                 const ProjDev *__restrict__ pjp,
+                                                 int64_t ng, int nb, int np, double dV) {
+  const ProjDev &pj = *pjp;
   const int atom = blockIdx.x;
   const int b0 = blockIdx.y * NBG;
   const int e0 = a_start[atom], e1 = a_start[atom + 1];
+  const double R0 = pos[3 * atom], R1 = pos[3 * atom + 1], R2 = pos[3 * atom + 2];
   T acc[NBG][NI];
 #pragma unroll
   for (int b = 0; b < NBG; ++b)
@@ -48,17 +53,24 @@ __global__ __launch_bounds__(256) void k_project(const T *__restrict__ psi, T *_
 
   for (int e = e0 + static_cast<int>(threadIdx.x); e < e1; e += 256) {
     const int64_t g = e_g[e];
-    T q[NI];
+    const short4 u = e_xyz[e];
+    T p[NBG];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) q[i] = (i < ni) ? St<T>::conj(e_q[i * nent + e]) : St<T>::zero();
+    for (int b = 0; b < NBG; ++b)
+      p[b] = (b0 + b < nb) ? psi[static_cast<int64_t>(b0 + b) * ng + g] : St<T>::zero();
+    double pv[NI];
+    eval_proj<NI>(pj, u.x * pj.h[0] - R0, u.y * pj.h[1] - R1, u.z * pj.h[2] - R2, pv);
+    if (St<T>::cplx) {
+      // conj(q) psi = p(r) conj(exp(-2 pi i k.w)) psi
+      const int c = u.w;
+      const z64 ph = zconj(image_phase(pj, ((c >> 8) & 15) - 8, ((c >> 4) & 15) - 8, (c & 15) - 8));
 #pragma unroll
-    for (int b = 0; b < NBG; ++b) {
-      if (b0 + b < nb) {
-        const T p = psi[static_cast<int64_t>(b0 + b) * ng + g];
-#pragma unroll
-        for (int i = 0; i < NI; ++i) acc[b][i] = acc[b][i] + St<T>::mul(q[i], p);
-      }
+      for (int b = 0; b < NBG; ++b) p[b] = St<T>::phase(p[b], ph);
     }
+#pragma unroll
+    for (int b = 0; b < NBG; ++b)
+#pragma unroll
+      for (int i = 0; i < NI; ++i) acc[b][i] = acc[b][i] + St<T>::scale(pv[i], p[b]);
   }
 
   __shared__ T red[4][NBG * NI];
@@ -73,8 +85,8 @@ __global__ __launch_bounds__(256) void k_project(const T *__restrict__ psi, T *_
   __syncthreads();
   for (int idx = threadIdx.x; idx < NBG * NI; idx += 256) {
     const int b = idx / NI, i = idx - b * NI;
-    if (b0 + b < nb && i < ni)
-      P[static_cast<int64_t>(b0 + b) * np + atom * ni + i] =
+    if (b0 + b < nb && i < pj.ni)
+      P[static_cast<int64_t>(b0 + b) * np + atom * pj.ni + i] =
           St<T>::scale(dV, (red[0][idx] + red[1][idx]) + (red[2][idx] + red[3][idx]));
   }
 }
@@ -99,7 +111,7 @@ void project_t(const gpaw_sys *s, const void *psi, int nb, void *P, hipStream_t 
   dim3 grid(s->natoms, (nb + NBG - 1) / NBG);
   k_project<T, NI, NBG><<<grid, 256, 0, st>>>(
       static_cast<const T *>(psi), static_cast<T *>(P), s->tab.a_start, s->tab.e_g,
-      static_cast<const T *>(s->tab.e_q), s->tab.nent, s->ng, nb, s->ni, s->np, s->dV);
+      s->tab.e_xyz, s->tab.pos, s->tab.proj, s->ng, nb, s->np, s->dV);
 }
 
 }  // namespace
@@ -107,7 +119,7 @@ void project_t(const gpaw_sys *s, const void *psi, int nb, void *P, hipStream_t 
 int launch_project(const gpaw_sys *s, const void *psi, int nb, void *P, hipStream_t st) {
   if (s->np == 0) return GPAW_OK;
   const bool cplx = s->dtype == GPAW_C128;
-  if (s->ni == 13) {
+  if (s->ni == 13 && s->proj.std13) {
     if (cplx) project_t<z64, 13, 2>(s, psi, nb, P, st);
     else project_t<double, 13, 4>(s, psi, nb, P, st);
   } else {

@@ -1,0 +1,91 @@
+// Device evaluation of the projector functions p~^a_i at a grid point.
+//
+// Channel (l, sigma, rc): N r^l exp(-r^2/2sigma^2) (1-(r/rc)^2)^2 Y_lm for
+// r < rc, N = [Gamma(l+3/2) sigma^(2l+3)/2]^(-1/2), real harmonics in the
+// order (1), (y, z, x), (xy, yz, 3z^2-r^2, xz, x^2-y^2) with the
+// normalisations 1/(2 sqrt(pi)), sqrt(3/4pi), (1/2)sqrt(15/pi),
+// (1/4)sqrt(5/pi), (1/4)sqrt(15/pi). The kernels recompute these values at
+// every use instead of streaming a table of them: a few dozen FP64 operations
+// per (point, atom) pair, shared by all bands a lane handles, replace
+// 8*ni bytes of table traffic per band.
+#pragma once
+
+#include "internal.h"
+
+namespace gfd {
+
+// Entry code of the point-major list: atom << 12 | (wx+8) << 8 | (wy+8) << 4 | (wz+8);
+// the unwrapped grid index along axis c is (folded index) + w_c n_c.
+__host__ __device__ inline int32_t pack_code(int atom, int wx, int wy, int wz) {
+  return (atom << 12) | ((wx + 8) << 8) | ((wy + 8) << 4) | (wz + 8);
+}
+
+// r^l Y_lm for harmonic slot 0..8 at displacement (x, y, z), r2 = r^2
+__device__ inline double solid_slot(int slot, double x, double y, double z, double r2) {
+  constexpr double c0 = 0.28209479177387814;   // 1/(2 sqrt(pi))
+  constexpr double c1 = 0.48860251190291992;   // sqrt(3/(4 pi))
+  constexpr double c2 = 1.0925484305920792;    // (1/2) sqrt(15/pi)
+  constexpr double c20 = 0.31539156525252005;  // (1/4) sqrt(5/pi)
+  constexpr double c22 = 0.54627421529603959;  // (1/4) sqrt(15/pi)
+  switch (slot) {
+    case 0: return c0;
+    case 1: return c1 * y;
+    case 2: return c1 * z;
+    case 3: return c1 * x;
+    case 4: return c2 * x * y;
+    case 5: return c2 * y * z;
+    case 6: return c20 * (3.0 * z * z - r2);
+    case 7: return c2 * x * z;
+    default: return c22 * (x * x - y * y);
+  }
+}
+
+// radial factor N exp(-r^2/2sigma^2) (1 - r^2/rc^2)^2 of channel c (0 beyond rc)
+__device__ inline double radial(const ProjDev &P, int c, double r2) {
+  const double s2 = r2 * P.rc2inv[c];
+  if (!(s2 < 1.0)) return 0.0;
+  const double t = 1.0 - s2;
+  return P.norm[c] * exp(-r2 * P.a2[c]) * (t * t);
+}
+
+// Values of all NI projectors of one atom at displacement (x, y, z).
+// NI == 13 is the channel layout l = (0, 0, 1, 1, 2); any other layout takes
+// the generic path (NI = PROJ_MAX_NI, entries beyond ni are zero).
+template <int NI>
+__device__ inline void eval_proj(const ProjDev &P, double x, double y, double z, double *out) {
+  const double r2 = x * x + y * y + z * z;
+  if constexpr (NI == 13) {
+    constexpr double c0 = 0.28209479177387814;
+    constexpr double c1 = 0.48860251190291992;
+    constexpr double c2 = 1.0925484305920792;
+    constexpr double c20 = 0.31539156525252005;
+    constexpr double c22 = 0.54627421529603959;
+    const double r0 = radial(P, 0, r2), r1 = radial(P, 1, r2), rp = radial(P, 2, r2),
+                 rq = radial(P, 3, r2), rd = radial(P, 4, r2);
+    out[0] = r0 * c0;
+    out[1] = r1 * c0;
+    const double py = c1 * y, pz = c1 * z, px = c1 * x;
+    out[2] = rp * py;
+    out[3] = rp * pz;
+    out[4] = rp * px;
+    out[5] = rq * py;
+    out[6] = rq * pz;
+    out[7] = rq * px;
+    out[8] = rd * (c2 * x * y);
+    out[9] = rd * (c2 * y * z);
+    out[10] = rd * (c20 * (3.0 * z * z - r2));
+    out[11] = rd * (c2 * x * z);
+    out[12] = rd * (c22 * (x * x - y * y));
+  } else {
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+      out[i] = (i < P.ni) ? radial(P, P.ch[i], r2) * solid_slot(P.ym[i], x, y, z, r2) : 0.0;
+  }
+}
+
+// Bloch phase exp(-2 pi i k.w) of an image shift w (grid-cell units).
+__device__ inline z64 image_phase(const ProjDev &P, int wx, int wy, int wz) {
+  return P.ph[0][wx + 8] * P.ph[1][wy + 8] * P.ph[2][wz + 8];
+}
+
+}  // namespace gfd

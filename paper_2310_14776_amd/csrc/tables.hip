@@ -1,22 +1,20 @@
-// Host construction of the projector tables.
+// Host construction of the projector geometry.
 //
 // The non-local terms of H~ and S~ (Eq. (dh) and the overlap operator beside
 // it) need the grid values of every projector p~^a_i. For a Bloch system the
 // value at grid point r of the cell is q^a_i(r) = sum_R exp(i k.R) p~^a_i(r - R_a - R)
-// over all lattice vectors R that bring the sphere of radius rc onto r.
-// We enumerate the unwrapped grid points inside each atom's sphere, fold them
-// into the cell (this fold fixes R), evaluate the projector there and sum
-// duplicates (a sphere larger than the cell meets its own images).
-//
-// Projector shape (synthetic stand-in for setup data): channel (l, sigma, rc)
-// has 2l+1 functions N r^l exp(-r^2/2sigma^2) (1-(r/rc)^2)^2 Y_lm, with
-// N = [Gamma(l+3/2) sigma^(2l+3)/2]^(-1/2) and real harmonics in the order
-// m = -l..l: (y, z, x) for l = 1, (xy, yz, 3z^2-r^2, xz, x^2-y^2) for l = 2.
+// over the lattice vectors R that bring the sphere of radius rc onto r. Here
+// we only enumerate the unwrapped grid points inside each atom's sphere and
+// fold each into the cell; the fold fixes R = -w L (w = whole cells crossed).
+// Each (point, atom, image) triple is one entry; the kernels evaluate the
+// projector values of an entry when they need them (proj.h), and entries of
+// one point (several atoms, or one atom's own images in a small cell) are
+// summed there.
 #include <algorithm>
 #include <cmath>
 #include <vector>
 
-#include "internal.h"
+#include "proj.h"
 
 namespace gfd {
 
@@ -30,43 +28,11 @@ int64_t floor_div(int64_t a, int64_t b) {
   return q;
 }
 
-// All ni projector values at displacement (x, y, z) from the atom.
-void projector_values(const gpaw_channel *ch, int nchan, double x, double y, double z,
-                      double *out) {
-  const double r2 = x * x + y * y + z * z;
-  const double r = std::sqrt(r2);
-  int i = 0;
-  for (int c = 0; c < nchan; ++c) {
-    const int l = ch[c].l;
-    const double sg = ch[c].sigma, rc = ch[c].rc;
-    const double s = r / rc;
-    const double chi = s < 1.0 ? (1.0 - s * s) * (1.0 - s * s) : 0.0;
-    const double norm = 1.0 / std::sqrt(std::tgamma(l + 1.5) * std::pow(sg, 2 * l + 3) * 0.5);
-    const double rad = norm * std::exp(-r2 / (2.0 * sg * sg)) * chi;
-    if (l == 0) {
-      out[i++] = rad * 0.5 / std::sqrt(kPi);
-    } else if (l == 1) {
-      const double c1 = std::sqrt(3.0 / (4.0 * kPi));
-      out[i++] = rad * c1 * y;
-      out[i++] = rad * c1 * z;
-      out[i++] = rad * c1 * x;
-    } else {
-      const double c2 = 0.5 * std::sqrt(15.0 / kPi);
-      const double c20 = 0.25 * std::sqrt(5.0 / kPi);
-      const double c22 = 0.25 * std::sqrt(15.0 / kPi);
-      out[i++] = rad * c2 * x * y;
-      out[i++] = rad * c2 * y * z;
-      out[i++] = rad * c20 * (3.0 * z * z - r2);
-      out[i++] = rad * c2 * x * z;
-      out[i++] = rad * c22 * (x * x - y * y);
-    }
-  }
-}
-
 struct Entry {
-  int32_t g;
+  int32_t g;      // folded grid index
   int32_t atom;
-  int64_t slot;  // offset of this entry's ni values in the value pool
+  int16_t u[3];   // unwrapped grid indices
+  int8_t w[3];    // cells crossed per axis
 };
 
 template <typename T>
@@ -78,31 +44,55 @@ int upload(T **dst, const std::vector<T> &src) {
   return GPAW_OK;
 }
 
+int setup_proj(const gpaw_sys_desc *d, ProjDev &P) {
+  P = ProjDev{};
+  if (d->nchan > PROJ_MAX_CHAN) return fail(GPAW_EINVAL, "at most 8 projector channels");
+  P.nchan = d->nchan;
+  int i = 0;
+  for (int c = 0; c < d->nchan; ++c) {
+    const gpaw_channel &ch = d->chan[c];
+    P.l[c] = ch.l;
+    P.norm[c] = 1.0 / std::sqrt(std::tgamma(ch.l + 1.5) * std::pow(ch.sigma, 2 * ch.l + 3) * 0.5);
+    P.rc2inv[c] = 1.0 / (ch.rc * ch.rc);
+    P.a2[c] = 1.0 / (2.0 * ch.sigma * ch.sigma);
+    const int first_slot = ch.l == 0 ? 0 : (ch.l == 1 ? 1 : 4);
+    for (int m = 0; m < 2 * ch.l + 1; ++m) {
+      P.ch[i] = static_cast<signed char>(c);
+      P.ym[i] = static_cast<signed char>(first_slot + m);
+      ++i;
+    }
+  }
+  P.ni = i;
+  P.std13 = (d->nchan == 5 && P.l[0] == 0 && P.l[1] == 0 && P.l[2] == 1 && P.l[3] == 1 &&
+             P.l[4] == 2) ? 1 : 0;
+  for (int c = 0; c < 3; ++c) {
+    P.n[c] = d->n[c];
+    P.h[c] = d->h[c];
+    for (int w = -8; w <= 7; ++w) {
+      const double arg = -2.0 * kPi * d->k[c] * w;
+      P.ph[c][w + 8] = zmake(std::cos(arg), std::sin(arg));
+    }
+  }
+  return GPAW_OK;
+}
+
 }  // namespace
 
 int build_tables(const gpaw_sys_desc *d, gpaw_sys *s) {
-  const int ni = s->ni;
-  const bool cplx = s->dtype == GPAW_C128;
-  const int64_t n0 = d->n[0], n1 = d->n[1], n2 = d->n[2];
+  int rc = setup_proj(d, s->proj);
+  if (rc != GPAW_OK) return rc;
+  const int64_t n[3] = {d->n[0], d->n[1], d->n[2]};
   double rmax = 0.0;
   for (int c = 0; c < d->nchan; ++c) rmax = std::max(rmax, d->chan[c].rc);
 
-  std::vector<Entry> ent;        // atom-major, sorted by g within an atom
-  std::vector<double> pool_re, pool_im;
-  std::vector<int32_t> a_start(d->natoms + 1, 0);
-  std::vector<double> vals(ni);
-
+  std::vector<Entry> ent;
   for (int a = 0; a < d->natoms; ++a) {
-    a_start[a] = static_cast<int32_t>(ent.size());
     const double *R = d->pos + 3 * a;
     int64_t lo[3], hi[3];
     for (int c = 0; c < 3; ++c) {
       lo[c] = static_cast<int64_t>(std::ceil((R[c] - rmax) / d->h[c]));
       hi[c] = static_cast<int64_t>(std::floor((R[c] + rmax) / d->h[c]));
     }
-    // (g, phase-weighted values) of every unwrapped point in the sphere
-    struct Raw { int32_t g; double re[32]; double im[32]; };
-    std::vector<Raw> raw;
     for (int64_t i = lo[0]; i <= hi[0]; ++i) {
       const double dx = i * d->h[0] - R[0];
       for (int64_t j = lo[1]; j <= hi[1]; ++j) {
@@ -110,87 +100,75 @@ int build_tables(const gpaw_sys_desc *d, gpaw_sys *s) {
         for (int64_t l = lo[2]; l <= hi[2]; ++l) {
           const double dz = l * d->h[2] - R[2];
           if (dx * dx + dy * dy + dz * dz >= rmax * rmax) continue;
-          const int64_t wi = floor_div(i, n0), wj = floor_div(j, n1), wl = floor_div(l, n2);
-          const int64_t g = ((i - wi * n0) * n1 + (j - wj * n1)) * n2 + (l - wl * n2);
-          projector_values(d->chan, d->nchan, dx, dy, dz, vals.data());
-          // unwrapped point = cell point + w L, i.e. image R = -w L: phase exp(-2 pi i k.w)
-          const double arg = -2.0 * kPi * (d->k[0] * wi + d->k[1] * wj + d->k[2] * wl);
-          const double cr = cplx ? std::cos(arg) : 1.0, sr = cplx ? std::sin(arg) : 0.0;
-          Raw r;
-          r.g = static_cast<int32_t>(g);
-          for (int q = 0; q < ni; ++q) {
-            r.re[q] = cr * vals[q];
-            r.im[q] = sr * vals[q];
+          const int64_t u[3] = {i, j, l};
+          Entry e;
+          int64_t f[3];
+          for (int c = 0; c < 3; ++c) {
+            const int64_t w = floor_div(u[c], n[c]);
+            if (w < -8 || w > 7 || u[c] < -32768 || u[c] > 32767)
+              return fail(GPAW_EINVAL, "projector spheres reach too many cells away; "
+                                       "grow the cell or shrink rc");
+            f[c] = u[c] - w * n[c];
+            e.u[c] = static_cast<int16_t>(u[c]);
+            e.w[c] = static_cast<int8_t>(w);
           }
-          raw.push_back(r);
+          e.g = static_cast<int32_t>((f[0] * n[1] + f[1]) * n[2] + f[2]);
+          e.atom = a;
+          ent.push_back(e);
         }
       }
     }
-    std::stable_sort(raw.begin(), raw.end(), [](const Raw &x, const Raw &y) { return x.g < y.g; });
-    for (size_t p = 0; p < raw.size();) {
-      size_t q = p + 1;
-      Entry e{raw[p].g, a, static_cast<int64_t>(pool_re.size())};
-      double re[32], im[32];
-      for (int t = 0; t < ni; ++t) { re[t] = raw[p].re[t]; im[t] = raw[p].im[t]; }
-      while (q < raw.size() && raw[q].g == raw[p].g) {
-        for (int t = 0; t < ni; ++t) { re[t] += raw[q].re[t]; im[t] += raw[q].im[t]; }
-        ++q;
-      }
-      for (int t = 0; t < ni; ++t) { pool_re.push_back(re[t]); pool_im.push_back(im[t]); }
-      ent.push_back(e);
-      p = q;
-    }
   }
-  a_start[d->natoms] = static_cast<int32_t>(ent.size());
   const int64_t nent = static_cast<int64_t>(ent.size());
-  if (nent >= (int64_t(1) << 31) / std::max(ni, 1))
-    return fail(GPAW_EINVAL, "projector tables too large for 32-bit indexing");
+  if (nent >= (int64_t(1) << 31) - 1)
+    return fail(GPAW_EINVAL, "projector geometry too large for 32-bit indexing");
+  if (d->natoms >= (1 << 19)) return fail(GPAW_EINVAL, "too many atoms");
 
-  // atom-major arrays
+  // atom-major (already grouped by atom); sort by grid index inside an atom
+  std::vector<int32_t> a_start(d->natoms + 1, 0);
+  std::stable_sort(ent.begin(), ent.end(), [](const Entry &x, const Entry &y) {
+    return x.atom != y.atom ? x.atom < y.atom : x.g < y.g;
+  });
+  for (int64_t e = 0, a = 0; a <= d->natoms; ++a) {
+    while (e < nent && ent[e].atom < a) ++e;
+    a_start[a] = static_cast<int32_t>(e);
+  }
   std::vector<int32_t> e_g(nent);
-  std::vector<double> qa(cplx ? 2 * ni * nent : ni * nent);
+  std::vector<short4> e_xyz(nent);
   for (int64_t e = 0; e < nent; ++e) {
     e_g[e] = ent[e].g;
-    for (int t = 0; t < ni; ++t) {
-      const double re = pool_re[ent[e].slot + t], im = pool_im[ent[e].slot + t];
-      if (cplx) { qa[2 * (t * nent + e)] = re; qa[2 * (t * nent + e) + 1] = im; }
-      else qa[t * nent + e] = re;
-    }
+    const Entry &x = ent[e];
+    const int code = ((x.w[0] + 8) << 8) | ((x.w[1] + 8) << 4) | (x.w[2] + 8);
+    e_xyz[e] = make_short4(x.u[0], x.u[1], x.u[2], static_cast<short>(code));
   }
-  // point-major order: by grid point, then atom
-  std::vector<int64_t> order(nent);
-  for (int64_t e = 0; e < nent; ++e) order[e] = e;
-  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
-    return ent[x].g != ent[y].g ? ent[x].g < ent[y].g : ent[x].atom < ent[y].atom;
+  // point-major: by grid point, then atom, then image
+  std::stable_sort(ent.begin(), ent.end(), [](const Entry &x, const Entry &y) {
+    if (x.g != y.g) return x.g < y.g;
+    if (x.atom != y.atom) return x.atom < y.atom;
+    if (x.w[0] != y.w[0]) return x.w[0] < y.w[0];
+    if (x.w[1] != y.w[1]) return x.w[1] < y.w[1];
+    return x.w[2] < y.w[2];
   });
-  std::vector<int32_t> g2u(s->ng, -1), u_start, pm_atom(nent);
-  std::vector<double> qp(qa.size());
-  for (int64_t p = 0; p < nent; ++p) {
-    const Entry &e = ent[order[p]];
-    if (p == 0 || ent[order[p - 1]].g != e.g) {
-      g2u[e.g] = static_cast<int32_t>(u_start.size());
-      u_start.push_back(static_cast<int32_t>(p));
-    }
-    pm_atom[p] = e.atom;
-    for (int t = 0; t < ni; ++t) {
-      const double re = pool_re[e.slot + t], im = pool_im[e.slot + t];
-      if (cplx) { qp[2 * (t * nent + p)] = re; qp[2 * (t * nent + p) + 1] = im; }
-      else qp[t * nent + p] = re;
-    }
+  std::vector<int32_t> estart(s->ng + 1, 0), pm_code(nent);
+  int64_t ncov = 0;
+  for (int64_t e = 0; e < nent; ++e) {
+    const Entry &x = ent[e];
+    pm_code[e] = pack_code(x.atom, x.w[0], x.w[1], x.w[2]);
+    estart[x.g + 1] += 1;
+    if (e == 0 || ent[e - 1].g != x.g) ++ncov;
   }
-  const int64_t nu = static_cast<int64_t>(u_start.size());
-  u_start.push_back(static_cast<int32_t>(nent));
+  for (int64_t g = 0; g < s->ng; ++g) estart[g + 1] += estart[g];
 
+  std::vector<double> pos(d->pos, d->pos + 3 * d->natoms);
   s->tab.nent = nent;
-  s->tab.nu = nu;
-  int rc;
+  s->tab.ncov = ncov;
   if ((rc = upload(&s->tab.a_start, a_start)) != GPAW_OK) return rc;
   if ((rc = upload(&s->tab.e_g, e_g)) != GPAW_OK) return rc;
-  if ((rc = upload(reinterpret_cast<double **>(&s->tab.e_q), qa)) != GPAW_OK) return rc;
-  if ((rc = upload(&s->tab.g2u, g2u)) != GPAW_OK) return rc;
-  if ((rc = upload(&s->tab.u_start, u_start)) != GPAW_OK) return rc;
-  if ((rc = upload(&s->tab.pm_atom, pm_atom)) != GPAW_OK) return rc;
-  if ((rc = upload(reinterpret_cast<double **>(&s->tab.pm_q), qp)) != GPAW_OK) return rc;
+  if ((rc = upload(&s->tab.e_xyz, e_xyz)) != GPAW_OK) return rc;
+  if ((rc = upload(&s->tab.estart, estart)) != GPAW_OK) return rc;
+  if ((rc = upload(&s->tab.pm_code, pm_code)) != GPAW_OK) return rc;
+  if ((rc = upload(&s->tab.pos, pos)) != GPAW_OK) return rc;
+  if ((rc = upload(&s->tab.proj, std::vector<ProjDev>(1, s->proj))) != GPAW_OK) return rc;
   return GPAW_OK;
 }
 

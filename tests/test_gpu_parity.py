@@ -28,14 +28,38 @@ CASES = {
     "selfoverlap16_nb1": synth.ragged_cases()[1],
     "noatoms": synth.ragged_cases()[2],
     "tail20x18x66": synth.ragged_cases()[3],
+    "generic_channels": None,
+    # complex Bloch cases, k in reduced units (phases i, 1, -1 for the first)
+    "bloch16": dict(n=(16, 14, 18), h=0.2, nb=12, natoms=3, rc=1.8, seed=41, k=(0.25, 0.0, 0.5)),
+    "bloch_ragged": dict(n=(13, 11, 17), h=(0.21, 0.19, 0.23), nb=7, natoms=2, rc=1.6, seed=42,
+                         k=(0.1, 0.37, 0.8)),
+    "bloch_selfoverlap": dict(n=(16, 16, 16), h=0.2, nb=5, natoms=3, rc=2.0, seed=43,
+                              k=(0.3, 0.45, 0.05)),
+    "bloch_nb96": dict(n=(24, 20, 28), h=0.2, nb=96, natoms=5, rc=2.0, seed=44, k=(0.25, 0.0, 0.5)),
 }
 
 _cache = {}
 
 
+def _generic_channels():
+    """Channel set outside the standard 13-projector layout (ni = 9)."""
+    s = synth.make_system(n=(14, 12, 16), h=0.21, nb=6, natoms=3, rc=1.6, seed=31)
+    s.channels = [(1, 0.5, 1.5), (0, 0.4, 1.2), (2, 0.6, 1.7)]
+    rng = np.random.default_rng(32)
+    A = rng.uniform(-1, 1, (s.natoms, 9, 9))
+    B = rng.uniform(-1, 1, (s.natoms, 9, 9))
+    s.dH = 0.5 * (A + A.transpose(0, 2, 1))
+    s.dS = 0.05 * (B + B.transpose(0, 2, 1))
+    s.name = "generic_channels"
+    return s
+
+
 def case(name):
     if name not in _cache:
-        s = synth.make_system(name=name, **CASES[name])
+        if name == "generic_channels":
+            s = _generic_channels()
+        else:
+            s = synth.make_system(name=name, **CASES[name])
         ops = oracle.Operators.from_system(s)
         ref = oracle.fd_step(s, ops)
         _cache[name] = (s, ops, ref)
@@ -65,10 +89,11 @@ def test_step_parity(name):
     eps = host(out["eps"])
     assert np.abs(eps - ref["eps"]).max() <= TOL * np.abs(ref["eps"]).max()
     C = host(out["C"])
-    Hs = 0.5 * (ref["H"] + ref["H"].T)
-    Ss = 0.5 * (ref["S"] + ref["S"].T)
-    assert np.abs(C.T @ Ss @ C - np.eye(s.nb)).max() <= TOL
-    assert np.abs(C.T @ Hs @ C - np.diag(ref["eps"])).max() <= TOL * np.abs(ref["eps"]).max()
+    Hs = 0.5 * (ref["H"] + ref["H"].conj().T)
+    Ss = 0.5 * (ref["S"] + ref["S"].conj().T)
+    Ch = C.conj().T
+    assert np.abs(Ch @ Ss @ C - np.eye(s.nb)).max() <= TOL
+    assert np.abs(Ch @ Hs @ C - np.diag(ref["eps"])).max() <= TOL * np.abs(ref["eps"]).max()
     psi_h = s.psi.reshape(s.nb, -1)
     assert rel(host(out["psi_rot"]), oracle.rotate(psi_h, C)) <= TOL
     if s.natoms:
