@@ -56,7 +56,7 @@ int after_launch(const char *what) {
 
 void free_sys(gpaw_sys *s) {
   if (!s) return;
-  void *bufs[] = {s->tab.a_start, s->tab.e_g, s->tab.e_xyz, s->tab.estart, s->tab.pm_code,
+  void *bufs[] = {s->tab.a_start, s->tab.e_g, s->tab.e_xyz, s->tab.pinfo, s->tab.pm_code,
                   s->tab.pos,     s->dH,      s->dS,        s->v,          s->ws.P,
                   s->ws.X,        s->ws.part, s->ws.eig,    s->ws.info,    s->tab.proj};
   for (void *p : bufs)
@@ -266,7 +266,7 @@ int gpaw_subspace_diag(gpaw_sys *s, const void *H, const void *S, int32_t nb, do
   int rc;
   if ((rc = check_sys(s)) != GPAW_OK) return rc;
   if ((rc = check_nb(s, nb)) != GPAW_OK) return rc;
-  if (nb > 128) return fail(GPAW_ESHAPE, "gpaw_subspace_diag supports nb <= 128");
+  if (nb > 1024) return fail(GPAW_ESHAPE, "gpaw_subspace_diag supports nb <= 1024");
   if (!H || !S || !eps || !C) return fail(GPAW_EINVAL, "H_nn, S_nn, eps and C_nn must not be NULL");
   const size_t mbytes = static_cast<size_t>(nb) * nb * elem_size(s->dtype);
   if (overlaps(C, mbytes, H, mbytes) || overlaps(C, mbytes, S, mbytes) ||

@@ -28,6 +28,17 @@
 
 namespace gfd {
 
+template <typename T>
+int large_chol_linv(T *Sw, T *Linv, int n, double *piv, int32_t *info, hipStream_t st);
+template <typename T>
+int large_tridiag(T *A, int n, T *V, T *tau, double *d, double *e, T *p, int32_t *info,
+                  hipStream_t st);
+int large_vectors(int n, const double *d, const double *e, const double *lam, double *lu,
+                  double *Z, const int32_t *info, hipStream_t st);
+template <typename T>
+int large_back(int n, const double *Z, const T *V, const T *tau, const double *lam, T *U,
+               double *eps, const int32_t *info, hipStream_t st);
+
 namespace {
 
 constexpr int EIG_T = 1024;
@@ -41,9 +52,11 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // complex); Z, Z2, G, d, e, lam are real. Pointers are to doubles.
 struct EigWs {
   double *Linv, *T1, *A, *V, *Z, *Z2, *G, *tau, *d, *e, *lam;
+  double *Sw, *piv, *p, *lu;  // blocks above the LDS limit only
 };
 
-EigWs eig_layout(double *base, int n, int sz) {
+// sz = doubles per scalar; large = include the global-memory path's buffers
+EigWs eig_layout(double *base, int n, int sz, bool large) {
   const size_t nn = static_cast<size_t>(n) * n;
   EigWs w;
   w.Linv = base;
@@ -57,10 +70,25 @@ EigWs eig_layout(double *base, int n, int sz) {
   w.d = w.tau + sz * n;
   w.e = w.d + n;
   w.lam = w.e + n;
+  double *q = w.lam + n;
+  w.Sw = w.piv = w.p = w.lu = nullptr;
+  if (large) {
+    w.Sw = q;
+    w.piv = w.Sw + sz * nn;
+    w.p = w.piv + n;
+    w.lu = w.p + sz * n;
+  }
   return w;
 }
 
-template <typename T> __device__ inline T *as(double *p) { return reinterpret_cast<T *>(p); }
+size_t eig_layout_elems(int n, int sz, bool large) {
+  const size_t nn = static_cast<size_t>(n) * n;
+  size_t e = 4 * sz * nn + 3 * nn + sz * n + 3 * n;
+  if (large) e += sz * nn + n + sz * n + 4 * nn;
+  return e + 64;
+}
+
+template <typename T> __host__ __device__ inline T *as(double *p) { return reinterpret_cast<T *>(p); }
 
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
@@ -200,6 +228,22 @@ __global__ __launch_bounds__(EIG_T) void k_eig_chol(const T *__restrict__ S, int
     }
   }
   if (tid == 0) *info = 0;
+}
+
+__global__ void k_set_info(int32_t *info) { *info = 0; }
+
+// Y = (X + X^H)/2 for n x n row-major matrices (Y may equal X)
+template <typename T>
+__global__ __launch_bounds__(256) void k_hermitize(const T *X, T *Y, int n, const int32_t *info) {
+  if (*info != 0) return;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * n) return;
+  const int r = static_cast<int>(idx / n), c = static_cast<int>(idx - static_cast<int64_t>(r) * n);
+  if (c < r) return;
+  const T a = X[static_cast<int64_t>(r) * n + c], b = X[static_cast<int64_t>(c) * n + r];
+  const T h = St<T>::scale(0.5, a + cj(b));
+  Y[static_cast<int64_t>(r) * n + c] = h;
+  Y[static_cast<int64_t>(c) * n + r] = cj(h);
 }
 
 // ------------------------------------------------------------------ small GEMM
@@ -394,7 +438,8 @@ __global__ __launch_bounds__(EIG_T) void k_eig_tridiag(int n, EigWs w, const int
 // ------------------------------------------------------------------ values
 __global__ __launch_bounds__(256) void k_eig_values(int n, EigWs w, const int32_t *info) {
   if (*info != 0) return;
-  __shared__ double d[EIG_NMAX], e[EIG_NMAX], e2[EIG_NMAX];
+  extern __shared__ double sdv[];
+  double *d = sdv, *e = sdv + n, *e2 = sdv + 2 * n;
   for (int i = threadIdx.x; i < n; i += 256) {
     d[i] = w.d[i];
     e[i] = (i + 1 < n) ? w.e[i] : 0.0;
@@ -630,13 +675,49 @@ __global__ __launch_bounds__(128) void k_eig_back(int n, EigWs w, const double *
   if (s == 0) eps[rank] = lj;
 }
 
+constexpr int EIG_LARGE_MAX = 1024;
+
+// blocks above the LDS limit: global-memory pipeline (eigh_large.hip)
+template <typename T>
+int eigh_large_t(const gpaw_sys *s, const T *H, const T *S, int n, double *eps, T *C,
+                 int32_t *info, hipStream_t st) {
+  const int sz = St<T>::cplx ? 2 : 1;
+  const EigWs w = eig_layout(s->ws.eig, n, sz, true);
+  const int64_t nn = static_cast<int64_t>(n) * n;
+  const unsigned eb = static_cast<unsigned>((nn + 255) / 256);
+  const int tiles = ((n + 15) / 16) * ((n + 15) / 16);
+  const unsigned sg_blocks = static_cast<unsigned>((tiles + 3) / 4);
+  T *Sw = as<T>(w.Sw), *Linv = as<T>(w.Linv), *T1 = as<T>(w.T1), *Am = as<T>(w.A);
+  T *V = as<T>(w.V), *tau = as<T>(w.tau), *p = as<T>(w.p), *U = as<T>(w.T1);
+  k_set_info<<<1, 1, 0, st>>>(info);
+  k_hermitize<T><<<eb, 256, 0, st>>>(S, Sw, n, info);
+  large_chol_linv<T>(Sw, Linv, n, w.piv, info, st);
+  k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(H, 2, Linv, 1, T1, n, info);
+  k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Linv, 0, T1, 0, Am, n, info);
+  k_hermitize<T><<<eb, 256, 0, st>>>(Am, Am, n, info);
+  large_tridiag<T>(Am, n, V, tau, w.d, w.e, p, info, st);
+  k_eig_values<<<(n + 3) / 4, 256, 3 * n * sizeof(double), st>>>(n, w, info);
+  large_vectors(n, w.d, w.e, w.lam, w.lu, w.Z, info, st);
+  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z, 1, w.Z, 0, w.G, n, info);
+  k_gram_check<<<1, 256, 0, st>>>(w.G, n, 0.5, info);
+  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z, 0, w.G, 3, w.Z2, n, info);
+  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z2, 1, w.Z2, 0, w.G, n, info);
+  k_gram_check<<<1, 256, 0, st>>>(w.G, n, 1e-7, info);
+  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z2, 0, w.G, 3, w.Z, n, info);
+  large_back<T>(n, w.Z, V, tau, w.lam, U, eps, info, st);
+  k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Linv, 1, U, 0, C, n, info);
+  return GPAW_OK;
+}
+
 template <typename T>
 int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps, void *C,
            int32_t *info, hipStream_t st) {
   constexpr int NMAX = EigMax<T>::n;
+  if (nb > EIG_LARGE_MAX)
+    return fail(GPAW_ESHAPE, "subspace eigensolver supports nb <= 1024");
   if (nb > NMAX)
-    return fail(GPAW_ESHAPE, "subspace eigensolver supports nb <= " + std::to_string(NMAX) +
-                                 (St<T>::cplx ? " for complex systems" : ""));
+    return eigh_large_t<T>(s, static_cast<const T *>(H), static_cast<const T *>(S), nb, eps,
+                           static_cast<T *>(C), info, st);
   static std::once_flag once;
   static hipError_t attr_err = hipSuccess;
   std::call_once(once, [] {
@@ -650,7 +731,7 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
   if (attr_err != hipSuccess) return hip_fail(attr_err, "hipFuncSetAttribute(eigensolver)");
   const int n = nb;
   const int sz = St<T>::cplx ? 2 : 1;
-  const EigWs w = eig_layout(s->ws.eig, n, sz);
+  const EigWs w = eig_layout(s->ws.eig, n, sz, false);
   const T *Hd = static_cast<const T *>(H);
   const T *Sd = static_cast<const T *>(S);
   const size_t lda_bytes = (static_cast<size_t>(n) * (n + 1)) * sizeof(T);
@@ -665,7 +746,7 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
   k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Linv, 0, T1, 0, Am, n, info);
   k_eig_tridiag<T><<<1, EIG_T, lda_bytes + 3 * n * sizeof(T) + 2 * n * sizeof(double) + 16 * sizeof(T),
                      st>>>(n, w, info);
-  k_eig_values<<<(n + 3) / 4, 256, 0, st>>>(n, w, info);
+  k_eig_values<<<(n + 3) / 4, 256, 3 * n * sizeof(double), st>>>(n, w, info);
   k_eig_vectors<<<(n + VEC_T - 1) / VEC_T, VEC_T, (3 * n + 4 * n * VEC_T) * sizeof(double), st>>>(
       n, w, info);
   // two Newton-Schulz steps Z <- Z (3I - Z^T Z)/2 on the real tridiagonal
@@ -687,8 +768,9 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
 }  // namespace
 
 size_t eig_ws_elems(int nmax, bool cplx) {
-  const size_t n = static_cast<size_t>(std::min(nmax, cplx ? EigMax<z64>::n : EigMax<double>::n));
-  return (7 * n * n + 6 * n + 64) * (cplx ? 2 : 1);
+  const int small = cplx ? EigMax<z64>::n : EigMax<double>::n;
+  const int n = std::min(nmax, EIG_LARGE_MAX);
+  return eig_layout_elems(n, cplx ? 2 : 1, n > small);
 }
 
 int launch_eigh(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps, void *C,

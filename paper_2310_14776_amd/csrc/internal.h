@@ -66,6 +66,7 @@ constexpr int PROJ_MAX_NI = 32;
 struct ProjDev {
   int nchan, ni;
   int std13;                       // channel l sequence is (0, 0, 1, 1, 2)
+  int same_sigma[PROJ_MAX_CHAN];   // std13: 0/1 = shares channel 0/1's sigma, -1 = own
   int l[PROJ_MAX_CHAN];
   double norm[PROJ_MAX_CHAN];
   double rc2inv[PROJ_MAX_CHAN];    // 1 / rc^2
@@ -89,7 +90,8 @@ struct Tables {
   int32_t *a_start = nullptr;  // [natoms+1] atom-major entry ranges
   int32_t *e_g = nullptr;      // [nent] folded grid index (atom-major)
   short4 *e_xyz = nullptr;     // [nent] unwrapped grid indices + image code (atom-major)
-  int32_t *estart = nullptr;   // [Ng+1] point-major entry range of every grid point
+  int2 *pinfo = nullptr;       // [Ng] {code of the point's first entry,
+                               //       count << 24 | index of that entry}
   int32_t *pm_code = nullptr;  // [nent] atom << 12 | image code (point-major)
   double *pos = nullptr;       // [natoms][3] atom positions
   ProjDev *proj = nullptr;     // device copy of the projector parameters

@@ -48,6 +48,16 @@ __device__ inline double radial(const ProjDev &P, int c, double r2) {
   return P.norm[c] * exp(-r2 * P.a2[c]) * (t * t);
 }
 
+// same, reusing the Gaussian of channel 0 or 1 when the sigmas agree
+__device__ inline double radial_shared(const ProjDev &P, int c, double r2, double E0, double E1) {
+  const double s2 = r2 * P.rc2inv[c];
+  if (!(s2 < 1.0)) return 0.0;
+  const double t = 1.0 - s2;
+  const int sh = P.same_sigma[c];
+  const double E = sh == 0 ? E0 : (sh == 1 ? E1 : exp(-r2 * P.a2[c]));
+  return P.norm[c] * E * (t * t);
+}
+
 // Values of all NI projectors of one atom at displacement (x, y, z).
 // NI == 13 is the channel layout l = (0, 0, 1, 1, 2); any other layout takes
 // the generic path (NI = PROJ_MAX_NI, entries beyond ni are zero).
@@ -60,8 +70,15 @@ __device__ inline void eval_proj(const ProjDev &P, double x, double y, double z,
     constexpr double c2 = 1.0925484305920792;
     constexpr double c20 = 0.31539156525252005;
     constexpr double c22 = 0.54627421529603959;
-    const double r0 = radial(P, 0, r2), r1 = radial(P, 1, r2), rp = radial(P, 2, r2),
-                 rq = radial(P, 3, r2), rd = radial(P, 4, r2);
+    const double E0 = exp(-r2 * P.a2[0]), E1 = exp(-r2 * P.a2[1]);
+    double r0 = 0.0, r1 = 0.0;
+    {
+      const double s0 = r2 * P.rc2inv[0], s1 = r2 * P.rc2inv[1];
+      if (s0 < 1.0) r0 = P.norm[0] * E0 * (1.0 - s0) * (1.0 - s0);
+      if (s1 < 1.0) r1 = P.norm[1] * E1 * (1.0 - s1) * (1.0 - s1);
+    }
+    const double rp = radial_shared(P, 2, r2, E0, E1), rq = radial_shared(P, 3, r2, E0, E1),
+                 rd = radial_shared(P, 4, r2, E0, E1);
     out[0] = r0 * c0;
     out[1] = r1 * c0;
     const double py = c1 * y, pz = c1 * z, px = c1 * x;

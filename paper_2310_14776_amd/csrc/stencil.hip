@@ -5,13 +5,14 @@
 //
 // Kernel shape (gfx950): a workgroup of 256 lanes owns 256 consecutive points
 // of one y-z plane (flattened, z contiguous, so every load is coalesced) for
-// one band, and marches along x over a segment of planes. The x neighbours
-// live in a 7-deep register queue per lane; the y and z neighbours come from
-// an LDS copy of the current plane slice widened by three rows on each side.
-// Periodic/Bloch folding happens at load time (x and y) and when a z
-// neighbour crosses its row (z). The non-local add-back is fused into the
-// store: each covered grid point sums q^a_i(r) (Delta.P)^a_i over the atoms
-// whose spheres reach it, so H~psi leaves the kernel in one HBM pass.
+// a group of bands, and marches along x over a segment of planes. The x
+// neighbours live in a 7-deep register queue per lane and band; the y and z
+// neighbours are read straight from the current plane, which the wavefronts
+// of the workgroup have just brought into L1/L2, so the kernel needs no LDS
+// tile and no barrier. Periodic/Bloch folding of every neighbour offset is
+// worked out once per lane. The non-local add-back is fused into the store:
+// each covered grid point sums q^a_i(r) (Delta.P)^a_i over the atoms whose
+// spheres reach it, so H~psi leaves the kernel in one HBM pass.
 #include <algorithm>
 
 #include "proj.h"
@@ -31,13 +32,16 @@ struct StencilGeom {
 };
 
 struct AddArgs {
-  const int32_t *estart;   // [Ng+1] point-major entry ranges
+  const int2 *pinfo;       // [Ng] first entry code, count << 24 | first index
   const int32_t *pm_code;  // atom << 12 | image code
   const double *pos;       // [natoms][3]
   const void *X;           // [nb][Np] Delta.P
   const ProjDev *pj;
   int np;
+  int natoms;
 };
+
+constexpr int POS_LDS_MAX = 1024;  // atoms whose positions are staged in LDS
 
 // floor(a / b) for b > 0 and small |a / b| (|quotient| <= 3 in every use)
 __device__ inline int fold_count(int a, int b) {
@@ -51,20 +55,23 @@ __device__ inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + 
 
 __device__ inline int clamp3(int w) { return w < -3 ? -3 : (w > 3 ? 3 : w); }
 
-// Non-local add-back for NB bands at grid point g = (ix, iy, iz):
-// acc[b] += sum_entries phase * sum_i p_i(r) X[b][atom*ni + i]. The projector
-// values of an entry are evaluated once and reused for every band; X rows
-// of the band group come from LDS (Xs, row stride ldx) or global memory.
+// Non-local add-back for NB bands at grid point (ix, iy, iz) whose entry
+// summary is pi: acc[b] += sum_entries phase * sum_i p_i(r) X[b][atom*ni + i].
+// The projector values of an entry are evaluated once and reused for every
+// band; X rows of the band group and the atom positions come from LDS when
+// they fit (generic pointers otherwise).
 template <typename T, int NI, int NB>
-__device__ inline void addback_group(const AddArgs &ab, int64_t g, int ix, int iy, int iz,
-                                     const T *Xs, int ldx, int b0, int nb, T *acc) {
-  const int e0 = ab.estart[g], e1 = ab.estart[g + 1];
+__device__ inline void addback_group(const AddArgs &ab, int2 pi, int ix, int iy, int iz,
+                                     const double *pos, const T *Xs, int ldx, int b0, int nb,
+                                     T *acc) {
+  const int cnt = static_cast<int>(static_cast<unsigned>(pi.y) >> 24);
+  const int first = pi.y & 0xFFFFFF;
   const ProjDev &pj = *ab.pj;
-  for (int e = e0; e < e1; ++e) {
-    const int code = ab.pm_code[e];
+  for (int j = 0; j < cnt; ++j) {
+    const int code = j == 0 ? pi.x : ab.pm_code[first + j];
     const int a = code >> 12;
     const int wx = ((code >> 8) & 15) - 8, wy = ((code >> 4) & 15) - 8, wz = (code & 15) - 8;
-    const double *R = ab.pos + 3 * a;
+    const double *R = pos + 3 * a;
     double pv[NI];
     eval_proj<NI>(pj, (ix + wx * pj.n[0]) * pj.h[0] - R[0], (iy + wy * pj.n[1]) * pj.h[1] - R[1],
                   (iz + wz * pj.n[2]) * pj.h[2] - R[2], pv);
@@ -83,6 +90,13 @@ __device__ inline void addback_group(const AddArgs &ab, int64_t g, int ix, int i
   }
 }
 
+// Atom positions into LDS (when they fit), else the global array.
+__device__ inline const double *stage_pos(const AddArgs &ab, double *lds_pos, int natoms_lds) {
+  if (!lds_pos) return ab.pos;
+  for (int idx = threadIdx.x; idx < 3 * natoms_lds; idx += blockDim.x) lds_pos[idx] = ab.pos[idx];
+  return lds_pos;
+}
+
 // Copies the band group's X rows into LDS (rows b >= nb are left unset).
 template <typename T, int NB>
 __device__ inline void stage_x(const AddArgs &ab, int b0, int nb, T *xs) {
@@ -94,69 +108,52 @@ __device__ inline void stage_x(const AddArgs &ab, int b0, int nb, T *xs) {
   }
 }
 
-constexpr int HALO_SLOTS = 4;  // 6*n2 <= 4*256, i.e. n2 <= 170
-
 template <typename T, bool BLOCH, bool ADD, bool XLDS, int NI, int NB>
 __global__ __launch_bounds__(ST_THREADS) void k_stencil(const T *__restrict__ psi,
                                                         T *__restrict__ out,
                                                         const double *__restrict__ v,
                                                         StencilGeom G, AddArgs ab, int nb) {
   extern __shared__ unsigned char smem[];
-  const int n0 = G.n0, n2 = G.n2;
-  const int plane = G.n1 * n2;
-  const int halo = 3 * n2;
-  const int span = ST_THREADS + 2 * halo;  // LDS slots per band
-  T *lds = reinterpret_cast<T *>(smem);
+  const int n0 = G.n0, n1 = G.n1, n2 = G.n2;
+  const int plane = n1 * n2;
   const int t = threadIdx.x;
-  const int start = blockIdx.x * ST_THREADS;
   const int b0 = blockIdx.y * NB;
   const int64_t bstride = static_cast<int64_t>(n0) * plane;
   const int x0 = blockIdx.z * G.xseg;
   const int x1 = min(n0, x0 + G.xseg);
 
-  // this lane's slot of the flattened plane, folded into the cell
-  const int f = start + t;
-  const int wy = floor_div(f, plane);
-  const int pw = f - wy * plane;
-  const bool active = f < plane;
-  const int y = pw / n2;
-  const int z = pw - y * n2;
-  z64 ph_self = G.phy[clamp3(wy) + 3];
-  // X rows of this band group (after the plane tiles in LDS)
+  // X rows of this band group and the atom positions, staged in LDS
   const T *Xs = static_cast<const T *>(ab.X) + static_cast<int64_t>(b0) * ab.np;
-  if (ADD && XLDS) {
-    T *xs = lds + NB * span;
-    stage_x<T, NB>(ab, b0, nb, xs);
-    Xs = xs;
-  }
-
-  // halo slots this lane fills for every plane: folded index and y phase
-  int hp[HALO_SLOTS], hl[HALO_SLOTS];
-  z64 hph[HALO_SLOTS];
-#pragma unroll
-  for (int s = 0; s < HALO_SLOTS; ++s) {
-    const int i = t + s * ST_THREADS;
-    hl[s] = -1;
-    hp[s] = 0;
-    hph[s] = zmake(1.0, 0.0);
-    if (i < 2 * halo) {
-      const int ff = (i < halo) ? (start - halo + i) : (start + ST_THREADS + (i - halo));
-      const int w = floor_div(ff, plane);
-      hp[s] = ff - w * plane;
-      hl[s] = (i < halo) ? i : i + ST_THREADS;
-      hph[s] = G.phy[clamp3(w) + 3];
+  const double *pos = ab.pos;
+  if (ADD) {
+    T *after = reinterpret_cast<T *>(smem);
+    if (XLDS) {
+      stage_x<T, NB>(ab, b0, nb, after);
+      Xs = after;
+      after += NB * ab.np;
     }
+    pos = stage_pos(ab, ab.natoms <= POS_LDS_MAX ? reinterpret_cast<double *>(after) : nullptr,
+                    ab.natoms);
+    __syncthreads();
   }
-  // z neighbours: LDS offsets and phases (fixed per lane)
-  int zo[6];
-  z64 zph[6];
+  const int f = blockIdx.x * ST_THREADS + t;
+  if (f >= plane) return;
+  const int y = f / n2, z = f - (f / n2) * n2;
+
+  // in-plane neighbour offsets (folded) and Bloch phases: y +-d, z +-d
+  int yo[6], zo[6];
+  z64 yph[6], zph[6];
 #pragma unroll
   for (int d = 1; d <= 3; ++d) {
-    const int wp = fold_count(z + d, n2), wm = fold_count(z - d, n2);
-    zo[2 * (d - 1)] = d - wp * n2;
-    zo[2 * (d - 1) + 1] = -d - wm * n2;
-    zph[2 * (d - 1)] = G.phz[clamp3(wp) + 3];
-    zph[2 * (d - 1) + 1] = G.phz[clamp3(wm) + 3];
+#pragma unroll
+    for (int sgn = 0; sgn < 2; ++sgn) {
+      const int dd = sgn ? -d : d;
+      const int wy = fold_count(y + dd, n1), wz = fold_count(z + dd, n2);
+      yo[2 * (d - 1) + sgn] = (y + dd - wy * n1) * n2 + z;
+      zo[2 * (d - 1) + sgn] = y * n2 + (z + dd - wz * n2);
+      yph[2 * (d - 1) + sgn] = G.phy[clamp3(wy) + 3];
+      zph[2 * (d - 1) + sgn] = G.phz[clamp3(wz) + 3];
+    }
   }
 
   auto plane_of = [&](int x, z64 &ph) -> int64_t {
@@ -170,12 +167,11 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil(const T *__restrict__ ps
   for (int d = 0; d < 6; ++d) {
     z64 ph;
     const int64_t off = plane_of(x0 + d - 3, ph);
-    const z64 pt = ph * ph_self;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       T val = St<T>::zero();
-      if (b0 + b < nb) val = psi[(b0 + b) * bstride + off + pw];
-      q[b][d] = BLOCH ? St<T>::phase(val, pt) : val;
+      if (b0 + b < nb) val = psi[(b0 + b) * bstride + off + f];
+      q[b][d] = BLOCH ? St<T>::phase(val, ph) : val;
     }
   }
 
@@ -183,57 +179,40 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil(const T *__restrict__ ps
     {
       z64 ph;
       const int64_t off = plane_of(x + 3, ph);
-      const z64 pt = ph * ph_self;
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         T val = St<T>::zero();
-        if (b0 + b < nb) val = psi[(b0 + b) * bstride + off + pw];
-        q[b][6] = BLOCH ? St<T>::phase(val, pt) : val;
+        if (b0 + b < nb) val = psi[(b0 + b) * bstride + off + f];
+        q[b][6] = BLOCH ? St<T>::phase(val, ph) : val;
       }
     }
-    __syncthreads();  // previous plane's LDS reads are done
-    {
-      z64 ph;
-      const int64_t off = plane_of(x, ph);
+    const int64_t xoff = static_cast<int64_t>(x) * plane;
+    const int64_t g = xoff + f;
+    T acc[NB];
 #pragma unroll
-      for (int s = 0; s < HALO_SLOTS; ++s) {
-        if (hl[s] < 0) continue;
-        const z64 pt = ph * hph[s];
+    for (int b = 0; b < NB; ++b) acc[b] = St<T>::zero();
+    if (ADD) addback_group<T, NI, NB>(ab, ab.pinfo[g], x, y, z, pos, Xs, ab.np, b0, nb, acc);
+    const double cv = G.c0 + v[g];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          T val = St<T>::zero();
-          if (b0 + b < nb) val = psi[(b0 + b) * bstride + off + hp[s]];
-          lds[b * span + hl[s]] = BLOCH ? St<T>::phase(val, pt) : val;
+    for (int b = 0; b < NB; ++b) {
+      if (b0 + b >= nb) continue;
+      const T *Pb = psi + (b0 + b) * bstride + xoff;
+      T r = acc[b] + St<T>::scale(cv, q[b][3]);
+#pragma unroll
+      for (int d = 1; d <= 3; ++d) {
+        const int ip = 2 * (d - 1), im = ip + 1;
+        T yp = Pb[yo[ip]], ym = Pb[yo[im]], zp = Pb[zo[ip]], zm = Pb[zo[im]];
+        if (BLOCH) {
+          yp = St<T>::phase(yp, yph[ip]);
+          ym = St<T>::phase(ym, yph[im]);
+          zp = St<T>::phase(zp, zph[ip]);
+          zm = St<T>::phase(zm, zph[im]);
         }
+        r = r + St<T>::scale(G.cx[d - 1], q[b][3 + d] + q[b][3 - d]);
+        r = r + St<T>::scale(G.cy[d - 1], yp + ym);
+        r = r + St<T>::scale(G.cz[d - 1], zp + zm);
       }
-    }
-#pragma unroll
-    for (int b = 0; b < NB; ++b) lds[b * span + halo + t] = q[b][3];
-    __syncthreads();
-    if (active) {
-      const int64_t g = static_cast<int64_t>(x) * plane + f;
-      T acc[NB];
-#pragma unroll
-      for (int b = 0; b < NB; ++b) acc[b] = St<T>::zero();
-      if (ADD) addback_group<T, NI, NB>(ab, g, x, y, z, Xs, ab.np, b0, nb, acc);
-      const double cv = G.c0 + v[g];
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const T *L = lds + b * span + halo + t;
-        T r = acc[b] + St<T>::scale(cv, q[b][3]);
-#pragma unroll
-        for (int d = 1; d <= 3; ++d) {
-          r = r + St<T>::scale(G.cx[d - 1], q[b][3 + d] + q[b][3 - d]);
-          r = r + St<T>::scale(G.cy[d - 1], L[d * n2] + L[-d * n2]);
-          T vp = L[zo[2 * (d - 1)]], vm = L[zo[2 * (d - 1) + 1]];
-          if (BLOCH) {
-            vp = St<T>::phase(vp, zph[2 * (d - 1)]);
-            vm = St<T>::phase(vm, zph[2 * (d - 1) + 1]);
-          }
-          r = r + St<T>::scale(G.cz[d - 1], vp + vm);
-        }
-        if (b0 + b < nb) out[(b0 + b) * bstride + g] = r;
-      }
+      out[(b0 + b) * bstride + g] = r;
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b)
@@ -249,11 +228,17 @@ __global__ __launch_bounds__(256) void k_apply_S(const T *__restrict__ psi, T *_
   extern __shared__ unsigned char smem[];
   const int b0 = blockIdx.y * NB;
   const T *Xs = static_cast<const T *>(ab.X) + static_cast<int64_t>(b0) * ab.np;
-  if (ADD && XLDS) {
-    T *xs = reinterpret_cast<T *>(smem);
-    stage_x<T, NB>(ab, b0, nb, xs);
+  const double *pos = ab.pos;
+  if (ADD) {
+    T *after = reinterpret_cast<T *>(smem);
+    if (XLDS) {
+      stage_x<T, NB>(ab, b0, nb, after);
+      Xs = after;
+      after += NB * ab.np;
+    }
+    pos = stage_pos(ab, ab.natoms <= POS_LDS_MAX ? reinterpret_cast<double *>(after) : nullptr,
+                    ab.natoms);
     __syncthreads();
-    Xs = xs;
   }
   const int64_t g = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (g >= ng) return;
@@ -266,7 +251,7 @@ __global__ __launch_bounds__(256) void k_apply_S(const T *__restrict__ psi, T *_
     const int ix = static_cast<int>(g / plane);
     const int r = static_cast<int>(g - static_cast<int64_t>(ix) * plane);
     const int iy = r / n2, iz = r - iy * n2;
-    addback_group<T, NI, NB>(ab, g, ix, iy, iz, Xs, ab.np, b0, nb, acc);
+    addback_group<T, NI, NB>(ab, ab.pinfo[g], ix, iy, iz, pos, Xs, ab.np, b0, nb, acc);
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b)
@@ -313,12 +298,13 @@ StencilGeom make_geom(const gpaw_sys *s, int nb) {  // nb: band groups
 
 AddArgs make_add(const gpaw_sys *s, const void *X) {
   AddArgs ab;
-  ab.estart = s->tab.estart;
+  ab.pinfo = s->tab.pinfo;
   ab.pm_code = s->tab.pm_code;
   ab.pos = s->tab.pos;
   ab.X = X;
   ab.pj = s->tab.proj;
   ab.np = s->np;
+  ab.natoms = s->natoms;
   return ab;
 }
 
@@ -331,12 +317,11 @@ int stencil_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *o
   const StencilGeom G = make_geom(s, ngroups);
   const AddArgs ab = make_add(s, X);
   const int plane = s->n[1] * s->n[2];
-  if (6 * s->n[2] > HALO_SLOTS * ST_THREADS)
-    return fail(GPAW_EINVAL, "n[2] > 170 is not supported by the stencil tile");
-  const size_t tile = static_cast<size_t>(NB) * (ST_THREADS + 6 * s->n[2]) * sizeof(T);
+  const size_t tile = 0;
   const size_t xbytes = static_cast<size_t>(NB) * s->np * sizeof(T);
-  const bool xlds = X && xbytes <= XLDS_MAX / 2;
-  const size_t lds = tile + (xlds ? xbytes : 0);
+  const bool xlds = X && xbytes <= XLDS_MAX;
+  const size_t pbytes = (X && s->natoms <= POS_LDS_MAX) ? 3 * sizeof(double) * s->natoms : 0;
+  const size_t lds = tile + (xlds ? xbytes : 0) + pbytes;
   dim3 grid((plane + ST_THREADS - 1) / ST_THREADS, ngroups, (s->n[0] + G.xseg - 1) / G.xseg);
   const T *ps = static_cast<const T *>(psi);
   T *po = static_cast<T *>(out);
@@ -356,14 +341,15 @@ int apply_S_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *o
   dim3 grid(static_cast<unsigned>((s->ng + 255) / 256), (nb + NB - 1) / NB);
   const size_t xbytes = static_cast<size_t>(NB) * s->np * sizeof(T);
   const bool xlds = X && xbytes <= XLDS_MAX;
+  const size_t pbytes = (X && s->natoms <= POS_LDS_MAX) ? 3 * sizeof(double) * s->natoms : 0;
   const T *ps = static_cast<const T *>(psi);
   T *po = static_cast<T *>(out);
   if (!X)
     k_apply_S<T, false, false, NI, NB><<<grid, 256, 0, st>>>(ps, po, s->ng, nb, ab);
   else if (xlds)
-    k_apply_S<T, true, true, NI, NB><<<grid, 256, xbytes, st>>>(ps, po, s->ng, nb, ab);
+    k_apply_S<T, true, true, NI, NB><<<grid, 256, xbytes + pbytes, st>>>(ps, po, s->ng, nb, ab);
   else
-    k_apply_S<T, true, false, NI, NB><<<grid, 256, 0, st>>>(ps, po, s->ng, nb, ab);
+    k_apply_S<T, true, false, NI, NB><<<grid, 256, pbytes, st>>>(ps, po, s->ng, nb, ab);
   return GPAW_OK;
 }
 

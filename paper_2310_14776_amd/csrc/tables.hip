@@ -65,6 +65,11 @@ int setup_proj(const gpaw_sys_desc *d, ProjDev &P) {
   P.ni = i;
   P.std13 = (d->nchan == 5 && P.l[0] == 0 && P.l[1] == 0 && P.l[2] == 1 && P.l[3] == 1 &&
              P.l[4] == 2) ? 1 : 0;
+  for (int c = 0; c < d->nchan; ++c) {
+    P.same_sigma[c] = -1;
+    if (c >= 2 && d->chan[c].sigma == d->chan[0].sigma) P.same_sigma[c] = 0;
+    else if (c >= 2 && d->chan[c].sigma == d->chan[1].sigma) P.same_sigma[c] = 1;
+  }
   for (int c = 0; c < 3; ++c) {
     P.n[c] = d->n[c];
     P.h[c] = d->h[c];
@@ -149,15 +154,21 @@ int build_tables(const gpaw_sys_desc *d, gpaw_sys *s) {
     if (x.w[1] != y.w[1]) return x.w[1] < y.w[1];
     return x.w[2] < y.w[2];
   });
-  std::vector<int32_t> estart(s->ng + 1, 0), pm_code(nent);
+  if (nent >= (int64_t(1) << 24)) return fail(GPAW_EINVAL, "more than 2^24 projector entries");
+  std::vector<int32_t> pm_code(nent);
+  std::vector<int2> pinfo(s->ng, make_int2(0, 0));
   int64_t ncov = 0;
   for (int64_t e = 0; e < nent; ++e) {
     const Entry &x = ent[e];
     pm_code[e] = pack_code(x.atom, x.w[0], x.w[1], x.w[2]);
-    estart[x.g + 1] += 1;
-    if (e == 0 || ent[e - 1].g != x.g) ++ncov;
+    if (e == 0 || ent[e - 1].g != x.g) {
+      ++ncov;
+      pinfo[x.g] = make_int2(pm_code[e], static_cast<int>(e));
+    }
+    const int cnt = (pinfo[x.g].y >> 24) + 1;
+    if (cnt > 255) return fail(GPAW_EINVAL, "more than 255 projector entries at one grid point");
+    pinfo[x.g].y = (cnt << 24) | (pinfo[x.g].y & 0xFFFFFF);
   }
-  for (int64_t g = 0; g < s->ng; ++g) estart[g + 1] += estart[g];
 
   std::vector<double> pos(d->pos, d->pos + 3 * d->natoms);
   s->tab.nent = nent;
@@ -165,7 +176,7 @@ int build_tables(const gpaw_sys_desc *d, gpaw_sys *s) {
   if ((rc = upload(&s->tab.a_start, a_start)) != GPAW_OK) return rc;
   if ((rc = upload(&s->tab.e_g, e_g)) != GPAW_OK) return rc;
   if ((rc = upload(&s->tab.e_xyz, e_xyz)) != GPAW_OK) return rc;
-  if ((rc = upload(&s->tab.estart, estart)) != GPAW_OK) return rc;
+  if ((rc = upload(&s->tab.pinfo, pinfo)) != GPAW_OK) return rc;
   if ((rc = upload(&s->tab.pm_code, pm_code)) != GPAW_OK) return rc;
   if ((rc = upload(&s->tab.pos, pos)) != GPAW_OK) return rc;
   if ((rc = upload(&s->tab.proj, std::vector<ProjDev>(1, s->proj))) != GPAW_OK) return rc;

@@ -36,6 +36,10 @@ CASES = {
     "bloch_selfoverlap": dict(n=(16, 16, 16), h=0.2, nb=5, natoms=3, rc=2.0, seed=43,
                               k=(0.3, 0.45, 0.05)),
     "bloch_nb96": dict(n=(24, 20, 28), h=0.2, nb=96, natoms=5, rc=2.0, seed=44, k=(0.25, 0.0, 0.5)),
+    # blocks above one workgroup's LDS: global-memory eigensolver path
+    "large_real_nb200": dict(n=(20, 18, 22), h=0.2, nb=200, natoms=3, rc=1.6, seed=45),
+    "large_bloch_nb130": dict(n=(18, 20, 16), h=0.2, nb=130, natoms=2, rc=1.6, seed=46,
+                              k=(0.25, 0.0, 0.5)),
 }
 
 _cache = {}
@@ -167,4 +171,31 @@ def test_error_paths():
     # a later good call on the same system still works
     eps, C = sysg.subspace_diag(to_dev(ref["H"]), to_dev(ref["S"]))
     assert np.abs(host(eps) - ref["eps"]).max() <= TOL * np.abs(ref["eps"]).max()
+    sysg.close()
+
+
+@pytest.mark.parametrize("n,cplx", [(320, False), (150, True), (129, False), (97, True)])
+def test_large_eigensolver_against_scipy(n, cplx):
+    """Direct generalised eigensolve above the LDS limit vs LAPACK (SciPy)."""
+    import scipy.linalg
+    say(f"[diag-large] n={n} complex={cplx}")
+    rng = np.random.default_rng(n)
+    def rnd(*shape):
+        x = rng.standard_normal(shape)
+        return x + 1j * rng.standard_normal(shape) if cplx else x
+    B = rnd(n, n)
+    S = B.conj().T @ B / n + np.eye(n)
+    H = rnd(n, n)
+    H = H + H.conj().T + 5.0 * np.diag(np.arange(n) / n)
+    # a system object only supplies the workspace; grid and atoms are irrelevant here
+    sysg = gfd.System(n=(4, 4, 4), h=0.2, k=(0.25, 0.0, 0.0) if cplx else (0, 0, 0),
+                      pos=np.zeros((0, 3)), channels=[], dH=np.zeros(0), dS=np.zeros(0),
+                      v=np.zeros(64), max_bands=n, complex_=cplx)
+    eps, C = sysg.subspace_diag(to_dev(H), to_dev(S))
+    torch.cuda.synchronize()
+    want = scipy.linalg.eigh(H, S, eigvals_only=True)
+    assert np.abs(host(eps) - want).max() <= TOL * np.abs(want).max()
+    Ch = host(C)
+    assert np.abs(Ch.conj().T @ S @ Ch - np.eye(n)).max() <= 1e-11
+    assert np.abs(Ch.conj().T @ H @ Ch - np.diag(want)).max() <= TOL * np.abs(want).max() * 10
     sysg.close()
