@@ -20,7 +20,7 @@ real PAW dataset).
 """
 from .stencil import WEIGHTS, laplacian, kinetic, symbol_1d
 from .projectors import (radial_norm, solid_harmonics, projector_values,
-                         projector_matrix)
+                         projector_matrix, projector_matrix_sparse)
 from .paw import project, addback, apply_H, apply_S, block_diag_atoms
 from .subspace import (subspace_matrices, hermiticity_defect, diagonalize,
                        rotate)
@@ -28,6 +28,7 @@ from .step import Operators, fd_step
 
 __all__ = ["WEIGHTS", "laplacian", "kinetic", "symbol_1d", "radial_norm",
            "solid_harmonics", "projector_values", "projector_matrix",
+           "projector_matrix_sparse",
            "project", "addback", "apply_H", "apply_S", "block_diag_atoms",
            "subspace_matrices", "hermiticity_defect", "diagonalize", "rotate",
            "Operators", "fd_step"]

@@ -50,7 +50,7 @@ def apply_H(psi, grid_shape, h, k, v, Q, dH, dV, P=None):
 def apply_S(psi, Q, dS, dV, P=None):
     if P is None:
         P = project(Q, psi, dV)
-    out = psi.astype(np.result_type(psi, Q, 1.0), copy=True)
+    out = psi.astype(np.result_type(psi.dtype, Q.dtype, 1.0), copy=True)
     if Q.shape[0]:
         out = out + addback(Q, P, dS)
     return out

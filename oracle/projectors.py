@@ -81,3 +81,53 @@ def projector_matrix(n, h, k, pos, channels):
                         vals = vals * np.exp(2j * np.pi * (k[0] * m0 + k[1] * m1 + k[2] * m2))
                     Q[a * ni:(a + 1) * ni, inside] += vals
     return Q
+
+
+def projector_matrix_sparse(n, h, k, pos, channels):
+    """Same matrix as projector_matrix, stored sparse (CSR): for each atom and
+    lattice image only the grid points in the box around the sphere are
+    visited, so that large grids fit in memory."""
+    from scipy.sparse import coo_matrix
+    n = tuple(n)
+    ni = sum(2 * l + 1 for (l, _, _) in channels)
+    rmax = max(rc for (_, _, rc) in channels)
+    cplx = any(kc != 0.0 for kc in k)
+    L = np.array([n[c] * h[c] for c in range(3)])
+    M = [int(ceil(rmax / L[c])) + 1 for c in range(3)]
+    rows, cols, vals = [], [], []
+    for a in range(pos.shape[0]):
+        for m0 in range(-M[0], M[0] + 1):
+            for m1 in range(-M[1], M[1] + 1):
+                for m2 in range(-M[2], M[2] + 1):
+                    m = (m0, m1, m2)
+                    centre = [pos[a, c] + m[c] * L[c] for c in range(3)]
+                    axes = []
+                    for c in range(3):
+                        lo = max(0, int(np.floor((centre[c] - rmax) / h[c])))
+                        hi = min(n[c] - 1, int(np.ceil((centre[c] + rmax) / h[c])))
+                        axes.append(np.arange(lo, hi + 1))
+                    if any(len(ax) == 0 for ax in axes):
+                        continue
+                    I, J, K = np.meshgrid(*axes, indexing="ij")
+                    dx = I.ravel() * h[0] - centre[0]
+                    dy = J.ravel() * h[1] - centre[1]
+                    dz = K.ravel() * h[2] - centre[2]
+                    inside = dx * dx + dy * dy + dz * dz < rmax * rmax
+                    if not inside.any():
+                        continue
+                    g = ((I.ravel() * n[1] + J.ravel()) * n[2] + K.ravel())[inside]
+                    v = projector_values(channels, dx[inside], dy[inside], dz[inside])
+                    if cplx:
+                        v = v * np.exp(2j * np.pi * (k[0] * m0 + k[1] * m1 + k[2] * m2))
+                    for i in range(ni):
+                        rows.append(np.full(g.size, a * ni + i))
+                        cols.append(g)
+                        vals.append(v[i])
+    npj = pos.shape[0] * ni
+    ng = n[0] * n[1] * n[2]
+    dtype = complex if cplx else float
+    if not rows:
+        return coo_matrix((npj, ng), dtype=dtype).tocsr()
+    Q = coo_matrix((np.concatenate(vals).astype(dtype),
+                    (np.concatenate(rows), np.concatenate(cols))), shape=(npj, ng))
+    return Q.tocsr()  # duplicates (a sphere meeting its own image) are summed

@@ -8,7 +8,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .projectors import projector_matrix
+from .projectors import projector_matrix, projector_matrix_sparse
 from .paw import project, apply_H, apply_S
 from .subspace import subspace_matrices, diagonalize, rotate
 
@@ -29,9 +29,13 @@ class Operators:
         return float(self.h[0] * self.h[1] * self.h[2])
 
     @classmethod
-    def from_system(cls, s):
-        Q = projector_matrix(s.n, s.h, s.k, s.pos, s.channels)
-        return cls(n=tuple(s.n), h=tuple(s.h), k=tuple(s.k), v=s.v, Q=Q, dH=s.dH, dS=s.dS)
+    def from_system(cls, s, sparse=False, k=None):
+        """sparse: store the projector matrix as CSR (large grids). k: the
+        Bloch vector when s carries no block to infer it from."""
+        build = projector_matrix_sparse if sparse else projector_matrix
+        kk = tuple(s.k) if k is None else tuple(k)
+        Q = build(s.n, s.h, kk, s.pos, s.channels)
+        return cls(n=tuple(s.n), h=tuple(s.h), k=kk, v=s.v, Q=Q, dH=s.dH, dS=s.dS)
 
     def project(self, psi):
         return project(self.Q, psi, self.dV)

@@ -91,8 +91,35 @@ def gaussian_potential(n, h, pos, depth=-2.0, width=1.0):
     return depth * v
 
 
+def smooth_bands(rng, nb, n, h, k, complex_psi, g0=2.0):
+    """Band-limited random blocks: plane-wave coefficients drawn from a
+    standard normal, damped by exp(-|G + k|^2 / (2 g0^2)) (g0 in 1/bohr), then
+    the Bloch factor exp(i k.r) applied so that psi(r + L_c e_c) equals
+    exp(2 pi i k_c) psi(r). Real blocks (k = 0) take the real part. The
+    amplitude is scaled to an RMS of 1/sqrt(3) per component, that of U[-1, 1].
+    The Rayleigh quotients of such bands lie in the 1-10 Ha range."""
+    L = [n[c] * h[c] for c in range(3)]
+    G = [2.0 * np.pi * np.fft.fftfreq(n[c], d=h[c]) + 2.0 * np.pi * k[c] / L[c] for c in range(3)]
+    G2 = G[0][:, None, None] ** 2 + G[1][None, :, None] ** 2 + G[2][None, None, :] ** 2
+    env = np.exp(-G2 / (2.0 * g0 * g0))
+    shape = (nb,) + tuple(n)
+    c = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    psi = np.fft.ifftn(c * env[None], axes=(1, 2, 3))
+    if complex_psi:
+        x = [np.arange(n[c]) * h[c] for c in range(3)]
+        kr = (2.0 * np.pi * k[0] / L[0]) * x[0][:, None, None] \
+            + (2.0 * np.pi * k[1] / L[1]) * x[1][None, :, None] \
+            + (2.0 * np.pi * k[2] / L[2]) * x[2][None, None, :]
+        psi = psi * np.exp(1j * kr)[None]
+        rms = np.sqrt(np.mean(np.abs(psi) ** 2) / 2.0)
+    else:
+        psi = psi.real
+        rms = np.sqrt(np.mean(psi ** 2))
+    return psi * (1.0 / (np.sqrt(3.0) * rms))
+
+
 def make_system(n, h, nb, natoms, rc, seed, k=(0.0, 0.0, 0.0), complex_psi=None,
-                ds_scale=0.1, depth=-2.0, width=1.0, name=""):
+                ds_scale=0.1, depth=-2.0, width=1.0, name="", bands="noise"):
     n = tuple(int(x) for x in n)
     h = (float(h),) * 3 if np.isscalar(h) else tuple(float(x) for x in h)
     k = tuple(float(x) for x in k)
@@ -108,14 +135,17 @@ def make_system(n, h, nb, natoms, rc, seed, k=(0.0, 0.0, 0.0), complex_psi=None,
     B = rng.uniform(-1.0, 1.0, (natoms, ni, ni))
     dS = ds_scale * 0.5 * (B + B.transpose(0, 2, 1))
     shape = (nb,) + n
-    if complex_psi:
+    if bands == "smooth":
+        psi = smooth_bands(rng, nb, n, h, k, complex_psi)
+    elif complex_psi:
         psi = rng.uniform(-1.0, 1.0, shape) + 1j * rng.uniform(-1.0, 1.0, shape)
     else:
         psi = rng.uniform(-1.0, 1.0, shape)
     v = gaussian_potential(n, h, pos, depth, width)
     return System(n=n, h=h, k=k, pos=pos, channels=channels, dH=dH, dS=dS, v=v,
                   psi=psi, name=name,
-                  meta=dict(seed=seed, rc=rc, ds_scale=ds_scale, depth=depth, width=width))
+                  meta=dict(seed=seed, rc=rc, ds_scale=ds_scale, depth=depth, width=width,
+                            bands=bands))
 
 
 # The five workloads: small real case, the single-GPU FP64 case, the precision

@@ -58,6 +58,29 @@ def test_projector_matrix_brute_force(k):
         assert Q.dtype == np.float64
 
 
+@pytest.mark.parametrize("k", [(0.0, 0.0, 0.0), (0.25, 0.0, 0.5), (0.1, 0.37, 0.8)])
+def test_sparse_projector_matrix_brute_force(k):
+    # the box-restricted sparse build against the element-by-element brute force,
+    # on a cell where spheres meet their own images and one where they do not
+    for n, h, rc in (((5, 6, 4), (0.3, 0.25, 0.35), 1.0), ((14, 12, 16), (0.2, 0.21, 0.19), 1.1)):
+        channels = synth.standard_channels(rc)
+        pos = np.array([[0.1, 0.7, 0.5], [1.2, 0.05, 1.3], [2.6, 2.4, 0.02]])
+        Q = oracle.projector_matrix_sparse(n, h, k, pos, channels).toarray()
+        B = brute.projector_matrix(n, h, k, pos, channels)
+        assert np.abs(Q - B).max() < 1e-12 * np.abs(B).max()
+
+
+def test_sparse_operators_match_dense():
+    s = synth.make_system(n=(12, 10, 14), h=0.22, nb=3, natoms=3, rc=1.5, seed=9,
+                          k=(0.25, 0.1, 0.5))
+    d = oracle.Operators.from_system(s)
+    sp = oracle.Operators.from_system(s, sparse=True)
+    psi = s.psi.reshape(s.nb, -1)
+    for f in ("project", "apply_H", "apply_S"):
+        a, b = getattr(d, f)(psi), getattr(sp, f)(psi)
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max(), f
+
+
 def _system(k=(0.0, 0.0, 0.0), seed=7):
     return synth.make_system(n=(12, 10, 14), h=0.22, nb=4, natoms=3, rc=1.5, seed=seed, k=k)
 
