@@ -32,8 +32,9 @@
  * Layouts (row-major, C order):
  *   psi, Hpsi, Spsi, psi_out : [nb][n0][n1][n2]  of the system dtype
  *   P, P_out                 : [nb][Np]          of the system dtype
- *   H_nn, S_nn, C_nn         : [nb][nb]          double (real systems) or
+ *   H_nn, S_nn, C_nn         : [nb][nb]          double (GPAW_F64, GPAW_F32) or
  *                                                interleaved complex double
+ *                                                (GPAW_C128, GPAW_C64)
  *   eps                      : [nb]              double
  * Complex data are interleaved (re, im).
  * Memory: pointers named *_dev, and every array argument of the compute calls,
@@ -78,7 +79,12 @@ enum gpaw_status {
   GPAW_ENOCONV = -8       /* eigenvector orthogonalisation did not settle */
 };
 
-typedef enum { GPAW_F64 = 0, GPAW_C128 = 1 } gpaw_dtype;
+/* Storage/arithmetic type of the wave functions. GPAW_F32 and GPAW_C64 are
+ * the precision form: single-precision stencil and projector add-back,
+ * projections accumulated in double, subspace matrices and rotations as
+ * split-BF16 products on the matrix cores (FP32 accumulators promoted to
+ * FP64), and the Cholesky and eigensolve in FP64. */
+typedef enum { GPAW_F64 = 0, GPAW_C128 = 1, GPAW_F32 = 2, GPAW_C64 = 3 } gpaw_dtype;
 
 typedef struct {
   int32_t l;       /* 0, 1 or 2 */
@@ -90,7 +96,7 @@ typedef struct {
   int32_t n[3];             /* grid points per axis, each >= 1 */
   double h[3];              /* grid spacing per axis (bohr), > 0 */
   double k[3];              /* Bloch vector, reduced units */
-  int32_t dtype;            /* gpaw_dtype of psi; GPAW_F64 needs k = 0 */
+  int32_t dtype;            /* gpaw_dtype of psi; GPAW_F64 and GPAW_F32 need k = 0 */
   int32_t natoms;           /* >= 0 */
   const double *pos;        /* host [natoms][3] cartesian positions (bohr) */
   int32_t nchan;            /* >= 1 when natoms > 0 */
@@ -148,7 +154,9 @@ GPAW_API int gpaw_subspace_matrices(gpaw_sys *sys, const void *psi, const void *
  * device: symmetrise X <- (X + X^H)/2, S = L L^H, eigen-decompose
  * L^-1 H L^-H, C = L^-H U. Output: eps ascending [nb], C_nn [nb][nb] with
  * column j the j-th eigenvector (C^H S C = I, C^H H C = diag eps).
- * H_nn and S_nn are not modified. nb <= 128.
+ * H_nn and S_nn are not modified. nb <= 1024 (blocks up to 128 real / 96
+ * complex are factorised inside one workgroup's LDS, larger ones through
+ * global memory).
  * info: device int32 or NULL. Non-NULL: the call is asynchronous and the
  * device writes 0 on success, j > 0 when the leading j x j minor of S_nm is
  * not positive definite, or -1 when orthogonalisation did not settle.
@@ -161,6 +169,71 @@ GPAW_API int gpaw_subspace_diag(gpaw_sys *sys, const void *H_nn, const void *S_n
  * the rotated block). psi_out must not overlap psi, nor P_out P. */
 GPAW_API int gpaw_rotate(gpaw_sys *sys, const void *psi, const void *C_nn, int32_t nb,
                 void *psi_out, const void *P, void *P_out, void *stream);
+
+/* Orthonormality correction of a rotated block: S' = dV psi^H Spsi (Spsi =
+ * S~ psi, e.g. the rotated S~psi, since S~ is linear), S' = L L^H in FP64 on
+ * the device, psi_out = psi L^-H in band space (psi_out_n =
+ * sum_m (L^-H)_mn psi_m), so that psi_out^H S~ psi_out = I; P_out likewise
+ * from P when both are non-NULL. Cholesky-based re-orthonormalisation (the
+ * paper lists Cholesky decomposition among the subspace dense linear algebra,
+ * Sec. "Parallelization"). info: as for gpaw_subspace_diag (j > 0 when the
+ * leading j x j minor of S' is not positive definite). nb <= 1024. */
+GPAW_API int gpaw_orthonormalize(gpaw_sys *sys, const void *psi, const void *Spsi, int32_t nb,
+                                 void *psi_out, const void *P, void *P_out, int32_t *info,
+                                 void *stream);
+
+/* ------------------------------------------------------------ batched form
+ * Many independent systems (uneven grids and band counts, real and Bloch)
+ * stepped by one HIP graph launch: for every system the chain
+ * gpaw_project -> apply H~ -> apply S~ -> gpaw_subspace_matrices ->
+ * gpaw_subspace_diag -> gpaw_rotate, with the same kernels and results as
+ * those calls. Independent systems or k-points are the method's natural
+ * unit of parallel work (Sec. "Parallelization"); the chains are recorded on
+ * up to 16 concurrent graph branches so that small systems overlap. */
+typedef struct gpaw_batch gpaw_batch;
+
+typedef struct {
+  const void *psi;   /* device [nb][Ng] block of this system (system dtype) */
+  int32_t nb;        /* bands, 1 <= nb <= the system's max_bands */
+  void *psi_out;     /* device [nb][Ng] rotated block (must not overlap psi) */
+  double *eps;       /* device [nb] Ritz values, ascending */
+  void *P_out;       /* device [nb][Np] rotated projections, or NULL */
+  void *H_nn;        /* device [nb][nb] subspace H, or NULL (batch workspace) */
+  void *S_nn;        /* device [nb][nb] subspace S, or NULL (batch workspace) */
+  void *C_nn;        /* device [nb][nb] eigenvectors, or NULL (batch workspace) */
+} gpaw_batch_io;
+
+/* Batch over nsys existing systems (host array of handles, all on the
+ * current device, each at most once). The batch allocates per-system
+ * intermediates (P, H~psi, S~psi, H, S, C at max_bands) and its own streams;
+ * it does not own the systems, which must outlive it. */
+GPAW_API int gpaw_batch_create(gpaw_sys *const *systems, int32_t nsys, gpaw_batch **out);
+
+/* Waits for the device, then frees the batch (not its systems). NULL is a no-op. */
+GPAW_API void gpaw_batch_destroy(gpaw_batch *b);
+
+/* One step of every system. io: host array [nsys]; info: device int32
+ * [nsys], written per system as gpaw_subspace_diag's info. The first call,
+ * and any call whose io contents or info pointer differ from the previous
+ * call's, synchronises `stream` and records the graph (the graph holds the
+ * buffer addresses); otherwise the call only enqueues one graph launch on
+ * `stream`. Calls of one batch must not overlap (they share its workspace
+ * and the systems' workspaces). */
+GPAW_API int gpaw_batch_step(gpaw_batch *b, const gpaw_batch_io *io, int32_t *info, void *stream);
+
+/* Autotuner (synchronous, runs on the batch's own stream and overwrites the
+ * io outputs): times the launch-shape choices of every system (bands per
+ * lane and x segments of the stencil, split-K width of the subspace product,
+ * row tiles of the rotation, bands per projection workgroup) and then the
+ * number of graph branches (1..16), keeps the fastest of each and records
+ * the graph for io. Results change only in the order of floating-point sums. */
+GPAW_API int gpaw_batch_tune(gpaw_batch *b, const gpaw_batch_io *io, int32_t *info);
+
+/* Chosen shapes: out[0] = graph branches, then per system 5 values
+ * (stencil bands per lane, stencil x segments, subspace workgroup target,
+ * rotation row tiles, projection bands per workgroup; 0 = built-in choice).
+ * out holds 1 + 5 nsys int32 (host). */
+GPAW_API int gpaw_batch_tuning(const gpaw_batch *b, int32_t *out);
 
 /* Message for the calling host thread's last non-zero return ("" if none). */
 GPAW_API const char *gpaw_last_error(void);

@@ -1,9 +1,12 @@
 """MI355X (gfx950) library for one block step of the real-space FD-PAW
 eigensolver: H~psi, S~psi, projector overlaps, subspace matrices, FP64
 generalised eigensolve and rotation, behind the C ABI in include/gpaw_fd.h.
+A precision form (single-precision storage, split-BF16 matrix-core
+products) and a batched form (many systems in one graph launch) use the same
+calls.
 """
-from ._binding import (System, GpawError, load, library_path, ENTRY_POINTS,
-                       GPAW_F64, GPAW_C128)
+from ._binding import (System, Batch, GpawError, load, library_path, ENTRY_POINTS,
+                       GPAW_F64, GPAW_C128, GPAW_F32, GPAW_C64)
 
-__all__ = ["System", "GpawError", "load", "library_path", "ENTRY_POINTS",
-           "GPAW_F64", "GPAW_C128"]
+__all__ = ["System", "Batch", "GpawError", "load", "library_path", "ENTRY_POINTS",
+           "GPAW_F64", "GPAW_C128", "GPAW_F32", "GPAW_C64"]

@@ -13,7 +13,7 @@ import torch
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libgpawfd.so")
 
-GPAW_F64, GPAW_C128 = 0, 1
+GPAW_F64, GPAW_C128, GPAW_F32, GPAW_C64 = 0, 1, 2, 3
 
 STATUS = {0: "GPAW_OK", -1: "GPAW_EINVAL", -2: "GPAW_EDTYPE", -3: "GPAW_ESHAPE",
           -4: "GPAW_EALIAS", -5: "GPAW_EHIP", -6: "GPAW_ENOTPD", -7: "GPAW_ENOMEM",
@@ -44,7 +44,16 @@ _lib = None
 
 ENTRY_POINTS = ["gpaw_sys_create", "gpaw_sys_destroy", "gpaw_sys_info", "gpaw_project",
                 "gpaw_fd_apply_H", "gpaw_fd_apply_S", "gpaw_subspace_matrices",
-                "gpaw_subspace_diag", "gpaw_rotate", "gpaw_last_error", "gpaw_version"]
+                "gpaw_subspace_diag", "gpaw_rotate", "gpaw_orthonormalize",
+                "gpaw_batch_create", "gpaw_batch_destroy", "gpaw_batch_step",
+                "gpaw_batch_tune", "gpaw_batch_tuning",
+                "gpaw_last_error", "gpaw_version"]
+
+
+class BatchIO(ctypes.Structure):
+    _fields_ = [("psi", ctypes.c_void_p), ("nb", ctypes.c_int32), ("psi_out", ctypes.c_void_p),
+                ("eps", ctypes.c_void_p), ("P_out", ctypes.c_void_p), ("H_nn", ctypes.c_void_p),
+                ("S_nn", ctypes.c_void_p), ("C_nn", ctypes.c_void_p)]
 
 
 def library_path():
@@ -70,11 +79,18 @@ def load():
     lib.gpaw_subspace_matrices.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
     lib.gpaw_subspace_diag.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
     lib.gpaw_rotate.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+    lib.gpaw_orthonormalize.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
+    lib.gpaw_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
+    lib.gpaw_batch_destroy.argtypes = [vp]
+    lib.gpaw_batch_destroy.restype = None
+    lib.gpaw_batch_step.argtypes = [vp, ctypes.POINTER(BatchIO), vp, vp]
+    lib.gpaw_batch_tune.argtypes = [vp, ctypes.POINTER(BatchIO), vp]
+    lib.gpaw_batch_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.gpaw_last_error.restype = ctypes.c_char_p
     lib.gpaw_last_error.argtypes = []
     lib.gpaw_version.argtypes = []
     for name in ENTRY_POINTS:
-        if name not in ("gpaw_sys_destroy", "gpaw_last_error"):
+        if name not in ("gpaw_sys_destroy", "gpaw_batch_destroy", "gpaw_last_error"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -105,12 +121,24 @@ def _host(a, dtype=np.float64):
 class System:
     """One FD-PAW system on the current GPU (owns the library's gpaw_sys)."""
 
-    def __init__(self, n, h, k, pos, channels, dH, dS, v, max_bands, complex_=None):
+    def __init__(self, n, h, k, pos, channels, dH, dS, v, max_bands, complex_=None,
+                 precision="double"):
         lib = load()
         k = tuple(float(x) for x in k)
         if complex_ is None:
             complex_ = any(x != 0.0 for x in k)
-        self.dtype = torch.complex128 if complex_ else torch.float64
+        if precision not in ("double", "single"):
+            raise ValueError("precision must be 'double' or 'single'")
+        single = precision == "single"
+        self.precision = precision
+        if complex_:
+            self.dtype = torch.complex64 if single else torch.complex128
+            self.mat_dtype = torch.complex128
+            code = GPAW_C64 if single else GPAW_C128
+        else:
+            self.dtype = torch.float32 if single else torch.float64
+            self.mat_dtype = torch.float64
+            code = GPAW_F32 if single else GPAW_F64
         self.n = tuple(int(x) for x in n)
         self.ng = int(np.prod(self.n))
         pos = _host(pos).reshape(-1, 3)
@@ -122,7 +150,7 @@ class System:
         d.n[:] = self.n
         d.h[:] = [float(x) for x in (h if np.ndim(h) else (h, h, h))]
         d.k[:] = k
-        d.dtype = GPAW_C128 if complex_ else GPAW_F64
+        d.dtype = code
         d.natoms = pos.shape[0]
         dp = ctypes.POINTER(ctypes.c_double)
         d.pos = self._keep[0].ctypes.data_as(dp)
@@ -144,9 +172,9 @@ class System:
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     @classmethod
-    def from_synth(cls, s, max_bands=None):
+    def from_synth(cls, s, max_bands=None, precision="double"):
         return cls(s.n, s.h, s.k, s.pos, s.channels, s.dH, s.dS, s.v,
-                   max_bands or s.nb, complex_=s.is_complex)
+                   max_bands or s.nb, complex_=s.is_complex, precision=precision)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -191,9 +219,9 @@ class System:
 
     def subspace_matrices(self, psi, Hpsi, Spsi=None, H=None, S=None, stream=None):
         nb = self._nb(psi)
-        H = self._new(nb, nb) if H is None else H
+        H = self._new(nb, nb, dtype=self.mat_dtype) if H is None else H
         if Spsi is not None and S is None:
-            S = self._new(nb, nb)
+            S = self._new(nb, nb, dtype=self.mat_dtype)
         _check(load().gpaw_subspace_matrices(self._h, _ptr(psi), _ptr(Hpsi), _ptr(Spsi), nb,
                                              _ptr(H), _ptr(S), _stream(stream)))
         return H, S
@@ -201,7 +229,7 @@ class System:
     def subspace_diag(self, H, S, eps=None, C=None, info=None, stream=None):
         nb = H.shape[0]
         eps = self._new(nb, dtype=torch.float64) if eps is None else eps
-        C = self._new(nb, nb) if C is None else C
+        C = self._new(nb, nb, dtype=self.mat_dtype) if C is None else C
         _check(load().gpaw_subspace_diag(self._h, _ptr(H), _ptr(S), nb, _ptr(eps), _ptr(C),
                                          _ptr(info), _stream(stream)))
         return eps, C
@@ -215,6 +243,15 @@ class System:
                                   _ptr(P_out), _stream(stream)))
         return out, P_out
 
+    def orthonormalize(self, psi, Spsi, out=None, P=None, P_out=None, info=None, stream=None):
+        nb = self._nb(psi)
+        out = torch.empty_like(psi) if out is None else out
+        if P is not None and P_out is None:
+            P_out = torch.empty_like(P)
+        _check(load().gpaw_orthonormalize(self._h, _ptr(psi), _ptr(Spsi), nb, _ptr(out), _ptr(P),
+                                          _ptr(P_out), _ptr(info), _stream(stream)))
+        return out, P_out
+
     def step(self, psi, stream=None):
         """One block step: P, H~psi, S~psi, H_nm, S_nm, eigensolve, rotation."""
         P = self.project(psi, stream=stream)
@@ -225,3 +262,56 @@ class System:
         psi_rot, P_rot = self.rotate(psi, C, P=P, stream=stream)
         return dict(P=P, Hpsi=Hpsi, Spsi=Spsi, H=H, S=S, eps=eps, C=C,
                     psi_rot=psi_rot, P_rot=P_rot)
+
+
+class Batch:
+    """Many independent systems stepped by one graph launch (owns the
+    library's gpaw_batch, not the systems)."""
+
+    def __init__(self, systems):
+        lib = load()
+        self.systems = list(systems)
+        arr = (ctypes.c_void_p * len(self.systems))(*[s._h.value for s in self.systems])
+        handle = ctypes.c_void_p()
+        _check(lib.gpaw_batch_create(arr, len(self.systems), ctypes.byref(handle)))
+        self._h = handle
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gpaw_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def io(self, psis, psi_outs, eps, P_outs=None, Hs=None, Ss=None, Cs=None):
+        """Host array of per-system buffers (lists of tensors; None entries allowed
+        for the optional ones)."""
+        n = len(self.systems)
+        arr = (BatchIO * n)()
+        for i, s in enumerate(self.systems):
+            arr[i].psi = _ptr(psis[i])
+            arr[i].nb = s._nb(psis[i])
+            arr[i].psi_out = _ptr(psi_outs[i])
+            arr[i].eps = _ptr(eps[i])
+            arr[i].P_out = _ptr(P_outs[i]) if P_outs else None
+            arr[i].H_nn = _ptr(Hs[i]) if Hs else None
+            arr[i].S_nn = _ptr(Ss[i]) if Ss else None
+            arr[i].C_nn = _ptr(Cs[i]) if Cs else None
+        return arr
+
+    def step(self, io, info, stream=None):
+        _check(load().gpaw_batch_step(self._h, io, _ptr(info), _stream(stream)))
+
+    def tune(self, io, info):
+        _check(load().gpaw_batch_tune(self._h, io, _ptr(info)))
+
+    def tuning(self):
+        n = len(self.systems)
+        out = (ctypes.c_int32 * (1 + 5 * n))()
+        _check(load().gpaw_batch_tuning(self._h, out))
+        keys = ("stencil_nb", "stencil_xseg", "subspace_wgs", "rotate_rb", "project_nbg")
+        return int(out[0]), [dict(zip(keys, out[1 + 5 * i: 6 + 5 * i])) for i in range(n)]

@@ -24,7 +24,21 @@ int hip_fail(hipError_t err, const char *what) {
   return err == hipErrorOutOfMemory ? GPAW_ENOMEM : GPAW_EHIP;
 }
 
-size_t elem_size(int32_t dtype) { return dtype == GPAW_C128 ? 16 : 8; }
+size_t elem_size(int32_t dtype) {
+  switch (dtype) {
+    case GPAW_C128: return 16;
+    case GPAW_F32: return 4;
+    case GPAW_C64: return 8;
+    default: return 8;
+  }
+}
+
+// element size of the subspace matrices (double or complex double)
+size_t mat_elem_size(int32_t dtype) {
+  return (dtype == GPAW_C128 || dtype == GPAW_C64) ? 16 : 8;
+}
+
+bool is_complex(int32_t dtype) { return dtype == GPAW_C128 || dtype == GPAW_C64; }
 
 namespace {
 
@@ -58,7 +72,8 @@ void free_sys(gpaw_sys *s) {
   if (!s) return;
   void *bufs[] = {s->tab.a_start, s->tab.e_g, s->tab.e_xyz, s->tab.pinfo, s->tab.pm_code,
                   s->tab.pos,     s->dH,      s->dS,        s->v,          s->ws.P,
-                  s->ws.X,        s->ws.part, s->ws.eig,    s->ws.info,    s->tab.proj};
+                  s->ws.X,        s->ws.part, s->ws.eig,    s->ws.info,    s->tab.proj,
+                  s->ws.split,    s->ws.mat};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   delete s;
@@ -95,9 +110,9 @@ int gpaw_sys_create(const gpaw_sys_desc *d, gpaw_sys **out) {
     ng *= d->n[c];
   }
   if (ng > (int64_t(1) << 31) - 1) return fail(GPAW_EINVAL, "grid has more than 2^31-1 points");
-  if (d->dtype != GPAW_F64 && d->dtype != GPAW_C128) return fail(GPAW_EDTYPE, "unknown dtype");
-  if (d->dtype == GPAW_F64 && (d->k[0] != 0.0 || d->k[1] != 0.0 || d->k[2] != 0.0))
-    return fail(GPAW_EDTYPE, "a real (GPAW_F64) system needs k = 0; use GPAW_C128");
+  if (d->dtype < GPAW_F64 || d->dtype > GPAW_C64) return fail(GPAW_EDTYPE, "unknown dtype");
+  if (!is_complex(d->dtype) && (d->k[0] != 0.0 || d->k[1] != 0.0 || d->k[2] != 0.0))
+    return fail(GPAW_EDTYPE, "a real system needs k = 0; use a complex dtype");
   if (d->natoms < 0) return fail(GPAW_EINVAL, "natoms must be >= 0");
   if (!d->v) return fail(GPAW_EINVAL, "v must not be NULL");
   if (d->max_bands < 1) return fail(GPAW_EINVAL, "max_bands must be >= 1");
@@ -160,9 +175,17 @@ int gpaw_sys_create(const gpaw_sys_desc *d, gpaw_sys **out) {
     }
     s->ws.part_elems = subspace_part_elems(s, s->max_bands);
     if ((rc = dev_alloc(&s->ws.part, s->ws.part_elems)) != GPAW_OK) break;
-    s->ws.eig_elems = eig_ws_elems(s->max_bands, s->dtype == GPAW_C128);
+    s->ws.eig_elems = eig_ws_elems(s->max_bands, is_complex(s->dtype));
     if ((rc = dev_alloc(&s->ws.eig, s->ws.eig_elems)) != GPAW_OK) break;
     if ((rc = dev_alloc(&s->ws.info, 1)) != GPAW_OK) break;
+    if ((rc = dev_alloc(reinterpret_cast<char **>(&s->ws.mat),
+                        2 * static_cast<size_t>(s->max_bands) * s->max_bands *
+                            mat_elem_size(s->dtype))) != GPAW_OK)
+      break;
+    if (s->dtype == GPAW_F32 || s->dtype == GPAW_C64)
+      if ((rc = dev_alloc(reinterpret_cast<char **>(&s->ws.split),
+                          split_c_bytes(s->max_bands, s->dtype == GPAW_C64))) != GPAW_OK)
+        break;
   } while (false);
   if (rc != GPAW_OK) {
     free_sys(s);
@@ -253,7 +276,7 @@ int gpaw_subspace_matrices(gpaw_sys *s, const void *psi, const void *Hpsi, const
   if ((rc = check_nb(s, nb)) != GPAW_OK) return rc;
   if (!psi || !Hpsi || !H) return fail(GPAW_EINVAL, "psi, Hpsi and H_nn must not be NULL");
   if (Spsi && !S) return fail(GPAW_EINVAL, "S_nn must not be NULL when Spsi is given");
-  const size_t mbytes = static_cast<size_t>(nb) * nb * elem_size(s->dtype);
+  const size_t mbytes = static_cast<size_t>(nb) * nb * mat_elem_size(s->dtype);
   if (Spsi && overlaps(H, mbytes, S, mbytes)) return fail(GPAW_EALIAS, "H_nn overlaps S_nn");
   if ((rc = launch_subspace(s, psi, Hpsi, Spsi, nb, H, Spsi ? S : nullptr,
                             static_cast<hipStream_t>(stream))) != GPAW_OK)
@@ -268,7 +291,7 @@ int gpaw_subspace_diag(gpaw_sys *s, const void *H, const void *S, int32_t nb, do
   if ((rc = check_nb(s, nb)) != GPAW_OK) return rc;
   if (nb > 1024) return fail(GPAW_ESHAPE, "gpaw_subspace_diag supports nb <= 1024");
   if (!H || !S || !eps || !C) return fail(GPAW_EINVAL, "H_nn, S_nn, eps and C_nn must not be NULL");
-  const size_t mbytes = static_cast<size_t>(nb) * nb * elem_size(s->dtype);
+  const size_t mbytes = static_cast<size_t>(nb) * nb * mat_elem_size(s->dtype);
   if (overlaps(C, mbytes, H, mbytes) || overlaps(C, mbytes, S, mbytes) ||
       overlaps(eps, nb * 8, C, mbytes) || overlaps(eps, nb * 8, H, mbytes) ||
       overlaps(eps, nb * 8, S, mbytes))
@@ -288,6 +311,43 @@ int gpaw_subspace_diag(gpaw_sys *s, const void *H, const void *S, int32_t nb, do
   return GPAW_OK;
 }
 
+int gpaw_orthonormalize(gpaw_sys *s, const void *psi, const void *Spsi, int32_t nb,
+                        void *psi_out, const void *P, void *P_out, int32_t *info, void *stream) {
+  int rc;
+  if ((rc = check_sys(s)) != GPAW_OK) return rc;
+  if ((rc = check_nb(s, nb)) != GPAW_OK) return rc;
+  if (nb > 1024) return fail(GPAW_ESHAPE, "gpaw_orthonormalize supports nb <= 1024");
+  if (!psi || !Spsi || !psi_out) return fail(GPAW_EINVAL, "psi, Spsi and psi_out must not be NULL");
+  if ((P == nullptr) != (P_out == nullptr))
+    return fail(GPAW_EINVAL, "P and P_out must be both NULL or both set");
+  const size_t es = elem_size(s->dtype);
+  const size_t bytes = static_cast<size_t>(nb) * s->ng * es;
+  const size_t pbytes = static_cast<size_t>(nb) * s->np * es;
+  if (overlaps(psi_out, bytes, psi, bytes) || overlaps(psi_out, bytes, Spsi, bytes))
+    return fail(GPAW_EALIAS, "psi_out overlaps psi or Spsi");
+  if (P && s->np > 0 && (overlaps(P_out, pbytes, P, pbytes) || overlaps(P_out, pbytes, psi_out, bytes)))
+    return fail(GPAW_EALIAS, "P_out overlaps P or psi_out");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t mbytes = static_cast<size_t>(nb) * nb * mat_elem_size(s->dtype);
+  char *Sm = static_cast<char *>(s->ws.mat);
+  char *Cm = Sm + mbytes;
+  int32_t *dinfo = info ? info : s->ws.info;
+  if ((rc = launch_subspace(s, psi, Spsi, nullptr, nb, Sm, nullptr, st)) != GPAW_OK) return rc;
+  if ((rc = launch_chol_inv(s, Sm, nb, Cm, dinfo, st)) != GPAW_OK) return rc;
+  if ((rc = launch_rotate(s, Cm, psi, nb, s->ng, psi_out, st)) != GPAW_OK) return rc;
+  if (P && s->np > 0)
+    if ((rc = launch_rotate(s, Cm, P, nb, s->np, P_out, st)) != GPAW_OK) return rc;
+  if ((rc = after_launch("gpaw_orthonormalize")) != GPAW_OK) return rc;
+  if (info) return GPAW_OK;
+  int32_t h_info = 0;
+  GFD_HIP(hipMemcpyAsync(&h_info, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  GFD_HIP(hipStreamSynchronize(st));
+  if (h_info > 0)
+    return fail(GPAW_ENOTPD, "overlap of the block is not positive definite (leading minor " +
+                                 std::to_string(h_info) + ")");
+  return GPAW_OK;
+}
+
 int gpaw_rotate(gpaw_sys *s, const void *psi, const void *C, int32_t nb, void *psi_out,
                 const void *P, void *P_out, void *stream) {
   int rc;
@@ -300,7 +360,7 @@ int gpaw_rotate(gpaw_sys *s, const void *psi, const void *C, int32_t nb, void *p
   const size_t bytes = static_cast<size_t>(nb) * s->ng * es;
   const size_t pbytes = static_cast<size_t>(nb) * s->np * es;
   if (overlaps(psi_out, bytes, psi, bytes)) return fail(GPAW_EALIAS, "psi_out overlaps psi");
-  if (overlaps(psi_out, bytes, C, static_cast<size_t>(nb) * nb * es))
+  if (overlaps(psi_out, bytes, C, static_cast<size_t>(nb) * nb * mat_elem_size(s->dtype)))
     return fail(GPAW_EALIAS, "psi_out overlaps C_nn");
   if (P && s->np > 0 && (overlaps(P_out, pbytes, P, pbytes) || overlaps(P_out, pbytes, psi_out, bytes)))
     return fail(GPAW_EALIAS, "P_out overlaps P or psi_out");

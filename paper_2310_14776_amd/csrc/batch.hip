@@ -1,0 +1,422 @@
+// Batched form: one block eigensolver step for many independent systems
+// (uneven grids and band counts, real and Bloch) issued as one graph launch.
+//
+// Independent systems or k-points are the natural unit of parallel work in
+// the method (Sec. "Parallelization"). Each system's step is the chain
+// project -> Delta H P -> stencil + add-back -> Delta S P -> S~ -> subspace
+// matrices -> Cholesky + eigensolve -> rotation; the chains share nothing, so
+// they are dealt onto several capture streams (largest first, to the least
+// loaded stream) and recorded once into a HIP graph whose branches run
+// concurrently. Small systems then overlap their latency-bound eigensolver
+// and short kernels instead of running back to back. The autotuner times the
+// launch-shape choices of every system and the number of branches.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+struct gpaw_batch {
+  struct Buf {
+    void *P = nullptr, *Hpsi = nullptr, *Spsi = nullptr, *H = nullptr, *S = nullptr,
+         *C = nullptr;
+  };
+  int device = 0;
+  std::vector<gpaw_sys *> sys;
+  std::vector<Buf> buf;
+  int nbranch = 0;  // 0: default
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> joins;
+  hipStream_t cap = nullptr;
+  hipEvent_t fork = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<gpaw_batch_io> key;  // io the graph was recorded with
+  int32_t *key_info = nullptr;
+  int key_branches = 0;
+};
+
+namespace gfd {
+namespace {
+
+constexpr int kMaxBranches = 16;
+constexpr int kDefaultBranches = 8;
+
+int check_batch(const gpaw_batch *b) {
+  if (!b) return fail(GPAW_EINVAL, "batch is NULL");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != b->device)
+    return fail(GPAW_EINVAL, "current HIP device differs from the batch's device");
+  return GPAW_OK;
+}
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+  if (!a || !b) return false;
+  const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+int check_io(const gpaw_batch *b, const gpaw_batch_io *io, const int32_t *info) {
+  if (!io) return fail(GPAW_EINVAL, "io must not be NULL");
+  if (!info) return fail(GPAW_EINVAL, "info must not be NULL");
+  for (size_t i = 0; i < b->sys.size(); ++i) {
+    const gpaw_sys *s = b->sys[i];
+    const gpaw_batch_io &x = io[i];
+    const std::string tag = "system " + std::to_string(i) + ": ";
+    if (x.nb < 1 || x.nb > s->max_bands)
+      return fail(GPAW_ESHAPE, tag + "nb outside [1, max_bands]");
+    if (!x.psi || !x.psi_out || !x.eps)
+      return fail(GPAW_EINVAL, tag + "psi, psi_out and eps must not be NULL");
+    const size_t es = elem_size(s->dtype);
+    const size_t bytes = static_cast<size_t>(x.nb) * s->ng * es;
+    const size_t mbytes = static_cast<size_t>(x.nb) * x.nb * mat_elem_size(s->dtype);
+    const size_t pbytes = static_cast<size_t>(x.nb) * s->np * es;
+    if (overlaps(x.psi_out, bytes, x.psi, bytes))
+      return fail(GPAW_EALIAS, tag + "psi_out overlaps psi");
+    const void *mats[3] = {x.H_nn, x.S_nn, x.C_nn};
+    for (int a = 0; a < 3; ++a)
+      for (int c = a + 1; c < 3; ++c)
+        if (overlaps(mats[a], mbytes, mats[c], mbytes))
+          return fail(GPAW_EALIAS, tag + "H_nn, S_nn and C_nn must not overlap");
+    if (overlaps(x.C_nn, mbytes, x.psi_out, bytes))
+      return fail(GPAW_EALIAS, tag + "C_nn overlaps psi_out");
+    if (x.P_out && s->np > 0 && overlaps(x.P_out, pbytes, x.psi_out, bytes))
+      return fail(GPAW_EALIAS, tag + "P_out overlaps psi_out");
+  }
+  return GPAW_OK;
+}
+
+// The whole step of system i on one stream.
+int chain(const gpaw_batch *b, size_t i, const gpaw_batch_io &io, int32_t *info, hipStream_t st) {
+  gpaw_sys *s = b->sys[i];
+  const gpaw_batch::Buf &w = b->buf[i];
+  const int nb = io.nb;
+  void *H = io.H_nn ? io.H_nn : w.H;
+  void *S = io.S_nn ? io.S_nn : w.S;
+  void *C = io.C_nn ? io.C_nn : w.C;
+  const void *X = s->np > 0 ? s->ws.X : nullptr;
+  int rc;
+  if (s->np > 0) {
+    if ((rc = launch_project(s, io.psi, nb, w.P, st)) != GPAW_OK) return rc;
+    if ((rc = launch_dmat(s, s->dH, w.P, nb, s->ws.X, st)) != GPAW_OK) return rc;
+  }
+  if ((rc = launch_stencil(s, io.psi, nb, X, w.Hpsi, st)) != GPAW_OK) return rc;
+  if (s->np > 0)
+    if ((rc = launch_dmat(s, s->dS, w.P, nb, s->ws.X, st)) != GPAW_OK) return rc;
+  if ((rc = launch_apply_S(s, io.psi, nb, X, w.Spsi, st)) != GPAW_OK) return rc;
+  if ((rc = launch_subspace(s, io.psi, w.Hpsi, w.Spsi, nb, H, S, st)) != GPAW_OK) return rc;
+  if ((rc = launch_eigh(s, H, S, nb, io.eps, C, info + i, st)) != GPAW_OK) return rc;
+  if ((rc = launch_rotate(s, C, io.psi, nb, s->ng, io.psi_out, st)) != GPAW_OK) return rc;
+  if (s->np > 0 && io.P_out)
+    if ((rc = launch_rotate(s, C, w.P, nb, s->np, io.P_out, st)) != GPAW_OK) return rc;
+  return GPAW_OK;
+}
+
+// relative cost of one system's step (grid work, contractions, eigensolver latency)
+double cost(const gpaw_sys *s, int nb) {
+  const double ng = static_cast<double>(s->ng);
+  const double c = is_complex(s->dtype) ? 4.0 : 1.0;
+  return ng * nb * (40.0 + c * nb) + 4.0e6 + 2.0e3 * nb * nb;
+}
+
+void drop_graph(gpaw_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->key.clear();
+}
+
+int record(gpaw_batch *b, const gpaw_batch_io *io, int32_t *info, int branches) {
+  drop_graph(b);
+  const size_t n = b->sys.size();
+  branches = std::max(1, std::min<int>(branches, static_cast<int>(std::min<size_t>(n, kMaxBranches))));
+  // largest first onto the least loaded branch
+  std::vector<size_t> order(n);
+  std::iota(order.begin(), order.end(), size_t(0));
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+    return cost(b->sys[x], io[x].nb) > cost(b->sys[y], io[y].nb);
+  });
+  std::vector<std::vector<size_t>> lanes(branches);
+  std::vector<double> load(branches, 0.0);
+  for (size_t i : order) {
+    const int l = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+    lanes[l].push_back(i);
+    load[l] += cost(b->sys[i], io[i].nb);
+  }
+  GFD_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+  int rc = GPAW_OK;
+  hipError_t e = hipEventRecord(b->fork, b->cap);
+  for (int l = 0; l < branches && e == hipSuccess; ++l) e = hipStreamWaitEvent(b->streams[l], b->fork, 0);
+  if (e != hipSuccess) rc = hip_fail(e, "graph fork");
+  for (int l = 0; l < branches && rc == GPAW_OK; ++l)
+    for (size_t i : lanes[l])
+      if ((rc = chain(b, i, io[i], info, b->streams[l])) != GPAW_OK) break;
+  // join every branch, also after a failed launch, so that no stream is
+  // left in capture mode
+  for (int l = 0; l < branches; ++l) {
+    e = hipEventRecord(b->joins[l], b->streams[l]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->joins[l], 0);
+    if (e != hipSuccess && rc == GPAW_OK) rc = hip_fail(e, "graph join");
+  }
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(b->cap, &g);
+  if (rc == GPAW_OK && e != hipSuccess) rc = hip_fail(e, "hipStreamEndCapture");
+  if (rc == GPAW_OK) {
+    e = hipGetLastError();
+    if (e != hipSuccess) rc = hip_fail(e, "batched step launch");
+  }
+  if (rc != GPAW_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return rc;
+  }
+  e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    b->exec = nullptr;
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  b->graph = g;
+  b->key.assign(io, io + n);
+  b->key_info = info;
+  b->key_branches = branches;
+  return GPAW_OK;
+}
+
+bool same_io(const gpaw_batch *b, const gpaw_batch_io *io, const int32_t *info) {
+  if (!b->exec || b->key_info != info || b->key.size() != b->sys.size()) return false;
+  return std::memcmp(b->key.data(), io, b->key.size() * sizeof(gpaw_batch_io)) == 0;
+}
+
+int branches_of(const gpaw_batch *b) {
+  return b->nbranch > 0 ? b->nbranch : kDefaultBranches;
+}
+
+void free_batch(gpaw_batch *b) {
+  drop_graph(b);
+  for (auto &w : b->buf) {
+    void *p[] = {w.P, w.Hpsi, w.Spsi, w.H, w.S, w.C};
+    for (void *q : p)
+      if (q) (void)hipFree(q);
+  }
+  for (hipStream_t st : b->streams) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : b->joins) (void)hipEventDestroy(ev);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+}
+
+// ------------------------------------------------------------------ autotuner
+// Mean time of fn over reps launches on stream st after one warm-up launch.
+template <typename F>
+int time_ms(F fn, hipStream_t st, int reps, float *ms) {
+  hipEvent_t a, z;
+  GFD_HIP(hipEventCreate(&a));
+  GFD_HIP(hipEventCreate(&z));
+  int rc = fn();
+  if (rc == GPAW_OK) {
+    (void)hipEventRecord(a, st);
+    for (int r = 0; r < reps && rc == GPAW_OK; ++r) rc = fn();
+    (void)hipEventRecord(z, st);
+    (void)hipEventSynchronize(z);
+    (void)hipEventElapsedTime(ms, a, z);
+    *ms /= reps;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(z);
+  if (rc == GPAW_OK) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "autotuner launch");
+  }
+  return rc;
+}
+
+// Try each value of one knob, keep the fastest.
+template <typename F>
+int pick(int *knob, const std::vector<int> &values, F fn, hipStream_t st) {
+  int best = *knob;
+  float best_ms = 1e30f;
+  for (int v : values) {
+    *knob = v;
+    float ms = 0.0f;
+    int rc = time_ms(fn, st, 3, &ms);
+    if (rc != GPAW_OK) return rc;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = v;
+    }
+  }
+  *knob = best;
+  return GPAW_OK;
+}
+
+int tune_system(gpaw_batch *b, size_t i, const gpaw_batch_io &io, int32_t *info, hipStream_t st) {
+  gpaw_sys *s = b->sys[i];
+  const gpaw_batch::Buf &w = b->buf[i];
+  const int nb = io.nb;
+  const bool cplx = is_complex(s->dtype);
+  if (s->dtype == GPAW_F32 || s->dtype == GPAW_C64) return GPAW_OK;  // fixed shapes
+  s->tune = Tune{};
+  int rc;
+  // one full chain so P, X, Hpsi, Spsi, C hold valid data for the part timings
+  if ((rc = chain(b, i, io, info, st)) != GPAW_OK) return rc;
+  void *C = io.C_nn ? io.C_nn : w.C;
+  const void *X = s->np > 0 ? s->ws.X : nullptr;
+  if (s->np > 0)
+    if ((rc = pick(&s->tune.prj_nbg, cplx ? std::vector<int>{1, 2} : std::vector<int>{2, 4},
+                   [&] { return launch_project(s, io.psi, nb, w.P, st); }, st)) != GPAW_OK)
+      return rc;
+  if (s->np > 0)
+    if ((rc = launch_dmat(s, s->dH, w.P, nb, s->ws.X, st)) != GPAW_OK) return rc;
+  auto stencil = [&] { return launch_stencil(s, io.psi, nb, X, w.Hpsi, st); };
+  if ((rc = pick(&s->tune.st_nb, cplx ? std::vector<int>{1, 2} : std::vector<int>{2, 4}, stencil,
+                 st)) != GPAW_OK)
+    return rc;
+  std::vector<int> segs = {0};
+  for (int v : {1, 2, 4, 8})
+    if (v <= std::max(1, s->n[0] / 4)) segs.push_back(v);
+  if ((rc = pick(&s->tune.st_nseg, segs, stencil, st)) != GPAW_OK) return rc;
+  if ((rc = pick(&s->tune.sub_wgs, {128, 256, 512, 1024},
+                 [&] {
+                   return launch_subspace(s, io.psi, w.Hpsi, w.Spsi, nb, w.H, w.S, st);
+                 },
+                 st)) != GPAW_OK)
+    return rc;
+  if ((rc = pick(&s->tune.rot_rb, cplx ? std::vector<int>{2, 4} : std::vector<int>{4, 8},
+                 [&] { return launch_rotate(s, C, io.psi, nb, s->ng, io.psi_out, st); }, st)) !=
+      GPAW_OK)
+    return rc;
+  return GPAW_OK;
+}
+
+}  // namespace
+}  // namespace gfd
+
+using namespace gfd;
+
+extern "C" {
+
+int gpaw_batch_create(gpaw_sys *const *systems, int32_t nsys, gpaw_batch **out) {
+  if (!systems || !out) return fail(GPAW_EINVAL, "systems and out must not be NULL");
+  *out = nullptr;
+  if (nsys < 1) return fail(GPAW_EINVAL, "nsys must be >= 1");
+  int dev = 0;
+  GFD_HIP(hipGetDevice(&dev));
+  for (int32_t i = 0; i < nsys; ++i) {
+    if (!systems[i]) return fail(GPAW_EINVAL, "system " + std::to_string(i) + " is NULL");
+    if (systems[i]->device != dev)
+      return fail(GPAW_EINVAL, "system " + std::to_string(i) + " lives on another device");
+    for (int32_t j = 0; j < i; ++j)
+      if (systems[j] == systems[i])
+        return fail(GPAW_EINVAL, "a system appears twice in the batch (its workspace would race)");
+  }
+  gpaw_batch *b = new gpaw_batch();
+  b->device = dev;
+  b->sys.assign(systems, systems + nsys);
+  b->buf.resize(nsys);
+  int rc = GPAW_OK;
+  for (int32_t i = 0; i < nsys && rc == GPAW_OK; ++i) {
+    const gpaw_sys *s = systems[i];
+    const size_t es = elem_size(s->dtype);
+    const size_t blk = static_cast<size_t>(s->max_bands) * s->ng * es;
+    const size_t mat = static_cast<size_t>(s->max_bands) * s->max_bands * mat_elem_size(s->dtype);
+    const size_t pb = static_cast<size_t>(s->max_bands) * s->np * es;
+    void **dst[] = {&b->buf[i].Hpsi, &b->buf[i].Spsi, &b->buf[i].H, &b->buf[i].S, &b->buf[i].C,
+                    &b->buf[i].P};
+    const size_t sz[] = {blk, blk, mat, mat, mat, pb};
+    for (int k = 0; k < 6 && rc == GPAW_OK; ++k) {
+      if (sz[k] == 0) continue;
+      hipError_t e = hipMalloc(dst[k], sz[k]);
+      if (e != hipSuccess) rc = hip_fail(e, "hipMalloc(batch workspace)");
+    }
+  }
+  hipError_t e = hipSuccess;
+  if (rc == GPAW_OK) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (rc == GPAW_OK && e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  for (int l = 0; l < kMaxBranches && rc == GPAW_OK && e == hipSuccess; ++l) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) b->streams.push_back(st);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) b->joins.push_back(ev);
+  }
+  if (rc == GPAW_OK && e != hipSuccess) rc = hip_fail(e, "batch streams");
+  if (rc != GPAW_OK) {
+    free_batch(b);
+    return rc;
+  }
+  *out = b;
+  return GPAW_OK;
+}
+
+void gpaw_batch_destroy(gpaw_batch *b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  free_batch(b);
+}
+
+int gpaw_batch_step(gpaw_batch *b, const gpaw_batch_io *io, int32_t *info, void *stream) {
+  int rc;
+  if ((rc = check_batch(b)) != GPAW_OK) return rc;
+  if ((rc = check_io(b, io, info)) != GPAW_OK) return rc;
+  if (!same_io(b, io, info)) {
+    // the graph reads the caller's buffers by address: re-record when they change
+    GFD_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    if ((rc = record(b, io, info, branches_of(b))) != GPAW_OK) return rc;
+  }
+  GFD_HIP(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+  return GPAW_OK;
+}
+
+int gpaw_batch_tune(gpaw_batch *b, const gpaw_batch_io *io, int32_t *info) {
+  int rc;
+  if ((rc = check_batch(b)) != GPAW_OK) return rc;
+  if ((rc = check_io(b, io, info)) != GPAW_OK) return rc;
+  drop_graph(b);
+  GFD_HIP(hipDeviceSynchronize());
+  for (size_t i = 0; i < b->sys.size(); ++i)
+    if ((rc = tune_system(b, i, io[i], info, b->cap)) != GPAW_OK) return rc;
+  GFD_HIP(hipStreamSynchronize(b->cap));
+  // branch count: record and time the whole graph for each candidate
+  int best = kDefaultBranches;
+  float best_ms = 1e30f;
+  const int nmax = static_cast<int>(std::min<size_t>(b->sys.size(), kMaxBranches));
+  for (int nbr : {1, 2, 4, 8, 16}) {
+    if (nbr > nmax && nbr != 1) continue;
+    if ((rc = record(b, io, info, nbr)) != GPAW_OK) return rc;
+    float ms = 0.0f;
+    rc = time_ms([&] {
+      hipError_t e = hipGraphLaunch(b->exec, b->cap);
+      return e == hipSuccess ? GPAW_OK : hip_fail(e, "hipGraphLaunch");
+    }, b->cap, 3, &ms);
+    if (rc != GPAW_OK) return rc;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = nbr;
+    }
+  }
+  b->nbranch = best;
+  if ((rc = record(b, io, info, best)) != GPAW_OK) return rc;
+  return GPAW_OK;
+}
+
+int gpaw_batch_tuning(const gpaw_batch *b, int32_t *out) {
+  if (!b || !out) return fail(GPAW_EINVAL, "batch and out must not be NULL");
+  out[0] = branches_of(b);
+  for (size_t i = 0; i < b->sys.size(); ++i) {
+    const Tune &t = b->sys[i]->tune;
+    int32_t *o = out + 1 + 5 * i;
+    o[0] = t.st_nb;
+    o[1] = t.st_nseg;
+    o[2] = t.sub_wgs;
+    o[3] = t.rot_rb;
+    o[4] = t.prj_nbg;
+  }
+  return GPAW_OK;
+}
+
+}  // extern "C"

@@ -10,7 +10,7 @@
 //   k_eig_tridiag  (1 workgroup, A in LDS) Householder A = Q T Q^T;
 //   k_eig_values   (one wavefront per eigenvalue) T splits where
 //                  |e_i| <= eps (|d_i| + |d_i+1|); each eigenvalue is found in
-//                  its unreduced block by 65-way multisection on Sturm counts;
+//                  its unreduced block by 129-way multisection on Sturm counts;
 //   k_eig_vectors  (one lane per eigenvalue) inverse iteration with a pivoted
 //                  tridiagonal LU; shifts closer than 10 eps ||T|| are pulled
 //                  apart by that amount;
@@ -463,37 +463,67 @@ __global__ __launch_bounds__(256) void k_eig_values(int n, EigWs w, const int32_
   gl = wave_min(gl);
   gu = wave_max(gu);
   emax2 = wave_max(emax2);
-  const double tn = fmax(fabs(gl), fabs(gu));
-  const double pivmin = DBL_MIN * fmax(1.0, emax2);
-  double a = gl - (2.0 * DBL_EPSILON * tn + 2.0 * pivmin);
-  double b = gu + (2.0 * DBL_EPSILON * tn + 2.0 * pivmin);
+  // Work on T scaled by a power of two (exact) so that |T| < 1: the leading
+  // minors then grow by at most a factor 3 per step, and rescaling them is
+  // needed only every 8 steps.
+  int ex = 0;
+  (void)frexp(fmax(fmax(fabs(gl), fabs(gu)), DBL_MIN), &ex);
+  const double s = ldexp(1.0, -ex), s2 = s * s;
+  const double tn = fmax(fabs(gl), fabs(gu)) * s;
+  const double pivmin = DBL_MIN * fmax(1.0, emax2 * s2);
+  double a = gl * s - (2.0 * DBL_EPSILON * tn + 2.0 * pivmin);
+  double b = gu * s + (2.0 * DBL_EPSILON * tn + 2.0 * pivmin);
+  constexpr int K = 2;  // shifts per lane: 129-way multisection
   for (int it = 0; it < 64; ++it) {
     const double width = b - a;
     if (width <= 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + pivmin) break;
-    const double x = a + width * ((lane + 1) / 65.0);
     // number of eigenvalues below x = sign changes along the leading minors
     // P_i = (d_i - x) P_{i-1} - e_{i-1}^2 P_{i-2}; an exact zero takes the sign
-    // opposite to its predecessor; power-of-two rescaling keeps P in range
-    int cnt = 0;
-    double pm = 1.0, pc = d[lo] - x;
-    bool neg = pc < 0.0 || pc == 0.0;
-    cnt += neg;
+    // opposite to its predecessor; K independent shifts per lane interleave
+    double x[K], pm[K], pc[K];
+    int cnt[K];
+    bool neg[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      x[k] = a + width * ((lane * K + k + 1) / (64.0 * K + 1.0));
+      pm[k] = 1.0;
+      pc[k] = fma(d[lo], s, -x[k]);
+      neg[k] = pc[k] <= 0.0;
+      cnt[k] = neg[k];
+    }
     for (int i = lo + 1; i <= hi; ++i) {
-      const double pn = (d[i] - x) * pc - e2[i - 1] * pm;
-      const bool nn = pn < 0.0 || (pn == 0.0 && !neg);
-      cnt += (nn != neg);
-      neg = nn;
-      const double mag = fmax(fabs(pn), fabs(pc));
-      const double sc = mag > 0x1p+400 ? 0x1p-400 : (mag < 0x1p-400 ? 0x1p+400 : 1.0);
-      pm = pc * sc;
-      pc = pn * sc;
+      const double di = d[i] * s, ei = e2[i - 1] * s2;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double pn = fma(di - x[k], pc[k], -ei * pm[k]);
+        const bool nn = pn < 0.0 || (pn == 0.0 && !neg[k]);
+        cnt[k] += (nn != neg[k]);
+        neg[k] = nn;
+        pm[k] = pc[k];
+        pc[k] = pn;
+      }
+      if (((i - lo) & 7) == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const double mag = fmax(fabs(pc[k]), fabs(pm[k]));
+          const double sc = mag > 0x1p+400 ? 0x1p-400 : (mag < 0x1p-400 ? 0x1p+400 : 1.0);
+          pm[k] *= sc;
+          pc[k] *= sc;
+        }
+      }
     }
     // eigenvalue li lies at or above x exactly when at most li lie below x
-    const double na = wave_max(cnt <= li ? x : -DBL_MAX);
-    const double nbnd = wave_min(cnt > li ? x : DBL_MAX);
-    a = fmax(a, na);
-    b = fmin(b, nbnd);
+    double na = -DBL_MAX, nbnd = DBL_MAX;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (cnt[k] <= li) na = fmax(na, x[k]);
+      else nbnd = fmin(nbnd, x[k]);
+    }
+    a = fmax(a, wave_max(na));
+    b = fmin(b, wave_min(nbnd));
   }
+  a /= s;
+  b /= s;
   if (lane == 0) w.lam[j] = 0.5 * (a + b);
 }
 
@@ -765,7 +795,54 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
   return GPAW_OK;
 }
 
+// Cout = Linv^H with S = L L^H (the orthonormalising rotation: the block
+// psi_out_n = sum_m Cout_mn psi_m has psi_out^H S~ psi_out = I)
+template <typename T>
+__global__ __launch_bounds__(256) void k_conj_transpose(const T *__restrict__ X, T *__restrict__ Y,
+                                                        int n, const int32_t *info) {
+  if (*info != 0) return;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * n) return;
+  const int r = static_cast<int>(idx / n), c = static_cast<int>(idx - static_cast<int64_t>(r) * n);
+  Y[idx] = cj(X[static_cast<int64_t>(c) * n + r]);
+}
+
+template <typename T>
+int chol_inv_t(const gpaw_sys *s, const void *S, int n, void *Cout, int32_t *info, hipStream_t st) {
+  constexpr int NMAX = EigMax<T>::n;
+  if (n > EIG_LARGE_MAX) return fail(GPAW_ESHAPE, "orthonormalisation supports nb <= 1024");
+  static std::once_flag once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(once, [] {
+    attr_err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_eig_chol<T>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  });
+  if (attr_err != hipSuccess) return hip_fail(attr_err, "hipFuncSetAttribute(k_eig_chol)");
+  const int sz = St<T>::cplx ? 2 : 1;
+  const bool large = n > NMAX;
+  const EigWs w = eig_layout(s->ws.eig, n, sz, large);
+  const T *Sd = static_cast<const T *>(S);
+  const int64_t nn = static_cast<int64_t>(n) * n;
+  const unsigned eb = static_cast<unsigned>((nn + 255) / 256);
+  if (!large) {
+    const size_t lda_bytes = (static_cast<size_t>(n) * (n + 1)) * sizeof(T);
+    k_eig_chol<T><<<1, EIG_T, lda_bytes + n * sizeof(double), st>>>(Sd, n, w, info);
+  } else {
+    k_set_info<<<1, 1, 0, st>>>(info);
+    k_hermitize<T><<<eb, 256, 0, st>>>(Sd, as<T>(w.Sw), n, info);
+    large_chol_linv<T>(as<T>(w.Sw), as<T>(w.Linv), n, w.piv, info, st);
+  }
+  k_conj_transpose<T><<<eb, 256, 0, st>>>(as<T>(w.Linv), static_cast<T *>(Cout), n, info);
+  return GPAW_OK;
+}
+
 }  // namespace
+
+int launch_chol_inv(const gpaw_sys *s, const void *S, int nb, void *Cout, int32_t *info,
+                    hipStream_t st) {
+  if (is_complex(s->dtype)) return chol_inv_t<z64>(s, S, nb, Cout, info, st);
+  return chol_inv_t<double>(s, S, nb, Cout, info, st);
+}
 
 size_t eig_ws_elems(int nmax, bool cplx) {
   const int small = cplx ? EigMax<z64>::n : EigMax<double>::n;
@@ -775,7 +852,7 @@ size_t eig_ws_elems(int nmax, bool cplx) {
 
 int launch_eigh(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps, void *C,
                 int32_t *info, hipStream_t st) {
-  if (s->dtype == GPAW_C128) return eigh_t<z64>(s, H, S, nb, eps, C, info, st);
+  if (s->dtype == GPAW_C128 || s->dtype == GPAW_C64) return eigh_t<z64>(s, H, S, nb, eps, C, info, st);
   return eigh_t<double>(s, H, S, nb, eps, C, info, st);
 }
 

@@ -183,12 +183,14 @@ struct SplitPlan {
   int64_t kchunk;
 };
 
-SplitPlan plan_subspace(int nb, int64_t ng, int nmat, int tile) {
+SplitPlan plan_subspace(int nb, int64_t ng, int nmat, int tile, int target) {
   SplitPlan p;
   p.tiles_n = (nb + tile - 1) / tile;
   p.tiles = p.tiles_n * p.tiles_n;
   // aim at ~512 workgroups (two per CU) with at least 1024 K per workgroup
-  const int64_t want = std::max<int64_t>(1, 512 / (p.tiles * nmat));
+  if (target <= 0) target = 512;
+  target = std::min(target, 1024);
+  const int64_t want = std::max<int64_t>(1, target / (p.tiles * nmat));
   const int64_t kmax_split = std::max<int64_t>(1, ng / 1024);
   int64_t nsplit = std::min(want, kmax_split);
   int64_t kchunk = (ng + nsplit - 1) / nsplit;
@@ -268,7 +270,7 @@ template <typename T, int BM>
 int subspace_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi, int nb,
                void *H, void *S, hipStream_t st) {
   const int nmat = Spsi ? 2 : 1;
-  const SplitPlan p = plan_subspace(nb, s->ng, nmat, 16 * BM);
+  const SplitPlan p = plan_subspace(nb, s->ng, nmat, 16 * BM, s->tune.sub_wgs);
   const int64_t need = static_cast<int64_t>(p.nsplit) * nmat * nb * nb * Cx<T>::parts;
   if (need > static_cast<int64_t>(s->ws.part_elems))
     return fail(GPAW_EINVAL, "subspace workspace too small");
@@ -294,16 +296,20 @@ int rotate_t(const void *C, const void *src, int nb, int64_t cols, void *dst, hi
 }  // namespace
 
 size_t subspace_part_elems(const gpaw_sys *s, int nb) {
-  // nsplit * tiles * nmat <= 512 whenever that allows one split, else nsplit = 1;
-  // complex tiles are 32 x 32 (a quarter of the real 64 x 64)
+  if (s->dtype == GPAW_F32 || s->dtype == GPAW_C64) return split_part_elems(nb, s->dtype == GPAW_C64);
+  // nsplit * tiles * nmat <= 1024 (the largest target) whenever that allows
+  // one split, else nsplit = 1; complex tiles are 32 x 32 (a quarter of the
+  // real 64 x 64)
   const bool cplx = s->dtype == GPAW_C128;
   const int64_t tile = cplx ? 32 : SUB_TILE;
-  const int64_t bound = std::max<int64_t>(512 * tile * tile, 2 * int64_t(nb) * nb);
+  const int64_t bound = std::max<int64_t>(1024 * tile * tile, 2 * int64_t(nb) * nb);
   return static_cast<size_t>(bound) * (cplx ? 2 : 1);
 }
 
 int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
                     int nb, void *H, void *S, hipStream_t st) {
+  if (s->dtype == GPAW_F32 || s->dtype == GPAW_C64)
+    return launch_subspace_split(s, psi, Hpsi, Spsi, nb, H, S, st);
   if (s->dtype == GPAW_C128) return subspace_t<z64, 2>(s, psi, Hpsi, Spsi, nb, H, S, st);
   return subspace_t<double, 4>(s, psi, Hpsi, Spsi, nb, H, S, st);
 }
@@ -311,8 +317,13 @@ int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const 
 int launch_rotate(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
                   void *dst, hipStream_t st) {
   if (cols == 0) return GPAW_OK;
-  if (s->dtype == GPAW_C128) return rotate_t<z64, 4>(C, src, nb, cols, dst, st);
-  return rotate_t<double, 8>(C, src, nb, cols, dst, st);
+  if (s->dtype == GPAW_F32 || s->dtype == GPAW_C64)
+    return launch_rotate_split(s, C, src, nb, cols, dst, st);
+  if (s->dtype == GPAW_C128)
+    return s->tune.rot_rb == 2 ? rotate_t<z64, 2>(C, src, nb, cols, dst, st)
+                               : rotate_t<z64, 4>(C, src, nb, cols, dst, st);
+  return s->tune.rot_rb == 4 ? rotate_t<double, 4>(C, src, nb, cols, dst, st)
+                             : rotate_t<double, 8>(C, src, nb, cols, dst, st);
 }
 
 }  // namespace gfd

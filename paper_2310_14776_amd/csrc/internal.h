@@ -37,24 +37,74 @@ __host__ __device__ inline z64 operator*(z64 a, z64 b) {
 __host__ __device__ inline z64 operator*(double s, z64 a) { return z64{s * a.x, s * a.y}; }
 __host__ __device__ inline z64 zconj(z64 a) { return z64{a.x, -a.y}; }
 
-// Scalar traits: one kernel body serves real and complex grids.
+struct z32 {
+  float x, y;
+};
+__host__ __device__ inline z32 operator+(z32 a, z32 b) { return z32{a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline z32 operator-(z32 a, z32 b) { return z32{a.x - b.x, a.y - b.y}; }
+__host__ __device__ inline z32 operator*(z32 a, z32 b) {
+  return z32{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// Scalar traits: one kernel body serves real and complex grids in double
+// precision and, for the precision form, in single precision. Acc is the
+// type partial sums are kept in (always double precision).
 template <typename T> struct St;
 template <> struct St<double> {
+  using Acc = double;
   static constexpr bool cplx = false;
+  static constexpr bool single = false;
   __host__ __device__ static double zero() { return 0.0; }
   __host__ __device__ static double conj(double a) { return a; }
   // a * b where b is a Bloch phase (identity for real systems)
   __host__ __device__ static double phase(double a, z64) { return a; }
   __host__ __device__ static double mul(double a, double b) { return a * b; }
   __host__ __device__ static double scale(double s, double a) { return s * a; }
+  __host__ __device__ static double widen(double a) { return a; }
+  __host__ __device__ static double narrow(double a) { return a; }
 };
 template <> struct St<z64> {
+  using Acc = z64;
   static constexpr bool cplx = true;
+  static constexpr bool single = false;
   __host__ __device__ static z64 zero() { return z64{0.0, 0.0}; }
   __host__ __device__ static z64 conj(z64 a) { return zconj(a); }
   __host__ __device__ static z64 phase(z64 a, z64 p) { return a * p; }
   __host__ __device__ static z64 mul(z64 a, z64 b) { return a * b; }
   __host__ __device__ static z64 scale(double s, z64 a) { return s * a; }
+  __host__ __device__ static z64 widen(z64 a) { return a; }
+  __host__ __device__ static z64 narrow(z64 a) { return a; }
+};
+template <> struct St<float> {
+  using Acc = double;
+  static constexpr bool cplx = false;
+  static constexpr bool single = true;
+  __host__ __device__ static float zero() { return 0.0f; }
+  __host__ __device__ static float conj(float a) { return a; }
+  __host__ __device__ static float phase(float a, z64) { return a; }
+  __host__ __device__ static float mul(float a, float b) { return a * b; }
+  __host__ __device__ static float scale(double s, float a) { return static_cast<float>(s) * a; }
+  __host__ __device__ static double widen(float a) { return a; }
+  __host__ __device__ static float narrow(double a) { return static_cast<float>(a); }
+};
+template <> struct St<z32> {
+  using Acc = z64;
+  static constexpr bool cplx = true;
+  static constexpr bool single = true;
+  __host__ __device__ static z32 zero() { return z32{0.0f, 0.0f}; }
+  __host__ __device__ static z32 conj(z32 a) { return z32{a.x, -a.y}; }
+  __host__ __device__ static z32 phase(z32 a, z64 p) {
+    return a * z32{static_cast<float>(p.x), static_cast<float>(p.y)};
+  }
+  __host__ __device__ static z32 mul(z32 a, z32 b) { return a * b; }
+  __host__ __device__ static z32 scale(double s, z32 a) {
+    const float f = static_cast<float>(s);
+    return z32{f * a.x, f * a.y};
+  }
+  __host__ __device__ static z64 widen(z32 a) { return z64{a.x, a.y}; }
+  __host__ __device__ static z32 narrow(z64 a) {
+    return z32{static_cast<float>(a.x), static_cast<float>(a.y)};
+  }
 };
 
 // ---------------------------------------------------------------- projectors
@@ -102,11 +152,26 @@ struct Workspace {
   void *X = nullptr;       // [max_bands][Np] Delta.P
   double *part = nullptr;  // subspace split-K partial sums
   size_t part_elems = 0;
+  void *split = nullptr;   // BF16 planes of C for the split rotation
   double *eig = nullptr;   // dense eigensolver scratch
   size_t eig_elems = 0;
   int32_t *info = nullptr; // device status word for synchronous diag
+  void *mat = nullptr;     // [2][max_bands][max_bands] subspace-sized scratch
 };
 
+}  // namespace gfd
+
+namespace gfd {
+// Launch shapes of one system (0 = the built-in heuristic). The batched
+// form's autotuner sets them per system; every choice computes the same
+// result up to the order of floating-point sums.
+struct Tune {
+  int st_nb = 0;    // bands per lane in the stencil: real 2 or 4, complex 1 or 2
+  int st_nseg = 0;  // x segments of the stencil grid (>= 1)
+  int sub_wgs = 0;  // target workgroup count of the split-K subspace product (<= 1024)
+  int rot_rb = 0;   // 16-row tiles per rotation workgroup: real 4 or 8, complex 2 or 4
+  int prj_nbg = 0;  // bands per projection workgroup: real 2 or 4, complex 1 or 2
+};
 }  // namespace gfd
 
 struct gpaw_sys {
@@ -125,11 +190,14 @@ struct gpaw_sys {
   double *dH = nullptr, *dS = nullptr;  // device [natoms][ni][ni]
   double *v = nullptr;                  // device [Ng]
   gfd::Workspace ws;
+  gfd::Tune tune;
 };
 
 namespace gfd {
 
 size_t elem_size(int32_t dtype);
+size_t mat_elem_size(int32_t dtype);
+bool is_complex(int32_t dtype);
 
 // Host construction of the projector geometry (tables.hip).
 int build_tables(const gpaw_sys_desc *d, gpaw_sys *s);
@@ -148,8 +216,17 @@ int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const 
 size_t subspace_part_elems(const gpaw_sys *s, int nb);
 int launch_rotate(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
                   void *dst, hipStream_t st);
+// precision form (gemm_split.hip)
+size_t split_part_elems(int nb, bool cplx);
+size_t split_c_bytes(int nb, bool cplx);
+int launch_subspace_split(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
+                          int nb, void *H, void *S, hipStream_t st);
+int launch_rotate_split(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
+                        void *dst, hipStream_t st);
 size_t eig_ws_elems(int nmax, bool cplx);
 int launch_eigh(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps, void *C,
                 int32_t *info, hipStream_t st);
+int launch_chol_inv(const gpaw_sys *s, const void *S, int nb, void *Cout, int32_t *info,
+                    hipStream_t st);
 
 }  // namespace gfd

@@ -45,19 +45,20 @@ __global__ __launch_bounds__(256) void k_project(const T *__restrict__ psi, T *_
   const int b0 = blockIdx.y * NBG;
   const int e0 = a_start[atom], e1 = a_start[atom + 1];
   const double R0 = pos[3 * atom], R1 = pos[3 * atom + 1], R2 = pos[3 * atom + 2];
-  T acc[NBG][NI];
+  using A = typename St<T>::Acc;
+  A acc[NBG][NI];
 #pragma unroll
   for (int b = 0; b < NBG; ++b)
 #pragma unroll
-    for (int i = 0; i < NI; ++i) acc[b][i] = St<T>::zero();
+    for (int i = 0; i < NI; ++i) acc[b][i] = St<A>::zero();
 
   for (int e = e0 + static_cast<int>(threadIdx.x); e < e1; e += 256) {
     const int64_t g = e_g[e];
     const short4 u = e_xyz[e];
-    T p[NBG];
+    A p[NBG];
 #pragma unroll
     for (int b = 0; b < NBG; ++b)
-      p[b] = (b0 + b < nb) ? psi[static_cast<int64_t>(b0 + b) * ng + g] : St<T>::zero();
+      p[b] = St<T>::widen((b0 + b < nb) ? psi[static_cast<int64_t>(b0 + b) * ng + g] : St<T>::zero());
     double pv[NI];
     eval_proj<NI>(pj, u.x * pj.h[0] - R0, u.y * pj.h[1] - R1, u.z * pj.h[2] - R2, pv);
     if (St<T>::cplx) {
@@ -65,29 +66,29 @@ __global__ __launch_bounds__(256) void k_project(const T *__restrict__ psi, T *_
       const int c = u.w;
       const z64 ph = zconj(image_phase(pj, ((c >> 8) & 15) - 8, ((c >> 4) & 15) - 8, (c & 15) - 8));
 #pragma unroll
-      for (int b = 0; b < NBG; ++b) p[b] = St<T>::phase(p[b], ph);
+      for (int b = 0; b < NBG; ++b) p[b] = St<A>::phase(p[b], ph);
     }
 #pragma unroll
     for (int b = 0; b < NBG; ++b)
 #pragma unroll
-      for (int i = 0; i < NI; ++i) acc[b][i] = acc[b][i] + St<T>::scale(pv[i], p[b]);
+      for (int i = 0; i < NI; ++i) acc[b][i] = acc[b][i] + St<A>::scale(pv[i], p[b]);
   }
 
-  __shared__ T red[4][NBG * NI];
+  __shared__ A red[4][NBG * NI];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int b = 0; b < NBG; ++b)
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-      const T r = Red<T>::wave_sum(acc[b][i]);
+      const A r = Red<A>::wave_sum(acc[b][i]);
       if (lane == 0) red[wave][b * NI + i] = r;
     }
   __syncthreads();
   for (int idx = threadIdx.x; idx < NBG * NI; idx += 256) {
     const int b = idx / NI, i = idx - b * NI;
     if (b0 + b < nb && i < pj.ni)
-      P[static_cast<int64_t>(b0 + b) * np + atom * pj.ni + i] =
-          St<T>::scale(dV, (red[0][idx] + red[1][idx]) + (red[2][idx] + red[3][idx]));
+      P[static_cast<int64_t>(b0 + b) * np + atom * pj.ni + i] = St<T>::narrow(
+          St<A>::scale(dV, (red[0][idx] + red[1][idx]) + (red[2][idx] + red[3][idx])));
   }
 }
 
@@ -101,9 +102,10 @@ __global__ __launch_bounds__(256) void k_dmat(const double *__restrict__ D, cons
   const int a = ai / ni, i = ai - a * ni;
   const double *Da = D + (static_cast<int64_t>(a) * ni + i) * ni;
   const T *Pa = P + n * np + a * ni;
-  T acc = St<T>::zero();
-  for (int j = 0; j < ni; ++j) acc = acc + St<T>::scale(Da[j], Pa[j]);
-  X[idx] = acc;
+  using A = typename St<T>::Acc;
+  A acc = St<A>::zero();
+  for (int j = 0; j < ni; ++j) acc = acc + St<A>::scale(Da[j], St<T>::widen(Pa[j]));
+  X[idx] = St<T>::narrow(acc);
 }
 
 template <typename T, int NI, int NBG>
@@ -118,28 +120,44 @@ void project_t(const gpaw_sys *s, const void *psi, int nb, void *P, hipStream_t 
 
 int launch_project(const gpaw_sys *s, const void *psi, int nb, void *P, hipStream_t st) {
   if (s->np == 0) return GPAW_OK;
-  const bool cplx = s->dtype == GPAW_C128;
-  if (s->ni == 13 && s->proj.std13) {
-    if (cplx) project_t<z64, 13, 2>(s, psi, nb, P, st);
-    else project_t<double, 13, 4>(s, psi, nb, P, st);
-  } else {
-    if (cplx) project_t<z64, 32, 1>(s, psi, nb, P, st);
-    else project_t<double, 32, 1>(s, psi, nb, P, st);
+  const bool std13 = s->ni == 13 && s->proj.std13;
+  switch (s->dtype) {
+    case GPAW_C128:
+      if (std13 && s->tune.prj_nbg == 1) project_t<z64, 13, 1>(s, psi, nb, P, st);
+      else if (std13) project_t<z64, 13, 2>(s, psi, nb, P, st);
+      else project_t<z64, 32, 1>(s, psi, nb, P, st);
+      break;
+    case GPAW_F32:
+      std13 ? project_t<float, 13, 4>(s, psi, nb, P, st) : project_t<float, 32, 1>(s, psi, nb, P, st);
+      break;
+    case GPAW_C64:
+      std13 ? project_t<z32, 13, 2>(s, psi, nb, P, st) : project_t<z32, 32, 1>(s, psi, nb, P, st);
+      break;
+    default:
+      if (std13 && s->tune.prj_nbg == 2) project_t<double, 13, 2>(s, psi, nb, P, st);
+      else if (std13) project_t<double, 13, 4>(s, psi, nb, P, st);
+      else project_t<double, 32, 1>(s, psi, nb, P, st);
   }
   return GPAW_OK;
+}
+
+template <typename T>
+void dmat_t(const gpaw_sys *s, const double *D, const void *P, int nb, void *X, hipStream_t st) {
+  const int64_t total = static_cast<int64_t>(nb) * s->np;
+  const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
+  k_dmat<T><<<blocks, 256, 0, st>>>(D, static_cast<const T *>(P), static_cast<T *>(X), total,
+                                    s->ni, s->np);
 }
 
 int launch_dmat(const gpaw_sys *s, const double *D, const void *P, int nb, void *X,
                 hipStream_t st) {
   if (s->np == 0) return GPAW_OK;
-  const int64_t total = static_cast<int64_t>(nb) * s->np;
-  const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
-  if (s->dtype == GPAW_C128)
-    k_dmat<z64><<<blocks, 256, 0, st>>>(D, static_cast<const z64 *>(P), static_cast<z64 *>(X),
-                                        total, s->ni, s->np);
-  else
-    k_dmat<double><<<blocks, 256, 0, st>>>(D, static_cast<const double *>(P),
-                                           static_cast<double *>(X), total, s->ni, s->np);
+  switch (s->dtype) {
+    case GPAW_C128: dmat_t<z64>(s, D, P, nb, X, st); break;
+    case GPAW_F32: dmat_t<float>(s, D, P, nb, X, st); break;
+    case GPAW_C64: dmat_t<z32>(s, D, P, nb, X, st); break;
+    default: dmat_t<double>(s, D, P, nb, X, st);
+  }
   return GPAW_OK;
 }
 

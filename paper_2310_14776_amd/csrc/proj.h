@@ -48,19 +48,18 @@ __device__ inline double radial(const ProjDev &P, int c, double r2) {
   return P.norm[c] * exp(-r2 * P.a2[c]) * (t * t);
 }
 
-// same, reusing the Gaussian of channel 0 or 1 when the sigmas agree
+// same, with the Gaussian of channel 0 or 1 (whose sigma channel c shares)
 __device__ inline double radial_shared(const ProjDev &P, int c, double r2, double E0, double E1) {
   const double s2 = r2 * P.rc2inv[c];
-  if (!(s2 < 1.0)) return 0.0;
   const double t = 1.0 - s2;
-  const int sh = P.same_sigma[c];
-  const double E = sh == 0 ? E0 : (sh == 1 ? E1 : exp(-r2 * P.a2[c]));
-  return P.norm[c] * E * (t * t);
+  const double E = P.same_sigma[c] == 0 ? E0 : E1;
+  return s2 < 1.0 ? P.norm[c] * E * (t * t) : 0.0;
 }
 
 // Values of all NI projectors of one atom at displacement (x, y, z).
-// NI == 13 is the channel layout l = (0, 0, 1, 1, 2); any other layout takes
-// the generic path (NI = PROJ_MAX_NI, entries beyond ni are zero).
+// NI == 13 is the channel layout l = (0, 0, 1, 1, 2) with the last three
+// channels sharing the sigma of channel 0 or 1; any other layout takes the
+// generic path (NI = PROJ_MAX_NI, entries beyond ni are zero).
 template <int NI>
 __device__ inline void eval_proj(const ProjDev &P, double x, double y, double z, double *out) {
   const double r2 = x * x + y * y + z * z;

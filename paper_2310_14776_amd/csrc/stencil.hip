@@ -63,7 +63,8 @@ __device__ inline int clamp3(int w) { return w < -3 ? -3 : (w > 3 ? 3 : w); }
 template <typename T, int NI, int NB>
 __device__ inline void addback_group(const AddArgs &ab, int2 pi, int ix, int iy, int iz,
                                      const double *pos, const T *Xs, int ldx, int b0, int nb,
-                                     T *acc) {
+                                     typename St<T>::Acc *acc) {
+  using A = typename St<T>::Acc;
   const int cnt = static_cast<int>(static_cast<unsigned>(pi.y) >> 24);
   const int first = pi.y & 0xFFFFFF;
   const ProjDev &pj = *ab.pj;
@@ -81,11 +82,11 @@ __device__ inline void addback_group(const AddArgs &ab, int2 pi, int ix, int iy,
     for (int b = 0; b < NB; ++b) {
       if (b0 + b >= nb) continue;
       const T *Xb = Xs + static_cast<int64_t>(b) * ldx + a * pj.ni;
-      T sum = St<T>::zero();
+      A sum = St<A>::zero();
 #pragma unroll
       for (int i = 0; i < NI; ++i)
-        if (i < pj.ni) sum = sum + St<T>::scale(pv[i], Xb[i]);
-      acc[b] = acc[b] + St<T>::phase(sum, ph);
+        if (i < pj.ni) sum = sum + St<A>::scale(pv[i], St<T>::widen(Xb[i]));
+      acc[b] = acc[b] + St<A>::phase(sum, ph);
     }
   }
 }
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil(const T *__restrict__ ps
     for (int b = 0; b < NB; ++b) {
       T val = St<T>::zero();
       if (b0 + b < nb) val = psi[(b0 + b) * bstride + off + f];
-      q[b][d] = BLOCH ? St<T>::phase(val, ph) : val;
+      q[b][d] = BLOCH ? St<T>::narrow(St<typename St<T>::Acc>::phase(St<T>::widen(val), ph)) : val;
     }
   }
 
@@ -183,36 +184,38 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil(const T *__restrict__ ps
       for (int b = 0; b < NB; ++b) {
         T val = St<T>::zero();
         if (b0 + b < nb) val = psi[(b0 + b) * bstride + off + f];
-        q[b][6] = BLOCH ? St<T>::phase(val, ph) : val;
+        q[b][6] = BLOCH ? St<T>::narrow(St<typename St<T>::Acc>::phase(St<T>::widen(val), ph)) : val;
       }
     }
     const int64_t xoff = static_cast<int64_t>(x) * plane;
     const int64_t g = xoff + f;
-    T acc[NB];
+    using A = typename St<T>::Acc;
+    A acc[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = St<T>::zero();
+    for (int b = 0; b < NB; ++b) acc[b] = St<A>::zero();
     if (ADD) addback_group<T, NI, NB>(ab, ab.pinfo[g], x, y, z, pos, Xs, ab.np, b0, nb, acc);
     const double cv = G.c0 + v[g];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       if (b0 + b >= nb) continue;
       const T *Pb = psi + (b0 + b) * bstride + xoff;
-      T r = acc[b] + St<T>::scale(cv, q[b][3]);
+      A r = acc[b] + St<A>::scale(cv, St<T>::widen(q[b][3]));
 #pragma unroll
       for (int d = 1; d <= 3; ++d) {
         const int ip = 2 * (d - 1), im = ip + 1;
-        T yp = Pb[yo[ip]], ym = Pb[yo[im]], zp = Pb[zo[ip]], zm = Pb[zo[im]];
+        A yp = St<T>::widen(Pb[yo[ip]]), ym = St<T>::widen(Pb[yo[im]]);
+        A zp = St<T>::widen(Pb[zo[ip]]), zm = St<T>::widen(Pb[zo[im]]);
         if (BLOCH) {
-          yp = St<T>::phase(yp, yph[ip]);
-          ym = St<T>::phase(ym, yph[im]);
-          zp = St<T>::phase(zp, zph[ip]);
-          zm = St<T>::phase(zm, zph[im]);
+          yp = St<A>::phase(yp, yph[ip]);
+          ym = St<A>::phase(ym, yph[im]);
+          zp = St<A>::phase(zp, zph[ip]);
+          zm = St<A>::phase(zm, zph[im]);
         }
-        r = r + St<T>::scale(G.cx[d - 1], q[b][3 + d] + q[b][3 - d]);
-        r = r + St<T>::scale(G.cy[d - 1], yp + ym);
-        r = r + St<T>::scale(G.cz[d - 1], zp + zm);
+        r = r + St<A>::scale(G.cx[d - 1], St<T>::widen(q[b][3 + d]) + St<T>::widen(q[b][3 - d]));
+        r = r + St<A>::scale(G.cy[d - 1], yp + ym);
+        r = r + St<A>::scale(G.cz[d - 1], zp + zm);
       }
-      out[(b0 + b) * bstride + g] = r;
+      out[(b0 + b) * bstride + g] = St<T>::narrow(r);
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b)
@@ -242,9 +245,10 @@ __global__ __launch_bounds__(256) void k_apply_S(const T *__restrict__ psi, T *_
   }
   const int64_t g = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (g >= ng) return;
-  T acc[NB];
+  using A = typename St<T>::Acc;
+  A acc[NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) acc[b] = St<T>::zero();
+  for (int b = 0; b < NB; ++b) acc[b] = St<A>::zero();
   if (ADD) {
     const int n1 = ab.pj->n[1], n2 = ab.pj->n[2];
     const int plane = n1 * n2;
@@ -257,7 +261,7 @@ __global__ __launch_bounds__(256) void k_apply_S(const T *__restrict__ psi, T *_
   for (int b = 0; b < NB; ++b)
     if (b0 + b < nb) {
       const int64_t idx = static_cast<int64_t>(b0 + b) * ng + g;
-      out[idx] = psi[idx] + acc[b];
+      out[idx] = St<T>::narrow(St<T>::widen(psi[idx]) + acc[b]);
     }
 }
 
@@ -287,11 +291,15 @@ StencilGeom make_geom(const gpaw_sys *s, int nb) {  // nb: band groups
       ph[c][3 - w] = zconj(pw);
     }
   }
+  // The x march is latency-bound: split x into segments until the grid has
+  // ~4096 workgroups, keeping segments >= 6 planes (each segment first reads
+  // the 6 planes around its start).
   const int plane = s->n[1] * s->n[2];
   const int chunks = (plane + ST_THREADS - 1) / ST_THREADS;
   const int64_t wgs = static_cast<int64_t>(chunks) * nb;
-  int nseg = static_cast<int>((2048 + wgs - 1) / wgs);
-  nseg = std::max(1, std::min(nseg, std::max(1, s->n[0] / 16)));
+  int nseg = static_cast<int>((4096 + wgs - 1) / wgs);
+  nseg = std::max(1, std::min(nseg, std::max(1, s->n[0] / 6)));
+  if (s->tune.st_nseg > 0) nseg = std::min(s->tune.st_nseg, s->n[0]);
   G.xseg = (s->n[0] + nseg - 1) / nseg;
   return G;
 }
@@ -358,21 +366,45 @@ int apply_S_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *o
 int launch_stencil(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,
                    hipStream_t st) {
   const bool std13 = s->ni == 13 && s->proj.std13;
-  if (s->dtype == GPAW_C128)
-    return std13 ? stencil_t<z64, true, 2, 13>(s, psi, nb, X, out, st)
-                 : stencil_t<z64, true, 2, PROJ_MAX_NI>(s, psi, nb, X, out, st);
-  return std13 ? stencil_t<double, false, 4, 13>(s, psi, nb, X, out, st)
-               : stencil_t<double, false, 4, PROJ_MAX_NI>(s, psi, nb, X, out, st);
+  switch (s->dtype) {
+    case GPAW_C128:
+      // one band per lane with projectors (shorter add-back per wave), two without
+      if (std13 && (s->tune.st_nb == 1 || (s->tune.st_nb == 0 && X)))
+        return stencil_t<z64, true, 1, 13>(s, psi, nb, X, out, st);
+      return std13 ? stencil_t<z64, true, 2, 13>(s, psi, nb, X, out, st)
+                   : stencil_t<z64, true, 2, PROJ_MAX_NI>(s, psi, nb, X, out, st);
+    case GPAW_F32:
+      return std13 ? stencil_t<float, false, 4, 13>(s, psi, nb, X, out, st)
+                   : stencil_t<float, false, 4, PROJ_MAX_NI>(s, psi, nb, X, out, st);
+    case GPAW_C64:
+      return std13 ? stencil_t<z32, true, 2, 13>(s, psi, nb, X, out, st)
+                   : stencil_t<z32, true, 2, PROJ_MAX_NI>(s, psi, nb, X, out, st);
+    default:
+      // two bands per lane with projectors, four without
+      if (std13 && (s->tune.st_nb == 2 || (s->tune.st_nb == 0 && X)))
+        return stencil_t<double, false, 2, 13>(s, psi, nb, X, out, st);
+      return std13 ? stencil_t<double, false, 4, 13>(s, psi, nb, X, out, st)
+                   : stencil_t<double, false, 4, PROJ_MAX_NI>(s, psi, nb, X, out, st);
+  }
 }
 
 int launch_apply_S(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,
                    hipStream_t st) {
   const bool std13 = s->ni == 13 && s->proj.std13;
-  if (s->dtype == GPAW_C128)
-    return std13 ? apply_S_t<z64, 8, 13>(s, psi, nb, X, out, st)
-                 : apply_S_t<z64, 8, PROJ_MAX_NI>(s, psi, nb, X, out, st);
-  return std13 ? apply_S_t<double, 16, 13>(s, psi, nb, X, out, st)
-               : apply_S_t<double, 16, PROJ_MAX_NI>(s, psi, nb, X, out, st);
+  switch (s->dtype) {
+    case GPAW_C128:
+      return std13 ? apply_S_t<z64, 8, 13>(s, psi, nb, X, out, st)
+                   : apply_S_t<z64, 8, PROJ_MAX_NI>(s, psi, nb, X, out, st);
+    case GPAW_F32:
+      return std13 ? apply_S_t<float, 16, 13>(s, psi, nb, X, out, st)
+                   : apply_S_t<float, 16, PROJ_MAX_NI>(s, psi, nb, X, out, st);
+    case GPAW_C64:
+      return std13 ? apply_S_t<z32, 8, 13>(s, psi, nb, X, out, st)
+                   : apply_S_t<z32, 8, PROJ_MAX_NI>(s, psi, nb, X, out, st);
+    default:
+      return std13 ? apply_S_t<double, 16, 13>(s, psi, nb, X, out, st)
+                   : apply_S_t<double, 16, PROJ_MAX_NI>(s, psi, nb, X, out, st);
+  }
 }
 
 }  // namespace gfd

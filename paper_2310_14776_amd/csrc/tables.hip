@@ -63,13 +63,16 @@ int setup_proj(const gpaw_sys_desc *d, ProjDev &P) {
     }
   }
   P.ni = i;
-  P.std13 = (d->nchan == 5 && P.l[0] == 0 && P.l[1] == 0 && P.l[2] == 1 && P.l[3] == 1 &&
-             P.l[4] == 2) ? 1 : 0;
   for (int c = 0; c < d->nchan; ++c) {
     P.same_sigma[c] = -1;
     if (c >= 2 && d->chan[c].sigma == d->chan[0].sigma) P.same_sigma[c] = 0;
     else if (c >= 2 && d->chan[c].sigma == d->chan[1].sigma) P.same_sigma[c] = 1;
   }
+  // straight-line layout: l = (0, 0, 1, 1, 2) and the last three channels
+  // reuse the Gaussian of channel 0 or 1 (two exponentials per point)
+  P.std13 = (d->nchan == 5 && P.l[0] == 0 && P.l[1] == 0 && P.l[2] == 1 && P.l[3] == 1 &&
+             P.l[4] == 2 && P.same_sigma[2] >= 0 && P.same_sigma[3] >= 0 &&
+             P.same_sigma[4] >= 0) ? 1 : 0;
   for (int c = 0; c < 3; ++c) {
     P.n[c] = d->n[c];
     P.h[c] = d->h[c];

@@ -8,7 +8,7 @@ eigensolve and the rotation live in the HIP library and, independently, in
 the CPU oracle. Both sides read the same arrays from here.
 """
 from .systems import (System, make_system, standard_channels, config_system,
-                      CONFIGS, ragged_cases)
+                      CONFIGS, ragged_cases, batched_systems, smooth_bands)
 
 __all__ = ["System", "make_system", "standard_channels", "config_system",
-           "CONFIGS", "ragged_cases"]
+           "CONFIGS", "ragged_cases", "batched_systems", "smooth_bands"]
