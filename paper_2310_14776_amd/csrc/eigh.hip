@@ -4,13 +4,13 @@
 // Kohn-Sham equation").
 //
 // Pipeline (real symmetric, nb <= 128), all on one stream:
-//   k_eig_chol     (1 workgroup, matrix in LDS) S <- (S+S^T)/2 = L L^T,
-//                  Linv = L^-1 by column-parallel forward substitution;
+//   k_eig_chol     (1 workgroup, matrix in LDS) S <- (S+S^T)/2 = L L^T and
+//                  Linv = L^-1, blocked by 16x16 tiles on FP64 MFMA;
 //   k_small_gemm   A = Linv ((H+H^T)/2) Linv^T on FP64 MFMA (two products);
 //   k_eig_tridiag  (1 workgroup, A in LDS) Householder A = Q T Q^T;
 //   k_eig_values   (one wavefront per eigenvalue) T splits where
 //                  |e_i| <= eps (|d_i| + |d_i+1|); each eigenvalue is found in
-//                  its unreduced block by 129-way multisection on Sturm counts;
+//                  its unreduced block by 65-way multisection on Sturm counts;
 //   k_eig_vectors  (one lane per eigenvalue) inverse iteration with a pivoted
 //                  tridiagonal LU; shifts closer than 10 eps ||T|| are pulled
 //                  apart by that amount;
@@ -45,6 +45,7 @@ constexpr int EIG_T = 1024;
 constexpr int EIG_NMAX = 128;
 constexpr int VEC_T = 8;  // lanes (eigenvectors) per inverse-iteration workgroup
 constexpr int SG_T = 256;  // small-GEMM workgroup: four 16x16 output tiles
+constexpr int CH_T = 512;  // blocked Cholesky: 8 wavefronts (256 VGPRs each)
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -90,26 +91,51 @@ size_t eig_layout_elems(int n, int sz, bool large) {
 
 template <typename T> __host__ __device__ inline T *as(double *p) { return reinterpret_cast<T *>(p); }
 
+// Wavefront reductions on DPP lane moves (gfx9 row permutations: lane ^ 1,
+// lane ^ 2, half-row and row mirrors) plus readlane across the four rows;
+// every lane gets the same value. The wavefront must be fully active.
+template <int CTRL>
+__device__ inline double dpp(double v) {
+  const int2 u = __builtin_bit_cast(int2, v);
+  return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_mov_dpp(u.x, CTRL, 0xF, 0xF, false),
+                                              __builtin_amdgcn_mov_dpp(u.y, CTRL, 0xF, 0xF, false)));
+}
+__device__ inline double lane_read(double v, int lane) {
+  const int2 u = __builtin_bit_cast(int2, v);
+  return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readlane(u.x, lane),
+                                              __builtin_amdgcn_readlane(u.y, lane)));
+}
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
+
 __device__ inline double wave_sum(double v) {
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+  v += dpp<DPP_XOR1>(v);
+  v += dpp<DPP_XOR2>(v);
+  v += dpp<DPP_HALF_MIRROR>(v);
+  v += dpp<DPP_MIRROR>(v);
+  return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 __device__ inline double wave_max(double v) {
-  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
+  v = fmax(v, dpp<DPP_XOR1>(v));
+  v = fmax(v, dpp<DPP_XOR2>(v));
+  v = fmax(v, dpp<DPP_HALF_MIRROR>(v));
+  v = fmax(v, dpp<DPP_MIRROR>(v));
+  return fmax(fmax(lane_read(v, 0), lane_read(v, 16)), fmax(lane_read(v, 32), lane_read(v, 48)));
 }
 __device__ inline double wave_min(double v) {
-  for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off));
-  return v;
+  v = fmin(v, dpp<DPP_XOR1>(v));
+  v = fmin(v, dpp<DPP_XOR2>(v));
+  v = fmin(v, dpp<DPP_HALF_MIRROR>(v));
+  v = fmin(v, dpp<DPP_MIRROR>(v));
+  return fmin(fmin(lane_read(v, 0), lane_read(v, 16)), fmin(lane_read(v, 32), lane_read(v, 48)));
 }
 
 __device__ inline z64 wave_sum(z64 v) { return z64{wave_sum(v.x), wave_sum(v.y)}; }
 
-// 8-lane group reductions (lanes 8q..8q+7)
+// 8-lane group reductions (lanes 8q..8q+7, the half-rows)
 __device__ inline double group8_sum(double v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 4);
+  v += dpp<DPP_XOR1>(v);
+  v += dpp<DPP_XOR2>(v);
+  v += dpp<DPP_HALF_MIRROR>(v);
   return v;
 }
 __device__ inline z64 group8_sum(z64 v) { return z64{group8_sum(v.x), group8_sum(v.y)}; }
@@ -136,98 +162,210 @@ __device__ inline bool split_at(const double *d, const double *e, int i) {
 }
 
 // ------------------------------------------------------------------ Cholesky
-// S <- (S+S^H)/2 = L L^H in LDS, then Linv = L^-1 to global memory.
-// Thread (ty, tx) = (tid/32, tid%32) owns rows ty+32a and columns tx+32b.
+// S <- (S+S^H)/2 = L L^H and Linv = L^-1, blocked by 16x16 tiles in LDS.
+// The matrix is padded to N = 16 ceil(n/16) with an identity block, so every
+// tile is full. Right-looking over tile columns k:
+//   wave 0   factors the diagonal tile (lane r owns row r, column values
+//            broadcast by readlane) and overwrites it with its inverse;
+//   panel    L_ik = A_ik L_kk^-H, one wavefront per tile (FP64 MFMA);
+//   update   A_ij -= L_ik L_jk^H for k < j <= i, one wavefront per tile.
+// Then block rows of Linv: X_ik = -L_ii^-1 sum_{j=k}^{i-1} L_ij X_jk, the
+// blocks X_jk (j > k) kept transposed in the unused upper tile (k, j).
+
+__device__ inline double rl(double v, int lane) {
+  const int2 u = __builtin_bit_cast(int2, v);
+  return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readlane(u.x, lane),
+                                              __builtin_amdgcn_readlane(u.y, lane)));
+}
+__device__ inline z64 rl(z64 v, int lane) { return z64{rl(v.x, lane), rl(v.y, lane)}; }
+
+// acc += op(A) op(B) over one 16-deep tile product on FP64 MFMA; fa(i, k) and
+// fb(k, j) return the operand elements (complex: four real products).
+template <typename T, typename FA, typename FB>
+__device__ inline void tile_mma(d4 &accr, d4 &acci, FA fa, FB fb) {
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const T a = fa(i, 4 * ks + kq), b = fb(4 * ks + kq, i);
+    if constexpr (St<T>::cplx) {
+      accr = __builtin_amdgcn_mfma_f64_16x16x4f64(re_of(a), re_of(b), accr, 0, 0, 0);
+      accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, acci, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, acci, 0, 0, 0);
+    } else {
+      accr = __builtin_amdgcn_mfma_f64_16x16x4f64(re_of(a), re_of(b), accr, 0, 0, 0);
+    }
+  }
+}
+
+template <typename T> __device__ inline T from_acc(const d4 &r, const d4 &i, int e);
+template <> __device__ inline double from_acc<double>(const d4 &r, const d4 &, int e) { return r[e]; }
+template <> __device__ inline z64 from_acc<z64>(const d4 &r, const d4 &i, int e) {
+  return z64{r[e], i[e]};
+}
+
+// Wave 0: factor diagonal tile D (in LDS, stride lda) = L L^H and overwrite it
+// with L^-1 (zeros above the diagonal). Returns j+1 of the first pivot that
+// is not positive (uniform), else 0.
 template <typename T>
-__global__ __launch_bounds__(EIG_T) void k_eig_chol(const T *__restrict__ S, int n, EigWs w,
+__device__ inline int diag_factor_inverse(T *D, int lda) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15;
+  T row[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) row[c] = D[r * lda + c];
+  double dinv[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const double d = rl(re_of(row[j]), j);
+    if (!(d > 0.0)) return j + 1;
+    const double sd = sqrt(d);
+    dinv[j] = 1.0 / sd;
+    const T lrj = r > j ? row[j] * dinv[j] : (r == j ? realv<T>(sd) : T{});
+    row[j] = lrj;
+#pragma unroll
+    for (int c = j + 1; c < 16; ++c) {
+      const T lcj = rl(lrj, c);
+      if (r >= c) row[c] = row[c] - lrj * cj(lcj);
+    }
+  }
+  // L back to the tile; its row r is read again one element per step below
+  if (lane < 16) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) D[r * lda + c] = row[c];
+  }
+  // X = L^-1 by rows: X[i][:] = (e_i - sum_{m<i} L[i][m] X[m][:]) / L[i][i]
+  T acc[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) acc[c] = realv<T>(c == r ? 1.0 : 0.0);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const T lri = D[r * lda + i];
+    // row i is final: X[i][c] = acc[c] / L[i][i] in lane i
+#pragma unroll
+    for (int c = 0; c <= i; ++c) {
+      const T xic = rl(acc[c] * dinv[i], i);
+      if (r == i) acc[c] = xic;
+      else if (r > i) acc[c] = acc[c] - lri * xic;
+    }
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) D[r * lda + c] = c <= r ? acc[c] : T{};
+  }
+  return 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(CH_T) void k_eig_chol(const T *__restrict__ S, int n, EigWs w,
                                                     int32_t *info) {
   extern __shared__ double sm[];
-  constexpr int NMAX = EigMax<T>::n;
-  const int lda = n + 1;
+  const int NT = (n + 15) / 16, N = 16 * NT, lda = N + 1;
   T *A = reinterpret_cast<T *>(sm);
-  double *dinv = reinterpret_cast<double *>(A + n * lda);
-  const int tid = threadIdx.x;
-  const int ty = tid >> 5, tx = tid & 31;
-
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int r = ty + 32 * a, c = tx + 32 * b;
-      if (r < n && c < n) A[r * lda + c] = St<T>::scale(0.5, S[r * n + c] + cj(S[c * n + r]));
-    }
+  int &fail_sh = *reinterpret_cast<int *>(A + N * lda);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  // lower triangle of (S + S^H)/2, identity on the padding
+  for (int idx = tid; idx < N * N; idx += CH_T) {
+    const int r = idx / N, c = idx - (idx / N) * N;
+    if (c > r) continue;
+    T v = realv<T>(r == c ? 1.0 : 0.0);
+    if (r < n && c < n) v = St<T>::scale(0.5, S[r * n + c] + cj(S[c * n + r]));
+    A[r * lda + c] = v;
+  }
+  if (tid == 0) fail_sh = 0;
   __syncthreads();
+  auto tile = [&](int bi, int bj) { return A + (16 * bi) * lda + 16 * bj; };
 
-  // right-looking, lower; column j-1 is scaled while step j updates j+1..n-1
-  int failed = 0;
-  double prev_rs = 0.0;
-  for (int j = 0; j < n; ++j) {
-    const double djj = re_of(A[j * lda + j]);
-    if (!(djj > 0.0)) {
-      failed = j + 1;
-      break;
+  for (int k = 0; k < NT; ++k) {
+    if (wave == 0) {
+      const int f = diag_factor_inverse<T>(tile(k, k), lda);
+      if (f && lane == 0) fail_sh = 16 * k + f;
     }
-    if (j > 0 && tid < n && tid >= j) A[tid * lda + j - 1] = A[tid * lda + j - 1] * prev_rs;
-    const double inv = 1.0 / djj;
-    T lc[4];
+    __syncthreads();
+    if (fail_sh) break;
+    // panel: L_ik = A_ik Dinv_k^H
+    const T *Dk = tile(k, k);
+    for (int i = k + 1 + wave; i < NT; i += CH_T / 64) {
+      T *Ti = tile(i, k);
+      d4 ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0};
+      tile_mma<T>(ar, ai, [&](int r, int c) { return Ti[r * lda + c]; },
+                  [&](int kk, int c) { return cj(Dk[c * lda + kk]); });
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int c = tx + 32 * b;
-      lc[b] = (c > j && c < n) ? cj(A[c * lda + j]) * inv : T{};
+      for (int e = 0; e < 4; ++e) Ti[(lq + 4 * e) * lda + li] = from_acc<T>(ar, ai, e);
     }
+    __syncthreads();
+    // trailing update of the lower tiles (i, j), k < j <= i
+    const int m = NT - k - 1;
+    for (int t = wave; t < m * (m + 1) / 2; t += CH_T / 64) {
+      int i = 0;
+      while ((i + 1) * (i + 2) / 2 <= t) ++i;
+      const int j = t - i * (i + 1) / 2;
+      const T *Li = tile(k + 1 + i, k), *Lj = tile(k + 1 + j, k);
+      T *Tij = tile(k + 1 + i, k + 1 + j);
+      d4 ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0};
+      tile_mma<T>(ar, ai, [&](int r, int c) { return Li[r * lda + c]; },
+                  [&](int kk, int c) { return cj(Lj[c * lda + kk]); });
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int r = ty + 32 * a;
-      if (r <= j || r >= n) continue;
-      const T lr = A[r * lda + j];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int c = tx + 32 * b;
-        if (c > j && c <= r) A[r * lda + c] = A[r * lda + c] - lr * lc[b];
+      for (int e = 0; e < 4; ++e) {
+        T *p = Tij + (lq + 4 * e) * lda + li;
+        *p = *p - from_acc<T>(ar, ai, e);
       }
     }
-    prev_rs = 1.0 / sqrt(djj);
     __syncthreads();
   }
-  if (failed) {
-    if (tid == 0) *info = failed;
+  if (fail_sh) {
+    if (tid == 0) *info = fail_sh <= n ? fail_sh : n;
     return;
   }
-  if (tid < n) {
-    const double r = sqrt(re_of(A[tid * lda + tid]));
-    A[tid * lda + tid] = realv<T>(r);
-    dinv[tid] = 1.0 / r;
-  }
-  __syncthreads();
-
-  // Linv column col by 8 lanes; lane s keeps rows 8t+s in xr[t]
-  T *Linv = as<T>(w.Linv);
-  const int col = tid >> 3, s = tid & 7;
-  T xr[NMAX / 8];
-#pragma unroll
-  for (int t = 0; t < NMAX / 8; ++t) xr[t] = T{};
-  if (col < n) {
-    for (int i = col; i < n; ++i) {
-      T part = T{};
-      const T *Li = A + i * lda;
-#pragma unroll
-      for (int t = 0; t < NMAX / 8; ++t) {
-        const int kk = 8 * t + s;
-        if (kk >= col && kk < i) part = part + Li[kk] * xr[t];
+  // block rows of Linv; X_kk = tile(k,k), X_jk (j > k) transposed in tile(k, j)
+  for (int i = 1; i < NT; ++i) {
+    for (int k = wave; k < i; k += CH_T / 64) {
+      d4 ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0};
+      for (int j = k; j < i; ++j) {
+        const T *Lij = tile(i, j);
+        const T *X = tile(k, j);  // j == k: X_kk as stored; j > k: transposed
+        if (j == k)
+          tile_mma<T>(ar, ai, [&](int r, int c) { return Lij[r * lda + c]; },
+                      [&](int kk, int c) { return X[kk * lda + c]; });
+        else
+          tile_mma<T>(ar, ai, [&](int r, int c) { return Lij[r * lda + c]; },
+                      [&](int kk, int c) { return X[c * lda + kk]; });
       }
-      part = group8_sum(part);
-      const T xi = (i == col) ? realv<T>(dinv[i]) : part * (-dinv[i]);
+      // Y (16x16) into tile (k, i) transposed, then X_ik = -Dinv_i Y there
+      T *Y = tile(k, i);
 #pragma unroll
-      for (int t = 0; t < NMAX / 8; ++t)
-        if (8 * t + s == i) xr[t] = xi;
-    }
+      for (int e = 0; e < 4; ++e) Y[li * lda + lq + 4 * e] = from_acc<T>(ar, ai, e);
+      const T *Di = tile(i, i);
+      d4 br = {0, 0, 0, 0}, bi = {0, 0, 0, 0};
+      tile_mma<T>(br, bi, [&](int r, int c) { return Di[r * lda + c]; },
+                  [&](int kk, int c) { return Y[c * lda + kk]; });
 #pragma unroll
-    for (int t = 0; t < NMAX / 8; ++t) {
-      const int row = 8 * t + s;
-      if (row < n) Linv[row * n + col] = xr[t];
+      for (int e = 0; e < 4; ++e)
+        Y[li * lda + lq + 4 * e] = St<T>::scale(-1.0, from_acc<T>(br, bi, e));
     }
+    __syncthreads();
+  }
+  T *Linv = as<T>(w.Linv);
+  for (int idx = tid; idx < n * n; idx += CH_T) {
+    const int r = idx / n, c = idx - (idx / n) * n;
+    T v = T{};
+    if (c <= r) {
+      const int bi = r >> 4, bj = c >> 4;
+      v = bi == bj ? tile(bi, bi)[(r & 15) * lda + (c & 15)]
+                   : tile(bj, bi)[(c & 15) * lda + (r & 15)];
+    }
+    Linv[idx] = v;
   }
   if (tid == 0) *info = 0;
+}
+
+// LDS bytes of k_eig_chol for an n x n block
+template <typename T>
+size_t chol_lds_bytes(int n) {
+  const size_t N = 16 * ((n + 15) / 16);
+  return N * (N + 1) * sizeof(T) + 16;
 }
 
 __global__ void k_set_info(int32_t *info) { *info = 0; }
@@ -313,14 +451,59 @@ __global__ __launch_bounds__(SG_T) void k_small_gemm(const T *__restrict__ A, in
 // sub-diagonal beta_k is real). Reflector k is kept in column k of A below
 // the diagonal (that column is not read again), so the loop issues no
 // global stores; V, tau, d, e go out at the end.
+// Householder reflector of the column x = A[k+1.., col] (in LDS, wave 0):
+// H = I - tau v v^H with v_0 = 1 maps x to (beta, 0, ..., 0), beta real.
+// Writes v into vout[k+1..] and into the column (that column is not read
+// again), tau/beta/d into the tables.
+template <typename T>
+__device__ inline void make_reflector(T *A, int lda, int n, int k, T *vout, T *taus, double *dd,
+                                      double *ee) {
+  const int lane = threadIdx.x & 63;
+  double xn2 = 0.0;
+  for (int r = k + 2 + lane; r < n; r += 64) xn2 += abs2(A[r * lda + k]);
+  xn2 = wave_sum(xn2);
+  const T alpha = A[(k + 1) * lda + k];
+  const double ar = re_of(alpha);
+  double beta;
+  T tau, scl;
+  if (xn2 == 0.0 && abs2(alpha) == ar * ar) {
+    beta = ar;
+    tau = T{};
+    scl = T{};
+  } else {
+    beta = -copysign(sqrt(abs2(alpha) + xn2), ar);
+    // tau = (beta - alpha)/beta, scl = 1/(alpha - beta)
+    const T amb = alpha - realv<T>(beta);
+    tau = St<T>::scale(-1.0 / beta, amb);
+    scl = cj(amb) * (1.0 / abs2(amb));
+  }
+  for (int r = k + 1 + lane; r < n; r += 64) {
+    const T vr = (r == k + 1) ? realv<T>(1.0) : A[r * lda + k] * scl;
+    vout[r] = vr;
+    A[r * lda + k] = vr;
+  }
+  if (lane == 0) {
+    taus[k] = tau;
+    dd[k] = re_of(A[k * lda + k]);
+    ee[k] = beta;
+  }
+}
+
+// A (global, made Hermitian on load) -> LDS; Householder A = Q T Q^H with
+// H_k = I - tau_k v_k v_k^H chosen so that T is real symmetric (the
+// sub-diagonal beta_k is real). Reflector k is kept in column k of A below
+// the diagonal. Each step: p = tau A v (8 lanes per row), then the rank-2
+// update A -= v w^H + w v^H with w = p - (tau/2)(p^H v) v; wavefront 0
+// updates column k+1 itself and builds reflector k+1 from it while the other
+// wavefronts update the rest, so a step costs two barriers.
 template <typename T>
 __global__ __launch_bounds__(EIG_T) void k_eig_tridiag(int n, EigWs w, const int32_t *info) {
   if (*info != 0) return;
   extern __shared__ double sm[];
   const int lda = n + 1;
   T *A = reinterpret_cast<T *>(sm);
-  T *vv = A + n * lda;
-  T *pp = vv + n;
+  T *vbuf = A + n * lda;  // two reflector buffers [2][n]
+  T *pp = vbuf + 2 * n;
   T *taus = pp + n;
   double *dd = reinterpret_cast<double *>(taus + n);
   double *ee = dd + n;
@@ -337,39 +520,13 @@ __global__ __launch_bounds__(EIG_T) void k_eig_tridiag(int n, EigWs w, const int
       if (r < n && c < n) A[r * lda + c] = St<T>::scale(0.5, Ag[r * n + c] + cj(Ag[c * n + r]));
     }
   __syncthreads();
+  if (n >= 2 && wave == 0) make_reflector<T>(A, lda, n, 0, vbuf, taus, dd, ee);
+  if (n == 1 && tid == 0) dd[0] = re_of(A[0]);
+  __syncthreads();
 
   for (int k = 0; k + 1 < n; ++k) {
-    if (wave == 0) {
-      double xn2 = 0.0;
-      for (int r = k + 2 + lane; r < n; r += 64) xn2 += abs2(A[r * lda + k]);
-      xn2 = wave_sum(xn2);
-      const T alpha = A[(k + 1) * lda + k];
-      const double ar = re_of(alpha);
-      double beta;
-      T tau, scl;
-      if (xn2 == 0.0 && abs2(alpha) == ar * ar) {
-        beta = ar;
-        tau = T{};
-        scl = T{};
-      } else {
-        beta = -copysign(sqrt(abs2(alpha) + xn2), ar);
-        // tau = (beta - alpha)/beta, scl = 1/(alpha - beta)
-        const T amb = alpha - realv<T>(beta);
-        tau = St<T>::scale(-1.0 / beta, amb);
-        scl = cj(amb) * (1.0 / abs2(amb));
-      }
-      for (int r = k + 1 + lane; r < n; r += 64) {
-        const T vr = (r == k + 1) ? realv<T>(1.0) : A[r * lda + k] * scl;
-        vv[r] = vr;
-        A[r * lda + k] = vr;
-      }
-      if (lane == 0) {
-        taus[k] = tau;
-        dd[k] = re_of(A[k * lda + k]);
-        ee[k] = beta;
-      }
-    }
-    __syncthreads();
+    const T *vv = vbuf + (k & 1) * n;
+    T *vnext = vbuf + ((k + 1) & 1) * n;
     const T tau = taus[k];
     {
       const int r = k + 1 + (tid >> 3), s = tid & 7;
@@ -389,35 +546,44 @@ __global__ __launch_bounds__(EIG_T) void k_eig_tridiag(int n, EigWs w, const int
       if (lane == 0) red[wave] = contrib;
     }
     __syncthreads();
-    {
-      T pv = T{};
+    T pv = T{};
 #pragma unroll
-      for (int q = 0; q < EIG_T / 64; ++q) pv = pv + red[q];
-      const T K = St<T>::scale(-0.5, tau * pv);
+    for (int q = 0; q < EIG_T / 64; ++q) pv = pv + red[q];
+    const T K = St<T>::scale(-0.5, tau * pv);
+    const int c1 = k + 1;
+    if (wave == 0) {
+      // column k+1 of the updated matrix, then reflector k+1 from it
+      const T v1 = cj(vv[c1]), w1 = cj(pp[c1] + K * vv[c1]);
+      for (int r = c1 + lane; r < n; r += 64) {
+        const T vr = vv[r], wr = pp[r] + K * vv[r];
+        A[r * lda + c1] = A[r * lda + c1] - (vr * w1 + wr * v1);
+      }
+      if (c1 + 1 < n) make_reflector<T>(A, lda, n, c1, vnext, taus, dd, ee);
+      else if (lane == 0) dd[c1] = re_of(A[c1 * lda + c1]);
+    }
+    {
       T vc[4], wc[4];
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int c = tx + 32 * b;
-        const bool in = c > k && c < n;
+        const bool in = c > c1 && c < n;
         vc[b] = in ? cj(vv[c]) : T{};
         wc[b] = in ? cj(pp[c] + K * vv[c]) : T{};
       }
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const int r = ty + 32 * a;
-        if (r <= k || r >= n) continue;
+        if (r <= c1 || r >= n) continue;
         const T vr = vv[r], wr = pp[r] + K * vv[r];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const int c = tx + 32 * b;
-          if (c > k && c < n) A[r * lda + c] = A[r * lda + c] - (vr * wc[b] + wr * vc[b]);
+          if (c > c1 && c < n) A[r * lda + c] = A[r * lda + c] - (vr * wc[b] + wr * vc[b]);
         }
       }
     }
     __syncthreads();
   }
-  if (tid == 0) dd[n - 1] = re_of(A[(n - 1) * lda + n - 1]);
-  __syncthreads();
   T *tg = as<T>(w.tau);
   for (int i = tid; i < n; i += EIG_T) {
     w.d[i] = dd[i];
@@ -473,7 +639,7 @@ __global__ __launch_bounds__(256) void k_eig_values(int n, EigWs w, const int32_
   const double pivmin = DBL_MIN * fmax(1.0, emax2 * s2);
   double a = gl * s - (2.0 * DBL_EPSILON * tn + 2.0 * pivmin);
   double b = gu * s + (2.0 * DBL_EPSILON * tn + 2.0 * pivmin);
-  constexpr int K = 2;  // shifts per lane: 129-way multisection
+  constexpr int K = 1;  // shifts per lane: 65-way multisection
   for (int it = 0; it < 64; ++it) {
     const double width = b - a;
     if (width <= 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + pivmin) break;
@@ -554,6 +720,8 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
   double *u1 = scratch + 1 * n * VEC_T + t;
   double *u2 = scratch + 2 * n * VEC_T + t;
   double *y = scratch + 3 * n * VEC_T + t;
+  double *ml = scratch + 4 * n * VEC_T + t;  // < 0 where rows were swapped
+  double *ms = scratch + 5 * n * VEC_T + t;  // row multipliers
 #define AT(p, i) (p)[(i) * VEC_T]
   int lo = j, hi = j;
   while (lo > 0 && !split_at(d, e, lo - 1)) --lo;
@@ -569,8 +737,11 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
   const double tiny = DBL_EPSILON * fmax(tn, DBL_MIN);
 
   for (int i = 0; i < m; ++i) AT(y, i) = start_value(j, i);
-  for (int iter = 0; iter < 2; ++iter) {
-    // LU with partial pivoting of (T_block - x I), forward-eliminating y
+  // LU with partial pivoting of (T_block - x I) once, forward-eliminating y;
+  // the row multipliers (negative when the rows were swapped) are kept for
+  // the second solve and the pivots are stored as reciprocals, tiny pivots
+  // replaced by +-eps ||T||
+  {
     double c0 = d[lo] - x, c1 = (m > 1) ? e[lo] : 0.0;
     for (int i = 0; i + 1 < m; ++i) {
       const double n0 = e[lo + i], n1 = d[lo + i + 1] - x;
@@ -583,6 +754,8 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
         AT(u2, i) = n2;
         AT(y, i) = yn;
         AT(y, i + 1) = yi - l * yn;
+        AT(ml, i) = -1.0;
+        AT(ms, i) = l;
         c0 = c1 - l * n1;
         c1 = -l * n2;
       } else {
@@ -591,20 +764,39 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
         AT(u1, i) = c1;
         AT(u2, i) = 0.0;
         AT(y, i + 1) = yn - l * yi;
+        AT(ml, i) = 0.0;
+        AT(ms, i) = l;
         c0 = n1 - l * c1;
         c1 = n2;
       }
     }
     AT(u0, m - 1) = c0;
-    // back substitution, tiny pivots replaced by +-eps ||T||
+  }
+  for (int i = 0; i < m; ++i) {
+    double p = AT(u0, i);
+    if (fabs(p) < tiny) p = (p < 0.0) ? -tiny : tiny;
+    AT(u0, i) = 1.0 / p;
+  }
+  for (int iter = 0; iter < 2; ++iter) {
+    if (iter > 0) {
+      // replay the forward elimination on the new right-hand side
+      for (int i = 0; i + 1 < m; ++i) {
+        const double yi = AT(y, i), yn = AT(y, i + 1), l = AT(ms, i);
+        if (AT(ml, i) < 0.0) {
+          AT(y, i) = yn;
+          AT(y, i + 1) = yi - l * yn;
+        } else {
+          AT(y, i + 1) = yn - l * yi;
+        }
+      }
+    }
+    // back substitution with the reciprocal pivots
     double y1 = 0.0, y2 = 0.0, ymax = 0.0;
     for (int i = m - 1; i >= 0; --i) {
-      double p = AT(u0, i);
-      if (fabs(p) < tiny) p = (p < 0.0) ? -tiny : tiny;
       double sacc = AT(y, i);
       if (i + 1 < m) sacc -= AT(u1, i) * y1;
       if (i + 2 < m) sacc -= AT(u2, i) * y2;
-      const double yi = sacc / p;
+      const double yi = sacc * AT(u0, i);
       AT(y, i) = yi;
       y2 = y1;
       y1 = yi;
@@ -770,14 +962,14 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
   T *Linv = reinterpret_cast<T *>(w.Linv), *T1 = reinterpret_cast<T *>(w.T1);
   T *Am = reinterpret_cast<T *>(w.A), *U = reinterpret_cast<T *>(w.T1);
 
-  k_eig_chol<T><<<1, EIG_T, lda_bytes + n * sizeof(double), st>>>(Sd, n, w, info);
+  k_eig_chol<T><<<1, CH_T, chol_lds_bytes<T>(n), st>>>(Sd, n, w, info);
   // A = Linv ((H + H^H)/2) Linv^H
   k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Hd, 2, Linv, 1, T1, n, info);
   k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Linv, 0, T1, 0, Am, n, info);
-  k_eig_tridiag<T><<<1, EIG_T, lda_bytes + 3 * n * sizeof(T) + 2 * n * sizeof(double) + 16 * sizeof(T),
+  k_eig_tridiag<T><<<1, EIG_T, lda_bytes + 4 * n * sizeof(T) + 2 * n * sizeof(double) + 16 * sizeof(T),
                      st>>>(n, w, info);
   k_eig_values<<<(n + 3) / 4, 256, 3 * n * sizeof(double), st>>>(n, w, info);
-  k_eig_vectors<<<(n + VEC_T - 1) / VEC_T, VEC_T, (3 * n + 4 * n * VEC_T) * sizeof(double), st>>>(
+  k_eig_vectors<<<(n + VEC_T - 1) / VEC_T, VEC_T, (3 * n + 6 * n * VEC_T) * sizeof(double), st>>>(
       n, w, info);
   // two Newton-Schulz steps Z <- Z (3I - Z^T Z)/2 on the real tridiagonal
   // eigenvectors; the second Gram matrix must be within 1e-7 of I, so the
@@ -825,8 +1017,7 @@ int chol_inv_t(const gpaw_sys *s, const void *S, int n, void *Cout, int32_t *inf
   const int64_t nn = static_cast<int64_t>(n) * n;
   const unsigned eb = static_cast<unsigned>((nn + 255) / 256);
   if (!large) {
-    const size_t lda_bytes = (static_cast<size_t>(n) * (n + 1)) * sizeof(T);
-    k_eig_chol<T><<<1, EIG_T, lda_bytes + n * sizeof(double), st>>>(Sd, n, w, info);
+    k_eig_chol<T><<<1, CH_T, chol_lds_bytes<T>(n), st>>>(Sd, n, w, info);
   } else {
     k_set_info<<<1, 1, 0, st>>>(info);
     k_hermitize<T><<<eb, 256, 0, st>>>(Sd, as<T>(w.Sw), n, info);

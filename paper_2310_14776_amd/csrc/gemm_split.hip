@@ -92,156 +92,202 @@ template <> struct Parts<z32> {
   __device__ static float im(z32 a) { return a.y; }
 };
 
-// part[(split*nmat + mat)][nb][nb] (double / complex double) =
-//   sum_{k in range} conj(A[n][k]) B_mat[m][k]; BM x BM 16x16 blocks per wavefront
-template <typename T, int BM>
-__global__ __launch_bounds__(256) void k_subspace_split(const T *__restrict__ A,
-                                                        const T *__restrict__ B0,
-                                                        const T *__restrict__ B1,
-                                                        double *__restrict__ part, int nb,
-                                                        int64_t ng, int64_t kchunk, int tiles_n,
-                                                        int nmat) {
-  constexpr int TILE = 16 * BM;
-  constexpr int NP = Parts<T>::n;
-  __shared__ d4 red[2][NP][BM][BM][64];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x - tm * tiles_n;
-  const int mat = blockIdx.y;
-  const T *B = mat ? B1 : B0;
-  const int64_t kb = static_cast<int64_t>(blockIdx.z) * kchunk;
-  const int64_t ke = std::min(ng, kb + kchunk);
-  const int r = lane & 15, kq = lane >> 4;
+// ---------------------------------------------------------------------------
+// LDS-staged split products. A workgroup stages 32-wide K slices of both
+// operands in LDS, splitting every element once into its three BF16 parts
+// (planes h, m, l, each row padded to LROW values so that the 16-byte
+// fragment reads of a wavefront spread over the banks); the next slice is
+// fetched from global memory while the matrix cores work on the current one.
+// Workgroup ids are laid out so that the workgroups sharing an operand slice
+// (same K chunk for the subspace products, same grid columns for the
+// rotation) land on the same XCD and find it in that XCD's L2.
+constexpr int KS = 32;
+constexpr int LROW = 40;
 
-  const T *ap[BM];
-  const T *bp[BM];
-  bool av[BM], bv[BM];
+__device__ inline void split_to(float x, __bf16 &h, __bf16 &m, __bf16 &l) {
+  const uint32_t uh = bf16_rne(__float_as_uint(x));
+  const float r1 = x - __uint_as_float(uh);
+  const uint32_t um = bf16_rne(__float_as_uint(r1));
+  const float r2 = r1 - __uint_as_float(um);
+  h = top_half(uh);
+  m = top_half(um);
+  l = top_half(__float_as_uint(r2));
+}
+
+// eight consecutive values (real or one part of complex) -> three planes
+__device__ inline void split_store8(const float *x, __bf16 *ph, __bf16 *pm, __bf16 *pl) {
+  bf8 h, m, l;
 #pragma unroll
-  for (int q = 0; q < BM; ++q) {
-    const int ra = tm * TILE + q * 16 + r;
-    const int rb = tn * TILE + q * 16 + r;
-    av[q] = ra < nb;
-    bv[q] = rb < nb;
-    ap[q] = A + static_cast<int64_t>(av[q] ? ra : 0) * ng;
-    bp[q] = B + static_cast<int64_t>(bv[q] ? rb : 0) * ng;
+  for (int e = 0; e < 8; ++e) {
+    __bf16 a, b, c;
+    split_to(x[e], a, b, c);
+    h[e] = a;
+    m[e] = b;
+    l[e] = c;
   }
-  d4 dacc[NP][BM][BM];
-  f4 facc[NP][BM][BM];
+  *reinterpret_cast<bf8 *>(ph) = h;
+  *reinterpret_cast<bf8 *>(pm) = m;
+  *reinterpret_cast<bf8 *>(pl) = l;
+}
+
+// eight consecutive values p[0..7] (zero where e >= avail or !row_ok), as
+// 16-byte loads when the address allows
+template <typename T>
+__device__ inline void load8(const T *p, bool row_ok, int64_t avail, T *v) {
+  if (row_ok && avail >= 8 && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    constexpr int W = static_cast<int>(sizeof(T) * 8 / 16);  // 16-byte words
+    f4v w[W];
 #pragma unroll
-  for (int c = 0; c < NP; ++c)
+    for (int q = 0; q < W; ++q) w[q] = reinterpret_cast<const f4v *>(p)[q];
+    __builtin_memcpy(v, w, sizeof(T) * 8);
+  } else {
 #pragma unroll
-    for (int i = 0; i < BM; ++i)
+    for (int e = 0; e < 8; ++e) v[e] = (row_ok && e < avail) ? p[e] : T{};
+  }
+}
+
+__device__ inline Split8 frag(const __bf16 *plane0, int plane_stride, int off) {
+  Split8 f;
+  f.h = *reinterpret_cast<const bf8 *>(plane0 + off);
+  f.m = *reinterpret_cast<const bf8 *>(plane0 + plane_stride + off);
+  f.l = *reinterpret_cast<const bf8 *>(plane0 + 2 * plane_stride + off);
+  return f;
+}
+
+__device__ inline Split8 neg(Split8 a) {
+  a.h = -a.h;
+  a.m = -a.m;
+  a.l = -a.l;
+  return a;
+}
+
+// part[(split*nmat + mat)][nb][nb] (double / complex double) =
+//   sum_{k in chunk} conj(A[n][k]) B_mat[m][k].
+// Workgroup tile TM x TM (TM = 32 WT), four wavefronts in a 2 x 2 layout,
+// each owning WT x WT 16x16 blocks; FP32 tiles are added into FP64
+// accumulators after every 32-wide step.
+template <typename T, int WT>
+__global__ __launch_bounds__(256) void k_sub_lds(const T *__restrict__ A, const T *__restrict__ B0,
+                                                 const T *__restrict__ B1, double *__restrict__ part,
+                                                 int nb, int64_t ng, int64_t kchunk, int tiles_n,
+                                                 int nmat, int nsplit) {
+  constexpr int NP = Parts<T>::n;
+  constexpr int TM = 32 * WT;
+  constexpr int PS = TM * LROW;  // plane stride (bf16)
+  constexpr int RPP = 256 / 4;   // rows staged per pass (4 threads x 8 values per row)
+  __shared__ __attribute__((aligned(16))) __bf16 sA[3 * NP * PS];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[3 * NP * PS];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tiles = tiles_n * tiles_n, TT = tiles * nmat;
+  const int x = blockIdx.x & 7, jj = blockIdx.x >> 3;
+  const int split = (jj / TT) * 8 + x, tt = jj - (jj / TT) * TT;
+  if (split >= nsplit) return;
+  const int mat = tt / tiles, tile = tt - mat * tiles;
+  const int tm = tile / tiles_n, tn = tile - tm * tiles_n;
+  const T *B = mat ? B1 : B0;
+  const int64_t kb = static_cast<int64_t>(split) * kchunk;
+  const int64_t ke = std::min(ng, kb + kchunk);
+  const int nsteps = kb < ke ? static_cast<int>((ke - kb + KS - 1) / KS) : 0;
+
+  // staging: thread -> row r0 + RPP*pass, values k = 8c..8c+7 of the slice
+  const int sr = tid >> 2, sc = (tid & 3) * 8;
+  constexpr int PASSES = TM / RPP;
+  float ra[PASSES][NP][8], rbv[PASSES][NP][8];
+  auto fetch = [&](int step) {
+    const int64_t k0 = kb + static_cast<int64_t>(step) * KS + sc;
 #pragma unroll
-      for (int j = 0; j < BM; ++j) {
-        dacc[c][i][j] = d4{0.0, 0.0, 0.0, 0.0};
-        facc[c][i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-      }
-  // each wavefront takes every fourth 32-wide K step of the range
-  for (int64_t kg = kb + wave * 32; kg < ke; kg += 128) {
-    const int64_t k = kg + 8 * kq;
-    Split8 sa[NP][BM], sb[NP][BM];
-#pragma unroll
-    for (int q = 0; q < BM; ++q) {
-      float xr[8], xi[8], yr[8], yi[8];
+    for (int ps = 0; ps < PASSES; ++ps) {
+      const int rowa = tm * TM + ps * RPP + sr, rowb = tn * TM + ps * RPP + sr;
+      const T *pa = A + static_cast<int64_t>(rowa < nb ? rowa : 0) * ng;
+      const T *pb = B + static_cast<int64_t>(rowb < nb ? rowb : 0) * ng;
+      T va[8], vb[8];
+      load8(pa + k0, rowa < nb, ke - k0, va);
+      load8(pb + k0, rowb < nb, ke - k0, vb);
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const bool in = k + e < ke;
-        const T a = (av[q] && in) ? ap[q][k + e] : T{};
-        const T b = (bv[q] && in) ? bp[q][k + e] : T{};
-        xr[e] = Parts<T>::re(a);
-        xi[e] = Parts<T>::im(a);
-        yr[e] = Parts<T>::re(b);
-        yi[e] = Parts<T>::im(b);
-      }
-      sa[0][q] = split8(xr);
-      sb[0][q] = split8(yr);
-      if constexpr (NP == 2) {
-        sa[1][q] = split8(xi);
-        sb[1][q] = split8(yi);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < BM; ++i)
-#pragma unroll
-      for (int j = 0; j < BM; ++j) {
-        // conj(a) b: re = ar br + ai bi, im = ar bi - ai br
-        facc[0][i][j] = mm6(sa[0][i], sb[0][j], facc[0][i][j]);
+        ra[ps][0][e] = Parts<T>::re(va[e]);
+        rbv[ps][0][e] = Parts<T>::re(vb[e]);
         if constexpr (NP == 2) {
-          facc[0][i][j] = mm6(sa[1][i], sb[1][j], facc[0][i][j]);
-          facc[1][i][j] = mm6(sa[0][i], sb[1][j], facc[1][i][j]);
-          Split8 nai = sa[1][i];
-          nai.h = -nai.h;
-          nai.m = -nai.m;
-          nai.l = -nai.l;
-          facc[1][i][j] = mm6(nai, sb[0][j], facc[1][i][j]);
+          ra[ps][NP - 1][e] = Parts<T>::im(va[e]);
+          rbv[ps][NP - 1][e] = Parts<T>::im(vb[e]);
         }
       }
-    {
-#pragma unroll
-      for (int c = 0; c < NP; ++c)
-#pragma unroll
-        for (int i = 0; i < BM; ++i)
-#pragma unroll
-          for (int j = 0; j < BM; ++j) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) dacc[c][i][j][e] += static_cast<double>(facc[c][i][j][e]);
-            facc[c][i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-          }
     }
-  }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps)
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+        const int o = (c * 3) * PS + (ps * RPP + sr) * LROW + sc;
+        split_store8(ra[ps][c], sA + o, sA + o + PS, sA + o + 2 * PS);
+        split_store8(rbv[ps][c], sB + o, sB + o + PS, sB + o + 2 * PS);
+      }
+  };
+
+  const int wr = wave >> 1, wc = wave & 1;
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  d4 dacc[NP][WT][WT];
 #pragma unroll
   for (int c = 0; c < NP; ++c)
 #pragma unroll
-    for (int i = 0; i < BM; ++i)
+    for (int i = 0; i < WT; ++i)
 #pragma unroll
-      for (int j = 0; j < BM; ++j)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) dacc[c][i][j][e] += static_cast<double>(facc[c][i][j][e]);
+      for (int j = 0; j < WT; ++j) dacc[c][i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  // fixed-order sum of the four wavefronts' tiles: (w0 + w2) + (w1 + w3)
-  if (wave >= 2)
+  if (nsteps > 0) fetch(0);
+  for (int step = 0; step < nsteps; ++step) {
+    __syncthreads();
+    stage();
+    __syncthreads();
+    if (step + 1 < nsteps) fetch(step + 1);
+    Split8 fa[NP][WT];
 #pragma unroll
-    for (int c = 0; c < NP; ++c)
+    for (int i = 0; i < WT; ++i)
 #pragma unroll
-      for (int i = 0; i < BM; ++i)
+      for (int c = 0; c < NP; ++c)
+        fa[c][i] = frag(sA + (c * 3) * PS, PS, (wr * 16 * WT + i * 16 + fr) * LROW + fk);
 #pragma unroll
-        for (int j = 0; j < BM; ++j) red[wave - 2][c][i][j][lane] = dacc[c][i][j];
-  __syncthreads();
-  if (wave < 2)
+    for (int j = 0; j < WT; ++j) {
+      Split8 fb[NP];
 #pragma unroll
-    for (int c = 0; c < NP; ++c)
+      for (int c = 0; c < NP; ++c)
+        fb[c] = frag(sB + (c * 3) * PS, PS, (wc * 16 * WT + j * 16 + fr) * LROW + fk);
 #pragma unroll
-      for (int i = 0; i < BM; ++i)
+      for (int i = 0; i < WT; ++i) {
+        const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+        // conj(a) b: re = ar br + ai bi, im = ar bi - ai br
+        f4 re = mm6(fa[0][i], fb[0], z);
+        if constexpr (NP == 2) {
+          re = mm6(fa[1][i], fb[1], re);
+          f4 im = mm6(fa[0][i], fb[1], z);
+          im = mm6(neg(fa[1][i]), fb[0], im);
 #pragma unroll
-        for (int j = 0; j < BM; ++j) dacc[c][i][j] += red[wave][c][i][j][lane];
-  __syncthreads();
-  if (wave == 1)
+          for (int e = 0; e < 4; ++e) dacc[1][i][j][e] += static_cast<double>(im[e]);
+        }
 #pragma unroll
-    for (int c = 0; c < NP; ++c)
+        for (int e = 0; e < 4; ++e) dacc[0][i][j][e] += static_cast<double>(re[e]);
+      }
+    }
+  }
+
+  double *out = part + (static_cast<int64_t>(split) * nmat + mat) * nb * nb * NP;
 #pragma unroll
-      for (int i = 0; i < BM; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int j = 0; j < BM; ++j) red[0][c][i][j][lane] = dacc[c][i][j];
-  __syncthreads();
-  if (wave == 0) {
-    double *out = part + (static_cast<int64_t>(blockIdx.z) * nmat + mat) * nb * nb * NP;
+    for (int j = 0; j < WT; ++j) {
+      const int col = tn * TM + wc * 16 * WT + j * 16 + (lane & 15);
 #pragma unroll
-    for (int i = 0; i < BM; ++i)
-#pragma unroll
-      for (int j = 0; j < BM; ++j) {
-        const d4 vr = dacc[0][i][j] + red[0][0][i][j][lane];
-        const d4 vi = dacc[NP - 1][i][j] + red[0][NP - 1][i][j][lane];
-        const int col = tn * TILE + j * 16 + (lane & 15);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int row = tm * TILE + i * 16 + 4 * (lane >> 4) + e;
-          if (row < nb && col < nb) {
-            const int64_t o = (static_cast<int64_t>(row) * nb + col) * NP;
-            out[o] = vr[e];
-            if constexpr (NP == 2) out[o + 1] = vi[e];
-          }
+      for (int e = 0; e < 4; ++e) {
+        const int row = tm * TM + wr * 16 * WT + i * 16 + 4 * (lane >> 4) + e;
+        if (row < nb && col < nb) {
+          const int64_t o = (static_cast<int64_t>(row) * nb + col) * NP;
+          out[o] = dacc[0][i][j][e];
+          if constexpr (NP == 2) out[o + 1] = dacc[NP - 1][i][j][e];
         }
       }
-  }
+    }
 }
 
 template <int NP>
@@ -285,180 +331,225 @@ __global__ __launch_bounds__(256) void k_split_c(const double *__restrict__ C, _
   }
 }
 
-// out[n][g] = sum_m C[m][n] src[m][g] (no conjugation): A[i=n][k=m] from the
-// transposed planes, B[k=m][j=g] split on the fly. Each wavefront owns
-// RB*16 rows (row group blockIdx.y) by 32 columns.
-template <typename T, int RB>
-__global__ __launch_bounds__(256) void k_rotate_split(const __bf16 *__restrict__ Ct,
-                                                      const T *__restrict__ src,
-                                                      T *__restrict__ dst, int nb, int64_t cols) {
+// out[n][g] = sum_m C[m][n] src[m][g] (no conjugation). A[i=n][k=m] comes
+// from the pre-split transposed planes of C; the src slice (32 rows m x TN
+// columns g) is split once and stored column-major in LDS, so that the B
+// fragment B[k=m][j=g] of a lane is eight consecutive values. FP32 tiles are
+// added into FP64 accumulators every 8 steps.
+template <typename T, int WT>
+__global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
+                                                 const T *__restrict__ src, T *__restrict__ dst,
+                                                 int nb, int64_t cols, int ntiles_n,
+                                                 int64_t gtiles) {
   constexpr int NP = Parts<T>::n;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int j = lane & 15, kq = lane >> 4;
-  const int64_t g0 = static_cast<int64_t>(blockIdx.x) * 128 + wave * 32;
-  const int n0 = blockIdx.y * RB * 16;
+  constexpr int TM = 32 * WT;
+  constexpr int PS = TM * LROW;
+  __shared__ __attribute__((aligned(16))) __bf16 sA[3 * NP * PS];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[3 * NP * PS];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int x = blockIdx.x & 7;
+  const int64_t jj = blockIdx.x >> 3;
+  const int ntile = static_cast<int>(jj % ntiles_n);
+  const int64_t gtile = (jj / ntiles_n) * 8 + x;
+  if (gtile >= gtiles) return;
   const int64_t nn = static_cast<int64_t>(nb) * nb;
-  int64_t gc[2];
-  bool gv[2];
+  const int n0 = ntile * TM;
+  const int64_t g0 = gtile * TM;
+  const int nsteps = (nb + KS - 1) / KS;
+
+  // A staging: row n = n0 + tid/4 (+64 per pass), 8 values m = 8c..8c+7 per plane
+  constexpr int PASSES = TM / 64;
+  const int sr = tid >> 2, sc = (tid & 3) * 8;
+  bf8 ca[PASSES][NP][3];
+  // B staging: column g = g0 + (tid % TM), values m = mh*MPT .. +MPT-1
+  constexpr int MPT = KS * TM / 256;  // real 16, complex 8
+  const int bg = tid % TM, bm = (tid / TM) * MPT;
+  float rb[NP][MPT];
+  auto fetch = [&](int step) {
+    const int m0 = step * KS;
 #pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
-    gc[cb] = g0 + cb * 16 + j;
-    gv[cb] = gc[cb] < cols;
-  }
-  d4 dacc[NP][RB][2];
-  f4 facc[NP][RB][2];
-#pragma unroll
-  for (int c = 0; c < NP; ++c)
-#pragma unroll
-    for (int i = 0; i < RB; ++i)
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        dacc[c][i][q] = d4{0.0, 0.0, 0.0, 0.0};
-        facc[c][i][q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-      }
-  int steps = 0;
-  for (int m0 = 0; m0 < nb; m0 += 32) {
-    const int mb = m0 + 8 * kq;
-    Split8 sa[NP][RB], sb[NP][2];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const int n = n0 + rb * 16 + j;
-#pragma unroll
-      for (int c = 0; c < NP; ++c) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const bool in = n < nb && mb + e < nb;
-          const int64_t t = static_cast<int64_t>(n) * nb + mb + e;
-          const __bf16 zero = top_half(0u);
-          sa[c][rb].h[e] = in ? Ct[(3 * c + 0) * nn + t] : zero;
-          sa[c][rb].m[e] = in ? Ct[(3 * c + 1) * nn + t] : zero;
-          sa[c][rb].l[e] = in ? Ct[(3 * c + 2) * nn + t] : zero;
-        }
-      }
-    }
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      float xr[8], xi[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const bool in = gv[cb] && mb + e < nb;
-        const T v = in ? src[static_cast<int64_t>(mb + e) * cols + gc[cb]] : T{};
-        xr[e] = Parts<T>::re(v);
-        xi[e] = Parts<T>::im(v);
-      }
-      sb[0][cb] = split8(xr);
-      if constexpr (NP == 2) sb[1][cb] = split8(xi);
-    }
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        // C psi: re = Cr pr - Ci pi, im = Cr pi + Ci pr
-        facc[0][rb][cb] = mm6(sa[0][rb], sb[0][cb], facc[0][rb][cb]);
-        if constexpr (NP == 2) {
-          Split8 nci = sa[1][rb];
-          nci.h = -nci.h;
-          nci.m = -nci.m;
-          nci.l = -nci.l;
-          facc[0][rb][cb] = mm6(nci, sb[1][cb], facc[0][rb][cb]);
-          facc[1][rb][cb] = mm6(sa[0][rb], sb[1][cb], facc[1][rb][cb]);
-          facc[1][rb][cb] = mm6(sa[1][rb], sb[0][cb], facc[1][rb][cb]);
-        }
-      }
-    if (++steps == 8) {
-      steps = 0;
+    for (int ps = 0; ps < PASSES; ++ps) {
+      const int n = n0 + ps * 64 + sr;
 #pragma unroll
       for (int c = 0; c < NP; ++c)
 #pragma unroll
-        for (int i = 0; i < RB; ++i)
+        for (int p = 0; p < 3; ++p) {
+          const __bf16 *q = Ct + (3 * c + p) * nn + static_cast<int64_t>(n) * nb + m0 + sc;
+          bf8 v;
+          if (n < nb && m0 + sc + 8 <= nb && (reinterpret_cast<uintptr_t>(q) & 15) == 0) {
+            v = *reinterpret_cast<const bf8 *>(q);
+          } else {
 #pragma unroll
-          for (int q = 0; q < 2; ++q) {
+            for (int e = 0; e < 8; ++e) v[e] = (n < nb && m0 + sc + e < nb) ? q[e] : top_half(0u);
+          }
+          ca[ps][c][p] = v;
+        }
+    }
+    const int64_t g = g0 + bg;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) dacc[c][i][q][e] += static_cast<double>(facc[c][i][q][e]);
-            facc[c][i][q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int e = 0; e < MPT; ++e) {
+      const int m = m0 + bm + e;
+      const T v = (g < cols && m < nb) ? src[static_cast<int64_t>(m) * cols + g] : T{};
+      rb[0][e] = Parts<T>::re(v);
+      if constexpr (NP == 2) rb[NP - 1][e] = Parts<T>::im(v);
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps)
+#pragma unroll
+      for (int c = 0; c < NP; ++c)
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+          *reinterpret_cast<bf8 *>(sA + (c * 3 + p) * PS + (ps * 64 + sr) * LROW + sc) = ca[ps][c][p];
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+#pragma unroll
+      for (int h = 0; h < MPT / 8; ++h) {
+        const int o = (c * 3) * PS + bg * LROW + bm + 8 * h;
+        split_store8(rb[c] + 8 * h, sB + o, sB + o + PS, sB + o + 2 * PS);
+      }
+  };
+
+  const int wr = wave >> 1, wc = wave & 1;
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  d4 dacc[NP][WT][WT];
+  f4 facc[NP][WT][WT];
+#pragma unroll
+  for (int c = 0; c < NP; ++c)
+#pragma unroll
+    for (int i = 0; i < WT; ++i)
+#pragma unroll
+      for (int j = 0; j < WT; ++j) {
+        dacc[c][i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        facc[c][i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+      }
+  fetch(0);
+  for (int step = 0; step < nsteps; ++step) {
+    __syncthreads();
+    stage();
+    __syncthreads();
+    if (step + 1 < nsteps) fetch(step + 1);
+    Split8 fa[NP][WT];
+#pragma unroll
+    for (int i = 0; i < WT; ++i)
+#pragma unroll
+      for (int c = 0; c < NP; ++c)
+        fa[c][i] = frag(sA + (c * 3) * PS, PS, (wr * 16 * WT + i * 16 + fr) * LROW + fk);
+#pragma unroll
+    for (int j = 0; j < WT; ++j) {
+      Split8 fb[NP];
+#pragma unroll
+      for (int c = 0; c < NP; ++c)
+        fb[c] = frag(sB + (c * 3) * PS, PS, (wc * 16 * WT + j * 16 + fr) * LROW + fk);
+#pragma unroll
+      for (int i = 0; i < WT; ++i) {
+        // C psi: re = Cr pr - Ci pi, im = Cr pi + Ci pr
+        facc[0][i][j] = mm6(fa[0][i], fb[0], facc[0][i][j]);
+        if constexpr (NP == 2) {
+          facc[0][i][j] = mm6(neg(fa[1][i]), fb[1], facc[0][i][j]);
+          facc[1][i][j] = mm6(fa[0][i], fb[1], facc[1][i][j]);
+          facc[1][i][j] = mm6(fa[1][i], fb[0], facc[1][i][j]);
+        }
+      }
+    }
+    if ((step & 7) == 7 || step + 1 == nsteps) {
+#pragma unroll
+      for (int c = 0; c < NP; ++c)
+#pragma unroll
+        for (int i = 0; i < WT; ++i)
+#pragma unroll
+          for (int j = 0; j < WT; ++j) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dacc[c][i][j][e] += static_cast<double>(facc[c][i][j][e]);
+            facc[c][i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
           }
     }
   }
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      if (!gv[cb]) continue;
+    for (int j = 0; j < WT; ++j) {
+      const int64_t g = g0 + wc * 16 * WT + j * 16 + (lane & 15);
+      if (g >= cols) continue;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int n = n0 + rb * 16 + 4 * kq + e;
+        const int n = n0 + wr * 16 * WT + i * 16 + 4 * (lane >> 4) + e;
         if (n >= nb) continue;
-        const double vr = dacc[0][rb][cb][e] + static_cast<double>(facc[0][rb][cb][e]);
-        T out;
-        if constexpr (NP == 2) {
-          const double vi = dacc[1][rb][cb][e] + static_cast<double>(facc[1][rb][cb][e]);
-          out = T{static_cast<float>(vr), static_cast<float>(vi)};
-        } else {
-          out = static_cast<float>(vr);
-        }
-        dst[static_cast<int64_t>(n) * cols + gc[cb]] = out;
+        T o;
+        if constexpr (NP == 2) o = T{static_cast<float>(dacc[0][i][j][e]), static_cast<float>(dacc[1][i][j][e])};
+        else o = static_cast<float>(dacc[0][i][j][e]);
+        dst[static_cast<int64_t>(n) * cols + g] = o;
       }
     }
 }
-
 struct SplitPlanS {
   int tiles_n, tiles, nsplit;
   int64_t kchunk;
 };
 
+// split-K over ~512 workgroups, chunks a multiple of 32, split count a
+// multiple of 8 (one group of splits per XCD)
 SplitPlanS plan_split(int nb, int64_t ng, int nmat, int tile) {
   SplitPlanS p;
   p.tiles_n = (nb + tile - 1) / tile;
   p.tiles = p.tiles_n * p.tiles_n;
-  const int64_t want = std::max<int64_t>(1, 512 / (p.tiles * nmat));
-  const int64_t kmax_split = std::max<int64_t>(1, ng / 2048);
-  const int64_t nsplit = std::min(want, kmax_split);
+  const int64_t want = std::max<int64_t>(8, 512 / (p.tiles * nmat));
+  const int64_t kmax_split = std::max<int64_t>(1, ng / 256);
+  int64_t nsplit = std::max<int64_t>(1, std::min(want, kmax_split));
   int64_t kchunk = (ng + nsplit - 1) / nsplit;
-  kchunk = (kchunk + 127) / 128 * 128;
+  kchunk = (kchunk + KS - 1) / KS * KS;
+  nsplit = (ng + kchunk - 1) / kchunk;
   p.kchunk = kchunk;
-  p.nsplit = static_cast<int>((ng + kchunk - 1) / kchunk);
+  p.nsplit = static_cast<int>(nsplit);
   return p;
 }
 
-template <typename T, int BM>
+template <typename T, int WT>
 int subspace_split_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
                      int nb, void *H, void *S, hipStream_t st) {
   constexpr int NP = Parts<T>::n;
   const int nmat = Spsi ? 2 : 1;
-  const SplitPlanS p = plan_split(nb, s->ng, nmat, 16 * BM);
+  const SplitPlanS p = plan_split(nb, s->ng, nmat, 32 * WT);
   const int64_t need = static_cast<int64_t>(p.nsplit) * nmat * nb * nb * NP;
   if (need > static_cast<int64_t>(s->ws.part_elems))
     return fail(GPAW_EINVAL, "subspace workspace too small");
-  dim3 grid(p.tiles, nmat, p.nsplit);
-  k_subspace_split<T, BM><<<grid, 256, 0, st>>>(
+  const int64_t groups = (p.nsplit + 7) / 8;
+  const int64_t wgs = groups * 8 * p.tiles * nmat;
+  k_sub_lds<T, WT><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
       static_cast<const T *>(psi), static_cast<const T *>(Hpsi),
       static_cast<const T *>(Spsi ? Spsi : Hpsi), s->ws.part, nb, s->ng, p.kchunk, p.tiles_n,
-      nmat);
+      nmat, p.nsplit);
   const int64_t tot = static_cast<int64_t>(nb) * nb * nmat * NP;
   k_split_reduce<NP><<<static_cast<unsigned>((tot + 255) / 256), 256, 0, st>>>(
       s->ws.part, static_cast<double *>(H), static_cast<double *>(S), nb, p.nsplit, nmat, s->dV);
   return GPAW_OK;
 }
 
-template <typename T, int RB>
+template <typename T, int WT>
 int rotate_split_t(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
                    void *dst, hipStream_t st) {
   constexpr int NP = Parts<T>::n;
+  constexpr int TM = 32 * WT;
   __bf16 *Ct = reinterpret_cast<__bf16 *>(s->ws.split);
   const int64_t nn = static_cast<int64_t>(nb) * nb;
   k_split_c<NP><<<static_cast<unsigned>((nn + 255) / 256), 256, 0, st>>>(
       static_cast<const double *>(C), Ct, nb);
-  dim3 grid(static_cast<unsigned>((cols + 127) / 128), (nb + RB * 16 - 1) / (RB * 16));
-  k_rotate_split<T, RB><<<grid, 256, 0, st>>>(Ct, static_cast<const T *>(src),
-                                              static_cast<T *>(dst), nb, cols);
+  const int ntiles_n = (nb + TM - 1) / TM;
+  const int64_t gtiles = (cols + TM - 1) / TM;
+  const int64_t wgs = (gtiles + 7) / 8 * 8 * ntiles_n;
+  k_rot_lds<T, WT><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
+      Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, cols, ntiles_n, gtiles);
   return GPAW_OK;
 }
 
 }  // namespace
 
 size_t split_part_elems(int nb, bool cplx) {
-  const int64_t tile = cplx ? 32 : 64;
-  const int64_t bound = std::max<int64_t>(512 * tile * tile, 2 * int64_t(nb) * nb);
+  // nsplit * tiles * nmat stays within 512 (rounded up to whole groups of 8
+  // splits) unless a single split is already larger
+  const int64_t tile = cplx ? 64 : 128;
+  const int64_t bound = std::max<int64_t>(1024 * tile * tile, 16 * int64_t(nb) * nb);
   return static_cast<size_t>(bound) * (cplx ? 2 : 1);
 }
 

@@ -140,8 +140,8 @@ struct Tables {
   int32_t *a_start = nullptr;  // [natoms+1] atom-major entry ranges
   int32_t *e_g = nullptr;      // [nent] folded grid index (atom-major)
   short4 *e_xyz = nullptr;     // [nent] unwrapped grid indices + image code (atom-major)
-  int2 *pinfo = nullptr;       // [Ng] {code of the point's first entry,
-                               //       count << 24 | index of that entry}
+  int4 *pinfo = nullptr;       // [Ng] {codes of the point's first three
+                               //       entries, count << 24 | index of the first}
   int32_t *pm_code = nullptr;  // [nent] atom << 12 | image code (point-major)
   double *pos = nullptr;       // [natoms][3] atom positions
   ProjDev *proj = nullptr;     // device copy of the projector parameters

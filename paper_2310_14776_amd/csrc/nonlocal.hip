@@ -40,7 +40,14 @@ __global__ __launch_bounds__(256) void k_project(const T *__restrict__ psi, T *_
                                                  const double *__restrict__ pos,
                                                  const ProjDev *__restrict__ pjp,
                                                  int64_t ng, int nb, int np, double dV) {
-  const ProjDev &pj = *pjp;
+  typename PJSel<NI>::type pj = PJSel<NI>::get(pjp);
+  // per-axis image phases in LDS (complex only): divergent indices stay off
+  // global memory
+  __shared__ z64 phs[48];
+  if (St<T>::cplx) {
+    for (int idx = threadIdx.x; idx < 48; idx += 256) phs[idx] = pjp->ph[idx / 16][idx % 16];
+    __syncthreads();
+  }
   const int atom = blockIdx.x;
   const int b0 = blockIdx.y * NBG;
   const int e0 = a_start[atom], e1 = a_start[atom + 1];
@@ -60,11 +67,12 @@ __global__ __launch_bounds__(256) void k_project(const T *__restrict__ psi, T *_
     for (int b = 0; b < NBG; ++b)
       p[b] = St<T>::widen((b0 + b < nb) ? psi[static_cast<int64_t>(b0 + b) * ng + g] : St<T>::zero());
     double pv[NI];
-    eval_proj<NI>(pj, u.x * pj.h[0] - R0, u.y * pj.h[1] - R1, u.z * pj.h[2] - R2, pv);
+    if constexpr (NI == 13) eval_proj13(pj, u.x * pj.h[0] - R0, u.y * pj.h[1] - R1, u.z * pj.h[2] - R2, pv);
+    else eval_proj<NI>(pj, u.x * pj.h[0] - R0, u.y * pj.h[1] - R1, u.z * pj.h[2] - R2, pv);
     if (St<T>::cplx) {
       // conj(q) psi = p(r) conj(exp(-2 pi i k.w)) psi
       const int c = u.w;
-      const z64 ph = zconj(image_phase(pj, ((c >> 8) & 15) - 8, ((c >> 4) & 15) - 8, (c & 15) - 8));
+      const z64 ph = zconj(phs[((c >> 8) & 15)] * phs[16 + ((c >> 4) & 15)] * phs[32 + (c & 15)]);
 #pragma unroll
       for (int b = 0; b < NBG; ++b) p[b] = St<A>::phase(p[b], ph);
     }
@@ -86,8 +94,9 @@ __global__ __launch_bounds__(256) void k_project(const T *__restrict__ psi, T *_
   __syncthreads();
   for (int idx = threadIdx.x; idx < NBG * NI; idx += 256) {
     const int b = idx / NI, i = idx - b * NI;
-    if (b0 + b < nb && i < pj.ni)
-      P[static_cast<int64_t>(b0 + b) * np + atom * pj.ni + i] = St<T>::narrow(
+    const int ni = NI == 13 ? 13 : pjp->ni;
+    if (b0 + b < nb && i < ni)
+      P[static_cast<int64_t>(b0 + b) * np + atom * ni + i] = St<T>::narrow(
           St<A>::scale(dV, (red[0][idx] + red[1][idx]) + (red[2][idx] + red[3][idx])));
   }
 }

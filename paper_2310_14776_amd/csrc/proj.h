@@ -99,6 +99,76 @@ __device__ inline void eval_proj(const ProjDev &P, double x, double y, double z,
   }
 }
 
+// Parameters of the straight-line layout copied once per kernel into
+// registers (uniform values), so the inner loops issue no scalar loads.
+struct Proj13 {
+  double norm[5], rc2inv[5], a2[2];
+  bool sel1[5];  // channel c uses the Gaussian of channel 1 (else of channel 0)
+  int n[3];
+  double h[3];
+};
+
+__device__ inline Proj13 load_proj13(const ProjDev &P) {
+  Proj13 q;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    q.norm[c] = P.norm[c];
+    q.rc2inv[c] = P.rc2inv[c];
+    q.sel1[c] = c == 1 || (c >= 2 && P.same_sigma[c] == 1);
+  }
+  q.a2[0] = P.a2[0];
+  q.a2[1] = P.a2[1];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    q.n[c] = P.n[c];
+    q.h[c] = P.h[c];
+  }
+  return q;
+}
+
+// the 13 projector values of one atom at displacement (x, y, z)
+__device__ inline void eval_proj13(const Proj13 &P, double x, double y, double z, double *out) {
+  constexpr double c0 = 0.28209479177387814;
+  constexpr double c1 = 0.48860251190291992;
+  constexpr double c2 = 1.0925484305920792;
+  constexpr double c20 = 0.31539156525252005;
+  constexpr double c22 = 0.54627421529603959;
+  const double r2 = x * x + y * y + z * z;
+  const double E0 = exp(-r2 * P.a2[0]), E1 = exp(-r2 * P.a2[1]);
+  double rad[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    const double s2 = r2 * P.rc2inv[c];
+    const double t = 1.0 - s2;
+    rad[c] = s2 < 1.0 ? P.norm[c] * (P.sel1[c] ? E1 : E0) * (t * t) : 0.0;
+  }
+  out[0] = rad[0] * c0;
+  out[1] = rad[1] * c0;
+  const double py = c1 * y, pz = c1 * z, px = c1 * x;
+  out[2] = rad[2] * py;
+  out[3] = rad[2] * pz;
+  out[4] = rad[2] * px;
+  out[5] = rad[3] * py;
+  out[6] = rad[3] * pz;
+  out[7] = rad[3] * px;
+  out[8] = rad[4] * (c2 * x * y);
+  out[9] = rad[4] * (c2 * y * z);
+  out[10] = rad[4] * (c20 * (3.0 * z * z - r2));
+  out[11] = rad[4] * (c2 * x * z);
+  out[12] = rad[4] * (c22 * (x * x - y * y));
+}
+
+// Projector parameters as the kernels hold them: a register copy for the
+// 13-projector layout, the device table otherwise.
+template <int NI> struct PJSel {
+  using type = const ProjDev &;
+  __device__ static const ProjDev &get(const ProjDev *p) { return *p; }
+};
+template <> struct PJSel<13> {
+  using type = Proj13;
+  __device__ static Proj13 get(const ProjDev *p) { return load_proj13(*p); }
+};
+
 // Bloch phase exp(-2 pi i k.w) of an image shift w (grid-cell units).
 __device__ inline z64 image_phase(const ProjDev &P, int wx, int wy, int wz) {
   return P.ph[0][wx + 8] * P.ph[1][wy + 8] * P.ph[2][wz + 8];

@@ -32,7 +32,7 @@ struct StencilGeom {
 };
 
 struct AddArgs {
-  const int2 *pinfo;       // [Ng] first entry code, count << 24 | first index
+  const int4 *pinfo;       // [Ng] first three entry codes, count << 24 | first index
   const int32_t *pm_code;  // atom << 12 | image code
   const double *pos;       // [natoms][3]
   const void *X;           // [nb][Np] Delta.P
@@ -60,35 +60,46 @@ __device__ inline int clamp3(int w) { return w < -3 ? -3 : (w > 3 ? 3 : w); }
 // The projector values of an entry are evaluated once and reused for every
 // band; X rows of the band group and the atom positions come from LDS when
 // they fit (generic pointers otherwise).
-template <typename T, int NI, int NB>
-__device__ inline void addback_group(const AddArgs &ab, int2 pi, int ix, int iy, int iz,
-                                     const double *pos, const T *Xs, int ldx, int b0, int nb,
+template <typename T, int NI, int NB, typename PJ>
+__device__ inline void addback_group(const AddArgs &ab, const PJ &pj, int4 pi, int ix, int iy,
+                                     int iz, const double *pos, const z64 *phs, const T *Xs,
+                                     int ldx, int ni, int b0, int nb,
                                      typename St<T>::Acc *acc) {
   using A = typename St<T>::Acc;
-  const int cnt = static_cast<int>(static_cast<unsigned>(pi.y) >> 24);
-  const int first = pi.y & 0xFFFFFF;
-  const ProjDev &pj = *ab.pj;
+  constexpr bool FIXED = NI == 13;
+  const int cnt = static_cast<int>(static_cast<unsigned>(pi.w) >> 24);
+  const int first = pi.w & 0xFFFFFF;
   for (int j = 0; j < cnt; ++j) {
-    const int code = j == 0 ? pi.x : ab.pm_code[first + j];
+    const int code = j == 0 ? pi.x : (j == 1 ? pi.y : (j == 2 ? pi.z : ab.pm_code[first + j]));
     const int a = code >> 12;
     const int wx = ((code >> 8) & 15) - 8, wy = ((code >> 4) & 15) - 8, wz = (code & 15) - 8;
     const double *R = pos + 3 * a;
+    const double dx = (ix + wx * pj.n[0]) * pj.h[0] - R[0];
+    const double dy = (iy + wy * pj.n[1]) * pj.h[1] - R[1];
+    const double dz = (iz + wz * pj.n[2]) * pj.h[2] - R[2];
     double pv[NI];
-    eval_proj<NI>(pj, (ix + wx * pj.n[0]) * pj.h[0] - R[0], (iy + wy * pj.n[1]) * pj.h[1] - R[1],
-                  (iz + wz * pj.n[2]) * pj.h[2] - R[2], pv);
+    if constexpr (FIXED) eval_proj13(pj, dx, dy, dz, pv);
+    else eval_proj<NI>(pj, dx, dy, dz, pv);
     z64 ph = zmake(1.0, 0.0);
-    if (St<T>::cplx) ph = image_phase(pj, wx, wy, wz);
+    if (St<T>::cplx) ph = phs[wx + 8] * phs[16 + wy + 8] * phs[32 + wz + 8];
+    const T *Xa = Xs + a * (FIXED ? 13 : ni);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       if (b0 + b >= nb) continue;
-      const T *Xb = Xs + static_cast<int64_t>(b) * ldx + a * pj.ni;
+      const T *Xb = Xa + static_cast<int64_t>(b) * ldx;
       A sum = St<A>::zero();
 #pragma unroll
       for (int i = 0; i < NI; ++i)
-        if (i < pj.ni) sum = sum + St<A>::scale(pv[i], St<T>::widen(Xb[i]));
+        if (FIXED || i < ni) sum = sum + St<A>::scale(pv[i], St<T>::widen(Xb[i]));
       acc[b] = acc[b] + St<A>::phase(sum, ph);
     }
   }
+}
+
+// Per-axis image phases exp(-2 pi i k_c w), w = -8..7, into LDS (complex only)
+__device__ inline const z64 *stage_phases(const AddArgs &ab, z64 *lds) {
+  for (int idx = threadIdx.x; idx < 48; idx += blockDim.x) lds[idx] = ab.pj->ph[idx / 16][idx % 16];
+  return lds;
 }
 
 // Atom positions into LDS (when they fit), else the global array.
@@ -126,8 +137,13 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil(const T *__restrict__ ps
   // X rows of this band group and the atom positions, staged in LDS
   const T *Xs = static_cast<const T *>(ab.X) + static_cast<int64_t>(b0) * ab.np;
   const double *pos = ab.pos;
+  const z64 *phs = nullptr;
   if (ADD) {
     T *after = reinterpret_cast<T *>(smem);
+    if (St<T>::cplx) {
+      phs = stage_phases(ab, reinterpret_cast<z64 *>(smem));
+      after = reinterpret_cast<T *>(smem + 48 * sizeof(z64));
+    }
     if (XLDS) {
       stage_x<T, NB>(ab, b0, nb, after);
       Xs = after;
@@ -137,6 +153,8 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil(const T *__restrict__ ps
                     ab.natoms);
     __syncthreads();
   }
+  typename PJSel<NI>::type pj = PJSel<NI>::get(ab.pj);
+  const int ni = NI == 13 ? 13 : ab.pj->ni;
   const int f = blockIdx.x * ST_THREADS + t;
   if (f >= plane) return;
   const int y = f / n2, z = f - (f / n2) * n2;
@@ -193,7 +211,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil(const T *__restrict__ ps
     A acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = St<A>::zero();
-    if (ADD) addback_group<T, NI, NB>(ab, ab.pinfo[g], x, y, z, pos, Xs, ab.np, b0, nb, acc);
+    if (ADD) addback_group<T, NI, NB>(ab, pj, ab.pinfo[g], x, y, z, pos, phs, Xs, ab.np, ni, b0, nb, acc);
     const double cv = G.c0 + v[g];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -232,8 +250,13 @@ __global__ __launch_bounds__(256) void k_apply_S(const T *__restrict__ psi, T *_
   const int b0 = blockIdx.y * NB;
   const T *Xs = static_cast<const T *>(ab.X) + static_cast<int64_t>(b0) * ab.np;
   const double *pos = ab.pos;
+  const z64 *phs = nullptr;
   if (ADD) {
     T *after = reinterpret_cast<T *>(smem);
+    if (St<T>::cplx) {
+      phs = stage_phases(ab, reinterpret_cast<z64 *>(smem));
+      after = reinterpret_cast<T *>(smem + 48 * sizeof(z64));
+    }
     if (XLDS) {
       stage_x<T, NB>(ab, b0, nb, after);
       Xs = after;
@@ -243,6 +266,8 @@ __global__ __launch_bounds__(256) void k_apply_S(const T *__restrict__ psi, T *_
                     ab.natoms);
     __syncthreads();
   }
+  typename PJSel<NI>::type pj = PJSel<NI>::get(ab.pj);
+  const int ni = NI == 13 ? 13 : ab.pj->ni;
   const int64_t g = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (g >= ng) return;
   using A = typename St<T>::Acc;
@@ -250,12 +275,12 @@ __global__ __launch_bounds__(256) void k_apply_S(const T *__restrict__ psi, T *_
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = St<A>::zero();
   if (ADD) {
-    const int n1 = ab.pj->n[1], n2 = ab.pj->n[2];
+    const int n1 = pj.n[1], n2 = pj.n[2];
     const int plane = n1 * n2;
     const int ix = static_cast<int>(g / plane);
     const int r = static_cast<int>(g - static_cast<int64_t>(ix) * plane);
     const int iy = r / n2, iz = r - iy * n2;
-    addback_group<T, NI, NB>(ab, ab.pinfo[g], ix, iy, iz, pos, Xs, ab.np, b0, nb, acc);
+    addback_group<T, NI, NB>(ab, pj, ab.pinfo[g], ix, iy, iz, pos, phs, Xs, ab.np, ni, b0, nb, acc);
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b)
@@ -329,7 +354,8 @@ int stencil_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *o
   const size_t xbytes = static_cast<size_t>(NB) * s->np * sizeof(T);
   const bool xlds = X && xbytes <= XLDS_MAX;
   const size_t pbytes = (X && s->natoms <= POS_LDS_MAX) ? 3 * sizeof(double) * s->natoms : 0;
-  const size_t lds = tile + (xlds ? xbytes : 0) + pbytes;
+  const size_t phb = (X && St<T>::cplx) ? 48 * sizeof(z64) : 0;
+  const size_t lds = tile + phb + (xlds ? xbytes : 0) + pbytes;
   dim3 grid((plane + ST_THREADS - 1) / ST_THREADS, ngroups, (s->n[0] + G.xseg - 1) / G.xseg);
   const T *ps = static_cast<const T *>(psi);
   T *po = static_cast<T *>(out);
@@ -352,12 +378,13 @@ int apply_S_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *o
   const size_t pbytes = (X && s->natoms <= POS_LDS_MAX) ? 3 * sizeof(double) * s->natoms : 0;
   const T *ps = static_cast<const T *>(psi);
   T *po = static_cast<T *>(out);
+  const size_t phb = (X && St<T>::cplx) ? 48 * sizeof(z64) : 0;
   if (!X)
     k_apply_S<T, false, false, NI, NB><<<grid, 256, 0, st>>>(ps, po, s->ng, nb, ab);
   else if (xlds)
-    k_apply_S<T, true, true, NI, NB><<<grid, 256, xbytes + pbytes, st>>>(ps, po, s->ng, nb, ab);
+    k_apply_S<T, true, true, NI, NB><<<grid, 256, phb + xbytes + pbytes, st>>>(ps, po, s->ng, nb, ab);
   else
-    k_apply_S<T, true, false, NI, NB><<<grid, 256, pbytes, st>>>(ps, po, s->ng, nb, ab);
+    k_apply_S<T, true, false, NI, NB><<<grid, 256, phb + pbytes, st>>>(ps, po, s->ng, nb, ab);
   return GPAW_OK;
 }
 

@@ -158,19 +158,24 @@ int build_tables(const gpaw_sys_desc *d, gpaw_sys *s) {
     return x.w[2] < y.w[2];
   });
   if (nent >= (int64_t(1) << 24)) return fail(GPAW_EINVAL, "more than 2^24 projector entries");
+  // per point: the first three entry codes inline (most points have at most
+  // three), the count and the index of the first entry in pm_code
   std::vector<int32_t> pm_code(nent);
-  std::vector<int2> pinfo(s->ng, make_int2(0, 0));
+  std::vector<int4> pinfo(s->ng, make_int4(0, 0, 0, 0));
   int64_t ncov = 0;
   for (int64_t e = 0; e < nent; ++e) {
     const Entry &x = ent[e];
     pm_code[e] = pack_code(x.atom, x.w[0], x.w[1], x.w[2]);
+    int4 &pi = pinfo[x.g];
     if (e == 0 || ent[e - 1].g != x.g) {
       ++ncov;
-      pinfo[x.g] = make_int2(pm_code[e], static_cast<int>(e));
+      pi = make_int4(pm_code[e], 0, 0, static_cast<int>(e));
     }
-    const int cnt = (pinfo[x.g].y >> 24) + 1;
+    const int cnt = (pi.w >> 24) + 1;
     if (cnt > 255) return fail(GPAW_EINVAL, "more than 255 projector entries at one grid point");
-    pinfo[x.g].y = (cnt << 24) | (pinfo[x.g].y & 0xFFFFFF);
+    if (cnt == 2) pi.y = pm_code[e];
+    if (cnt == 3) pi.z = pm_code[e];
+    pi.w = (cnt << 24) | (pi.w & 0xFFFFFF);
   }
 
   std::vector<double> pos(d->pos, d->pos + 3 * d->natoms);
