@@ -35,7 +35,50 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision-form and batched-form measurements")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed steps, run a plain 256 MiB device copy three times "
+                         "(reference kernel for hardware byte counters)")
     return ap.parse_args()
+
+
+# kernels behind each timed call, and the sources they are built from
+PART_KERNELS = {
+    "project": (["k_project"], ["csrc/nonlocal.hip", "csrc/proj.h"]),
+    "apply_H": (["k_dmat", "k_stencil"], ["csrc/stencil.hip", "csrc/nonlocal.hip", "csrc/proj.h"]),
+    "apply_S": (["k_dmat", "k_apply_S"], ["csrc/stencil.hip", "csrc/nonlocal.hip", "csrc/proj.h"]),
+    "subspace": (["k_subspace", "k_subspace_reduce"], ["csrc/gemm.hip"]),
+    "rotate": (["k_rotate", "k_rotate"], ["csrc/gemm.hip"]),
+}
+
+
+def source_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    base = os.path.join(ROOT, "paper_2310_14776_amd")
+    for f in files:
+        with open(os.path.join(base, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(part, workload_tag):
+    """HBM bytes per launch of a part from the committed counter summary, or
+    None when there is none or the kernels' sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{part}_{workload_tag}.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    try:
+        if fields.get("source_sha256") != source_hash(PART_KERNELS[part][1]):
+            return None
+        return int(float(fields["fetch_bytes_per_launch"]) + float(fields["write_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def timed(fn, stream, steps, warmup):
@@ -336,8 +379,8 @@ def main():
         achieved = c["bytes"] / t / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
-    roof["kernel"] = dom
-    roof["traffic"] = None
+    roof["kernel"] = " + ".join(PART_KERNELS[dom][0])
+    roof["traffic"] = measured_traffic(dom, f"{s.n[0]}x{s.n[1]}x{s.n[2]}_nb{nb}")
 
     out = {
         "metric": "band*gridpoints/s for H|psi>+subspace step",
@@ -363,6 +406,13 @@ def main():
     sysg.close()
     del psi, Hpsi, Spsi, psi_rot, P, P_rot
     torch.cuda.empty_cache()
+    if args.calib_copy:
+        xa = torch.empty(32 << 20, dtype=torch.float64, device=dev)
+        xb = torch.empty_like(xa)
+        for _ in range(3):
+            xb.copy_(xa)
+        torch.cuda.synchronize()
+        del xa, xb
     if not args.no_forms:
         forms_steps = max(3, min(args.steps, 10))
         out["forms"] = {"precision": precision_form(forms_steps, 2),

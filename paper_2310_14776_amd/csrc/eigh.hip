@@ -414,16 +414,17 @@ __global__ __launch_bounds__(SG_T) void k_small_gemm(const T *__restrict__ A, in
   const int li = lane & 15, lk = lane >> 4;
   d4 accr = {0.0, 0.0, 0.0, 0.0}, acci = {0.0, 0.0, 0.0, 0.0};
   const int r = i0 + li, c = j0 + li;
-  for (int k0 = 0; k0 < n; k0 += 32) {
-    T a[8], b[8];
+  // 64 k per round: all loads of a round are issued before its MFMAs
+  for (int k0 = 0; k0 < n; k0 += 64) {
+    T a[16], b[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       const int k = k0 + 4 * u + lk;
       a[u] = (r < n && k < n) ? opval(A, amode, r, k, n) : T{};
       b[u] = (c < n && k < n) ? opval(B, bmode, k, c, n) : T{};
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       if constexpr (CX) {
         const z64 au = a[u], bu = b[u];
         accr = __builtin_amdgcn_mfma_f64_16x16x4f64(au.x, bu.x, accr, 0, 0, 0);
@@ -602,18 +603,23 @@ __global__ __launch_bounds__(EIG_T) void k_eig_tridiag(int n, EigWs w, const int
 }
 
 // ------------------------------------------------------------------ values
-__global__ __launch_bounds__(256) void k_eig_values(int n, EigWs w, const int32_t *info) {
+// d, e are read in the Sturm recurrence at wavefront-uniform indices, through
+// restrict-qualified pointers, so they come in as scalar loads.
+__global__ __launch_bounds__(256) void k_eig_values(int n, const double *__restrict__ dg,
+                                                    const double *__restrict__ eg,
+                                                    double *__restrict__ lam_out,
+                                                    const int32_t *__restrict__ info) {
   if (*info != 0) return;
   extern __shared__ double sdv[];
   double *d = sdv, *e = sdv + n, *e2 = sdv + 2 * n;
   for (int i = threadIdx.x; i < n; i += 256) {
-    d[i] = w.d[i];
-    e[i] = (i + 1 < n) ? w.e[i] : 0.0;
+    d[i] = dg[i];
+    e[i] = (i + 1 < n) ? eg[i] : 0.0;
     e2[i] = e[i] * e[i];
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (j >= n) return;
   int lo = j, hi = j;
   while (lo > 0 && !split_at(d, e, lo - 1)) --lo;
@@ -657,26 +663,40 @@ __global__ __launch_bounds__(256) void k_eig_values(int n, EigWs w, const int32_
       neg[k] = pc[k] <= 0.0;
       cnt[k] = neg[k];
     }
-    for (int i = lo + 1; i <= hi; ++i) {
-      const double di = d[i] * s, ei = e2[i - 1] * s2;
+    // blocks of 8 steps: the block's d and e come in as one batch of scalar
+    // loads, then the minors are rescaled
+    auto sturm_step = [&](double di, double ei) {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const double pn = fma(di - x[k], pc[k], -ei * pm[k]);
-        const bool nn = pn < 0.0 || (pn == 0.0 && !neg[k]);
-        cnt[k] += (nn != neg[k]);
+        const bool nn = (pn < 0.0) | ((pn == 0.0) & !neg[k]);
+        cnt[k] += static_cast<int>(nn != neg[k]);
         neg[k] = nn;
         pm[k] = pc[k];
         pc[k] = pn;
       }
-      if (((i - lo) & 7) == 0) {
+    };
+    int i = lo + 1;
+    for (; i + 8 <= hi + 1; i += 8) {
+      double db[8], eb[8];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const double mag = fmax(fabs(pc[k]), fabs(pm[k]));
-          const double sc = mag > 0x1p+400 ? 0x1p-400 : (mag < 0x1p-400 ? 0x1p+400 : 1.0);
-          pm[k] *= sc;
-          pc[k] *= sc;
-        }
+      for (int q = 0; q < 8; ++q) {
+        db[q] = dg[i + q];
+        eb[q] = eg[i + q - 1];
       }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sturm_step(db[q] * s, (eb[q] * eb[q]) * s2);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double mag = fmax(fabs(pc[k]), fabs(pm[k]));
+        const double sc = mag > 0x1p+400 ? 0x1p-400 : (mag < 0x1p-400 ? 0x1p+400 : 1.0);
+        pm[k] *= sc;
+        pc[k] *= sc;
+      }
+    }
+    for (; i <= hi; ++i) {
+      const double eu = eg[i - 1];
+      sturm_step(dg[i] * s, (eu * eu) * s2);
     }
     // eigenvalue li lies at or above x exactly when at most li lie below x
     double na = -DBL_MAX, nbnd = DBL_MAX;
@@ -690,7 +710,7 @@ __global__ __launch_bounds__(256) void k_eig_values(int n, EigWs w, const int32_
   }
   a /= s;
   b /= s;
-  if (lane == 0) w.lam[j] = 0.5 * (a + b);
+  if (lane == 0) lam_out[j] = 0.5 * (a + b);
 }
 
 // ------------------------------------------------------------------ vectors
@@ -742,33 +762,26 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
   // the second solve and the pivots are stored as reciprocals, tiny pivots
   // replaced by +-eps ||T||
   {
+    // branch-free: the lanes of a workgroup (different eigenvalues) pivot
+    // differently, so both cases are formed and selected
     double c0 = d[lo] - x, c1 = (m > 1) ? e[lo] : 0.0;
     for (int i = 0; i + 1 < m; ++i) {
       const double n0 = e[lo + i], n1 = d[lo + i + 1] - x;
       const double n2 = (i + 2 < m) ? e[lo + i + 1] : 0.0;
       const double yi = AT(y, i), yn = AT(y, i + 1);
-      if (fabs(n0) > fabs(c0)) {
-        const double l = c0 / n0;
-        AT(u0, i) = n0;
-        AT(u1, i) = n1;
-        AT(u2, i) = n2;
-        AT(y, i) = yn;
-        AT(y, i + 1) = yi - l * yn;
-        AT(ml, i) = -1.0;
-        AT(ms, i) = l;
-        c0 = c1 - l * n1;
-        c1 = -l * n2;
-      } else {
-        const double l = (c0 != 0.0) ? n0 / c0 : 0.0;
-        AT(u0, i) = c0;
-        AT(u1, i) = c1;
-        AT(u2, i) = 0.0;
-        AT(y, i + 1) = yn - l * yi;
-        AT(ml, i) = 0.0;
-        AT(ms, i) = l;
-        c0 = n1 - l * c1;
-        c1 = n2;
-      }
+      const bool sw = fabs(n0) > fabs(c0);
+      const double num = sw ? c0 : n0, den = sw ? n0 : c0;
+      const double l = den != 0.0 ? num / den : 0.0;
+      AT(u0, i) = sw ? n0 : c0;
+      AT(u1, i) = sw ? n1 : c1;
+      AT(u2, i) = sw ? n2 : 0.0;
+      AT(y, i) = sw ? yn : yi;
+      AT(y, i + 1) = sw ? yi - l * yn : yn - l * yi;
+      AT(ml, i) = sw ? -1.0 : 0.0;
+      AT(ms, i) = l;
+      const double c0n = sw ? c1 - l * n1 : n1 - l * c1;
+      c1 = sw ? -l * n2 : n2;
+      c0 = c0n;
     }
     AT(u0, m - 1) = c0;
   }
@@ -782,12 +795,9 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
       // replay the forward elimination on the new right-hand side
       for (int i = 0; i + 1 < m; ++i) {
         const double yi = AT(y, i), yn = AT(y, i + 1), l = AT(ms, i);
-        if (AT(ml, i) < 0.0) {
-          AT(y, i) = yn;
-          AT(y, i + 1) = yi - l * yn;
-        } else {
-          AT(y, i + 1) = yn - l * yi;
-        }
+        const bool sw = AT(ml, i) < 0.0;
+        AT(y, i) = sw ? yn : yi;
+        AT(y, i + 1) = sw ? yi - l * yn : yn - l * yi;
       }
     }
     // back substitution with the reciprocal pivots
@@ -823,20 +833,34 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
 
 // ------------------------------------------------------------------ orthogonality
 // dev[slot] = max |G - I| (one workgroup); info = -1 when above the limit
-__global__ __launch_bounds__(256) void k_gram_check(const double *__restrict__ G, int n,
-                                                    double limit, int32_t *info) {
+__global__ __launch_bounds__(1024) void k_gram_check(const double *__restrict__ G, int n,
+                                                     double limit, int32_t *info) {
   if (*info != 0) return;
-  __shared__ double red[4];
+  __shared__ double red[16];
   double dev = 0.0;
-  for (int idx = threadIdx.x; idx < n * n; idx += 256) {
-    const int r = idx / n, c = idx - r * n;
-    dev = fmax(dev, fabs(G[idx] - (r == c ? 1.0 : 0.0)));
+  const int nn = n * n;
+  for (int base = 0; base < nn; base += 1024 * 8) {
+    double g[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = base + q * 1024 + threadIdx.x;
+      g[q] = idx < nn ? G[idx] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = base + q * 1024 + threadIdx.x;
+      if (idx < nn) {
+        const int r = idx / n, c = idx - r * n;
+        dev = fmax(dev, fabs(g[q] - (r == c ? 1.0 : 0.0)));
+      }
+    }
   }
   dev = wave_max(dev);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dev;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double all = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    double all = 0.0;
+    for (int q = 0; q < 16; ++q) all = fmax(all, red[q]);
     if (!(all <= limit)) *info = -1;
   }
 }
@@ -871,13 +895,14 @@ __global__ __launch_bounds__(128) void k_eig_back(int n, EigWs w, const double *
   for (int k = n - 2; k >= 0; --k) {
     const T *vk = V + k * n;
     T vr[NMAX / 8];
-    T part = T{};
+    T pq[4] = {T{}, T{}, T{}, T{}};  // four partial sums: shorter dependent chains
 #pragma unroll
     for (int t = 0; t < NMAX / 8; ++t) {
       const int row = 8 * t + s;
       vr[t] = (row > k && row < n) ? vk[row] : T{};
-      part = part + cj(vr[t]) * zr[t];
+      pq[t & 3] = pq[t & 3] + cj(vr[t]) * zr[t];
     }
+    T part = (pq[0] + pq[1]) + (pq[2] + pq[3]);
     part = group8_sum(part);
     const T f = tau[k] * part;
 #pragma unroll
@@ -918,13 +943,13 @@ int eigh_large_t(const gpaw_sys *s, const T *H, const T *S, int n, double *eps, 
   k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Linv, 0, T1, 0, Am, n, info);
   k_hermitize<T><<<eb, 256, 0, st>>>(Am, Am, n, info);
   large_tridiag<T>(Am, n, V, tau, w.d, w.e, p, info, st);
-  k_eig_values<<<(n + 3) / 4, 256, 3 * n * sizeof(double), st>>>(n, w, info);
+  k_eig_values<<<(n + 3) / 4, 256, 3 * n * sizeof(double), st>>>(n, w.d, w.e, w.lam, info);
   large_vectors(n, w.d, w.e, w.lam, w.lu, w.Z, info, st);
   k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z, 1, w.Z, 0, w.G, n, info);
-  k_gram_check<<<1, 256, 0, st>>>(w.G, n, 0.5, info);
+  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 0.5, info);
   k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z, 0, w.G, 3, w.Z2, n, info);
   k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z2, 1, w.Z2, 0, w.G, n, info);
-  k_gram_check<<<1, 256, 0, st>>>(w.G, n, 1e-7, info);
+  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 1e-7, info);
   k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z2, 0, w.G, 3, w.Z, n, info);
   large_back<T>(n, w.Z, V, tau, w.lam, U, eps, info, st);
   k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Linv, 1, U, 0, C, n, info);
@@ -968,17 +993,17 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
   k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Linv, 0, T1, 0, Am, n, info);
   k_eig_tridiag<T><<<1, EIG_T, lda_bytes + 4 * n * sizeof(T) + 2 * n * sizeof(double) + 16 * sizeof(T),
                      st>>>(n, w, info);
-  k_eig_values<<<(n + 3) / 4, 256, 3 * n * sizeof(double), st>>>(n, w, info);
+  k_eig_values<<<(n + 3) / 4, 256, 3 * n * sizeof(double), st>>>(n, w.d, w.e, w.lam, info);
   k_eig_vectors<<<(n + VEC_T - 1) / VEC_T, VEC_T, (3 * n + 6 * n * VEC_T) * sizeof(double), st>>>(
       n, w, info);
   // two Newton-Schulz steps Z <- Z (3I - Z^T Z)/2 on the real tridiagonal
   // eigenvectors; the second Gram matrix must be within 1e-7 of I, so the
   // result is orthonormal to ~1e-14
   k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z, 1, w.Z, 0, w.G, n, info);
-  k_gram_check<<<1, 256, 0, st>>>(w.G, n, 0.5, info);
+  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 0.5, info);
   k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z, 0, w.G, 3, w.Z2, n, info);
   k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z2, 1, w.Z2, 0, w.G, n, info);
-  k_gram_check<<<1, 256, 0, st>>>(w.G, n, 1e-7, info);
+  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 1e-7, info);
   k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z2, 0, w.G, 3, w.Z, n, info);
   // U = Q Z in eigen-order, then C = Linv^H U
   k_eig_back<T><<<(n + 15) / 16, 128, (static_cast<size_t>(n) * n + n) * sizeof(T), st>>>(

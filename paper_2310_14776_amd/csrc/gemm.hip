@@ -58,15 +58,29 @@ template <typename T, int BM>
 __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const T *__restrict__ B0,
                                                   const T *__restrict__ B1, T *__restrict__ part,
                                                   int nb, int64_t ng, int64_t kchunk, int tiles_n,
-                                                  int nmat) {
+                                                  int nmat, int nsplit) {
   constexpr int TILE = 16 * BM;
   constexpr int NP = Cx<T>::parts;
   __shared__ d4 red[2][NP][BM][BM][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x - tm * tiles_n;
-  const int mat = blockIdx.y;
+  // workgroups are dealt to the 8 XCDs round-robin by id: give all tiles and
+  // matrices of one K chunk the same id residue so they share that XCD's L2
+  // (with fewer than 8 K chunks the plain order keeps every XCD busy)
+  const int tiles = tiles_n * tiles_n, TT = tiles * nmat;
+  int split, tt;
+  if (nsplit >= 8) {
+    const int xcd = blockIdx.x & 7, jj = blockIdx.x >> 3;
+    split = (jj / TT) * 8 + xcd;
+    tt = jj - (jj / TT) * TT;
+  } else {
+    split = blockIdx.x / TT;
+    tt = blockIdx.x - split * TT;
+  }
+  if (split >= nsplit) return;
+  const int mat = tt / tiles, tile = tt - mat * tiles;
+  const int tm = tile / tiles_n, tn = tile - tm * tiles_n;
   const T *B = mat ? B1 : B0;
-  const int64_t kb = static_cast<int64_t>(blockIdx.z) * kchunk;
+  const int64_t kb = static_cast<int64_t>(split) * kchunk;
   const int64_t ke = std::min(ng, kb + kchunk);
   const int r = lane & 15, kq = lane >> 4;
 
@@ -146,7 +160,7 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
         for (int j = 0; j < BM; ++j) red[0][c][i][j][lane] = acc[c][i][j];
   __syncthreads();
   if (wave == 0) {
-    T *out = part + (static_cast<int64_t>(blockIdx.z) * nmat + mat) * nb * nb;
+    T *out = part + (static_cast<int64_t>(split) * nmat + mat) * nb * nb;
 #pragma unroll
     for (int i = 0; i < BM; ++i)
 #pragma unroll
@@ -275,10 +289,12 @@ int subspace_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const void 
   if (need > static_cast<int64_t>(s->ws.part_elems))
     return fail(GPAW_EINVAL, "subspace workspace too small");
   T *part = reinterpret_cast<T *>(s->ws.part);
-  dim3 grid(p.tiles, nmat, p.nsplit);
-  k_subspace<T, BM><<<grid, 256, 0, st>>>(static_cast<const T *>(psi), static_cast<const T *>(Hpsi),
-                                          static_cast<const T *>(Spsi ? Spsi : Hpsi), part, nb,
-                                          s->ng, p.kchunk, p.tiles_n, nmat);
+  const int64_t slots = p.nsplit >= 8 ? (p.nsplit + 7) / 8 * 8 : p.nsplit;
+  const int64_t wgs = slots * p.tiles * nmat;
+  k_subspace<T, BM><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
+      static_cast<const T *>(psi), static_cast<const T *>(Hpsi),
+      static_cast<const T *>(Spsi ? Spsi : Hpsi), part, nb, s->ng, p.kchunk, p.tiles_n, nmat,
+      p.nsplit);
   const int64_t tot = static_cast<int64_t>(nb) * nb * nmat;
   k_subspace_reduce<T><<<static_cast<unsigned>((tot + 255) / 256), 256, 0, st>>>(
       part, static_cast<T *>(H), static_cast<T *>(S), nb, p.nsplit, nmat, s->dV);

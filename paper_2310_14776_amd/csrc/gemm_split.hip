@@ -180,8 +180,15 @@ __global__ __launch_bounds__(256) void k_sub_lds(const T *__restrict__ A, const 
   __shared__ __attribute__((aligned(16))) __bf16 sB[3 * NP * PS];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int tiles = tiles_n * tiles_n, TT = tiles * nmat;
-  const int x = blockIdx.x & 7, jj = blockIdx.x >> 3;
-  const int split = (jj / TT) * 8 + x, tt = jj - (jj / TT) * TT;
+  int split, tt;
+  if (nsplit >= 8) {
+    const int x = blockIdx.x & 7, jj = blockIdx.x >> 3;
+    split = (jj / TT) * 8 + x;
+    tt = jj - (jj / TT) * TT;
+  } else {  // fewer chunks than XCDs: plain order keeps every XCD busy
+    split = blockIdx.x / TT;
+    tt = blockIdx.x - split * TT;
+  }
   if (split >= nsplit) return;
   const int mat = tt / tiles, tile = tt - mat * tiles;
   const int tm = tile / tiles_n, tn = tile - tm * tiles_n;
@@ -514,8 +521,8 @@ int subspace_split_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const
   const int64_t need = static_cast<int64_t>(p.nsplit) * nmat * nb * nb * NP;
   if (need > static_cast<int64_t>(s->ws.part_elems))
     return fail(GPAW_EINVAL, "subspace workspace too small");
-  const int64_t groups = (p.nsplit + 7) / 8;
-  const int64_t wgs = groups * 8 * p.tiles * nmat;
+  const int64_t slots = p.nsplit >= 8 ? (p.nsplit + 7) / 8 * 8 : p.nsplit;
+  const int64_t wgs = slots * p.tiles * nmat;
   k_sub_lds<T, WT><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
       static_cast<const T *>(psi), static_cast<const T *>(Hpsi),
       static_cast<const T *>(Spsi ? Spsi : Hpsi), s->ws.part, nb, s->ng, p.kchunk, p.tiles_n,

@@ -29,6 +29,7 @@ struct StencilGeom {
   double cx[3], cy[3], cz[3]; // -1/2 w_d / h_c^2, d = 1..3
   z64 phx[7], phy[7], phz[7]; // Bloch phase to the power w = -3..3
   int xseg;
+  int chunks, ngroups, nseg;  // plane chunks of 256 points, band groups, x segments
 };
 
 struct AddArgs {
@@ -129,9 +130,25 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil(const T *__restrict__ ps
   const int n0 = G.n0, n1 = G.n1, n2 = G.n2;
   const int plane = n1 * n2;
   const int t = threadIdx.x;
-  const int b0 = blockIdx.y * NB;
+  // Workgroups are dealt to the 8 XCDs round-robin by id. All plane chunks of
+  // one (band group, x segment) get the same id residue, so the halo rows
+  // they read from each other come from the same XCD's L2.
+  // (with fewer than 8 such columns the plain order keeps every XCD busy)
+  const int ncols = G.ngroups * G.nseg;
+  int chunk, col;
+  if (ncols >= 8) {
+    const int xcd = blockIdx.x & 7, jj = blockIdx.x >> 3;
+    chunk = jj % G.chunks;
+    col = (jj / G.chunks) * 8 + xcd;
+  } else {
+    chunk = blockIdx.x % G.chunks;
+    col = blockIdx.x / G.chunks;
+  }
+  if (col >= ncols) return;
+  const int grp = col % G.ngroups, seg = col / G.ngroups;
+  const int b0 = grp * NB;
   const int64_t bstride = static_cast<int64_t>(n0) * plane;
-  const int x0 = blockIdx.z * G.xseg;
+  const int x0 = seg * G.xseg;
   const int x1 = min(n0, x0 + G.xseg);
 
   // X rows of this band group and the atom positions, staged in LDS
@@ -155,7 +172,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil(const T *__restrict__ ps
   }
   typename PJSel<NI>::type pj = PJSel<NI>::get(ab.pj);
   const int ni = NI == 13 ? 13 : ab.pj->ni;
-  const int f = blockIdx.x * ST_THREADS + t;
+  const int f = chunk * ST_THREADS + t;
   if (f >= plane) return;
   const int y = f / n2, z = f - (f / n2) * n2;
 
@@ -326,6 +343,9 @@ StencilGeom make_geom(const gpaw_sys *s, int nb) {  // nb: band groups
   nseg = std::max(1, std::min(nseg, std::max(1, s->n[0] / 6)));
   if (s->tune.st_nseg > 0) nseg = std::min(s->tune.st_nseg, s->n[0]);
   G.xseg = (s->n[0] + nseg - 1) / nseg;
+  G.chunks = chunks;
+  G.ngroups = nb;
+  G.nseg = (s->n[0] + G.xseg - 1) / G.xseg;
   return G;
 }
 
@@ -356,7 +376,8 @@ int stencil_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *o
   const size_t pbytes = (X && s->natoms <= POS_LDS_MAX) ? 3 * sizeof(double) * s->natoms : 0;
   const size_t phb = (X && St<T>::cplx) ? 48 * sizeof(z64) : 0;
   const size_t lds = tile + phb + (xlds ? xbytes : 0) + pbytes;
-  dim3 grid((plane + ST_THREADS - 1) / ST_THREADS, ngroups, (s->n[0] + G.xseg - 1) / G.xseg);
+  const int64_t cols = static_cast<int64_t>(G.ngroups) * G.nseg;
+  const unsigned grid = static_cast<unsigned>((cols >= 8 ? (cols + 7) / 8 * 8 : cols) * G.chunks);
   const T *ps = static_cast<const T *>(psi);
   T *po = static_cast<T *>(out);
   if (!X)
