@@ -266,13 +266,25 @@ __global__ __launch_bounds__(CH_T) void k_eig_chol(const T *__restrict__ S, int 
   int &fail_sh = *reinterpret_cast<int *>(A + N * lda);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lq = lane >> 4;
-  // lower triangle of (S + S^H)/2, identity on the padding
-  for (int idx = tid; idx < N * N; idx += CH_T) {
-    const int r = idx / N, c = idx - (idx / N) * N;
-    if (c > r) continue;
-    T v = realv<T>(r == c ? 1.0 : 0.0);
-    if (r < n && c < n) v = St<T>::scale(0.5, S[r * n + c] + cj(S[c * n + r]));
-    A[r * lda + c] = v;
+  // lower triangle of (S + S^H)/2, identity on the padding; eight elements
+  // per thread per round with their loads issued first
+  for (int base = 0; base < N * N; base += 8 * CH_T) {
+    T sa[8], sb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * CH_T + tid;
+      const int r = idx / N, c = idx - (idx / N) * N;
+      const bool in = idx < N * N && c <= r && r < n && c < n;
+      sa[u] = in ? S[r * n + c] : T{};
+      sb[u] = in ? S[c * n + r] : T{};
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * CH_T + tid;
+      const int r = idx / N, c = idx - (idx / N) * N;
+      if (idx >= N * N || c > r) continue;
+      A[r * lda + c] = (r < n && c < n) ? St<T>::scale(0.5, sa[u] + cj(sb[u])) : realv<T>(r == c ? 1.0 : 0.0);
+    }
   }
   if (tid == 0) fail_sh = 0;
   __syncthreads();
@@ -389,19 +401,17 @@ __global__ __launch_bounds__(256) void k_hermitize(const T *X, T *Y, int n, cons
 // per wavefront. Operand modes:
 //   A: 0 = A, 1 = A^H, 2 = (A + A^H)/2
 //   B: 0 = B, 1 = B^H, 3 = 1.5 I - 0.5 B
-template <typename T>
-__device__ inline T opval(const T *M, int mode, int r, int c, int n) {
-  switch (mode) {
-    case 0: return M[r * n + c];
-    case 1: return cj(M[c * n + r]);
-    case 2: return St<T>::scale(0.5, M[r * n + c] + cj(M[c * n + r]));
-    default: return realv<T>(r == c ? 1.5 : 0.0) - St<T>::scale(0.5, M[r * n + c]);
-  }
+template <int MODE, typename T>
+__device__ inline T opval(const T *M, int r, int c, int n) {
+  if constexpr (MODE == 0) return M[r * n + c];
+  else if constexpr (MODE == 1) return cj(M[c * n + r]);
+  else if constexpr (MODE == 2) return St<T>::scale(0.5, M[r * n + c] + cj(M[c * n + r]));
+  else return realv<T>(r == c ? 1.5 : 0.0) - St<T>::scale(0.5, M[r * n + c]);
 }
 
-template <typename T>
-__global__ __launch_bounds__(SG_T) void k_small_gemm(const T *__restrict__ A, int amode,
-                                                     const T *__restrict__ B, int bmode,
+template <typename T, int AM, int BM>
+__global__ __launch_bounds__(SG_T) void k_small_gemm(const T *__restrict__ A,
+                                                     const T *__restrict__ B,
                                                      T *__restrict__ C, int n,
                                                      const int32_t *info) {
   if (*info != 0) return;
@@ -420,8 +430,8 @@ __global__ __launch_bounds__(SG_T) void k_small_gemm(const T *__restrict__ A, in
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int k = k0 + 4 * u + lk;
-      a[u] = (r < n && k < n) ? opval(A, amode, r, k, n) : T{};
-      b[u] = (c < n && k < n) ? opval(B, bmode, k, c, n) : T{};
+      a[u] = (r < n && k < n) ? opval<AM>(A, r, k, n) : T{};
+      b[u] = (c < n && k < n) ? opval<BM>(B, k, c, n) : T{};
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -513,13 +523,29 @@ __global__ __launch_bounds__(EIG_T) void k_eig_tridiag(int n, EigWs w, const int
   const int lane = tid & 63, wave = tid >> 6;
   const int ty = tid >> 5, tx = tid & 31;
   const T *Ag = as<T>(w.A);
+  // loads of a thread issued in batches (all 32 for real data, 8 for
+  // complex), then the symmetrised stores
+  constexpr int AB = St<T>::cplx ? 1 : 4;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a0 = 0; a0 < 4; a0 += AB) {
+    T ga[AB][4], gb[AB][4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int r = ty + 32 * a, c = tx + 32 * b;
-      if (r < n && c < n) A[r * lda + c] = St<T>::scale(0.5, Ag[r * n + c] + cj(Ag[c * n + r]));
-    }
+    for (int a = 0; a < AB; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int r = ty + 32 * (a0 + a), c = tx + 32 * b;
+        const bool in = r < n && c < n;
+        ga[a][b] = in ? Ag[r * n + c] : T{};
+        gb[a][b] = in ? Ag[c * n + r] : T{};
+      }
+#pragma unroll
+    for (int a = 0; a < AB; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int r = ty + 32 * (a0 + a), c = tx + 32 * b;
+        if (r < n && c < n) A[r * lda + c] = St<T>::scale(0.5, ga[a][b] + cj(gb[a][b]));
+      }
+  }
   __syncthreads();
   if (n >= 2 && wave == 0) make_reflector<T>(A, lda, n, 0, vbuf, taus, dd, ee);
   if (n == 1 && tid == 0) dd[0] = re_of(A[0]);
@@ -530,6 +556,7 @@ __global__ __launch_bounds__(EIG_T) void k_eig_tridiag(int n, EigWs w, const int
     T *vnext = vbuf + ((k + 1) & 1) * n;
     const T tau = taus[k];
     {
+      // row r of p = tau A v by 8 lanes
       const int r = k + 1 + (tid >> 3), s = tid & 7;
       T part = T{};
       if (r < n) {
@@ -728,11 +755,11 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
   double *d = sv, *e = sv + n, *lam = sv + 2 * n;
   double *scratch = sv + 3 * n;
   const int t = threadIdx.x;
-  for (int i = t; i < n; i += VEC_T) {
-    d[i] = w.d[i];
-    e[i] = (i + 1 < n) ? w.e[i] : 0.0;
-    lam[i] = w.lam[i];
-  }
+  copy_rounds(d, w.d, n, t, VEC_T);
+  copy_rounds(e, w.e, n, t, VEC_T);
+  copy_rounds(lam, w.lam, n, t, VEC_T);
+  __syncthreads();
+  if (t == 0) e[n - 1] = 0.0;
   __syncthreads();
   const int j = blockIdx.x * VEC_T + t;
   if (j >= n) return;
@@ -881,8 +908,8 @@ __global__ __launch_bounds__(128) void k_eig_back(int n, EigWs w, const double *
   T *tau = V + n * n;                // [n]
   const T *Vg = as<T>(w.V);
   const T *tg = as<T>(w.tau);
-  for (int idx = threadIdx.x; idx < n * n; idx += 128) V[idx] = Vg[idx];
-  for (int idx = threadIdx.x; idx < n; idx += 128) tau[idx] = tg[idx];
+  copy_rounds(V, Vg, n * n, threadIdx.x, 128);
+  copy_rounds(tau, tg, n, threadIdx.x, 128);
   __syncthreads();
   const int col = blockIdx.x * 16 + (threadIdx.x >> 3), s = threadIdx.x & 7;
   if (col >= n) return;
@@ -939,20 +966,20 @@ int eigh_large_t(const gpaw_sys *s, const T *H, const T *S, int n, double *eps, 
   k_set_info<<<1, 1, 0, st>>>(info);
   k_hermitize<T><<<eb, 256, 0, st>>>(S, Sw, n, info);
   large_chol_linv<T>(Sw, Linv, n, w.piv, info, st);
-  k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(H, 2, Linv, 1, T1, n, info);
-  k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Linv, 0, T1, 0, Am, n, info);
+  k_small_gemm<T, 2, 1><<<sg_blocks, SG_T, 0, st>>>(H, Linv, T1, n, info);
+  k_small_gemm<T, 0, 0><<<sg_blocks, SG_T, 0, st>>>(Linv, T1, Am, n, info);
   k_hermitize<T><<<eb, 256, 0, st>>>(Am, Am, n, info);
   large_tridiag<T>(Am, n, V, tau, w.d, w.e, p, info, st);
   k_eig_values<<<(n + 3) / 4, 256, 3 * n * sizeof(double), st>>>(n, w.d, w.e, w.lam, info);
   large_vectors(n, w.d, w.e, w.lam, w.lu, w.Z, info, st);
-  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z, 1, w.Z, 0, w.G, n, info);
+  k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.Z, w.G, n, info);
   k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 0.5, info);
-  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z, 0, w.G, 3, w.Z2, n, info);
-  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z2, 1, w.Z2, 0, w.G, n, info);
+  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.G, w.Z2, n, info);
+  k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.Z2, w.G, n, info);
   k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 1e-7, info);
-  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z2, 0, w.G, 3, w.Z, n, info);
+  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.G, w.Z, n, info);
   large_back<T>(n, w.Z, V, tau, w.lam, U, eps, info, st);
-  k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Linv, 1, U, 0, C, n, info);
+  k_small_gemm<T, 1, 0><<<sg_blocks, SG_T, 0, st>>>(Linv, U, C, n, info);
   return GPAW_OK;
 }
 
@@ -989,8 +1016,8 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
 
   k_eig_chol<T><<<1, CH_T, chol_lds_bytes<T>(n), st>>>(Sd, n, w, info);
   // A = Linv ((H + H^H)/2) Linv^H
-  k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Hd, 2, Linv, 1, T1, n, info);
-  k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Linv, 0, T1, 0, Am, n, info);
+  k_small_gemm<T, 2, 1><<<sg_blocks, SG_T, 0, st>>>(Hd, Linv, T1, n, info);
+  k_small_gemm<T, 0, 0><<<sg_blocks, SG_T, 0, st>>>(Linv, T1, Am, n, info);
   k_eig_tridiag<T><<<1, EIG_T, lda_bytes + 4 * n * sizeof(T) + 2 * n * sizeof(double) + 16 * sizeof(T),
                      st>>>(n, w, info);
   k_eig_values<<<(n + 3) / 4, 256, 3 * n * sizeof(double), st>>>(n, w.d, w.e, w.lam, info);
@@ -999,16 +1026,16 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
   // two Newton-Schulz steps Z <- Z (3I - Z^T Z)/2 on the real tridiagonal
   // eigenvectors; the second Gram matrix must be within 1e-7 of I, so the
   // result is orthonormal to ~1e-14
-  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z, 1, w.Z, 0, w.G, n, info);
+  k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.Z, w.G, n, info);
   k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 0.5, info);
-  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z, 0, w.G, 3, w.Z2, n, info);
-  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z2, 1, w.Z2, 0, w.G, n, info);
+  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.G, w.Z2, n, info);
+  k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.Z2, w.G, n, info);
   k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 1e-7, info);
-  k_small_gemm<double><<<sg_blocks, SG_T, 0, st>>>(w.Z2, 0, w.G, 3, w.Z, n, info);
+  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.G, w.Z, n, info);
   // U = Q Z in eigen-order, then C = Linv^H U
   k_eig_back<T><<<(n + 15) / 16, 128, (static_cast<size_t>(n) * n + n) * sizeof(T), st>>>(
       n, w, w.Z, U, eps, info);
-  k_small_gemm<T><<<sg_blocks, SG_T, 0, st>>>(Linv, 1, U, 0, static_cast<T *>(C), n, info);
+  k_small_gemm<T, 1, 0><<<sg_blocks, SG_T, 0, st>>>(Linv, U, static_cast<T *>(C), n, info);
   return GPAW_OK;
 }
 

@@ -186,8 +186,18 @@ __global__ __launch_bounds__(256) void k_subspace_reduce(const T *__restrict__ p
   if (idx >= nn * nmat) return;
   const int mat = static_cast<int>(idx / nn);
   const int64_t e = idx - mat * nn;
+  // the partials are added in split order (bitwise reproducible), eight
+  // loads in flight at a time
   T acc{};
-  for (int s = 0; s < nsplit; ++s) acc = acc + part[(static_cast<int64_t>(s) * nmat + mat) * nn + e];
+  for (int s0 = 0; s0 < nsplit; s0 += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      v[u] = s0 + u < nsplit ? part[(static_cast<int64_t>(s0 + u) * nmat + mat) * nn + e] : T{};
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (s0 + u < nsplit) acc = acc + v[u];
+  }
   (mat ? S : H)[e] = St<T>::scale(dV, acc);
 }
 
@@ -280,6 +290,61 @@ __global__ __launch_bounds__(256) void k_rotate(const T *__restrict__ C, const T
     }
 }
 
+// Rotation of a short-row matrix (the projections: cols = Np): one wavefront
+// per 16 x 16 output tile, 64 m per round with all loads issued first.
+template <typename T>
+__global__ __launch_bounds__(256) void k_rot_small(const T *__restrict__ C, const T *__restrict__ src,
+                                                   T *__restrict__ dst, int nb, int64_t cols,
+                                                   int tiles_c) {
+  constexpr int NP = Cx<T>::parts;
+  const int lane = threadIdx.x & 63;
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int tiles_n = (nb + 15) / 16;
+  if (tile >= tiles_n * tiles_c) return;
+  const int n0 = (tile / tiles_c) * 16;
+  const int64_t c0 = static_cast<int64_t>(tile % tiles_c) * 16;
+  const int i = lane & 15, lk = lane >> 4;
+  d4 acc[NP];
+#pragma unroll
+  for (int c = 0; c < NP; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int m0 = 0; m0 < nb; m0 += 64) {
+    T a[16], b[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int m = m0 + 4 * u + lk;
+      a[u] = (m < nb && n0 + i < nb) ? C[static_cast<int64_t>(m) * nb + n0 + i] : T{};
+      b[u] = (m < nb && c0 + i < cols) ? src[static_cast<int64_t>(m) * cols + c0 + i] : T{};
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const double ax = Cx<T>::re(a[u]), bx = Cx<T>::re(b[u]);
+      acc[0] = mfma(ax, bx, acc[0]);
+      if constexpr (NP == 2) {
+        const double ay = Cx<T>::im(a[u]), by = Cx<T>::im(b[u]);
+        acc[0] = mfma(-ay, by, acc[0]);
+        acc[NP - 1] = mfma(ax, by, acc[NP - 1]);
+        acc[NP - 1] = mfma(ay, bx, acc[NP - 1]);
+      }
+    }
+  }
+  if (c0 + i >= cols) return;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int n = n0 + lk + 4 * e;
+    if (n < nb) dst[static_cast<int64_t>(n) * cols + c0 + i] = Cx<T>::make(acc[0][e], acc[NP - 1][e]);
+  }
+}
+
+template <typename T>
+int rotate_small_t(const void *C, const void *src, int nb, int64_t cols, void *dst, hipStream_t st) {
+  const int tiles_c = static_cast<int>((cols + 15) / 16);
+  const int64_t tiles = static_cast<int64_t>((nb + 15) / 16) * tiles_c;
+  k_rot_small<T><<<static_cast<unsigned>((tiles + 3) / 4), 256, 0, st>>>(
+      static_cast<const T *>(C), static_cast<const T *>(src), static_cast<T *>(dst), nb, cols,
+      tiles_c);
+  return GPAW_OK;
+}
+
 template <typename T, int BM>
 int subspace_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi, int nb,
                void *H, void *S, hipStream_t st) {
@@ -335,6 +400,12 @@ int launch_rotate(const gpaw_sys *s, const void *C, const void *src, int nb, int
   if (cols == 0) return GPAW_OK;
   if (s->dtype == GPAW_F32 || s->dtype == GPAW_C64)
     return launch_rotate_split(s, C, src, nb, cols, dst, st);
+  // short rows (projections): too few columns to fill the chip by column
+  // tiles, so one wavefront per 16 x 16 output tile instead
+  if (cols <= 4096) {
+    if (s->dtype == GPAW_C128) return rotate_small_t<z64>(C, src, nb, cols, dst, st);
+    return rotate_small_t<double>(C, src, nb, cols, dst, st);
+  }
   if (s->dtype == GPAW_C128)
     return s->tune.rot_rb == 2 ? rotate_t<z64, 2>(C, src, nb, cols, dst, st)
                                : rotate_t<z64, 4>(C, src, nb, cols, dst, st);

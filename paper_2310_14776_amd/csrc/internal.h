@@ -202,6 +202,25 @@ bool is_complex(int32_t dtype);
 // Host construction of the projector geometry (tables.hip).
 int build_tables(const gpaw_sys_desc *d, gpaw_sys *s);
 
+// Strided copy global -> LDS by nthr threads: eight loads in flight per
+// thread before the stores, so a round costs one memory latency.
+template <typename T>
+__device__ inline void copy_rounds(T *dst, const T *src, int count, int tid, int nthr) {
+  for (int base = 0; base < count; base += 8 * nthr) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * nthr + tid;
+      v[u] = idx < count ? src[idx] : T{};
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * nthr + tid;
+      if (idx < count) dst[idx] = v[u];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 // Each returns GPAW_OK or an error code with the message set.
 int launch_project(const gpaw_sys *s, const void *psi, int nb, void *P, hipStream_t st);

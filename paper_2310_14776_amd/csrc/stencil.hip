@@ -110,15 +110,13 @@ __device__ inline const double *stage_pos(const AddArgs &ab, double *lds_pos, in
   return lds_pos;
 }
 
-// Copies the band group's X rows into LDS (rows b >= nb are left unset).
+// Copies the band group's X rows into LDS (rows b >= nb are left unset); the
+// rows of a group are contiguous in X
 template <typename T, int NB>
 __device__ inline void stage_x(const AddArgs &ab, int b0, int nb, T *xs) {
-  const T *X = static_cast<const T *>(ab.X);
-  const int tot = NB * ab.np;
-  for (int idx = threadIdx.x; idx < tot; idx += blockDim.x) {
-    const int b = idx / ab.np;
-    if (b0 + b < nb) xs[idx] = X[static_cast<int64_t>(b0) * ab.np + idx];
-  }
+  const T *X = static_cast<const T *>(ab.X) + static_cast<int64_t>(b0) * ab.np;
+  const int rows = nb - b0 < NB ? nb - b0 : NB;
+  copy_rounds(xs, X, rows * ab.np, static_cast<int>(threadIdx.x), static_cast<int>(blockDim.x));
 }
 
 template <typename T, bool BLOCH, bool ADD, bool XLDS, int NI, int NB>
