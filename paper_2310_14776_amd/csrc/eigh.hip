@@ -85,7 +85,7 @@ EigWs eig_layout(double *base, int n, int sz, bool large) {
 size_t eig_layout_elems(int n, int sz, bool large) {
   const size_t nn = static_cast<size_t>(n) * n;
   size_t e = 4 * sz * nn + 3 * nn + sz * n + 3 * n;
-  if (large) e += sz * nn + n + sz * n + 4 * nn;
+  if (large) e += sz * nn + n + sz * n + 6 * nn;
   return e + 64;
 }
 
@@ -783,6 +783,7 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
   const double x = lam[j - ties] + ties * pert;
   const double tiny = DBL_EPSILON * fmax(tn, DBL_MIN);
 
+#pragma unroll 4
   for (int i = 0; i < m; ++i) AT(y, i) = start_value(j, i);
   // LU with partial pivoting of (T_block - x I) once, forward-eliminating y;
   // the row multipliers (negative when the rows were swapped) are kept for
@@ -791,27 +792,33 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
   {
     // branch-free: the lanes of a workgroup (different eigenvalues) pivot
     // differently, so both cases are formed and selected
+    // the running element y_i stays in a register (ycur); y_{i+1} is read
+    // before anything writes it, so no LDS round trip sits on the chain
     double c0 = d[lo] - x, c1 = (m > 1) ? e[lo] : 0.0;
+    double ycur = AT(y, 0);
+#pragma unroll 4
     for (int i = 0; i + 1 < m; ++i) {
       const double n0 = e[lo + i], n1 = d[lo + i + 1] - x;
       const double n2 = (i + 2 < m) ? e[lo + i + 1] : 0.0;
-      const double yi = AT(y, i), yn = AT(y, i + 1);
+      const double yn = AT(y, i + 1);
       const bool sw = fabs(n0) > fabs(c0);
       const double num = sw ? c0 : n0, den = sw ? n0 : c0;
       const double l = den != 0.0 ? num / den : 0.0;
       AT(u0, i) = sw ? n0 : c0;
       AT(u1, i) = sw ? n1 : c1;
       AT(u2, i) = sw ? n2 : 0.0;
-      AT(y, i) = sw ? yn : yi;
-      AT(y, i + 1) = sw ? yi - l * yn : yn - l * yi;
+      AT(y, i) = sw ? yn : ycur;
+      ycur = sw ? ycur - l * yn : yn - l * ycur;
       AT(ml, i) = sw ? -1.0 : 0.0;
       AT(ms, i) = l;
       const double c0n = sw ? c1 - l * n1 : n1 - l * c1;
       c1 = sw ? -l * n2 : n2;
       c0 = c0n;
     }
+    AT(y, m - 1) = ycur;
     AT(u0, m - 1) = c0;
   }
+#pragma unroll 4
   for (int i = 0; i < m; ++i) {
     double p = AT(u0, i);
     if (fabs(p) < tiny) p = (p < 0.0) ? -tiny : tiny;
@@ -820,15 +827,19 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
   for (int iter = 0; iter < 2; ++iter) {
     if (iter > 0) {
       // replay the forward elimination on the new right-hand side
+      double ycur = AT(y, 0);
+#pragma unroll 4
       for (int i = 0; i + 1 < m; ++i) {
-        const double yi = AT(y, i), yn = AT(y, i + 1), l = AT(ms, i);
+        const double yn = AT(y, i + 1), l = AT(ms, i);
         const bool sw = AT(ml, i) < 0.0;
-        AT(y, i) = sw ? yn : yi;
-        AT(y, i + 1) = sw ? yi - l * yn : yn - l * yi;
+        AT(y, i) = sw ? yn : ycur;
+        ycur = sw ? ycur - l * yn : yn - l * ycur;
       }
+      AT(y, m - 1) = ycur;
     }
     // back substitution with the reciprocal pivots
     double y1 = 0.0, y2 = 0.0, ymax = 0.0;
+#pragma unroll 4
     for (int i = m - 1; i >= 0; --i) {
       double sacc = AT(y, i);
       if (i + 1 < m) sacc -= AT(u1, i) * y1;
@@ -840,10 +851,12 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
       ymax = fmax(ymax, fabs(yi));
     }
     const double sc = 1.0 / fmax(ymax, DBL_MIN);
+#pragma unroll 8
     for (int i = 0; i < m; ++i) AT(y, i) *= sc;
   }
   double nrm = 0.0, big = 0.0;
   int ibig = 0;
+#pragma unroll 4
   for (int i = 0; i < m; ++i) {
     const double v = AT(y, i);
     nrm += v * v;
@@ -853,6 +866,7 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
     }
   }
   const double sc = copysign(1.0 / sqrt(nrm), AT(y, ibig));
+#pragma unroll 8
   for (int i = 0; i < n; ++i)
     w.Z[static_cast<int64_t>(i) * n + j] = (i >= lo && i <= hi) ? AT(y, i - lo) * sc : 0.0;
 #undef AT

@@ -293,40 +293,57 @@ __global__ __launch_bounds__(64) void k_lvectors(int n, const double *__restrict
   const double x = lam[j - ties] + ties * pert;
   const double tiny = DBL_EPSILON * fmax(tn, DBL_MIN);
   for (int i = 0; i < m; ++i) AT(y, i) = start_value_l(j, i);
-  for (int iter = 0; iter < 2; ++iter) {
+  // LU with partial pivoting of (T_block - x I) once (branch-free, the
+  // running y_i kept in a register), forward-eliminating y; multipliers and
+  // swap flags kept for the second solve, pivots stored as reciprocals
+  // (tiny ones replaced by +-eps ||T||)
+  double *ml = lu + 4 * nn, *ms = lu + 5 * nn;
+  {
     double c0 = d[lo] - x, c1 = (m > 1) ? e[lo] : 0.0;
+    double ycur = AT(y, 0);
     for (int i = 0; i + 1 < m; ++i) {
       const double n0 = e[lo + i], n1 = d[lo + i + 1] - x;
       const double n2 = (i + 2 < m) ? e[lo + i + 1] : 0.0;
-      const double yi = AT(y, i), yn = AT(y, i + 1);
-      if (fabs(n0) > fabs(c0)) {
-        const double l = c0 / n0;
-        AT(u0, i) = n0;
-        AT(u1, i) = n1;
-        AT(u2, i) = n2;
-        AT(y, i) = yn;
-        AT(y, i + 1) = yi - l * yn;
-        c0 = c1 - l * n1;
-        c1 = -l * n2;
-      } else {
-        const double l = (c0 != 0.0) ? n0 / c0 : 0.0;
-        AT(u0, i) = c0;
-        AT(u1, i) = c1;
-        AT(u2, i) = 0.0;
-        AT(y, i + 1) = yn - l * yi;
-        c0 = n1 - l * c1;
-        c1 = n2;
-      }
+      const double yn = AT(y, i + 1);
+      const bool sw = fabs(n0) > fabs(c0);
+      const double num = sw ? c0 : n0, den = sw ? n0 : c0;
+      const double l = den != 0.0 ? num / den : 0.0;
+      AT(u0, i) = sw ? n0 : c0;
+      AT(u1, i) = sw ? n1 : c1;
+      AT(u2, i) = sw ? n2 : 0.0;
+      AT(y, i) = sw ? yn : ycur;
+      ycur = sw ? ycur - l * yn : yn - l * ycur;
+      AT(ml, i) = sw ? -1.0 : 0.0;
+      AT(ms, i) = l;
+      const double c0n = sw ? c1 - l * n1 : n1 - l * c1;
+      c1 = sw ? -l * n2 : n2;
+      c0 = c0n;
     }
+    AT(y, m - 1) = ycur;
     AT(u0, m - 1) = c0;
+  }
+  for (int i = 0; i < m; ++i) {
+    double pv = AT(u0, i);
+    if (fabs(pv) < tiny) pv = (pv < 0.0) ? -tiny : tiny;
+    AT(u0, i) = 1.0 / pv;
+  }
+  for (int iter = 0; iter < 2; ++iter) {
+    if (iter > 0) {
+      double ycur = AT(y, 0);
+      for (int i = 0; i + 1 < m; ++i) {
+        const double yn = AT(y, i + 1), l = AT(ms, i);
+        const bool sw = AT(ml, i) < 0.0;
+        AT(y, i) = sw ? yn : ycur;
+        ycur = sw ? ycur - l * yn : yn - l * ycur;
+      }
+      AT(y, m - 1) = ycur;
+    }
     double y1 = 0.0, y2 = 0.0, ymax = 0.0;
     for (int i = m - 1; i >= 0; --i) {
-      double pv = AT(u0, i);
-      if (fabs(pv) < tiny) pv = (pv < 0.0) ? -tiny : tiny;
       double sacc = AT(y, i);
       if (i + 1 < m) sacc -= AT(u1, i) * y1;
       if (i + 2 < m) sacc -= AT(u2, i) * y2;
-      const double yi = sacc / pv;
+      const double yi = sacc * AT(u0, i);
       AT(y, i) = yi;
       y2 = y1;
       y1 = yi;
