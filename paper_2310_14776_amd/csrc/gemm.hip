@@ -21,6 +21,7 @@
 // B[k][j] = psi[k][g0 + j] (16 consecutive grid points), so both operands
 // and the output are read/written in 128-byte runs.
 #include <algorithm>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -54,7 +55,18 @@ template <> struct Cx<z64> {
 
 // part[(split*nmat + mat)][nb][nb] = sum_{k in range} conj(A[n][k]) B_mat[m][k]
 // BM x BM blocks of 16x16 per wavefront (a TILE x TILE output tile).
-template <typename T, int BM>
+// four consecutive elements p[0..3] (zero when !ok) as two 16-byte loads
+template <typename T>
+__device__ inline void load4(const T *p, bool ok, T *v) {
+  typedef double dv2 __attribute__((ext_vector_type(2)));
+  constexpr int W = static_cast<int>(sizeof(T) * 4 / 16);
+  dv2 w[W];
+#pragma unroll
+  for (int q = 0; q < W; ++q) w[q] = ok ? reinterpret_cast<const dv2 *>(p)[q] : dv2{0.0, 0.0};
+  __builtin_memcpy(v, w, sizeof(T) * 4);
+}
+
+template <typename T, int BM, bool VEC>
 __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const T *__restrict__ B0,
                                                   const T *__restrict__ B1, T *__restrict__ part,
                                                   int nb, int64_t ng, int64_t kchunk, int tiles_n,
@@ -105,18 +117,31 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
 #pragma unroll
       for (int j = 0; j < BM; ++j) acc[c][i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int64_t kg = kb + wave * 16; kg < ke; kg += 64) {
+  // Software pipeline: the operands of the wavefront's next 16-wide K step
+  // are requested before the MFMAs of the current one (two register
+  // buffers), so the load latency hides behind the matrix-core work.
+  auto load_step = [&](int64_t kg, T (&a)[BM][4], T (&b)[BM][4]) {
     const int64_t k = kg + 4 * kq;
-    T a[BM][4], b[BM][4];
     const bool full = kg + 16 <= ke;
+    if (VEC && full) {
+      // four consecutive k of a row: two 16-byte loads (rows 32-byte aligned)
 #pragma unroll
-    for (int q = 0; q < BM; ++q)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const bool in = full || k + s < ke;
-        a[q][s] = (av[q] && in) ? ap[q][k + s] : T{};
-        b[q][s] = (bv[q] && in) ? bp[q][k + s] : T{};
+      for (int q = 0; q < BM; ++q) {
+        load4(ap[q] + k, av[q], a[q]);
+        load4(bp[q] + k, bv[q], b[q]);
       }
+    } else {
+#pragma unroll
+      for (int q = 0; q < BM; ++q)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const bool in = k + s < ke;
+          a[q][s] = (av[q] && in) ? ap[q][k + s] : T{};
+          b[q][s] = (bv[q] && in) ? bp[q][k + s] : T{};
+        }
+    }
+  };
+  auto compute = [&](const T (&a)[BM][4], const T (&b)[BM][4]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -132,6 +157,17 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
             acc[NP - 1][i][j] = mfma(-ay, bx, acc[NP - 1][i][j]);
           }
         }
+  };
+  T a0[BM][4], b0[BM][4], a1[BM][4], b1[BM][4];
+  int64_t kg = kb + wave * 16;
+  if (kg < ke) load_step(kg, a0, b0);
+  for (; kg < ke; kg += 128) {
+    const bool more = kg + 64 < ke;
+    if (more) load_step(kg + 64, a1, b1);
+    compute(a0, b0);
+    if (!more) break;
+    if (kg + 128 < ke) load_step(kg + 128, a0, b0);
+    compute(a1, b1);
   }
 
   // fixed-order sum of the four wavefronts' tiles: (w0 + w2) + (w1 + w3)
@@ -356,10 +392,18 @@ int subspace_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const void 
   T *part = reinterpret_cast<T *>(s->ws.part);
   const int64_t slots = p.nsplit >= 8 ? (p.nsplit + 7) / 8 * 8 : p.nsplit;
   const int64_t wgs = slots * p.tiles * nmat;
-  k_subspace<T, BM><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
-      static_cast<const T *>(psi), static_cast<const T *>(Hpsi),
-      static_cast<const T *>(Spsi ? Spsi : Hpsi), part, nb, s->ng, p.kchunk, p.tiles_n, nmat,
-      p.nsplit);
+  // rows are 32-byte aligned when Ng is a multiple of 4 (the tensors' bases are)
+  const bool vec = (s->ng % 4) == 0 &&
+                   (reinterpret_cast<uintptr_t>(psi) | reinterpret_cast<uintptr_t>(Hpsi) |
+                    reinterpret_cast<uintptr_t>(Spsi ? Spsi : Hpsi)) % 32 == 0;
+  auto go = [&](auto vflag) {
+    k_subspace<T, BM, decltype(vflag)::value><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
+        static_cast<const T *>(psi), static_cast<const T *>(Hpsi),
+        static_cast<const T *>(Spsi ? Spsi : Hpsi), part, nb, s->ng, p.kchunk, p.tiles_n, nmat,
+        p.nsplit);
+  };
+  if (vec) go(std::true_type{});
+  else go(std::false_type{});
   const int64_t tot = static_cast<int64_t>(nb) * nb * nmat;
   k_subspace_reduce<T><<<static_cast<unsigned>((tot + 255) / 256), 256, 0, st>>>(
       part, static_cast<T *>(H), static_cast<T *>(S), nb, p.nsplit, nmat, s->dV);
