@@ -55,14 +55,14 @@ template <> struct Cx<z64> {
 
 // part[(split*nmat + mat)][nb][nb] = sum_{k in range} conj(A[n][k]) B_mat[m][k]
 // BM x BM blocks of 16x16 per wavefront (a TILE x TILE output tile).
-// four consecutive elements p[0..3] (zero when !ok) as two 16-byte loads
+// four consecutive elements p[0..3] as 16-byte loads
 template <typename T>
-__device__ inline void load4(const T *p, bool ok, T *v) {
+__device__ inline void load4(const T *p, T *v) {
   typedef double dv2 __attribute__((ext_vector_type(2)));
   constexpr int W = static_cast<int>(sizeof(T) * 4 / 16);
   dv2 w[W];
 #pragma unroll
-  for (int q = 0; q < W; ++q) w[q] = ok ? reinterpret_cast<const dv2 *>(p)[q] : dv2{0.0, 0.0};
+  for (int q = 0; q < W; ++q) w[q] = reinterpret_cast<const dv2 *>(p)[q];
   __builtin_memcpy(v, w, sizeof(T) * 4);
 }
 
@@ -96,17 +96,14 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
   const int64_t ke = std::min(ng, kb + kchunk);
   const int r = lane & 15, kq = lane >> 4;
 
+  // rows past nb are clamped to the last row: they only feed outputs that
+  // are never stored
   const T *ap[BM];
   const T *bp[BM];
-  bool av[BM], bv[BM];
 #pragma unroll
   for (int q = 0; q < BM; ++q) {
-    const int ra = tm * TILE + q * 16 + r;
-    const int rb = tn * TILE + q * 16 + r;
-    av[q] = ra < nb;
-    bv[q] = rb < nb;
-    ap[q] = A + static_cast<int64_t>(av[q] ? ra : 0) * ng;
-    bp[q] = B + static_cast<int64_t>(bv[q] ? rb : 0) * ng;
+    ap[q] = A + static_cast<int64_t>(std::min(tm * TILE + q * 16 + r, nb - 1)) * ng;
+    bp[q] = B + static_cast<int64_t>(std::min(tn * TILE + q * 16 + r, nb - 1)) * ng;
   }
 
   d4 acc[NP][BM][BM];
@@ -117,30 +114,6 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
 #pragma unroll
       for (int j = 0; j < BM; ++j) acc[c][i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  // Software pipeline: the operands of the wavefront's next 16-wide K step
-  // are requested before the MFMAs of the current one (two register
-  // buffers), so the load latency hides behind the matrix-core work.
-  auto load_step = [&](int64_t kg, T (&a)[BM][4], T (&b)[BM][4]) {
-    const int64_t k = kg + 4 * kq;
-    const bool full = kg + 16 <= ke;
-    if (VEC && full) {
-      // four consecutive k of a row: two 16-byte loads (rows 32-byte aligned)
-#pragma unroll
-      for (int q = 0; q < BM; ++q) {
-        load4(ap[q] + k, av[q], a[q]);
-        load4(bp[q] + k, bv[q], b[q]);
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < BM; ++q)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const bool in = k + s < ke;
-          a[q][s] = (av[q] && in) ? ap[q][k + s] : T{};
-          b[q][s] = (bv[q] && in) ? bp[q][k + s] : T{};
-        }
-    }
-  };
   auto compute = [&](const T (&a)[BM][4], const T (&b)[BM][4]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -158,16 +131,59 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
           }
         }
   };
-  T a0[BM][4], b0[BM][4], a1[BM][4], b1[BM][4];
-  int64_t kg = kb + wave * 16;
-  if (kg < ke) load_step(kg, a0, b0);
-  for (; kg < ke; kg += 128) {
-    const bool more = kg + 64 < ke;
-    if (more) load_step(kg + 64, a1, b1);
-    compute(a0, b0);
-    if (!more) break;
-    if (kg + 128 < ke) load_step(kg + 128, a0, b0);
-    compute(a1, b1);
+  // The wavefront's full 16-wide K steps run as a software pipeline: a ring
+  // of D register buffers, each step's operands requested D steps before its
+  // MFMAs. Every load in the ring is unconditional and in bounds (the
+  // prefetch past the last step re-reads it), so no branch sits between a
+  // load and its use and the waits count down instead of draining.
+  const int64_t k0 = kb + wave * 16;
+  const int64_t nfull = ke - k0 >= 16 ? (ke - k0 - 16) / 64 + 1 : 0;
+  auto load_full = [&](int64_t t, T (&a)[BM][4], T (&b)[BM][4]) {
+    const int64_t k = k0 + 64 * t + 4 * kq;
+    if constexpr (VEC) {
+      // four consecutive k of a row: 16-byte loads (rows 32-byte aligned)
+#pragma unroll
+      for (int q = 0; q < BM; ++q) {
+        load4(ap[q] + k, a[q]);
+        load4(bp[q] + k, b[q]);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < BM; ++q)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          a[q][s] = ap[q][k + s];
+          b[q][s] = bp[q][k + s];
+        }
+    }
+  };
+  constexpr int D = 3;
+  T a[D][BM][4], b[D][BM][4];
+  if (nfull > 0) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) load_full(std::min<int64_t>(d, nfull - 1), a[d], b[d]);
+  }
+  for (int64_t t = 0; t < nfull; t += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (t + d < nfull) compute(a[d], b[d]);
+      load_full(std::min<int64_t>(t + d + D, nfull - 1), a[d], b[d]);
+    }
+  }
+  // at most one partial step (the end of the last K chunk): masked loads
+  {
+    const int64_t k = k0 + 64 * nfull + 4 * kq;
+    if (k0 + 64 * nfull < ke) {
+#pragma unroll
+      for (int q = 0; q < BM; ++q)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const bool in = k + s < ke;
+          a[0][q][s] = in ? ap[q][k + s] : T{};
+          b[0][q][s] = in ? bp[q][k + s] : T{};
+        }
+      compute(a[0], b[0]);
+    }
   }
 
   // fixed-order sum of the four wavefronts' tiles: (w0 + w2) + (w1 + w3)
@@ -285,31 +301,53 @@ __global__ __launch_bounds__(256) void k_rotate(const T *__restrict__ C, const T
 #pragma unroll
       for (int q = 0; q < 2; ++q) acc[c][i][q] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int m0 = 0; m0 < nb; m0 += 4) {
-    const int m = m0 + kq;
-    const bool mv = m < nb;
-    T a[RB], b[2];
+  // Clamped addresses keep every load unconditional and in bounds (branches
+  // around loads would force a full wait at each loop turn): rows n >= nb
+  // and columns g >= cols only feed outputs that are never stored, and the
+  // steps past m = nb are zeroed on the src side where they are used.
+  const T *cp[RB];
+  const T *sp[2];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-      const int n = n0 + rb * 16 + j;
-      a[rb] = (mv && n < nb) ? C[static_cast<int64_t>(m) * nb + n] : T{};
-    }
+  for (int rb = 0; rb < RB; ++rb) cp[rb] = C + std::min(n0 + rb * 16 + j, nb - 1);
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-      b[cb] = (mv && gv[cb]) ? src[static_cast<int64_t>(m) * cols + gc[cb]] : T{};
+  for (int cb = 0; cb < 2; ++cb) sp[cb] = src + std::min<int64_t>(gc[cb], cols - 1);
+  auto load_step = [&](int m0, T (&a)[RB], T (&b)[2]) {
+    const int64_t m = std::min(m0 + kq, nb - 1);
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < RB; ++rb) a[rb] = cp[rb][m * nb];
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb) {
-        const double ax = Cx<T>::re(a[rb]), bx = Cx<T>::re(b[cb]);
-        acc[0][rb][cb] = mfma(ax, bx, acc[0][rb][cb]);
-        if constexpr (NP == 2) {
-          const double ay = Cx<T>::im(a[rb]), by = Cx<T>::im(b[cb]);
-          acc[0][rb][cb] = mfma(-ay, by, acc[0][rb][cb]);
-          acc[NP - 1][rb][cb] = mfma(ax, by, acc[NP - 1][rb][cb]);
-          acc[NP - 1][rb][cb] = mfma(ay, bx, acc[NP - 1][rb][cb]);
-        }
+    for (int cb = 0; cb < 2; ++cb) b[cb] = sp[cb][m * cols];
+  };
+  // a ring of D steps in flight: step s is requested D steps before its
+  // MFMAs run, so the HBM latency of the src stream hides behind them
+  constexpr int D = 4;
+  T a[D][RB], b[D][2];
+#pragma unroll
+  for (int d = 0; d < D; ++d) load_step(4 * d, a[d], b[d]);
+  for (int m0 = 0; m0 < nb; m0 += 4 * D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      if (m0 + 4 * d < nb) {
+        const bool mv = m0 + 4 * d + kq < nb;
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+          if (!mv) b[d][cb] = T{};
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) {
+            const double ax = Cx<T>::re(a[d][rb]), bx = Cx<T>::re(b[d][cb]);
+            acc[0][rb][cb] = mfma(ax, bx, acc[0][rb][cb]);
+            if constexpr (NP == 2) {
+              const double ay = Cx<T>::im(a[d][rb]), by = Cx<T>::im(b[d][cb]);
+              acc[0][rb][cb] = mfma(-ay, by, acc[0][rb][cb]);
+              acc[NP - 1][rb][cb] = mfma(ax, by, acc[NP - 1][rb][cb]);
+              acc[NP - 1][rb][cb] = mfma(ay, bx, acc[NP - 1][rb][cb]);
+            }
+          }
       }
+      load_step(m0 + 4 * (d + D), a[d], b[d]);
+    }
   }
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb)
