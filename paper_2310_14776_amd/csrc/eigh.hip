@@ -7,7 +7,7 @@
 //   k_eig_chol     (1 workgroup, matrix in LDS) S <- (S+S^T)/2 = L L^T and
 //                  Linv = L^-1, blocked by 16x16 tiles on FP64 MFMA;
 //   k_small_gemm   A = Linv ((H+H^T)/2) Linv^T on FP64 MFMA (two products);
-//   k_eig_tridiag  (1 workgroup, A in LDS) Householder A = Q T Q^T;
+//   k_eig_tridiag  (1 workgroup, A in registers) Householder A = Q T Q^T;
 //   k_eig_values   (one wavefront per eigenvalue) T splits where
 //                  |e_i| <= eps (|d_i| + |d_i+1|); each eigenvalue is found in
 //                  its unreduced block by 65-way multisection on Sturm counts;
@@ -457,176 +457,211 @@ __global__ __launch_bounds__(SG_T) void k_small_gemm(const T *__restrict__ A,
 }
 
 // ------------------------------------------------------------------ tridiagonal
-// A (global, made Hermitian on load) -> LDS; Householder A = Q T Q^H with
-// H_k = I - tau_k v_k v_k^H chosen so that T is real symmetric (the
-// sub-diagonal beta_k is real). Reflector k is kept in column k of A below
-// the diagonal (that column is not read again), so the loop issues no
-// global stores; V, tau, d, e go out at the end.
-// Householder reflector of the column x = A[k+1.., col] (in LDS, wave 0):
-// H = I - tau v v^H with v_0 = 1 maps x to (beta, 0, ..., 0), beta real.
-// Writes v into vout[k+1..] and into the column (that column is not read
-// again), tau/beta/d into the tables.
+// Householder A = Q T Q^H with H_k = I - tau_k v_k v_k^H chosen so that T is
+// real symmetric (the sub-diagonal beta_k is real).
+//
+// Four wavefronts hold the whole (Hermitian, zero-padded) matrix in
+// registers: lane (ty, tx) (32 x 8) owns rows ty + 32i and columns tx + 8j,
+// RR x RC elements (4 x 16 real, 3 x 12 complex), so neither p = tau A v nor
+// the rank-2 update A -= v w^H + w v^H touches LDS, and a row's partial
+// products are summed over 8 lanes on DPP. A fifth wavefront builds the
+// reflectors. Each step k:
+//   A  (matrix waves) p over the live rows to LDS (zero at rows <= k); the
+//      owners of row k+1 copy it, conjugated, to LDS as column k+1;
+//   B  every wavefront forms K = -tau/2 p^H v (w = p + K v); the reflector
+//      wave updates column k+1 (rows > k, two per lane, in registers) and
+//      builds reflector k+1 from it while the matrix waves apply the rank-2
+//      update to their rows > k;
+// two barriers per step. Row blocks that are finished (all rows <= k) skip
+// their arithmetic on wavefront-uniform branches.
+constexpr int TRI_T = 320;
+
+// 8-lane DPP sum (lanes 8q..8q+7; every lane of the group gets it)
+__device__ inline z64 group8_sum_z(z64 v) { return z64{group8_sum(v.x), group8_sum(v.y)}; }
+__device__ inline double sum8(double v) { return group8_sum(v); }
+__device__ inline z64 sum8(z64 v) { return group8_sum_z(v); }
+__device__ inline z64 lane_read(z64 v, int lane) { return z64{lane_read(v.x, lane), lane_read(v.y, lane)}; }
+
+// a - x y and a + x y as fused multiply-adds
+__device__ inline double fms(double a, double x, double y) { return fma(-x, y, a); }
+__device__ inline z64 fms(z64 a, z64 x, z64 y) {
+  return z64{fma(x.y, y.y, fma(-x.x, y.x, a.x)), fma(-x.y, y.x, fma(-x.x, y.y, a.y))};
+}
+__device__ inline double fmad(double a, double x, double y) { return fma(x, y, a); }
+__device__ inline z64 fmad(z64 a, z64 x, z64 y) {
+  return z64{fma(-x.y, y.y, fma(x.x, y.x, a.x)), fma(x.y, y.x, fma(x.x, y.y, a.y))};
+}
+
+// LDS shared by the two roles
+template <typename T> struct TriLds {
+  static constexpr int NM = EigMax<T>::n;
+  T vb[2][NM];  // reflectors k and k+1 (zero at rows <= k and >= n)
+  T pb[NM];     // p = tau A v (zero at rows <= k)
+  T col[NM];    // column k+1
+  T taus[NM];
+  double dd[NM], ee[NM];
+};
+
+// Reflector k from x = column k at rows r0 = k + lane and r1 = r0 + 64 (one
+// wavefront; row k is the diagonal): H = I - tau v v^H with v_k+1 = 1 maps
+// x[k+1..] to (beta, 0, ..., 0), beta real. Writes v to vout and to row k of
+// V (zeros at rows <= k and >= n), tau and beta to the tables.
 template <typename T>
-__device__ inline void make_reflector(T *A, int lda, int n, int k, T *vout, T *taus, double *dd,
-                                      double *ee) {
+__device__ inline void tri_reflector(int n, int k, T x0, T x1, T *vout, TriLds<T> &L, T *Vg) {
+  constexpr int NM = EigMax<T>::n;
   const int lane = threadIdx.x & 63;
-  double xn2 = 0.0;
-  for (int r = k + 2 + lane; r < n; r += 64) xn2 += abs2(A[r * lda + k]);
-  xn2 = wave_sum(xn2);
-  const T alpha = A[(k + 1) * lda + k];
+  const int r0 = k + lane, r1 = r0 + 64;
+  const double s2 = (lane >= 2 && r0 < n ? abs2(x0) : 0.0) + (r1 < n ? abs2(x1) : 0.0);
+  const double xn2 = wave_sum(s2);
+  const T alpha = lane_read(x0, 1);
   const double ar = re_of(alpha);
   double beta;
-  T tau, scl;
+  T tn, scl;
   if (xn2 == 0.0 && abs2(alpha) == ar * ar) {
     beta = ar;
-    tau = T{};
+    tn = T{};
     scl = T{};
   } else {
     beta = -copysign(sqrt(abs2(alpha) + xn2), ar);
     // tau = (beta - alpha)/beta, scl = 1/(alpha - beta)
     const T amb = alpha - realv<T>(beta);
-    tau = St<T>::scale(-1.0 / beta, amb);
+    tn = St<T>::scale(-1.0 / beta, amb);
     scl = cj(amb) * (1.0 / abs2(amb));
   }
-  for (int r = k + 1 + lane; r < n; r += 64) {
-    const T vr = (r == k + 1) ? realv<T>(1.0) : A[r * lda + k] * scl;
-    vout[r] = vr;
-    A[r * lda + k] = vr;
-  }
+  const T y0 = lane == 1 ? realv<T>(1.0) : (lane >= 2 && r0 < n ? x0 * scl : T{});
+  const T y1 = r1 < n ? x1 * scl : T{};
+  if (r0 < NM) vout[r0] = y0;
+  if (r1 < NM) vout[r1] = y1;
+  T *Vk = Vg + static_cast<int64_t>(k) * n;
+  if (r0 < n) Vk[r0] = y0;
+  if (r1 < n) Vk[r1] = y1;
+  for (int r = lane; r < k; r += 64) Vk[r] = T{};
   if (lane == 0) {
-    taus[k] = tau;
-    dd[k] = re_of(A[k * lda + k]);
-    ee[k] = beta;
+    if (k > 0) vout[k - 1] = T{};  // left over from reflector k - 2
+    L.taus[k] = tn;
+    L.ee[k] = beta;
   }
 }
 
-// A (global, made Hermitian on load) -> LDS; Householder A = Q T Q^H with
-// H_k = I - tau_k v_k v_k^H chosen so that T is real symmetric (the
-// sub-diagonal beta_k is real). Reflector k is kept in column k of A below
-// the diagonal. Each step: p = tau A v (8 lanes per row), then the rank-2
-// update A -= v w^H + w v^H with w = p - (tau/2)(p^H v) v; wavefront 0
-// updates column k+1 itself and builds reflector k+1 from it while the other
-// wavefronts update the rest, so a step costs two barriers.
 template <typename T>
-__global__ __launch_bounds__(EIG_T) void k_eig_tridiag(int n, EigWs w, const int32_t *info) {
+__global__ __launch_bounds__(TRI_T) void k_eig_tridiag(int n, EigWs w, const int32_t *info) {
   if (*info != 0) return;
-  extern __shared__ double sm[];
-  const int lda = n + 1;
-  T *A = reinterpret_cast<T *>(sm);
-  T *vbuf = A + n * lda;  // two reflector buffers [2][n]
-  T *pp = vbuf + 2 * n;
-  T *taus = pp + n;
-  double *dd = reinterpret_cast<double *>(taus + n);
-  double *ee = dd + n;
-  T *red = reinterpret_cast<T *>(ee + n);  // 16 wavefront partials
+  constexpr int NM = EigMax<T>::n, RR = NM / 32, RC = NM / 8;
+  __shared__ TriLds<T> L;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int ty = tid >> 5, tx = tid & 31;
-  const T *Ag = as<T>(w.A);
-  // loads of a thread issued in batches (all 32 for real data, 8 for
-  // complex), then the symmetrised stores
-  constexpr int AB = St<T>::cplx ? 1 : 4;
+  T *Vg = as<T>(w.V);
+  // the two roles run separate loops with the same barriers
+  if (wave < 4) {
+    const int ty = tid >> 3, tx = tid & 7;
+    const T *Ag = as<T>(w.A);
+    // (A + A^H)/2, zero outside n x n
+    T a[RR][RC];
 #pragma unroll
-  for (int a0 = 0; a0 < 4; a0 += AB) {
-    T ga[AB][4], gb[AB][4];
+    for (int i = 0; i < RR; ++i)
 #pragma unroll
-    for (int a = 0; a < AB; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int r = ty + 32 * (a0 + a), c = tx + 32 * b;
+      for (int j = 0; j < RC; ++j) {
+        const int r = ty + 32 * i, c = tx + 8 * j;
         const bool in = r < n && c < n;
-        ga[a][b] = in ? Ag[r * n + c] : T{};
-        gb[a][b] = in ? Ag[c * n + r] : T{};
+        a[i][j] = in ? St<T>::scale(0.5, Ag[r * n + c] + cj(Ag[c * n + r])) : T{};
       }
+    if (ty == 0)
 #pragma unroll
-    for (int a = 0; a < AB; ++a)
+      for (int j = 0; j < RC; ++j) L.col[tx + 8 * j] = cj(a[0][j]);
+    __syncthreads();  // column 0 ready
+    __syncthreads();  // reflector 0 ready
+    for (int k = 0; k + 1 < n; ++k) {
+      const T *v = L.vb[k & 1];
+      const T tau = L.taus[k];
+      const int c1 = k + 1;
+      T vr[RR], vc[RC];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int r = ty + 32 * (a0 + a), c = tx + 32 * b;
-        if (r < n && c < n) A[r * lda + c] = St<T>::scale(0.5, ga[a][b] + cj(gb[a][b]));
+      for (int i = 0; i < RR; ++i) vr[i] = v[ty + 32 * i];
+#pragma unroll
+      for (int j = 0; j < RC; ++j) vc[j] = v[tx + 8 * j];
+      // row c1 as it stands (conjugated: column c1) to LDS by its owners;
+      // one uniform branch per candidate block, constant register indices
+      if (ty == (c1 & 31)) {
+        const int ib = c1 >> 5;
+#pragma unroll
+        for (int i = 0; i < RR; ++i)
+          if (i == ib)
+#pragma unroll
+            for (int j = 0; j < RC; ++j) L.col[tx + 8 * j] = cj(a[i][j]);
       }
-  }
-  __syncthreads();
-  if (n >= 2 && wave == 0) make_reflector<T>(A, lda, n, 0, vbuf, taus, dd, ee);
-  if (n == 1 && tid == 0) dd[0] = re_of(A[0]);
-  __syncthreads();
-
-  for (int k = 0; k + 1 < n; ++k) {
-    const T *vv = vbuf + (k & 1) * n;
-    T *vnext = vbuf + ((k + 1) & 1) * n;
-    const T tau = taus[k];
-    {
-      // row r of p = tau A v by 8 lanes
-      const int r = k + 1 + (tid >> 3), s = tid & 7;
-      T part = T{};
-      if (r < n) {
-        const T *Ar = A + r * lda;
-        for (int c = k + 1 + s; c < n; c += 8) part = part + Ar[c] * vv[c];
-      }
-      part = group8_sum(part);
-      T contrib = T{};
-      if (r < n && s == 0) {
-        const T p = tau * part;
-        pp[r] = p;
-        contrib = cj(p) * vv[r];
-      }
-      contrib = wave_sum(contrib);
-      if (lane == 0) red[wave] = contrib;
-    }
-    __syncthreads();
-    T pv = T{};
+      // p = tau A v over the live row blocks (two accumulators per row)
 #pragma unroll
-    for (int q = 0; q < EIG_T / 64; ++q) pv = pv + red[q];
-    const T K = St<T>::scale(-0.5, tau * pv);
-    const int c1 = k + 1;
-    if (wave == 0) {
-      // column k+1 of the updated matrix, then reflector k+1 from it
-      const T v1 = cj(vv[c1]), w1 = cj(pp[c1] + K * vv[c1]);
-      for (int r = c1 + lane; r < n; r += 64) {
-        const T vr = vv[r], wr = pp[r] + K * vv[r];
-        A[r * lda + c1] = A[r * lda + c1] - (vr * w1 + wr * v1);
-      }
-      if (c1 + 1 < n) make_reflector<T>(A, lda, n, c1, vnext, taus, dd, ee);
-      else if (lane == 0) dd[c1] = re_of(A[c1 * lda + c1]);
-    }
-    {
-      T vc[4], wc[4];
+      for (int i = 0; i < RR; ++i) {
+        if (32 * i + 31 <= k) continue;
+        T s0 = T{}, s1 = T{};
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int c = tx + 32 * b;
-        const bool in = c > c1 && c < n;
-        vc[b] = in ? cj(vv[c]) : T{};
-        wc[b] = in ? cj(pp[c] + K * vv[c]) : T{};
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int r = ty + 32 * a;
-        if (r <= c1 || r >= n) continue;
-        const T vr = vv[r], wr = pp[r] + K * vv[r];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int c = tx + 32 * b;
-          if (c > c1 && c < n) A[r * lda + c] = A[r * lda + c] - (vr * wc[b] + wr * vc[b]);
+        for (int j = 0; j < RC; j += 2) {
+          s0 = fmad(s0, a[i][j], vc[j]);
+          s1 = fmad(s1, a[i][j + 1], vc[j + 1]);
         }
+        const T sum = sum8(s0 + s1);
+        const int r = ty + 32 * i;
+        if (tx == 0) L.pb[r] = r > k ? tau * sum : T{};
       }
+      __syncthreads();  // p and column c1 ready
+      // K = -tau/2 p^H v over all rows (p and v vanish at rows <= k)
+      T pv = cj(L.pb[lane]) * v[lane];
+      if (lane + 64 < NM) pv = pv + cj(L.pb[lane + 64]) * v[lane + 64];
+      pv = wave_sum(pv);
+      const T K = St<T>::scale(-0.5, tau * pv);
+      // A -= v w^H + w v^H on the live row blocks (w vanishes at rows <= k)
+      T wr[RR], wc[RC];
+#pragma unroll
+      for (int i = 0; i < RR; ++i) wr[i] = L.pb[ty + 32 * i] + K * vr[i];
+#pragma unroll
+      for (int j = 0; j < RC; ++j) {
+        wc[j] = cj(L.pb[tx + 8 * j] + K * vc[j]);
+        vc[j] = cj(vc[j]);
+      }
+#pragma unroll
+      for (int i = 0; i < RR; ++i) {
+        if (32 * i + 31 <= k) continue;
+#pragma unroll
+        for (int j = 0; j < RC; ++j) a[i][j] = fms(fms(a[i][j], vr[i], wc[j]), wr[i], vc[j]);
+      }
+      __syncthreads();  // reflector c1 ready, update done
     }
-    __syncthreads();
+  } else {
+    for (int idx = lane; idx < 2 * NM; idx += 64) L.vb[idx / NM][idx % NM] = T{};
+    __syncthreads();  // column 0 ready
+    if (n >= 2)
+      tri_reflector<T>(n, 0, L.col[lane], lane + 64 < NM ? L.col[lane + 64] : T{}, L.vb[0], L, Vg);
+    if (lane == 0) L.dd[0] = re_of(L.col[0]);
+    __syncthreads();  // reflector 0 ready
+    for (int k = 0; k + 1 < n; ++k) {
+      const T *v = L.vb[k & 1];
+      const T tau = L.taus[k];
+      const int c1 = k + 1;
+      __syncthreads();  // p and column c1 ready
+      // column c1 on rows r0 = c1 + lane, r1 = r0 + 64 (v_c1 = 1: reflector
+      // k starts with a unit entry): x = col - v conj(w_c1) - w, w = p + K v
+      const int r0 = c1 + lane, r1 = r0 + 64;
+      const T p0 = r0 < NM ? L.pb[r0] : T{}, p1 = r1 < NM ? L.pb[r1] : T{};
+      const T v0 = r0 < NM ? v[r0] : T{}, v1 = r1 < NM ? v[r1] : T{};
+      const T c0 = r0 < NM ? L.col[r0] : T{}, cc1 = r1 < NM ? L.col[r1] : T{};
+      const T pc1 = L.pb[c1];
+      const T pv = wave_sum(cj(p0) * v0 + cj(p1) * v1);
+      const T K = St<T>::scale(-0.5, tau * pv);
+      const T w1c = cj(pc1 + K);
+      const T x0 = c0 - v0 * w1c - (p0 + K * v0);
+      const T x1 = cc1 - v1 * w1c - (p1 + K * v1);
+      if (lane == 0) L.dd[c1] = re_of(x0);
+      if (c1 + 1 < n) tri_reflector<T>(n, c1, x0, x1, L.vb[(k + 1) & 1], L, Vg);
+      __syncthreads();  // reflector c1 ready, update done
+    }
   }
   T *tg = as<T>(w.tau);
-  for (int i = tid; i < n; i += EIG_T) {
-    w.d[i] = dd[i];
-    w.e[i] = (i + 1 < n) ? ee[i] : 0.0;
-    tg[i] = (i + 1 < n) ? taus[i] : T{};
+  for (int i = tid; i < n; i += TRI_T) {
+    w.d[i] = L.dd[i];
+    w.e[i] = (i + 1 < n) ? L.ee[i] : 0.0;
+    tg[i] = (i + 1 < n) ? L.taus[i] : T{};
+    Vg[static_cast<int64_t>(n - 1) * n + i] = T{};  // no reflector n-1
   }
-  // V[k][r] = reflector k at row r (rows k+1.., zero elsewhere)
-  T *V = as<T>(w.V);
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int k = ty + 32 * a, r = tx + 32 * b;
-      if (k < n && r < n) V[k * n + r] = (k + 1 < n && r > k) ? A[r * lda + k] : T{};
-    }
 }
 
 // ------------------------------------------------------------------ values
@@ -1010,7 +1045,6 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
   static hipError_t attr_err = hipSuccess;
   std::call_once(once, [] {
     const void *fns[] = {reinterpret_cast<const void *>(&k_eig_chol<T>),
-                         reinterpret_cast<const void *>(&k_eig_tridiag<T>),
                          reinterpret_cast<const void *>(&k_eig_back<T>)};
     for (const void *f : fns)
       if (attr_err == hipSuccess)
@@ -1022,7 +1056,6 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
   const EigWs w = eig_layout(s->ws.eig, n, sz, false);
   const T *Hd = static_cast<const T *>(H);
   const T *Sd = static_cast<const T *>(S);
-  const size_t lda_bytes = (static_cast<size_t>(n) * (n + 1)) * sizeof(T);
   const int tiles = ((n + 15) / 16) * ((n + 15) / 16);
   const unsigned sg_blocks = static_cast<unsigned>((tiles + 3) / 4);
   T *Linv = reinterpret_cast<T *>(w.Linv), *T1 = reinterpret_cast<T *>(w.T1);
@@ -1032,8 +1065,7 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
   // A = Linv ((H + H^H)/2) Linv^H
   k_small_gemm<T, 2, 1><<<sg_blocks, SG_T, 0, st>>>(Hd, Linv, T1, n, info);
   k_small_gemm<T, 0, 0><<<sg_blocks, SG_T, 0, st>>>(Linv, T1, Am, n, info);
-  k_eig_tridiag<T><<<1, EIG_T, lda_bytes + 4 * n * sizeof(T) + 2 * n * sizeof(double) + 16 * sizeof(T),
-                     st>>>(n, w, info);
+  k_eig_tridiag<T><<<1, TRI_T, 0, st>>>(n, w, info);
   k_eig_values<<<(n + 3) / 4, 256, 3 * n * sizeof(double), st>>>(n, w.d, w.e, w.lam, info);
   k_eig_vectors<<<(n + VEC_T - 1) / VEC_T, VEC_T, (3 * n + 6 * n * VEC_T) * sizeof(double), st>>>(
       n, w, info);
