@@ -784,62 +784,97 @@ __device__ inline double start_value(int j, int i) {
   return static_cast<double>(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
+// LDS doubles of k_eig_vectors: d, e, lam, row sums, split words, then six
+// per-lane arrays of n (interleaved by lane)
+inline size_t vec_lds_doubles(int n) { return 4 * static_cast<size_t>(n) + 8 + 6 * n * VEC_T; }
+
 __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int32_t *info) {
   if (*info != 0) return;
   extern __shared__ double sv[];
-  double *d = sv, *e = sv + n, *lam = sv + 2 * n;
-  double *scratch = sv + 3 * n;
+  double *d = sv, *e = sv + n, *lam = sv + 2 * n, *rs = sv + 3 * n;
+  unsigned *spw = reinterpret_cast<unsigned *>(sv + 4 * n);  // split bits, 32 per word
+  double *scratch = sv + 4 * n + 8;
   const int t = threadIdx.x;
   copy_rounds(d, w.d, n, t, VEC_T);
   copy_rounds(e, w.e, n, t, VEC_T);
   copy_rounds(lam, w.lam, n, t, VEC_T);
   __syncthreads();
-  if (t == 0) e[n - 1] = 0.0;
+  // split points (the block boundary between i and i + 1) as bit words, and
+  // the row sums |d_i| + |e_i-1| + |e_i| within the blocks
+  const int nw = (n + 31) / 32;
+  for (int q = t; q < nw; q += VEC_T) {
+    unsigned bits = 0;
+    for (int b = 0; b < 32; ++b) {
+      const int i = 32 * q + b;
+      if (i + 1 < n && split_at(d, e, i)) bits |= 1u << b;
+    }
+    spw[q] = bits;
+  }
+  __syncthreads();
+  auto split = [&](int i) { return (spw[i >> 5] >> (i & 31)) & 1u; };
+  for (int i = t; i < n; i += VEC_T)
+    rs[i] = fabs(d[i]) + (i > 0 && !split(i - 1) ? fabs(e[i - 1]) : 0.0) +
+            (i + 1 < n && !split(i) ? fabs(e[i]) : 0.0);
   __syncthreads();
   const int j = blockIdx.x * VEC_T + t;
   if (j >= n) return;
-  double *u0 = scratch + 0 * n * VEC_T + t;
+  // the unreduced block [lo, hi] holding eigenvalue j: lo follows the last
+  // split below j, hi is the first split at or above j
+  int lo = 0, hi = n - 1;
+  for (int q = (j - 1) >> 5; j > 0 && q >= 0; --q) {
+    unsigned bits = spw[q];
+    if (q == (j - 1) >> 5) bits &= (((j - 1) & 31) == 31) ? ~0u : ((2u << ((j - 1) & 31)) - 1u);
+    if (bits) {
+      lo = 32 * q + 31 - __builtin_clz(bits) + 1;
+      break;
+    }
+  }
+  for (int q = j >> 5; q < nw; ++q) {
+    unsigned bits = spw[q];
+    if (q == j >> 5) bits &= ~((1u << (j & 31)) - 1u);
+    if (bits) {
+      hi = 32 * q + __builtin_ctz(bits);
+      break;
+    }
+  }
+  const int m = hi - lo + 1;
+  double tn = 0.0;
+#pragma unroll 8
+  for (int i = lo; i <= hi; ++i) tn = fmax(tn, rs[i]);
+  const double pert = 10.0 * DBL_EPSILON * fmax(tn, DBL_MIN);
+  int ties = 0;
+  for (int i = j; i > lo && lam[i] - lam[i - 1] < pert; --i) ++ties;
+  const double x = lam[j - ties] + ties * pert;
+  const double tiny = DBL_EPSILON * fmax(tn, DBL_MIN);
+  auto recip_pivot = [&](double p) { return 1.0 / (fabs(p) < tiny ? (p < 0.0 ? -tiny : tiny) : p); };
+
+  double *u0 = scratch + 0 * n * VEC_T + t;  // reciprocal pivots
   double *u1 = scratch + 1 * n * VEC_T + t;
   double *u2 = scratch + 2 * n * VEC_T + t;
   double *y = scratch + 3 * n * VEC_T + t;
   double *ml = scratch + 4 * n * VEC_T + t;  // < 0 where rows were swapped
   double *ms = scratch + 5 * n * VEC_T + t;  // row multipliers
 #define AT(p, i) (p)[(i) * VEC_T]
-  int lo = j, hi = j;
-  while (lo > 0 && !split_at(d, e, lo - 1)) --lo;
-  while (hi < n - 1 && !split_at(d, e, hi)) ++hi;
-  const int m = hi - lo + 1;
-  double tn = 0.0;
-  for (int i = lo; i <= hi; ++i)
-    tn = fmax(tn, fabs(d[i]) + (i > lo ? fabs(e[i - 1]) : 0.0) + (i < hi ? fabs(e[i]) : 0.0));
-  const double pert = 10.0 * DBL_EPSILON * fmax(tn, DBL_MIN);
-  int ties = 0;
-  for (int i = j; i > lo && lam[i] - lam[i - 1] < pert; --i) ++ties;
-  const double x = lam[j - ties] + ties * pert;
-  const double tiny = DBL_EPSILON * fmax(tn, DBL_MIN);
-
-#pragma unroll 4
-  for (int i = 0; i < m; ++i) AT(y, i) = start_value(j, i);
-  // LU with partial pivoting of (T_block - x I) once, forward-eliminating y;
-  // the row multipliers (negative when the rows were swapped) are kept for
-  // the second solve and the pivots are stored as reciprocals, tiny pivots
-  // replaced by +-eps ||T||
+  // LU with partial pivoting of (T_block - x I) once, forward-eliminating the
+  // start vector (generated on the fly); branch-free, since the lanes of a
+  // workgroup pivot differently. Every recurrence keeps its running values
+  // in registers and requests the next step's operands one step ahead, so
+  // no LDS round trip sits on the chain.
   {
-    // branch-free: the lanes of a workgroup (different eigenvalues) pivot
-    // differently, so both cases are formed and selected
-    // the running element y_i stays in a register (ycur); y_{i+1} is read
-    // before anything writes it, so no LDS round trip sits on the chain
     double c0 = d[lo] - x, c1 = (m > 1) ? e[lo] : 0.0;
-    double ycur = AT(y, 0);
+    double n0 = c1;
+    double dcur = (m > 1) ? d[lo + 1] : 0.0, ecur = (m > 2) ? e[lo + 1] : 0.0;
+    double ycur = start_value(j, 0);
 #pragma unroll 4
     for (int i = 0; i + 1 < m; ++i) {
-      const double n0 = e[lo + i], n1 = d[lo + i + 1] - x;
-      const double n2 = (i + 2 < m) ? e[lo + i + 1] : 0.0;
-      const double yn = AT(y, i + 1);
+      const double dnx = (i + 2 < m) ? d[lo + i + 2] : 0.0;
+      const double enx = (i + 3 < m) ? e[lo + i + 2] : 0.0;
+      const double yn = start_value(j, i + 1);
+      const double n1 = dcur - x, n2 = ecur;
       const bool sw = fabs(n0) > fabs(c0);
       const double num = sw ? c0 : n0, den = sw ? n0 : c0;
       const double l = den != 0.0 ? num / den : 0.0;
-      AT(u0, i) = sw ? n0 : c0;
+      AT(u0, i) = recip_pivot(sw ? n0 : c0);
       AT(u1, i) = sw ? n1 : c1;
       AT(u2, i) = sw ? n2 : 0.0;
       AT(y, i) = sw ? yn : ycur;
@@ -849,61 +884,72 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
       const double c0n = sw ? c1 - l * n1 : n1 - l * c1;
       c1 = sw ? -l * n2 : n2;
       c0 = c0n;
+      n0 = ecur;
+      dcur = dnx;
+      ecur = enx;
     }
     AT(y, m - 1) = ycur;
-    AT(u0, m - 1) = c0;
+    AT(u0, m - 1) = recip_pivot(c0);
+    AT(u1, m - 1) = 0.0;
+    AT(u2, m - 1) = 0.0;
   }
-#pragma unroll 4
-  for (int i = 0; i < m; ++i) {
-    double p = AT(u0, i);
-    if (fabs(p) < tiny) p = (p < 0.0) ? -tiny : tiny;
-    AT(u0, i) = 1.0 / p;
-  }
-  for (int iter = 0; iter < 2; ++iter) {
-    if (iter > 0) {
-      // replay the forward elimination on the new right-hand side
-      double ycur = AT(y, 0);
-#pragma unroll 4
-      for (int i = 0; i + 1 < m; ++i) {
-        const double yn = AT(y, i + 1), l = AT(ms, i);
-        const bool sw = AT(ml, i) < 0.0;
-        AT(y, i) = sw ? yn : ycur;
-        ycur = sw ? ycur - l * yn : yn - l * ycur;
-      }
-      AT(y, m - 1) = ycur;
-    }
-    // back substitution with the reciprocal pivots
-    double y1 = 0.0, y2 = 0.0, ymax = 0.0;
+  // back substitution with the reciprocal pivots, operands one step ahead;
+  // returns the largest |y_i|, and on the last pass the squared norm
+  auto back_solve = [&](double &nrm) {
+    double y1 = 0.0, y2 = 0.0, ymax = 0.0, s2 = 0.0;
+    double a0 = AT(u0, m - 1), a1 = AT(u1, m - 1), a2 = AT(u2, m - 1), ay = AT(y, m - 1);
 #pragma unroll 4
     for (int i = m - 1; i >= 0; --i) {
-      double sacc = AT(y, i);
-      if (i + 1 < m) sacc -= AT(u1, i) * y1;
-      if (i + 2 < m) sacc -= AT(u2, i) * y2;
-      const double yi = sacc * AT(u0, i);
+      const int ip = i > 0 ? i - 1 : 0;
+      const double b0 = AT(u0, ip), b1 = AT(u1, ip), b2 = AT(u2, ip), by = AT(y, ip);
+      const double yi = (ay - a1 * y1 - a2 * y2) * a0;
       AT(y, i) = yi;
       y2 = y1;
       y1 = yi;
       ymax = fmax(ymax, fabs(yi));
+      s2 += yi * yi;
+      a0 = b0;
+      a1 = b1;
+      a2 = b2;
+      ay = by;
     }
-    const double sc = 1.0 / fmax(ymax, DBL_MIN);
-#pragma unroll 8
-    for (int i = 0; i < m; ++i) AT(y, i) *= sc;
+    nrm = s2;
+    return ymax;
+  };
+  double nrm = 0.0;
+  const double sc = 1.0 / fmax(back_solve(nrm), DBL_MIN);
+  // replay the forward elimination on the scaled first solution
+  {
+    double ycur = AT(y, 0) * sc;
+    double yn = (m > 1) ? AT(y, 1) : 0.0, l = AT(ms, 0), sw = AT(ml, 0);
+#pragma unroll 4
+    for (int i = 0; i + 1 < m; ++i) {
+      const int in = i + 2 < m ? i + 1 : i;
+      const double ynn = AT(y, in + 1 < m ? in + 1 : in), lnx = AT(ms, in), swn = AT(ml, in);
+      const double ys = yn * sc;
+      AT(y, i) = sw < 0.0 ? ys : ycur;
+      ycur = sw < 0.0 ? ycur - l * ys : ys - l * ycur;
+      yn = ynn;
+      l = lnx;
+      sw = swn;
+    }
+    AT(y, m - 1) = ycur;
   }
-  double nrm = 0.0, big = 0.0;
-  int ibig = 0;
+  back_solve(nrm);
+  // unit 2-norm, largest component positive
+  double big = 0.0, sgn = 1.0;
 #pragma unroll 4
   for (int i = 0; i < m; ++i) {
     const double v = AT(y, i);
-    nrm += v * v;
     if (fabs(v) > big) {
       big = fabs(v);
-      ibig = i;
+      sgn = v;
     }
   }
-  const double sc = copysign(1.0 / sqrt(nrm), AT(y, ibig));
+  const double scl = copysign(1.0 / sqrt(nrm), sgn);
 #pragma unroll 8
   for (int i = 0; i < n; ++i)
-    w.Z[static_cast<int64_t>(i) * n + j] = (i >= lo && i <= hi) ? AT(y, i - lo) * sc : 0.0;
+    w.Z[static_cast<int64_t>(i) * n + j] = (i >= lo && i <= hi) ? AT(y, i - lo) * scl : 0.0;
 #undef AT
 }
 
@@ -1067,8 +1113,8 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
   k_small_gemm<T, 0, 0><<<sg_blocks, SG_T, 0, st>>>(Linv, T1, Am, n, info);
   k_eig_tridiag<T><<<1, TRI_T, 0, st>>>(n, w, info);
   k_eig_values<<<(n + 3) / 4, 256, 3 * n * sizeof(double), st>>>(n, w.d, w.e, w.lam, info);
-  k_eig_vectors<<<(n + VEC_T - 1) / VEC_T, VEC_T, (3 * n + 6 * n * VEC_T) * sizeof(double), st>>>(
-      n, w, info);
+  k_eig_vectors<<<(n + VEC_T - 1) / VEC_T, VEC_T, vec_lds_doubles(n) * sizeof(double), st>>>(n, w,
+                                                                                        info);
   // two Newton-Schulz steps Z <- Z (3I - Z^T Z)/2 on the real tridiagonal
   // eigenvectors; the second Gram matrix must be within 1e-7 of I, so the
   // result is orthonormal to ~1e-14
