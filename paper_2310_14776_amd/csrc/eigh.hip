@@ -776,34 +776,69 @@ __global__ __launch_bounds__(256) void k_eig_values(int n, const double *__restr
 }
 
 // ------------------------------------------------------------------ vectors
-__device__ inline double start_value(int j, int i) {
-  uint64_t z = (static_cast<uint64_t>(j) << 32) + static_cast<uint64_t>(i) + 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z ^= z >> 31;
-  return static_cast<double>(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+// Start vectors of inverse iteration: windows of one table of pseudo-random
+// values in [-1, 1) (MurmurHash3's 32-bit finaliser of the index), window j
+// starting at 61 j, so every eigenvector starts from a different vector.
+constexpr int RV_N = 256;
+__device__ inline double rv_value(unsigned q) {
+  unsigned h = q * 0x9E3779B1u + 0x7F4A7C15u;
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return static_cast<double>(h >> 8) * (1.0 / 8388608.0) - 1.0;
 }
 
-// LDS doubles of k_eig_vectors: d, e, lam, row sums, split words, then six
-// per-lane arrays of n (interleaved by lane)
-inline size_t vec_lds_doubles(int n) { return 4 * static_cast<size_t>(n) + 8 + 6 * n * VEC_T; }
+// 1/x from the hardware estimate and two Newton steps (x != 0, finite)
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// LDS doubles of k_eig_vectors: d, e, lam, row sums, split words, the start
+// table, then six per-lane arrays of n (interleaved by lane)
+inline size_t vec_lds_doubles(int n) {
+  return 4 * static_cast<size_t>(n) + 8 + RV_N + 6 * static_cast<size_t>(n) * VEC_T;
+}
 
 __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int32_t *info) {
   if (*info != 0) return;
   extern __shared__ double sv[];
   double *d = sv, *e = sv + n, *lam = sv + 2 * n, *rs = sv + 3 * n;
   unsigned *spw = reinterpret_cast<unsigned *>(sv + 4 * n);  // split bits, 32 per word
-  double *scratch = sv + 4 * n + 8;
+  double *rv = sv + 4 * n + 8;
+  double *scratch = rv + RV_N;
   const int t = threadIdx.x;
-  copy_rounds(d, w.d, n, t, VEC_T);
-  copy_rounds(e, w.e, n, t, VEC_T);
-  copy_rounds(lam, w.lam, n, t, VEC_T);
+  // d, e, lam in rounds of eight loads per array and lane, all issued first
+  for (int base = 0; base < n; base += 8 * VEC_T) {
+    double a[8], b[8], c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * VEC_T + t;
+      a[u] = idx < n ? w.d[idx] : 0.0;
+      b[u] = idx < n ? w.e[idx] : 0.0;
+      c[u] = idx < n ? w.lam[idx] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * VEC_T + t;
+      if (idx < n) {
+        d[idx] = a[u];
+        e[idx] = b[u];
+        lam[idx] = c[u];
+      }
+    }
+  }
+  for (int q = t; q < RV_N; q += VEC_T) rv[q] = rv_value(static_cast<unsigned>(q));
   __syncthreads();
   // split points (the block boundary between i and i + 1) as bit words, and
   // the row sums |d_i| + |e_i-1| + |e_i| within the blocks
   const int nw = (n + 31) / 32;
   for (int q = t; q < nw; q += VEC_T) {
     unsigned bits = 0;
+#pragma unroll
     for (int b = 0; b < 32; ++b) {
       const int i = 32 * q + b;
       if (i + 1 < n && split_at(d, e, i)) bits |= 1u << b;
@@ -846,40 +881,44 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
   for (int i = j; i > lo && lam[i] - lam[i - 1] < pert; --i) ++ties;
   const double x = lam[j - ties] + ties * pert;
   const double tiny = DBL_EPSILON * fmax(tn, DBL_MIN);
-  auto recip_pivot = [&](double p) { return 1.0 / (fabs(p) < tiny ? (p < 0.0 ? -tiny : tiny) : p); };
+  auto recip_pivot = [&](double p) {
+    return rcp_nr(fabs(p) < tiny ? (p < 0.0 ? -tiny : tiny) : p);
+  };
+  const int r0 = (61 * j) & (RV_N - 1);  // start window
 
   double *u0 = scratch + 0 * n * VEC_T + t;  // reciprocal pivots
   double *u1 = scratch + 1 * n * VEC_T + t;
   double *u2 = scratch + 2 * n * VEC_T + t;
   double *y = scratch + 3 * n * VEC_T + t;
-  double *ml = scratch + 4 * n * VEC_T + t;  // < 0 where rows were swapped
-  double *ms = scratch + 5 * n * VEC_T + t;  // row multipliers
+  int *sw_ = reinterpret_cast<int *>(scratch + 4 * n * VEC_T) + t;  // rows swapped
+  double *ms = scratch + 5 * n * VEC_T + t;                        // row multipliers
 #define AT(p, i) (p)[(i) * VEC_T]
   // LU with partial pivoting of (T_block - x I) once, forward-eliminating the
-  // start vector (generated on the fly); branch-free, since the lanes of a
-  // workgroup pivot differently. Every recurrence keeps its running values
-  // in registers and requests the next step's operands one step ahead, so
-  // no LDS round trip sits on the chain.
+  // start vector; branch-free, since the lanes of a workgroup pivot
+  // differently. Every recurrence keeps its running values in registers and
+  // requests the next step's operands one step ahead, so no LDS round trip
+  // sits on the chain.
   {
     double c0 = d[lo] - x, c1 = (m > 1) ? e[lo] : 0.0;
     double n0 = c1;
     double dcur = (m > 1) ? d[lo + 1] : 0.0, ecur = (m > 2) ? e[lo + 1] : 0.0;
-    double ycur = start_value(j, 0);
+    double ycur = rv[r0];
+    double yn = rv[(r0 + 1) & (RV_N - 1)];
 #pragma unroll 4
     for (int i = 0; i + 1 < m; ++i) {
       const double dnx = (i + 2 < m) ? d[lo + i + 2] : 0.0;
       const double enx = (i + 3 < m) ? e[lo + i + 2] : 0.0;
-      const double yn = start_value(j, i + 1);
+      const double ynx = rv[(r0 + i + 2) & (RV_N - 1)];
       const double n1 = dcur - x, n2 = ecur;
       const bool sw = fabs(n0) > fabs(c0);
       const double num = sw ? c0 : n0, den = sw ? n0 : c0;
-      const double l = den != 0.0 ? num / den : 0.0;
+      const double l = den != 0.0 ? num * rcp_nr(den) : 0.0;
       AT(u0, i) = recip_pivot(sw ? n0 : c0);
       AT(u1, i) = sw ? n1 : c1;
       AT(u2, i) = sw ? n2 : 0.0;
       AT(y, i) = sw ? yn : ycur;
       ycur = sw ? ycur - l * yn : yn - l * ycur;
-      AT(ml, i) = sw ? -1.0 : 0.0;
+      AT(sw_, i) = sw;
       AT(ms, i) = l;
       const double c0n = sw ? c1 - l * n1 : n1 - l * c1;
       c1 = sw ? -l * n2 : n2;
@@ -887,6 +926,7 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
       n0 = ecur;
       dcur = dnx;
       ecur = enx;
+      yn = ynx;
     }
     AT(y, m - 1) = ycur;
     AT(u0, m - 1) = recip_pivot(c0);
@@ -894,9 +934,10 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
     AT(u2, m - 1) = 0.0;
   }
   // back substitution with the reciprocal pivots, operands one step ahead;
-  // returns the largest |y_i|, and on the last pass the squared norm
-  auto back_solve = [&](double &nrm) {
-    double y1 = 0.0, y2 = 0.0, ymax = 0.0, s2 = 0.0;
+  // returns the largest |y_i| and the squared norm, and the entry of largest
+  // magnitude (lowest index among equals) in ybig
+  auto back_solve = [&](double &nrm, double &ybig) {
+    double y1 = 0.0, y2 = 0.0, ymax = 0.0, s2 = 0.0, yb = 0.0;
     double a0 = AT(u0, m - 1), a1 = AT(u1, m - 1), a2 = AT(u2, m - 1), ay = AT(y, m - 1);
 #pragma unroll 4
     for (int i = m - 1; i >= 0; --i) {
@@ -906,7 +947,10 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
       AT(y, i) = yi;
       y2 = y1;
       y1 = yi;
-      ymax = fmax(ymax, fabs(yi));
+      if (fabs(yi) >= ymax) {
+        ymax = fabs(yi);
+        yb = yi;
+      }
       s2 += yi * yi;
       a0 = b0;
       a1 = b1;
@@ -914,39 +958,33 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
       ay = by;
     }
     nrm = s2;
+    ybig = yb;
     return ymax;
   };
-  double nrm = 0.0;
-  const double sc = 1.0 / fmax(back_solve(nrm), DBL_MIN);
+  double nrm = 0.0, ybig = 0.0;
+  const double sc = 1.0 / fmax(back_solve(nrm, ybig), DBL_MIN);
   // replay the forward elimination on the scaled first solution
   {
     double ycur = AT(y, 0) * sc;
-    double yn = (m > 1) ? AT(y, 1) : 0.0, l = AT(ms, 0), sw = AT(ml, 0);
+    double yn = (m > 1) ? AT(y, 1) : 0.0, l = AT(ms, 0);
+    int sw = AT(sw_, 0);
 #pragma unroll 4
     for (int i = 0; i + 1 < m; ++i) {
       const int in = i + 2 < m ? i + 1 : i;
-      const double ynn = AT(y, in + 1 < m ? in + 1 : in), lnx = AT(ms, in), swn = AT(ml, in);
+      const double ynn = AT(y, in + 1 < m ? in + 1 : in), lnx = AT(ms, in);
+      const int swn = AT(sw_, in);
       const double ys = yn * sc;
-      AT(y, i) = sw < 0.0 ? ys : ycur;
-      ycur = sw < 0.0 ? ycur - l * ys : ys - l * ycur;
+      AT(y, i) = sw ? ys : ycur;
+      ycur = sw ? ycur - l * ys : ys - l * ycur;
       yn = ynn;
       l = lnx;
       sw = swn;
     }
     AT(y, m - 1) = ycur;
   }
-  back_solve(nrm);
+  back_solve(nrm, ybig);
   // unit 2-norm, largest component positive
-  double big = 0.0, sgn = 1.0;
-#pragma unroll 4
-  for (int i = 0; i < m; ++i) {
-    const double v = AT(y, i);
-    if (fabs(v) > big) {
-      big = fabs(v);
-      sgn = v;
-    }
-  }
-  const double scl = copysign(1.0 / sqrt(nrm), sgn);
+  const double scl = copysign(1.0 / sqrt(nrm), ybig);
 #pragma unroll 8
   for (int i = 0; i < n; ++i)
     w.Z[static_cast<int64_t>(i) * n + j] = (i >= lo && i <= hi) ? AT(y, i - lo) * scl : 0.0;
