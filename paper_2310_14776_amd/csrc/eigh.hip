@@ -43,6 +43,7 @@ namespace {
 
 constexpr int EIG_T = 1024;
 constexpr int EIG_NMAX = 128;
+constexpr int EIG_LARGE_MAX = 1024;
 constexpr int VEC_T = 8;  // lanes (eigenvectors) per inverse-iteration workgroup
 constexpr int SG_T = 256;  // small-GEMM workgroup: four 16x16 output tiles
 constexpr int CH_T = 512;  // blocked Cholesky: 8 wavefronts (256 VGPRs each)
@@ -665,27 +666,68 @@ __global__ __launch_bounds__(TRI_T) void k_eig_tridiag(int n, EigWs w, const int
 }
 
 // ------------------------------------------------------------------ values
-// d, e are read in the Sturm recurrence at wavefront-uniform indices, through
-// restrict-qualified pointers, so they come in as scalar loads.
+// The workgroup stages T once: split points as ballot bit masks, and
+// (d_i s, e_i-1^2 s^2) pairs for the Sturm recurrence, with s a power of two
+// (exact) that brings the Gershgorin bound of the whole matrix below 1.
+inline size_t values_lds_bytes(int n) { return (5 * static_cast<size_t>(n) + 1) * sizeof(double); }
+
 __global__ __launch_bounds__(256) void k_eig_values(int n, const double *__restrict__ dg,
                                                     const double *__restrict__ eg,
                                                     double *__restrict__ lam_out,
                                                     const int32_t *__restrict__ info) {
   if (*info != 0) return;
   extern __shared__ double sdv[];
-  double *d = sdv, *e = sdv + n, *e2 = sdv + 2 * n;
+  double2 *de = reinterpret_cast<double2 *>(sdv);  // [n] (d_i s, e_i-1^2 s^2)
+  double *d = sdv + 2 * n, *e = d + n, *e2 = e + n;
+  __shared__ unsigned long long spm[EIG_LARGE_MAX / 64];  // split bits: bit i of word i / 64
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int i = threadIdx.x; i < n; i += 256) {
     d[i] = dg[i];
     e[i] = (i + 1 < n) ? eg[i] : 0.0;
     e2[i] = e[i] * e[i];
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  {
+    double g = 0.0;
+    for (int i0 = 0; i0 < n; i0 += 256) {
+      const int i = i0 + threadIdx.x;
+      const bool sp = i + 1 < n && split_at(d, e, i);
+      const unsigned long long bits = __ballot(sp);
+      if (i < n) g = fmax(g, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + fabs(e[i]));
+      if (lane == 0 && i0 + 64 * wv < n) spm[(i0 >> 6) + wv] = bits;
+    }
+    g = wave_max(g);
+    if (lane == 0) red[wv] = g;
+  }
+  __syncthreads();
+  int ex = 0;
+  (void)frexp(fmax(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])), DBL_MIN), &ex);
+  const double s = ldexp(1.0, -ex), s2 = s * s;
+  for (int i = threadIdx.x; i < n; i += 256)
+    de[i] = make_double2(d[i] * s, i > 0 ? e2[i - 1] * s2 : 0.0);
+  __syncthreads();
+  const int j = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);
   if (j >= n) return;
-  int lo = j, hi = j;
-  while (lo > 0 && !split_at(d, e, lo - 1)) --lo;
-  while (hi < n - 1 && !split_at(d, e, hi)) ++hi;
+  // the unreduced block [lo, hi] of eigenvalue j from the split bits
+  int lo = 0, hi = n - 1;
+  for (int q = (j - 1) >> 6; j > 0 && q >= 0; --q) {
+    unsigned long long bits = spm[q];
+    const int top = (j - 1) & 63;
+    if (q == (j - 1) >> 6 && top < 63) bits &= (2ull << top) - 1ull;
+    if (bits) {
+      lo = 64 * q + 63 - __builtin_clzll(bits) + 1;
+      break;
+    }
+  }
+  for (int q = j >> 6; 64 * q < n; ++q) {
+    unsigned long long bits = spm[q];
+    if (q == j >> 6) bits &= ~((1ull << (j & 63)) - 1ull);
+    if (bits) {
+      hi = 64 * q + __builtin_ctzll(bits);
+      break;
+    }
+  }
   const int li = j - lo;
   double gl = DBL_MAX, gu = -DBL_MAX, emax2 = 0.0;
   for (int i = lo + lane; i <= hi; i += 64) {
@@ -697,78 +739,47 @@ __global__ __launch_bounds__(256) void k_eig_values(int n, const double *__restr
   gl = wave_min(gl);
   gu = wave_max(gu);
   emax2 = wave_max(emax2);
-  // Work on T scaled by a power of two (exact) so that |T| < 1: the leading
-  // minors then grow by at most a factor 3 per step, and rescaling them is
-  // needed only every 8 steps.
-  int ex = 0;
-  (void)frexp(fmax(fmax(fabs(gl), fabs(gu)), DBL_MIN), &ex);
-  const double s = ldexp(1.0, -ex), s2 = s * s;
+  // on the scaled T (|T| < 1) the leading minors grow by at most a factor 3
+  // per step, so rescaling them is needed only every 8 steps
   const double tn = fmax(fabs(gl), fabs(gu)) * s;
   const double pivmin = DBL_MIN * fmax(1.0, emax2 * s2);
   double a = gl * s - (2.0 * DBL_EPSILON * tn + 2.0 * pivmin);
   double b = gu * s + (2.0 * DBL_EPSILON * tn + 2.0 * pivmin);
-  constexpr int K = 1;  // shifts per lane: 65-way multisection
+  const double d0 = de[lo].x;
   for (int it = 0; it < 64; ++it) {
     const double width = b - a;
     if (width <= 2.0 * DBL_EPSILON * fmax(fabs(a), fabs(b)) + pivmin) break;
-    // number of eigenvalues below x = sign changes along the leading minors
-    // P_i = (d_i - x) P_{i-1} - e_{i-1}^2 P_{i-2}; an exact zero takes the sign
-    // opposite to its predecessor; K independent shifts per lane interleave
-    double x[K], pm[K], pc[K];
-    int cnt[K];
-    bool neg[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      x[k] = a + width * ((lane * K + k + 1) / (64.0 * K + 1.0));
-      pm[k] = 1.0;
-      pc[k] = fma(d[lo], s, -x[k]);
-      neg[k] = pc[k] <= 0.0;
-      cnt[k] = neg[k];
-    }
-    // blocks of 8 steps: the block's d and e come in as one batch of scalar
-    // loads, then the minors are rescaled
-    auto sturm_step = [&](double di, double ei) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const double pn = fma(di - x[k], pc[k], -ei * pm[k]);
-        const bool nn = (pn < 0.0) | ((pn == 0.0) & !neg[k]);
-        cnt[k] += static_cast<int>(nn != neg[k]);
-        neg[k] = nn;
-        pm[k] = pc[k];
-        pc[k] = pn;
-      }
+    // 65-way multisection: the number of eigenvalues below x = sign changes
+    // along the leading minors P_i = (d_i - x) P_i-1 - e_i-1^2 P_i-2; an
+    // exact zero takes the sign opposite to its predecessor
+    const double x = a + width * ((lane + 1) / 65.0);
+    double pm = 1.0, pc = d0 - x;
+    bool neg = pc <= 0.0;
+    int cnt = neg;
+    auto sturm_step = [&](double2 q) {
+      const double pn = fma(q.x - x, pc, -q.y * pm);
+      const bool nn = (pn < 0.0) | ((pn == 0.0) & !neg);
+      cnt += static_cast<int>(nn != neg);
+      neg = nn;
+      pm = pc;
+      pc = pn;
     };
     int i = lo + 1;
     for (; i + 8 <= hi + 1; i += 8) {
-      double db[8], eb[8];
+      double2 qb[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        db[q] = dg[i + q];
-        eb[q] = eg[i + q - 1];
-      }
+      for (int q = 0; q < 8; ++q) qb[q] = de[i + q];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sturm_step(db[q] * s, (eb[q] * eb[q]) * s2);
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const double mag = fmax(fabs(pc[k]), fabs(pm[k]));
-        const double sc = mag > 0x1p+400 ? 0x1p-400 : (mag < 0x1p-400 ? 0x1p+400 : 1.0);
-        pm[k] *= sc;
-        pc[k] *= sc;
-      }
+      for (int q = 0; q < 8; ++q) sturm_step(qb[q]);
+      const double mag = fmax(fabs(pc), fabs(pm));
+      const double sc = mag > 0x1p+400 ? 0x1p-400 : (mag < 0x1p-400 ? 0x1p+400 : 1.0);
+      pm *= sc;
+      pc *= sc;
     }
-    for (; i <= hi; ++i) {
-      const double eu = eg[i - 1];
-      sturm_step(dg[i] * s, (eu * eu) * s2);
-    }
+    for (; i <= hi; ++i) sturm_step(de[i]);
     // eigenvalue li lies at or above x exactly when at most li lie below x
-    double na = -DBL_MAX, nbnd = DBL_MAX;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (cnt[k] <= li) na = fmax(na, x[k]);
-      else nbnd = fmin(nbnd, x[k]);
-    }
-    a = fmax(a, wave_max(na));
-    b = fmin(b, wave_min(nbnd));
+    a = fmax(a, wave_max(cnt <= li ? x : -DBL_MAX));
+    b = fmin(b, wave_min(cnt <= li ? DBL_MAX : x));
   }
   a /= s;
   b /= s;
@@ -1082,7 +1093,6 @@ __global__ __launch_bounds__(128) void k_eig_back(int n, EigWs w, const double *
   if (s == 0) eps[rank] = lj;
 }
 
-constexpr int EIG_LARGE_MAX = 1024;
 
 // blocks above the LDS limit: global-memory pipeline (eigh_large.hip)
 template <typename T>
@@ -1103,7 +1113,7 @@ int eigh_large_t(const gpaw_sys *s, const T *H, const T *S, int n, double *eps, 
   k_small_gemm<T, 0, 0><<<sg_blocks, SG_T, 0, st>>>(Linv, T1, Am, n, info);
   k_hermitize<T><<<eb, 256, 0, st>>>(Am, Am, n, info);
   large_tridiag<T>(Am, n, V, tau, w.d, w.e, p, info, st);
-  k_eig_values<<<(n + 3) / 4, 256, 3 * n * sizeof(double), st>>>(n, w.d, w.e, w.lam, info);
+  k_eig_values<<<(n + 3) / 4, 256, values_lds_bytes(n), st>>>(n, w.d, w.e, w.lam, info);
   large_vectors(n, w.d, w.e, w.lam, w.lu, w.Z, info, st);
   k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.Z, w.G, n, info);
   k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 0.5, info);
@@ -1150,7 +1160,7 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
   k_small_gemm<T, 2, 1><<<sg_blocks, SG_T, 0, st>>>(Hd, Linv, T1, n, info);
   k_small_gemm<T, 0, 0><<<sg_blocks, SG_T, 0, st>>>(Linv, T1, Am, n, info);
   k_eig_tridiag<T><<<1, TRI_T, 0, st>>>(n, w, info);
-  k_eig_values<<<(n + 3) / 4, 256, 3 * n * sizeof(double), st>>>(n, w.d, w.e, w.lam, info);
+  k_eig_values<<<(n + 3) / 4, 256, values_lds_bytes(n), st>>>(n, w.d, w.e, w.lam, info);
   k_eig_vectors<<<(n + VEC_T - 1) / VEC_T, VEC_T, vec_lds_doubles(n) * sizeof(double), st>>>(n, w,
                                                                                         info);
   // two Newton-Schulz steps Z <- Z (3I - Z^T Z)/2 on the real tridiagonal

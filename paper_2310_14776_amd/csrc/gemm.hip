@@ -78,7 +78,9 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
   // workgroups are dealt to the 8 XCDs round-robin by id: give all tiles and
   // matrices of one K chunk the same id residue so they share that XCD's L2
   // (with fewer than 8 K chunks the plain order keeps every XCD busy)
-  const int tiles = tiles_n * tiles_n, TT = tiles * nmat;
+  // H and S are Hermitian: only the tiles on and above the diagonal are
+  // formed (the reduction mirrors the rest)
+  const int tiles = tiles_n * (tiles_n + 1) / 2, TT = tiles * nmat;
   int split, tt;
   if (nsplit >= 8) {
     const int xcd = blockIdx.x & 7, jj = blockIdx.x >> 3;
@@ -90,7 +92,12 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
   }
   if (split >= nsplit) return;
   const int mat = tt / tiles, tile = tt - mat * tiles;
-  const int tm = tile / tiles_n, tn = tile - tm * tiles_n;
+  int tm = 0, rest = tile;
+  while (rest >= tiles_n - tm) {
+    rest -= tiles_n - tm;
+    ++tm;
+  }
+  const int tn = tm + rest;
   const T *B = mat ? B1 : B0;
   const int64_t kb = static_cast<int64_t>(split) * kchunk;
   const int64_t ke = std::min(ng, kb + kchunk);
@@ -232,12 +239,19 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
 template <typename T>
 __global__ __launch_bounds__(256) void k_subspace_reduce(const T *__restrict__ part,
                                                          T *__restrict__ H, T *__restrict__ S,
-                                                         int nb, int nsplit, int nmat, double dV) {
+                                                         int nb, int nsplit, int nmat, double dV,
+                                                         int tile) {
   const int64_t nn = static_cast<int64_t>(nb) * nb;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (idx >= nn * nmat) return;
   const int mat = static_cast<int>(idx / nn);
-  const int64_t e = idx - mat * nn;
+  const int64_t eo = idx - mat * nn;
+  const int r = static_cast<int>(eo / nb), c = static_cast<int>(eo - static_cast<int64_t>(r) * nb);
+  // entries of tiles below the diagonal were not formed: the thread of the
+  // mirror entry writes them (as its conjugate)
+  if (r / tile > c / tile) return;
+  const bool mirror = r / tile < c / tile;
+  const int64_t e = eo;
   // the partials are added in split order (bitwise reproducible), eight
   // loads in flight at a time
   T acc{};
@@ -250,7 +264,10 @@ __global__ __launch_bounds__(256) void k_subspace_reduce(const T *__restrict__ p
     for (int u = 0; u < 8; ++u)
       if (s0 + u < nsplit) acc = acc + v[u];
   }
-  (mat ? S : H)[e] = St<T>::scale(dV, acc);
+  const T val = St<T>::scale(dV, acc);
+  T *M = mat ? S : H;
+  M[eo] = val;
+  if (mirror) M[static_cast<int64_t>(c) * nb + r] = Cx<T>::make(Cx<T>::re(val), -Cx<T>::im(val));
 }
 
 struct SplitPlan {
@@ -262,11 +279,14 @@ struct SplitPlan {
 SplitPlan plan_subspace(int nb, int64_t ng, int nmat, int tile, int target) {
   SplitPlan p;
   p.tiles_n = (nb + tile - 1) / tile;
-  p.tiles = p.tiles_n * p.tiles_n;
+  p.tiles = p.tiles_n * (p.tiles_n + 1) / 2;  // on and above the diagonal
   // aim at ~512 workgroups (two per CU) with at least 1024 K per workgroup
   if (target <= 0) target = 512;
   target = std::min(target, 1024);
-  const int64_t want = std::max<int64_t>(1, target / (p.tiles * nmat));
+  // (with 8 or more splits the launch rounds them up to whole groups of 8,
+  // so round down here to stay within the target)
+  int64_t want = std::max<int64_t>(1, target / (p.tiles * nmat));
+  if (want >= 8) want = want / 8 * 8;
   const int64_t kmax_split = std::max<int64_t>(1, ng / 1024);
   int64_t nsplit = std::min(want, kmax_split);
   int64_t kchunk = (ng + nsplit - 1) / nsplit;
@@ -444,7 +464,7 @@ int subspace_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const void 
   else go(std::false_type{});
   const int64_t tot = static_cast<int64_t>(nb) * nb * nmat;
   k_subspace_reduce<T><<<static_cast<unsigned>((tot + 255) / 256), 256, 0, st>>>(
-      part, static_cast<T *>(H), static_cast<T *>(S), nb, p.nsplit, nmat, s->dV);
+      part, static_cast<T *>(H), static_cast<T *>(S), nb, p.nsplit, nmat, s->dV, 16 * BM);
   return GPAW_OK;
 }
 
@@ -461,11 +481,13 @@ int rotate_t(const void *C, const void *src, int nb, int64_t cols, void *dst, hi
 size_t subspace_part_elems(const gpaw_sys *s, int nb) {
   if (s->dtype == GPAW_F32 || s->dtype == GPAW_C64) return split_part_elems(nb, s->dtype == GPAW_C64);
   // nsplit * tiles * nmat <= 1024 (the largest target) whenever that allows
-  // one split, else nsplit = 1; complex tiles are 32 x 32 (a quarter of the
-  // real 64 x 64)
+  // one split, else nsplit = 1; the tiles formed are those on and above the
+  // diagonal, T (T + 1) / 2 >= T^2 / 2 of them for T tiles a side, so
+  // nsplit * nmat * nb^2 <= 2048 tile^2; complex tiles are 32 x 32 (a quarter
+  // of the real 64 x 64)
   const bool cplx = s->dtype == GPAW_C128;
   const int64_t tile = cplx ? 32 : SUB_TILE;
-  const int64_t bound = std::max<int64_t>(1024 * tile * tile, 2 * int64_t(nb) * nb);
+  const int64_t bound = std::max<int64_t>(2048 * tile * tile, 2 * int64_t(nb) * nb);
   return static_cast<size_t>(bound) * (cplx ? 2 : 1);
 }
 
