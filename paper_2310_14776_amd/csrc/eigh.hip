@@ -1037,56 +1037,165 @@ __global__ __launch_bounds__(1024) void k_gram_check(const double *__restrict__ 
 }
 
 // ------------------------------------------------------------------ back-transform
-// Column j of Z (real): U = Q Z with the reflectors applied last to first
-// from LDS (8 lanes per column, rows 8t+s in registers):
-// u <- u - tau_k v_k (v_k^H u). U lands in column rank(j) of Uo, where rank
-// orders the eigenvalues by (value, slot).
+// U = Q Z with Q = H_0 H_1 ... H_n-2, in blocks of KB reflectors in compact
+// WY form: H_k0 ... H_k0+KB-1 = I - V_b T_b V_b^H with T_b upper triangular
+// (tau_i on the diagonal, T(0:i, i) = -tau_i T(0:i, 0:i) V_b(:, 0:i)^H v_i).
+// The workgroup first builds every T_b (8 lanes per block: Gram entries, then
+// the triangular recurrence), then each column of Z (8 lanes, rows 8t+s in
+// registers) takes the blocks last to first: W = V_b^H z (KB independent
+// sums), z -= V_b (T_b W). U lands in column rank(j) of Uo, where rank orders
+// the eigenvalues by (value, slot).
+// (KB = 8 real, 4 complex: a block's reflector entries stay in registers)
+template <typename T> struct BackKB { static constexpr int kb = St<T>::cplx ? 4 : 8; };
+__host__ __device__ inline int tpk(int r, int c) { return c * (c + 1) / 2 + r; }
+
+template <typename T>
+size_t back_lds_bytes(int n) {
+  constexpr int KB = BackKB<T>::kb, TP = KB * (KB + 1) / 2;
+  const int nblk = (n - 1 + KB - 1) / KB;
+  return (static_cast<size_t>(n) * EigMax<T>::n + n + static_cast<size_t>(nblk) * TP) * sizeof(T) +
+         static_cast<size_t>(n) * sizeof(double);
+}
+
 template <typename T>
 __global__ __launch_bounds__(128) void k_eig_back(int n, EigWs w, const double *__restrict__ Z,
                                                   T *__restrict__ Uo, double *__restrict__ eps,
                                                   const int32_t *info) {
   if (*info != 0) return;
-  constexpr int NMAX = EigMax<T>::n;
+  constexpr int NMAX = EigMax<T>::n, R = NMAX / 8, KB = BackKB<T>::kb, BK_TP = KB * (KB + 1) / 2;
   extern __shared__ double sv[];
-  T *V = reinterpret_cast<T *>(sv);  // [n][n]
-  T *tau = V + n * n;                // [n]
-  const T *Vg = as<T>(w.V);
-  const T *tg = as<T>(w.tau);
-  copy_rounds(V, Vg, n * n, threadIdx.x, 128);
-  copy_rounds(tau, tg, n, threadIdx.x, 128);
+  // reflector k in row k, rows padded to NMAX with zeros (so a lane's rows
+  // past n read zeros with no bounds test)
+  T *V = reinterpret_cast<T *>(sv);  // [n][NMAX]
+  T *tau = V + n * NMAX;             // [n]
+  T *Tm = tau + n;                   // [nblk][BK_TP]
+  double *lam = reinterpret_cast<double *>(Tm + ((n - 1 + KB - 1) / KB) * BK_TP);  // [n]
+  {
+    const T *Vg = as<T>(w.V);
+    const int tot = n * NMAX;
+    for (int base = 0; base < tot; base += 16 * 128) {
+      T u[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int idx = base + q * 128 + threadIdx.x;
+        const int k = idx / NMAX, r = idx - k * NMAX;
+        u[q] = idx < tot && r < n ? Vg[k * n + r] : T{};
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int idx = base + q * 128 + threadIdx.x;
+        if (idx < tot) V[idx] = u[q];
+      }
+    }
+  }
+  copy_rounds(tau, as<T>(w.tau), n, threadIdx.x, 128);
+  copy_rounds(lam, w.lam, n, threadIdx.x, 128);
+  __syncthreads();
+  const int nblk = (n - 1 + KB - 1) / KB;
+  // T_b of every block: the 8 lanes of a group take one block, with rows
+  // 8t+s of its reflectors in registers; the Gram entries G(r, c) = v_r^H v_c
+  // (r < c) come from 8-lane sums, then every lane of the group runs the
+  // triangular recurrence (unrolled, in registers) and lane 0 stores T_b
+  for (int bb = 0; bb < nblk; bb += 128 / 8) {
+    const int b = bb + (threadIdx.x >> 3), s = threadIdx.x & 7;
+    if (b < nblk) {
+      const int k0 = b * KB;
+      T vb[KB][R];
+#pragma unroll
+      for (int i = 0; i < KB; ++i)
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+          const int row = 8 * t + s;
+          vb[i][t] = V[min(k0 + i, n - 1) * NMAX + row];
+        }
+      T G[KB][KB];
+#pragma unroll
+      for (int c = 1; c < KB; ++c)
+#pragma unroll
+        for (int r = 0; r < c; ++r) {
+          T g = T{};
+#pragma unroll
+          for (int t = 0; t < R; ++t) g = g + cj(vb[r][t]) * vb[c][t];
+          G[r][c] = group8_sum(g);
+        }
+      T Tb[KB][KB];
+#pragma unroll
+      for (int i = 0; i < KB; ++i) {
+        const T ti = (k0 + i < n - 1) ? tau[k0 + i] : T{};
+#pragma unroll
+        for (int r = 0; r < i; ++r) {
+          T acc = T{};
+#pragma unroll
+          for (int c = r; c < i; ++c) acc = acc + Tb[r][c] * G[c][i];
+          Tb[r][i] = St<T>::scale(-1.0, ti * acc);
+        }
+        Tb[i][i] = ti;
+      }
+      if (s == 0)
+#pragma unroll
+        for (int c = 0; c < KB; ++c)
+#pragma unroll
+          for (int r = 0; r <= c; ++r) Tm[b * BK_TP + tpk(r, c)] = Tb[r][c];
+    }
+  }
   __syncthreads();
   const int col = blockIdx.x * 16 + (threadIdx.x >> 3), s = threadIdx.x & 7;
   if (col >= n) return;
-  T zr[NMAX / 8];
+  T zr[R];
 #pragma unroll
-  for (int t = 0; t < NMAX / 8; ++t) {
+  for (int t = 0; t < R; ++t) {
     const int row = 8 * t + s;
     zr[t] = realv<T>((row < n) ? Z[row * n + col] : 0.0);
   }
-  for (int k = n - 2; k >= 0; --k) {
-    const T *vk = V + k * n;
-    T vr[NMAX / 8];
-    T pq[4] = {T{}, T{}, T{}, T{}};  // four partial sums: shorter dependent chains
+  for (int b = nblk - 1; b >= 0; --b) {
+    const int k0 = b * KB;
+    // W = V_b^H z (row n - 1 of V, no reflector, is zero and stands in for
+    // the reflectors past n - 2)
+    T W[KB];
 #pragma unroll
-    for (int t = 0; t < NMAX / 8; ++t) {
-      const int row = 8 * t + s;
-      vr[t] = (row > k && row < n) ? vk[row] : T{};
-      pq[t & 3] = pq[t & 3] + cj(vr[t]) * zr[t];
+    for (int i = 0; i < KB; ++i) {
+      const T *vk = V + min(k0 + i, n - 1) * NMAX;
+      T pq[2] = {T{}, T{}};
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int row = 8 * t + s;
+        pq[t & 1] = pq[t & 1] + cj(vk[row]) * zr[t];
+      }
+      W[i] = group8_sum(pq[0] + pq[1]);
     }
-    T part = (pq[0] + pq[1]) + (pq[2] + pq[3]);
-    part = group8_sum(part);
-    const T f = tau[k] * part;
+    // Y = T_b W
+    const T *tb = Tm + b * BK_TP;
+    T Y[KB];
 #pragma unroll
-    for (int t = 0; t < NMAX / 8; ++t) zr[t] = zr[t] - f * vr[t];
+    for (int r = 0; r < KB; ++r) {
+      T acc = T{};
+#pragma unroll
+      for (int c = r; c < KB; ++c) acc = acc + tb[tpk(r, c)] * W[c];
+      Y[r] = acc;
+    }
+    // z -= V_b Y
+#pragma unroll
+    for (int i = 0; i < KB; ++i) {
+      const T *vk = V + min(k0 + i, n - 1) * NMAX;
+#pragma unroll
+      for (int t = 0; t < R; ++t) {
+        const int row = 8 * t + s;
+        zr[t] = zr[t] - vk[row] * Y[i];
+      }
+    }
   }
-  const double lj = w.lam[col];
+  // rank of eigenvalue col by (value, slot): the 8 lanes count a share each
+  const double lj = lam[col];
   int rank = 0;
-  for (int i = 0; i < n; ++i) {
-    const double li = w.lam[i];
+  for (int i = s; i < n; i += 8) {
+    const double li = lam[i];
     rank += (li < lj) || (li == lj && i < col);
   }
+  rank += __shfl_xor(rank, 1);
+  rank += __shfl_xor(rank, 2);
+  rank += __shfl_xor(rank, 4);
 #pragma unroll
-  for (int t = 0; t < NMAX / 8; ++t) {
+  for (int t = 0; t < R; ++t) {
     const int row = 8 * t + s;
     if (row < n) Uo[row * n + rank] = zr[t];
   }
@@ -1173,7 +1282,7 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
   k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 1e-7, info);
   k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.G, w.Z, n, info);
   // U = Q Z in eigen-order, then C = Linv^H U
-  k_eig_back<T><<<(n + 15) / 16, 128, (static_cast<size_t>(n) * n + n) * sizeof(T), st>>>(
+  k_eig_back<T><<<(n + 15) / 16, 128, back_lds_bytes<T>(n), st>>>(
       n, w, w.Z, U, eps, info);
   k_small_gemm<T, 1, 0><<<sg_blocks, SG_T, 0, st>>>(Linv, U, static_cast<T *>(C), n, info);
   return GPAW_OK;
