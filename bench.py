@@ -254,11 +254,14 @@ def part_costs(s, info):
                         + ent * (ni * es + 4), flops=0),
         "apply_S": dict(bytes=2 * nb * ng * es + info["covered"] * 8 + ent * (ni * es + 4),
                         flops=0),
-        # read psi, H~psi, S~psi; two full nb x nb products over Ng
-        "subspace": dict(bytes=3 * nb * ng * es, flops=2 * 2 * nb * nb * ng),
+        # read psi, H~psi, S~psi; two Hermitian nb x nb products over Ng, of
+        # which the nb (nb + 1) / 2 entries on and above the diagonal are
+        # needed (real FP64 flops: 2 per multiply-add, 4 times that complex)
+        "subspace": dict(bytes=3 * nb * ng * es, flops=2 * nb * (nb + 1) * ng * (4 if s.is_complex else 1)),
         "diag": dict(bytes=0, flops=0),
         # read psi, write psi'; nb x nb times nb x (Ng + Np)
-        "rotate": dict(bytes=2 * nb * (ng + npj) * es, flops=2 * nb * nb * (ng + npj)),
+        "rotate": dict(bytes=2 * nb * (ng + npj) * es,
+                       flops=2 * nb * nb * (ng + npj) * (4 if s.is_complex else 1)),
     }
 
 
