@@ -98,8 +98,9 @@ def timed(fn, stream, steps, warmup):
 
 def precision_form(steps, warmup):
     """FP64 step vs the precision form (single-precision storage, split-BF16
-    products, FP64 eigensolve, Cholesky orthonormality correction) on the same
-    FP32-rounded 96^3, 512-band, 64-atom block."""
+    products, FP64 eigensolve, Cholesky orthonormality correction of the
+    stored rotated block) on the same FP32-rounded 96^3, 512-band, 64-atom
+    block."""
     import torch
     import synth
     import paper_2310_14776_amd as gfd
@@ -133,7 +134,9 @@ def precision_form(steps, warmup):
             g.subspace_diag(H, S, eps=eps, C=C, info=info, stream=stream)
             g.rotate(psi, C, out=psi_rot, P=P, P_out=P_rot, stream=stream)
             if prec == "single":
-                g.rotate(Spsi, C, out=Spsi_rot, stream=stream)
+                # S~ applied to the stored rotated block (its projections are
+                # the rotated P), then the Cholesky correction
+                g.apply_S(psi_rot, P_rot, out=Spsi_rot, stream=stream)
                 g.orthonormalize(psi_rot, Spsi_rot, out=psi_fin, P=P_rot, P_out=P_fin,
                                  info=info, stream=stream)
         ms = timed(step, stream, steps, warmup)

@@ -334,9 +334,10 @@ int gpaw_orthonormalize(gpaw_sys *s, const void *psi, const void *Spsi, int32_t 
   int32_t *dinfo = info ? info : s->ws.info;
   if ((rc = launch_subspace(s, psi, Spsi, nullptr, nb, Sm, nullptr, st)) != GPAW_OK) return rc;
   if ((rc = launch_chol_inv(s, Sm, nb, Cm, dinfo, st)) != GPAW_OK) return rc;
-  if ((rc = launch_rotate(s, Cm, psi, nb, s->ng, psi_out, st)) != GPAW_OK) return rc;
+  // L^-H is upper triangular: the rotations skip the zero half
+  if ((rc = launch_rotate(s, Cm, psi, nb, s->ng, psi_out, st, true)) != GPAW_OK) return rc;
   if (P && s->np > 0)
-    if ((rc = launch_rotate(s, Cm, P, nb, s->np, P_out, st)) != GPAW_OK) return rc;
+    if ((rc = launch_rotate(s, Cm, P, nb, s->np, P_out, st, true)) != GPAW_OK) return rc;
   if ((rc = after_launch("gpaw_orthonormalize")) != GPAW_OK) return rc;
   if (info) return GPAW_OK;
   int32_t h_info = 0;

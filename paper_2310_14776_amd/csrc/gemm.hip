@@ -300,7 +300,8 @@ SplitPlan plan_subspace(int nb, int64_t ng, int nmat, int tile, int target) {
 // row group blockIdx.y) by 32 columns; no conjugation (psi' = C^T psi).
 template <typename T, int RB>
 __global__ __launch_bounds__(256) void k_rotate(const T *__restrict__ C, const T *__restrict__ src,
-                                                T *__restrict__ dst, int nb, int64_t cols) {
+                                                T *__restrict__ dst, int nb, int64_t cols,
+                                                int upper) {
   constexpr int NP = Cx<T>::parts;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = lane & 15, kq = lane >> 4;
@@ -344,10 +345,12 @@ __global__ __launch_bounds__(256) void k_rotate(const T *__restrict__ C, const T
   T a[D][RB], b[D][2];
 #pragma unroll
   for (int d = 0; d < D; ++d) load_step(4 * d, a[d], b[d]);
-  for (int m0 = 0; m0 < nb; m0 += 4 * D) {
+  // an upper-triangular C (m <= n) needs rows m < n0 + RB*16 only
+  const int mend = upper ? std::min(nb, n0 + RB * 16) : nb;
+  for (int m0 = 0; m0 < mend; m0 += 4 * D) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      if (m0 + 4 * d < nb) {
+      if (m0 + 4 * d < mend) {
         const bool mv = m0 + 4 * d + kq < nb;
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
@@ -389,7 +392,7 @@ __global__ __launch_bounds__(256) void k_rotate(const T *__restrict__ C, const T
 template <typename T>
 __global__ __launch_bounds__(256) void k_rot_small(const T *__restrict__ C, const T *__restrict__ src,
                                                    T *__restrict__ dst, int nb, int64_t cols,
-                                                   int tiles_c) {
+                                                   int tiles_c, int upper) {
   constexpr int NP = Cx<T>::parts;
   const int lane = threadIdx.x & 63;
   const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -401,7 +404,8 @@ __global__ __launch_bounds__(256) void k_rot_small(const T *__restrict__ C, cons
   d4 acc[NP];
 #pragma unroll
   for (int c = 0; c < NP; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int m0 = 0; m0 < nb; m0 += 64) {
+  const int mend = upper ? std::min(nb, n0 + 16) : nb;  // upper-triangular C: m <= n
+  for (int m0 = 0; m0 < mend; m0 += 64) {
     T a[16], b[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -430,12 +434,13 @@ __global__ __launch_bounds__(256) void k_rot_small(const T *__restrict__ C, cons
 }
 
 template <typename T>
-int rotate_small_t(const void *C, const void *src, int nb, int64_t cols, void *dst, hipStream_t st) {
+int rotate_small_t(const void *C, const void *src, int nb, int64_t cols, void *dst, hipStream_t st,
+                   bool upper) {
   const int tiles_c = static_cast<int>((cols + 15) / 16);
   const int64_t tiles = static_cast<int64_t>((nb + 15) / 16) * tiles_c;
   k_rot_small<T><<<static_cast<unsigned>((tiles + 3) / 4), 256, 0, st>>>(
       static_cast<const T *>(C), static_cast<const T *>(src), static_cast<T *>(dst), nb, cols,
-      tiles_c);
+      tiles_c, upper ? 1 : 0);
   return GPAW_OK;
 }
 
@@ -469,10 +474,11 @@ int subspace_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const void 
 }
 
 template <typename T, int RB>
-int rotate_t(const void *C, const void *src, int nb, int64_t cols, void *dst, hipStream_t st) {
+int rotate_t(const void *C, const void *src, int nb, int64_t cols, void *dst, hipStream_t st,
+             bool upper) {
   dim3 grid(static_cast<unsigned>((cols + 127) / 128), (nb + RB * 16 - 1) / (RB * 16));
   k_rotate<T, RB><<<grid, 256, 0, st>>>(static_cast<const T *>(C), static_cast<const T *>(src),
-                                        static_cast<T *>(dst), nb, cols);
+                                        static_cast<T *>(dst), nb, cols, upper ? 1 : 0);
   return GPAW_OK;
 }
 
@@ -500,21 +506,21 @@ int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const 
 }
 
 int launch_rotate(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
-                  void *dst, hipStream_t st) {
+                  void *dst, hipStream_t st, bool upper) {
   if (cols == 0) return GPAW_OK;
   if (s->dtype == GPAW_F32 || s->dtype == GPAW_C64)
-    return launch_rotate_split(s, C, src, nb, cols, dst, st);
+    return launch_rotate_split(s, C, src, nb, cols, dst, st, upper);
   // short rows (projections): too few columns to fill the chip by column
   // tiles, so one wavefront per 16 x 16 output tile instead
   if (cols <= 4096) {
-    if (s->dtype == GPAW_C128) return rotate_small_t<z64>(C, src, nb, cols, dst, st);
-    return rotate_small_t<double>(C, src, nb, cols, dst, st);
+    if (s->dtype == GPAW_C128) return rotate_small_t<z64>(C, src, nb, cols, dst, st, upper);
+    return rotate_small_t<double>(C, src, nb, cols, dst, st, upper);
   }
   if (s->dtype == GPAW_C128)
-    return s->tune.rot_rb == 2 ? rotate_t<z64, 2>(C, src, nb, cols, dst, st)
-                               : rotate_t<z64, 4>(C, src, nb, cols, dst, st);
-  return s->tune.rot_rb == 4 ? rotate_t<double, 4>(C, src, nb, cols, dst, st)
-                             : rotate_t<double, 8>(C, src, nb, cols, dst, st);
+    return s->tune.rot_rb == 2 ? rotate_t<z64, 2>(C, src, nb, cols, dst, st, upper)
+                               : rotate_t<z64, 4>(C, src, nb, cols, dst, st, upper);
+  return s->tune.rot_rb == 4 ? rotate_t<double, 4>(C, src, nb, cols, dst, st, upper)
+                             : rotate_t<double, 8>(C, src, nb, cols, dst, st, upper);
 }
 
 }  // namespace gfd

@@ -179,7 +179,9 @@ __global__ __launch_bounds__(256) void k_sub_lds(const T *__restrict__ A, const 
   __shared__ __attribute__((aligned(16))) __bf16 sA[3 * NP * PS];
   __shared__ __attribute__((aligned(16))) __bf16 sB[3 * NP * PS];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int tiles = tiles_n * tiles_n, TT = tiles * nmat;
+  // H and S are Hermitian: only the tiles on and above the diagonal are
+  // formed (the reduction mirrors the rest)
+  const int tiles = tiles_n * (tiles_n + 1) / 2, TT = tiles * nmat;
   int split, tt;
   if (nsplit >= 8) {
     const int x = blockIdx.x & 7, jj = blockIdx.x >> 3;
@@ -191,7 +193,12 @@ __global__ __launch_bounds__(256) void k_sub_lds(const T *__restrict__ A, const 
   }
   if (split >= nsplit) return;
   const int mat = tt / tiles, tile = tt - mat * tiles;
-  const int tm = tile / tiles_n, tn = tile - tm * tiles_n;
+  int tm = 0, rest = tile;
+  while (rest >= tiles_n - tm) {
+    rest -= tiles_n - tm;
+    ++tm;
+  }
+  const int tn = tm + rest;
   const T *B = mat ? B1 : B0;
   const int64_t kb = static_cast<int64_t>(split) * kchunk;
   const int64_t ke = std::min(ng, kb + kchunk);
@@ -301,15 +308,23 @@ template <int NP>
 __global__ __launch_bounds__(256) void k_split_reduce(const double *__restrict__ part,
                                                       double *__restrict__ H,
                                                       double *__restrict__ S, int nb, int nsplit,
-                                                      int nmat, double dV) {
+                                                      int nmat, double dV, int tile) {
   const int64_t nn = static_cast<int64_t>(nb) * nb * NP;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (idx >= nn * nmat) return;
   const int mat = static_cast<int>(idx / nn);
   const int64_t e = idx - mat * nn;
+  const int64_t el = e / NP;
+  const int c = static_cast<int>(e - el * NP);
+  const int r = static_cast<int>(el / nb), q = static_cast<int>(el - static_cast<int64_t>(r) * nb);
+  // entries of tiles below the diagonal were not formed: the thread of the
+  // mirror entry writes them (as its conjugate)
+  if (r / tile > q / tile) return;
   double acc = 0.0;
   for (int s = 0; s < nsplit; ++s) acc += part[(static_cast<int64_t>(s) * nmat + mat) * nn + e];
-  (mat ? S : H)[e] = dV * acc;
+  double *M = mat ? S : H;
+  M[e] = dV * acc;
+  if (r / tile < q / tile) M[(static_cast<int64_t>(q) * nb + r) * NP + c] = c ? -dV * acc : dV * acc;
 }
 
 // C (double / complex double, [nb][nb]) -> transposed BF16 planes
@@ -347,7 +362,7 @@ template <typename T, int WT>
 __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
                                                  const T *__restrict__ src, T *__restrict__ dst,
                                                  int nb, int64_t cols, int ntiles_n,
-                                                 int64_t gtiles) {
+                                                 int64_t gtiles, int upper) {
   constexpr int NP = Parts<T>::n;
   constexpr int TM = 32 * WT;
   constexpr int PS = TM * LROW;
@@ -362,7 +377,9 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
   const int64_t nn = static_cast<int64_t>(nb) * nb;
   const int n0 = ntile * TM;
   const int64_t g0 = gtile * TM;
-  const int nsteps = (nb + KS - 1) / KS;
+  // an upper-triangular C (m <= n) needs rows m < n0 + TM only
+  const int mend = upper ? std::min(nb, n0 + TM) : nb;
+  const int nsteps = (mend + KS - 1) / KS;
 
   // A staging: row n = n0 + tid/4 (+64 per pass), 8 values m = 8c..8c+7 per plane
   constexpr int PASSES = TM / 64;
@@ -500,8 +517,9 @@ struct SplitPlanS {
 SplitPlanS plan_split(int nb, int64_t ng, int nmat, int tile) {
   SplitPlanS p;
   p.tiles_n = (nb + tile - 1) / tile;
-  p.tiles = p.tiles_n * p.tiles_n;
-  const int64_t want = std::max<int64_t>(8, 512 / (p.tiles * nmat));
+  p.tiles = p.tiles_n * (p.tiles_n + 1) / 2;  // on and above the diagonal
+  // (the launch rounds the splits up to whole groups of 8: round down here)
+  const int64_t want = std::max<int64_t>(8, 512 / (p.tiles * nmat) / 8 * 8);
   const int64_t kmax_split = std::max<int64_t>(1, ng / 256);
   int64_t nsplit = std::max<int64_t>(1, std::min(want, kmax_split));
   int64_t kchunk = (ng + nsplit - 1) / nsplit;
@@ -529,13 +547,14 @@ int subspace_split_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const
       nmat, p.nsplit);
   const int64_t tot = static_cast<int64_t>(nb) * nb * nmat * NP;
   k_split_reduce<NP><<<static_cast<unsigned>((tot + 255) / 256), 256, 0, st>>>(
-      s->ws.part, static_cast<double *>(H), static_cast<double *>(S), nb, p.nsplit, nmat, s->dV);
+      s->ws.part, static_cast<double *>(H), static_cast<double *>(S), nb, p.nsplit, nmat, s->dV,
+      32 * WT);
   return GPAW_OK;
 }
 
 template <typename T, int WT>
 int rotate_split_t(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
-                   void *dst, hipStream_t st) {
+                   void *dst, hipStream_t st, bool upper) {
   constexpr int NP = Parts<T>::n;
   constexpr int TM = 32 * WT;
   __bf16 *Ct = reinterpret_cast<__bf16 *>(s->ws.split);
@@ -546,7 +565,8 @@ int rotate_split_t(const gpaw_sys *s, const void *C, const void *src, int nb, in
   const int64_t gtiles = (cols + TM - 1) / TM;
   const int64_t wgs = (gtiles + 7) / 8 * 8 * ntiles_n;
   k_rot_lds<T, WT><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
-      Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, cols, ntiles_n, gtiles);
+      Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, cols, ntiles_n, gtiles,
+      upper ? 1 : 0);
   return GPAW_OK;
 }
 
@@ -571,10 +591,10 @@ int launch_subspace_split(const gpaw_sys *s, const void *psi, const void *Hpsi, 
 }
 
 int launch_rotate_split(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
-                        void *dst, hipStream_t st) {
+                        void *dst, hipStream_t st, bool upper) {
   if (cols == 0) return GPAW_OK;
-  if (s->dtype == GPAW_C64) return rotate_split_t<z32, 2>(s, C, src, nb, cols, dst, st);
-  return rotate_split_t<float, 4>(s, C, src, nb, cols, dst, st);
+  if (s->dtype == GPAW_C64) return rotate_split_t<z32, 2>(s, C, src, nb, cols, dst, st, upper);
+  return rotate_split_t<float, 4>(s, C, src, nb, cols, dst, st, upper);
 }
 
 }  // namespace gfd

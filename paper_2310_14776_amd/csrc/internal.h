@@ -234,14 +234,14 @@ int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const 
                     int nb, void *H, void *S, hipStream_t st);
 size_t subspace_part_elems(const gpaw_sys *s, int nb);
 int launch_rotate(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
-                  void *dst, hipStream_t st);
+                  void *dst, hipStream_t st, bool upper = false);
 // precision form (gemm_split.hip)
 size_t split_part_elems(int nb, bool cplx);
 size_t split_c_bytes(int nb, bool cplx);
 int launch_subspace_split(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
                           int nb, void *H, void *S, hipStream_t st);
 int launch_rotate_split(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
-                        void *dst, hipStream_t st);
+                        void *dst, hipStream_t st, bool upper = false);
 size_t eig_ws_elems(int nmax, bool cplx);
 int launch_eigh(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps, void *C,
                 int32_t *info, hipStream_t st);

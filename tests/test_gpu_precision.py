@@ -53,7 +53,9 @@ def test_precision_form_against_fp64_oracle(name):
     assert g.dtype in (torch.float32, torch.complex64)
     psi = to_dev(s.psi.reshape(s.nb, -1).astype(np.complex64 if s.is_complex else np.float32))
     out = g.step(psi)
-    Spsi_rot, _ = g.rotate(out["Spsi"], out["C"])
+    # S~ on the stored rotated block (projections: the rotated P), then the
+    # Cholesky correction, as the precision form's step does
+    Spsi_rot = g.apply_S(out["psi_rot"], out["P_rot"] if s.natoms else None)
     psi_fin, _ = g.orthonormalize(out["psi_rot"], Spsi_rot)
     torch.cuda.synchronize()
     errs = {
