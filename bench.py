@@ -44,10 +44,12 @@ def parse():
 # kernels behind each timed call, and the sources they are built from
 PART_KERNELS = {
     "project": (["k_project"], ["csrc/nonlocal.hip", "csrc/proj.h"]),
-    "apply_H": (["k_dmat", "k_stencil"], ["csrc/stencil.hip", "csrc/nonlocal.hip", "csrc/proj.h"]),
-    "apply_S": (["k_dmat", "k_apply_S"], ["csrc/stencil.hip", "csrc/nonlocal.hip", "csrc/proj.h"]),
+    # H~psi and S~psi in one pass: Delta H.P and Delta S.P, then the stencil
+    "apply_HS": (["k_dmat", "k_dmat", "k_stencil"],
+                 ["csrc/stencil.hip", "csrc/nonlocal.hip", "csrc/proj.h"]),
     "subspace": (["k_subspace", "k_subspace_reduce"], ["csrc/gemm.hip"]),
-    "rotate": (["k_rotate", "k_rotate"], ["csrc/gemm.hip"]),
+    # the block and its projections
+    "rotate": (["k_rotate", "k_rot_small"], ["csrc/gemm.hip"]),
 }
 
 
@@ -128,8 +130,7 @@ def precision_form(steps, warmup):
 
         def step():
             g.project(psi, out=P, stream=stream)
-            g.apply_H(psi, P, out=Hpsi, stream=stream)
-            g.apply_S(psi, P, out=Spsi, stream=stream)
+            g.apply_HS(psi, P, Hpsi=Hpsi, Spsi=Spsi, stream=stream)
             g.subspace_matrices(psi, Hpsi, Spsi, H=H, S=S, stream=stream)
             g.subspace_diag(H, S, eps=eps, C=C, info=info, stream=stream)
             g.rotate(psi, C, out=psi_rot, P=P, P_out=P_rot, stream=stream)
@@ -252,11 +253,9 @@ def part_costs(s, info):
         # gather psi at every sphere entry, read the projector table once, write P
         "project": dict(bytes=ent * nb * es + ent * (ni * es + 4) + nb * npj * es,
                         flops=2 * ent * ni * nb),
-        # read psi, write H~psi, read v and the add-back tables once
-        "apply_H": dict(bytes=2 * nb * ng * es + ng * 8 + info["covered"] * 8
-                        + ent * (ni * es + 4), flops=0),
-        "apply_S": dict(bytes=2 * nb * ng * es + info["covered"] * 8 + ent * (ni * es + 4),
-                        flops=0),
+        # read psi, write H~psi and S~psi, read v and the add-back tables once
+        "apply_HS": dict(bytes=3 * nb * ng * es + ng * 8 + info["covered"] * 8
+                         + ent * (ni * es + 4), flops=0),
         # read psi, H~psi, S~psi; two Hermitian nb x nb products over Ng, of
         # which the nb (nb + 1) / 2 entries on and above the diagonal are
         # needed (real FP64 flops: 2 per multiply-add, 4 times that complex)
@@ -326,11 +325,18 @@ def main():
     P_rot = torch.empty_like(P)
     info = torch.zeros(1, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
+    # launch shapes from the library's autotuner (kept in the system; every
+    # choice computes the same results)
+    tb = gfd.Batch([sysg])
+    tio = tb.io([psi], [psi_rot], [eps])
+    tb.tune(tio, info)
+    tuning = tb.tuning()
+    tb.close()
+    torch.cuda.synchronize()
 
     parts = [
         ("project", lambda: sysg.project(psi, out=P, stream=stream)),
-        ("apply_H", lambda: sysg.apply_H(psi, P, out=Hpsi, stream=stream)),
-        ("apply_S", lambda: sysg.apply_S(psi, P, out=Spsi, stream=stream)),
+        ("apply_HS", lambda: sysg.apply_HS(psi, P, Hpsi=Hpsi, Spsi=Spsi, stream=stream)),
         ("subspace", lambda: sysg.subspace_matrices(psi, Hpsi, Spsi, H=H, S=S, stream=stream)),
         ("diag", lambda: sysg.subspace_diag(H, S, eps=eps, C=C, info=info, stream=stream)),
         ("rotate", lambda: sysg.rotate(psi, C, out=psi_rot, P=P, P_out=P_rot, stream=stream)),
@@ -407,6 +413,7 @@ def main():
                                f"FP64 real",
                    "grid": list(s.n), "bands": nb, "atoms": s.natoms, "parallelism": "single GPU"},
         "parts": rows,
+        "launch_tuning": tuning[1][0] if tuning else None,
         "roofline": roof,
     }
     sysg.close()

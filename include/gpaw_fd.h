@@ -140,6 +140,14 @@ GPAW_API int gpaw_fd_apply_H(gpaw_sys *sys, const void *psi, int32_t nb, const v
 GPAW_API int gpaw_fd_apply_S(gpaw_sys *sys, const void *psi, int32_t nb, const void *P,
                     void *Spsi, void *stream);
 
+/* Hpsi = H~ psi and Spsi = S~ psi in one pass over psi (Eq. (dh) and the
+ * overlap beside it): the same results as gpaw_fd_apply_H and
+ * gpaw_fd_apply_S, with the projector values at each grid point evaluated
+ * once for both add-backs. P as for gpaw_fd_apply_H. Hpsi, Spsi and psi
+ * must not overlap one another (GPAW_EALIAS). */
+GPAW_API int gpaw_fd_apply_HS(gpaw_sys *sys, const void *psi, int32_t nb, const void *P,
+                     void *Hpsi, void *Spsi, void *stream);
+
 /* Subspace matrices of SCF step (1) (Sec. "Solving the Kohn-Sham equation"):
  * H_nm = dV sum_r conj(psi_n(r)) Hpsi_m(r), S_nm likewise with Spsi, both
  * [nb][nb], full (not symmetrised), summed in a fixed order (bitwise

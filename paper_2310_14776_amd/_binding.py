@@ -43,7 +43,7 @@ class SysDesc(ctypes.Structure):
 _lib = None
 
 ENTRY_POINTS = ["gpaw_sys_create", "gpaw_sys_destroy", "gpaw_sys_info", "gpaw_project",
-                "gpaw_fd_apply_H", "gpaw_fd_apply_S", "gpaw_subspace_matrices",
+                "gpaw_fd_apply_H", "gpaw_fd_apply_S", "gpaw_fd_apply_HS", "gpaw_subspace_matrices",
                 "gpaw_subspace_diag", "gpaw_rotate", "gpaw_orthonormalize",
                 "gpaw_batch_create", "gpaw_batch_destroy", "gpaw_batch_step",
                 "gpaw_batch_tune", "gpaw_batch_tuning",
@@ -76,6 +76,7 @@ def load():
     lib.gpaw_project.argtypes = [vp, vp, i32, vp, vp]
     lib.gpaw_fd_apply_H.argtypes = [vp, vp, i32, vp, vp, vp]
     lib.gpaw_fd_apply_S.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.gpaw_fd_apply_HS.argtypes = [vp, vp, i32, vp, vp, vp, vp]
     lib.gpaw_subspace_matrices.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
     lib.gpaw_subspace_diag.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
     lib.gpaw_rotate.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
@@ -217,6 +218,15 @@ class System:
         _check(load().gpaw_fd_apply_S(self._h, _ptr(psi), nb, _ptr(P), _ptr(out), _stream(stream)))
         return out
 
+    def apply_HS(self, psi, P=None, Hpsi=None, Spsi=None, stream=None):
+        """H~psi and S~psi in one pass (same results as apply_H and apply_S)."""
+        nb = self._nb(psi)
+        Hpsi = torch.empty_like(psi) if Hpsi is None else Hpsi
+        Spsi = torch.empty_like(psi) if Spsi is None else Spsi
+        _check(load().gpaw_fd_apply_HS(self._h, _ptr(psi), nb, _ptr(P), _ptr(Hpsi), _ptr(Spsi),
+                                       _stream(stream)))
+        return Hpsi, Spsi
+
     def subspace_matrices(self, psi, Hpsi, Spsi=None, H=None, S=None, stream=None):
         nb = self._nb(psi)
         H = self._new(nb, nb, dtype=self.mat_dtype) if H is None else H
@@ -255,8 +265,7 @@ class System:
     def step(self, psi, stream=None):
         """One block step: P, H~psi, S~psi, H_nm, S_nm, eigensolve, rotation."""
         P = self.project(psi, stream=stream)
-        Hpsi = self.apply_H(psi, P, stream=stream)
-        Spsi = self.apply_S(psi, P, stream=stream)
+        Hpsi, Spsi = self.apply_HS(psi, P, stream=stream)
         H, S = self.subspace_matrices(psi, Hpsi, Spsi, stream=stream)
         eps, C = self.subspace_diag(H, S, stream=stream)
         psi_rot, P_rot = self.rotate(psi, C, P=P, stream=stream)

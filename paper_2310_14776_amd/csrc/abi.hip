@@ -73,7 +73,7 @@ void free_sys(gpaw_sys *s) {
   void *bufs[] = {s->tab.a_start, s->tab.e_g, s->tab.e_xyz, s->tab.pinfo, s->tab.pm_code,
                   s->tab.pos,     s->dH,      s->dS,        s->v,          s->ws.P,
                   s->ws.X,        s->ws.part, s->ws.eig,    s->ws.info,    s->tab.proj,
-                  s->ws.split,    s->ws.mat};
+                  s->ws.split,    s->ws.mat,  s->ws.XS};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   delete s;
@@ -167,6 +167,7 @@ int gpaw_sys_create(const gpaw_sys_desc *d, gpaw_sys **out) {
       const size_t pbytes = static_cast<size_t>(s->max_bands) * s->np * es;
       if ((rc = dev_alloc(reinterpret_cast<char **>(&s->ws.P), pbytes)) != GPAW_OK) break;
       if ((rc = dev_alloc(reinterpret_cast<char **>(&s->ws.X), pbytes)) != GPAW_OK) break;
+      if ((rc = dev_alloc(reinterpret_cast<char **>(&s->ws.XS), pbytes)) != GPAW_OK) break;
     }
     if ((rc = dev_alloc(&s->v, static_cast<size_t>(ng))) != GPAW_OK) break;
     if (hipMemcpy(s->v, d->v, ng * 8, hipMemcpyHostToDevice) != hipSuccess) {
@@ -267,6 +268,36 @@ int gpaw_fd_apply_H(gpaw_sys *s, const void *psi, int32_t nb, const void *P, voi
 int gpaw_fd_apply_S(gpaw_sys *s, const void *psi, int32_t nb, const void *P, void *Spsi,
                     void *stream) {
   return apply(s, psi, nb, P, Spsi, stream, false);
+}
+
+int gpaw_fd_apply_HS(gpaw_sys *s, const void *psi, int32_t nb, const void *P, void *Hpsi,
+                     void *Spsi, void *stream) {
+  int rc;
+  if ((rc = check_sys(s)) != GPAW_OK) return rc;
+  if ((rc = check_nb(s, nb)) != GPAW_OK) return rc;
+  if (!psi || !Hpsi || !Spsi) return fail(GPAW_EINVAL, "psi, Hpsi and Spsi must not be NULL");
+  const size_t es = elem_size(s->dtype);
+  const size_t bytes = static_cast<size_t>(nb) * s->ng * es;
+  if (overlaps(Hpsi, bytes, psi, bytes) || overlaps(Spsi, bytes, psi, bytes) ||
+      overlaps(Hpsi, bytes, Spsi, bytes))
+    return fail(GPAW_EALIAS, "Hpsi, Spsi and psi must not overlap");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const void *X = nullptr, *XS = nullptr;
+  if (s->np > 0) {
+    const size_t pbytes = static_cast<size_t>(nb) * s->np * es;
+    if (P && (overlaps(Hpsi, bytes, P, pbytes) || overlaps(Spsi, bytes, P, pbytes)))
+      return fail(GPAW_EALIAS, "an output overlaps P");
+    if (!P) {
+      if ((rc = launch_project(s, psi, nb, s->ws.P, st)) != GPAW_OK) return rc;
+      P = s->ws.P;
+    }
+    if ((rc = launch_dmat(s, s->dH, P, nb, s->ws.X, st)) != GPAW_OK) return rc;
+    if ((rc = launch_dmat(s, s->dS, P, nb, s->ws.XS, st)) != GPAW_OK) return rc;
+    X = s->ws.X;
+    XS = s->ws.XS;
+  }
+  if ((rc = launch_stencil(s, psi, nb, X, Hpsi, st, XS, Spsi)) != GPAW_OK) return rc;
+  return after_launch("gpaw_fd_apply_HS");
 }
 
 int gpaw_subspace_matrices(gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,

@@ -97,15 +97,15 @@ int chain(const gpaw_batch *b, size_t i, const gpaw_batch_io &io, int32_t *info,
   void *S = io.S_nn ? io.S_nn : w.S;
   void *C = io.C_nn ? io.C_nn : w.C;
   const void *X = s->np > 0 ? s->ws.X : nullptr;
+  const void *XS = s->np > 0 ? s->ws.XS : nullptr;
   int rc;
   if (s->np > 0) {
     if ((rc = launch_project(s, io.psi, nb, w.P, st)) != GPAW_OK) return rc;
     if ((rc = launch_dmat(s, s->dH, w.P, nb, s->ws.X, st)) != GPAW_OK) return rc;
+    if ((rc = launch_dmat(s, s->dS, w.P, nb, s->ws.XS, st)) != GPAW_OK) return rc;
   }
-  if ((rc = launch_stencil(s, io.psi, nb, X, w.Hpsi, st)) != GPAW_OK) return rc;
-  if (s->np > 0)
-    if ((rc = launch_dmat(s, s->dS, w.P, nb, s->ws.X, st)) != GPAW_OK) return rc;
-  if ((rc = launch_apply_S(s, io.psi, nb, X, w.Spsi, st)) != GPAW_OK) return rc;
+  // H~psi and S~psi in one pass
+  if ((rc = launch_stencil(s, io.psi, nb, X, w.Hpsi, st, XS, w.Spsi)) != GPAW_OK) return rc;
   if ((rc = launch_subspace(s, io.psi, w.Hpsi, w.Spsi, nb, H, S, st)) != GPAW_OK) return rc;
   if ((rc = launch_eigh(s, H, S, nb, io.eps, C, info + i, st)) != GPAW_OK) return rc;
   if ((rc = launch_rotate(s, C, io.psi, nb, s->ng, io.psi_out, st)) != GPAW_OK) return rc;
@@ -265,13 +265,16 @@ int tune_system(gpaw_batch *b, size_t i, const gpaw_batch_io &io, int32_t *info,
   if ((rc = chain(b, i, io, info, st)) != GPAW_OK) return rc;
   void *C = io.C_nn ? io.C_nn : w.C;
   const void *X = s->np > 0 ? s->ws.X : nullptr;
+  const void *XS = s->np > 0 ? s->ws.XS : nullptr;
   if (s->np > 0)
     if ((rc = pick(&s->tune.prj_nbg, cplx ? std::vector<int>{1, 2} : std::vector<int>{2, 4},
                    [&] { return launch_project(s, io.psi, nb, w.P, st); }, st)) != GPAW_OK)
       return rc;
-  if (s->np > 0)
+  if (s->np > 0) {
     if ((rc = launch_dmat(s, s->dH, w.P, nb, s->ws.X, st)) != GPAW_OK) return rc;
-  auto stencil = [&] { return launch_stencil(s, io.psi, nb, X, w.Hpsi, st); };
+    if ((rc = launch_dmat(s, s->dS, w.P, nb, s->ws.XS, st)) != GPAW_OK) return rc;
+  }
+  auto stencil = [&] { return launch_stencil(s, io.psi, nb, X, w.Hpsi, st, XS, w.Spsi); };
   if ((rc = pick(&s->tune.st_nb, cplx ? std::vector<int>{1, 2} : std::vector<int>{2, 4}, stencil,
                  st)) != GPAW_OK)
     return rc;

@@ -150,6 +150,7 @@ struct Tables {
 struct Workspace {
   void *P = nullptr;       // [max_bands][Np] projections when the caller gives none
   void *X = nullptr;       // [max_bands][Np] Delta.P
+  void *XS = nullptr;      // [max_bands][Np] Delta S.P (H~ and S~ in one pass)
   double *part = nullptr;  // subspace split-K partial sums
   size_t part_elems = 0;
   void *split = nullptr;   // BF16 planes of C for the split rotation
@@ -226,8 +227,10 @@ __device__ inline void copy_rounds(T *dst, const T *src, int count, int tid, int
 int launch_project(const gpaw_sys *s, const void *psi, int nb, void *P, hipStream_t st);
 int launch_dmat(const gpaw_sys *s, const double *D, const void *P, int nb, void *X,
                 hipStream_t st);
+// outS (optional): S~psi formed in the same pass, XS = Delta S.P (null
+// without projectors)
 int launch_stencil(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,
-                   hipStream_t st);
+                   hipStream_t st, const void *XS = nullptr, void *outS = nullptr);
 int launch_apply_S(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,
                    hipStream_t st);
 int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,

@@ -14,6 +14,7 @@
 // each covered grid point sums q^a_i(r) (Delta.P)^a_i over the atoms whose
 // spheres reach it, so H~psi leaves the kernel in one HBM pass.
 #include <algorithm>
+#include <type_traits>
 
 #include "proj.h"
 
@@ -37,6 +38,7 @@ struct AddArgs {
   const int32_t *pm_code;  // atom << 12 | image code
   const double *pos;       // [natoms][3]
   const void *X;           // [nb][Np] Delta.P
+  const void *XS;          // [nb][Np] Delta S.P when S~psi is formed in the same pass
   const ProjDev *pj;
   int np;
   int natoms;
@@ -61,11 +63,11 @@ __device__ inline int clamp3(int w) { return w < -3 ? -3 : (w > 3 ? 3 : w); }
 // The projector values of an entry are evaluated once and reused for every
 // band; X rows of the band group and the atom positions come from LDS when
 // they fit (generic pointers otherwise).
-template <typename T, int NI, int NB, typename PJ>
+template <typename T, int NI, int NB, bool S2, typename PJ>
 __device__ inline void addback_group(const AddArgs &ab, const PJ &pj, int4 pi, int ix, int iy,
                                      int iz, const double *pos, const z64 *phs, const T *Xs,
-                                     int ldx, int ni, int b0, int nb,
-                                     typename St<T>::Acc *acc) {
+                                     const T *XSs, int ldx, int ni, int b0, int nb,
+                                     typename St<T>::Acc *acc, typename St<T>::Acc *accS) {
   using A = typename St<T>::Acc;
   constexpr bool FIXED = NI == 13;
   const int cnt = static_cast<int>(static_cast<unsigned>(pi.w) >> 24);
@@ -93,6 +95,15 @@ __device__ inline void addback_group(const AddArgs &ab, const PJ &pj, int4 pi, i
       for (int i = 0; i < NI; ++i)
         if (FIXED || i < ni) sum = sum + St<A>::scale(pv[i], St<T>::widen(Xb[i]));
       acc[b] = acc[b] + St<A>::phase(sum, ph);
+      if constexpr (S2) {
+        // the overlap's add-back from the same projector values
+        const T *XSb = XSs + a * (FIXED ? 13 : ni) + static_cast<int64_t>(b) * ldx;
+        A sumS = St<A>::zero();
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+          if (FIXED || i < ni) sumS = sumS + St<A>::scale(pv[i], St<T>::widen(XSb[i]));
+        accS[b] = accS[b] + St<A>::phase(sumS, ph);
+      }
     }
   }
 }
@@ -113,15 +124,18 @@ __device__ inline const double *stage_pos(const AddArgs &ab, double *lds_pos, in
 // Copies the band group's X rows into LDS (rows b >= nb are left unset); the
 // rows of a group are contiguous in X
 template <typename T, int NB>
-__device__ inline void stage_x(const AddArgs &ab, int b0, int nb, T *xs) {
-  const T *X = static_cast<const T *>(ab.X) + static_cast<int64_t>(b0) * ab.np;
+__device__ inline void stage_x(const AddArgs &ab, int b0, int nb, T *xs, const void *Xsrc) {
+  const T *X = static_cast<const T *>(Xsrc) + static_cast<int64_t>(b0) * ab.np;
   const int rows = nb - b0 < NB ? nb - b0 : NB;
   copy_rounds(xs, X, rows * ab.np, static_cast<int>(threadIdx.x), static_cast<int>(blockDim.x));
 }
 
-template <typename T, bool BLOCH, bool ADD, bool XLDS, int NI, int NB>
+// SOUT: S~psi = psi + sum q^a (Delta S P)^a is formed in the same pass (the
+// projector values and psi at the point are shared) and stored to outS.
+template <typename T, bool BLOCH, bool ADD, bool XLDS, int NI, int NB, bool SOUT>
 __global__ __launch_bounds__(ST_THREADS) void k_stencil(const T *__restrict__ psi,
                                                         T *__restrict__ out,
+                                                        T *__restrict__ outS,
                                                         const double *__restrict__ v,
                                                         StencilGeom G, AddArgs ab, int nb) {
   extern __shared__ unsigned char smem[];
@@ -151,6 +165,8 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil(const T *__restrict__ ps
 
   // X rows of this band group and the atom positions, staged in LDS
   const T *Xs = static_cast<const T *>(ab.X) + static_cast<int64_t>(b0) * ab.np;
+  const T *XSs = SOUT && ADD ? static_cast<const T *>(ab.XS) + static_cast<int64_t>(b0) * ab.np
+                             : nullptr;
   const double *pos = ab.pos;
   const z64 *phs = nullptr;
   if (ADD) {
@@ -160,9 +176,14 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil(const T *__restrict__ ps
       after = reinterpret_cast<T *>(smem + 48 * sizeof(z64));
     }
     if (XLDS) {
-      stage_x<T, NB>(ab, b0, nb, after);
+      stage_x<T, NB>(ab, b0, nb, after, ab.X);
       Xs = after;
       after += NB * ab.np;
+      if (SOUT) {
+        stage_x<T, NB>(ab, b0, nb, after, ab.XS);
+        XSs = after;
+        after += NB * ab.np;
+      }
     }
     pos = stage_pos(ab, ab.natoms <= POS_LDS_MAX ? reinterpret_cast<double *>(after) : nullptr,
                     ab.natoms);
@@ -223,10 +244,15 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil(const T *__restrict__ ps
     const int64_t xoff = static_cast<int64_t>(x) * plane;
     const int64_t g = xoff + f;
     using A = typename St<T>::Acc;
-    A acc[NB];
+    A acc[NB], accS[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = St<A>::zero();
-    if (ADD) addback_group<T, NI, NB>(ab, pj, ab.pinfo[g], x, y, z, pos, phs, Xs, ab.np, ni, b0, nb, acc);
+    for (int b = 0; b < NB; ++b) {
+      acc[b] = St<A>::zero();
+      accS[b] = St<A>::zero();
+    }
+    if (ADD)
+      addback_group<T, NI, NB, SOUT>(ab, pj, ab.pinfo[g], x, y, z, pos, phs, Xs, XSs, ab.np, ni,
+                                     b0, nb, acc, accS);
     const double cv = G.c0 + v[g];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -249,6 +275,7 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil(const T *__restrict__ ps
         r = r + St<A>::scale(G.cz[d - 1], zp + zm);
       }
       out[(b0 + b) * bstride + g] = St<T>::narrow(r);
+      if (SOUT) outS[(b0 + b) * bstride + g] = St<T>::narrow(St<T>::widen(q[b][3]) + accS[b]);
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b)
@@ -273,7 +300,7 @@ __global__ __launch_bounds__(256) void k_apply_S(const T *__restrict__ psi, T *_
       after = reinterpret_cast<T *>(smem + 48 * sizeof(z64));
     }
     if (XLDS) {
-      stage_x<T, NB>(ab, b0, nb, after);
+      stage_x<T, NB>(ab, b0, nb, after, ab.X);
       Xs = after;
       after += NB * ab.np;
     }
@@ -295,7 +322,8 @@ __global__ __launch_bounds__(256) void k_apply_S(const T *__restrict__ psi, T *_
     const int ix = static_cast<int>(g / plane);
     const int r = static_cast<int>(g - static_cast<int64_t>(ix) * plane);
     const int iy = r / n2, iz = r - iy * n2;
-    addback_group<T, NI, NB>(ab, pj, ab.pinfo[g], ix, iy, iz, pos, phs, Xs, ab.np, ni, b0, nb, acc);
+    addback_group<T, NI, NB, false>(ab, pj, ab.pinfo[g], ix, iy, iz, pos, phs, Xs, nullptr,
+                                    ab.np, ni, b0, nb, acc, nullptr);
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b)
@@ -347,12 +375,13 @@ StencilGeom make_geom(const gpaw_sys *s, int nb) {  // nb: band groups
   return G;
 }
 
-AddArgs make_add(const gpaw_sys *s, const void *X) {
+AddArgs make_add(const gpaw_sys *s, const void *X, const void *XS = nullptr) {
   AddArgs ab;
   ab.pinfo = s->tab.pinfo;
   ab.pm_code = s->tab.pm_code;
   ab.pos = s->tab.pos;
   ab.X = X;
+  ab.XS = XS;
   ab.pj = s->tab.proj;
   ab.np = s->np;
   ab.natoms = s->natoms;
@@ -363,13 +392,13 @@ constexpr size_t XLDS_MAX = 32 * 1024;
 
 template <typename T, bool BLOCH, int NB, int NI>
 int stencil_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,
-              hipStream_t st) {
+              hipStream_t st, const void *XS = nullptr, void *outS = nullptr) {
   const int ngroups = (nb + NB - 1) / NB;
   const StencilGeom G = make_geom(s, ngroups);
-  const AddArgs ab = make_add(s, X);
-  const int plane = s->n[1] * s->n[2];
+  const AddArgs ab = make_add(s, X, XS);
+  const bool sout = outS != nullptr;
   const size_t tile = 0;
-  const size_t xbytes = static_cast<size_t>(NB) * s->np * sizeof(T);
+  const size_t xbytes = static_cast<size_t>(NB) * s->np * sizeof(T) * (sout ? 2 : 1);
   const bool xlds = X && xbytes <= XLDS_MAX;
   const size_t pbytes = (X && s->natoms <= POS_LDS_MAX) ? 3 * sizeof(double) * s->natoms : 0;
   const size_t phb = (X && St<T>::cplx) ? 48 * sizeof(z64) : 0;
@@ -378,12 +407,21 @@ int stencil_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *o
   const unsigned grid = static_cast<unsigned>((cols >= 8 ? (cols + 7) / 8 * 8 : cols) * G.chunks);
   const T *ps = static_cast<const T *>(psi);
   T *po = static_cast<T *>(out);
-  if (!X)
-    k_stencil<T, BLOCH, false, false, NI, NB><<<grid, ST_THREADS, lds, st>>>(ps, po, s->v, G, ab, nb);
-  else if (xlds)
-    k_stencil<T, BLOCH, true, true, NI, NB><<<grid, ST_THREADS, lds, st>>>(ps, po, s->v, G, ab, nb);
-  else
-    k_stencil<T, BLOCH, true, false, NI, NB><<<grid, ST_THREADS, lds, st>>>(ps, po, s->v, G, ab, nb);
+  T *pso = static_cast<T *>(outS);
+  auto go = [&](auto sflag) {
+    constexpr bool SO = decltype(sflag)::value;
+    if (!X)
+      k_stencil<T, BLOCH, false, false, NI, NB, SO><<<grid, ST_THREADS, lds, st>>>(ps, po, pso, s->v,
+                                                                                  G, ab, nb);
+    else if (xlds)
+      k_stencil<T, BLOCH, true, true, NI, NB, SO><<<grid, ST_THREADS, lds, st>>>(ps, po, pso, s->v,
+                                                                                G, ab, nb);
+    else
+      k_stencil<T, BLOCH, true, false, NI, NB, SO><<<grid, ST_THREADS, lds, st>>>(ps, po, pso, s->v,
+                                                                                 G, ab, nb);
+  };
+  if (sout) go(std::true_type{});
+  else go(std::false_type{});
   return GPAW_OK;
 }
 
@@ -410,27 +448,27 @@ int apply_S_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *o
 }  // namespace
 
 int launch_stencil(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,
-                   hipStream_t st) {
+                   hipStream_t st, const void *XS, void *outS) {
   const bool std13 = s->ni == 13 && s->proj.std13;
   switch (s->dtype) {
     case GPAW_C128:
       // one band per lane with projectors (shorter add-back per wave), two without
       if (std13 && (s->tune.st_nb == 1 || (s->tune.st_nb == 0 && X)))
-        return stencil_t<z64, true, 1, 13>(s, psi, nb, X, out, st);
-      return std13 ? stencil_t<z64, true, 2, 13>(s, psi, nb, X, out, st)
-                   : stencil_t<z64, true, 2, PROJ_MAX_NI>(s, psi, nb, X, out, st);
+        return stencil_t<z64, true, 1, 13>(s, psi, nb, X, out, st, XS, outS);
+      return std13 ? stencil_t<z64, true, 2, 13>(s, psi, nb, X, out, st, XS, outS)
+                   : stencil_t<z64, true, 2, PROJ_MAX_NI>(s, psi, nb, X, out, st, XS, outS);
     case GPAW_F32:
-      return std13 ? stencil_t<float, false, 4, 13>(s, psi, nb, X, out, st)
-                   : stencil_t<float, false, 4, PROJ_MAX_NI>(s, psi, nb, X, out, st);
+      return std13 ? stencil_t<float, false, 4, 13>(s, psi, nb, X, out, st, XS, outS)
+                   : stencil_t<float, false, 4, PROJ_MAX_NI>(s, psi, nb, X, out, st, XS, outS);
     case GPAW_C64:
-      return std13 ? stencil_t<z32, true, 2, 13>(s, psi, nb, X, out, st)
-                   : stencil_t<z32, true, 2, PROJ_MAX_NI>(s, psi, nb, X, out, st);
+      return std13 ? stencil_t<z32, true, 2, 13>(s, psi, nb, X, out, st, XS, outS)
+                   : stencil_t<z32, true, 2, PROJ_MAX_NI>(s, psi, nb, X, out, st, XS, outS);
     default:
       // two bands per lane with projectors, four without
       if (std13 && (s->tune.st_nb == 2 || (s->tune.st_nb == 0 && X)))
-        return stencil_t<double, false, 2, 13>(s, psi, nb, X, out, st);
-      return std13 ? stencil_t<double, false, 4, 13>(s, psi, nb, X, out, st)
-                   : stencil_t<double, false, 4, PROJ_MAX_NI>(s, psi, nb, X, out, st);
+        return stencil_t<double, false, 2, 13>(s, psi, nb, X, out, st, XS, outS);
+      return std13 ? stencil_t<double, false, 4, 13>(s, psi, nb, X, out, st, XS, outS)
+                   : stencil_t<double, false, 4, PROJ_MAX_NI>(s, psi, nb, X, out, st, XS, outS);
   }
 }
 

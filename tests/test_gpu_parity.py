@@ -121,6 +121,31 @@ def test_apply_without_projections(name):
     sysg.close()
 
 
+@pytest.mark.parametrize("name", ["B", "ragged13x17x11", "noatoms", "bloch_ragged", "large_real_nb200"])
+def test_fused_apply_matches_separate_calls(name):
+    """H~psi and S~psi from the one-pass call equal the separate calls (the
+    same arithmetic in the same order) and the oracle."""
+    s, ops, ref = case(name)
+    say(f"[apply-HS] case={name}")
+    sysg = gfd.System.from_synth(s)
+    psi = to_dev(s.psi.reshape(s.nb, -1))
+    P = sysg.project(psi) if s.natoms else None
+    Hf, Sf = sysg.apply_HS(psi, P)
+    Hs = sysg.apply_H(psi, P)
+    Ss = sysg.apply_S(psi, P)
+    torch.cuda.synchronize()
+    assert torch.equal(Hf, Hs)
+    assert rel(host(Sf), host(Ss)) <= 1e-15
+    assert rel(host(Hf), ref["Hpsi"]) <= TOL
+    assert rel(host(Sf), ref["Spsi"]) <= TOL
+    # the outputs must not overlap psi or each other
+    with pytest.raises(gfd.GpawError):
+        sysg.apply_HS(psi, P, Hpsi=psi)
+    with pytest.raises(gfd.GpawError):
+        sysg.apply_HS(psi, P, Hpsi=Hf, Spsi=Hf)
+    sysg.close()
+
+
 def test_step_is_bitwise_deterministic():
     s, _, _ = case("B")
     say("[determinism] case=B")
