@@ -45,6 +45,9 @@ constexpr int EIG_T = 1024;
 constexpr int EIG_NMAX = 128;
 constexpr int EIG_LARGE_MAX = 1024;
 constexpr int VEC_T = 8;  // lanes (eigenvectors) per inverse-iteration workgroup
+// max |Z^T Z - I| below which the Newton-Schulz steps are skipped (an eighth
+// of the 1e-12 orthonormality the eigenvectors are held to)
+constexpr double NS_SKIP = 1.25e-13;
 constexpr int SG_T = 256;  // small-GEMM workgroup: four 16x16 output tiles
 constexpr int CH_T = 512;  // blocked Cholesky: 8 wavefronts (256 VGPRs each)
 
@@ -55,7 +58,15 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 struct EigWs {
   double *Linv, *T1, *A, *V, *Z, *Z2, *G, *tau, *d, *e, *lam;
   double *Sw, *piv, *p, *lu;  // blocks above the LDS limit only
+  int32_t *skip;              // nonzero: the Newton-Schulz steps have nothing to do
 };
+
+size_t eig_layout_elems(int n, int sz, bool large) {
+  const size_t nn = static_cast<size_t>(n) * n;
+  size_t e = 4 * sz * nn + 3 * nn + sz * n + 3 * n;
+  if (large) e += sz * nn + n + sz * n + 6 * nn;
+  return e + 64;
+}
 
 // sz = doubles per scalar; large = include the global-memory path's buffers
 EigWs eig_layout(double *base, int n, int sz, bool large) {
@@ -80,15 +91,11 @@ EigWs eig_layout(double *base, int n, int sz, bool large) {
     w.p = w.piv + n;
     w.lu = w.p + sz * n;
   }
+  // the last double of the block (the layout keeps 64 spare at its end)
+  w.skip = reinterpret_cast<int32_t *>(base + eig_layout_elems(n, sz, large) - 1);
   return w;
 }
 
-size_t eig_layout_elems(int n, int sz, bool large) {
-  const size_t nn = static_cast<size_t>(n) * n;
-  size_t e = 4 * sz * nn + 3 * nn + sz * n + 3 * n;
-  if (large) e += sz * nn + n + sz * n + 6 * nn;
-  return e + 64;
-}
 
 template <typename T> __host__ __device__ inline T *as(double *p) { return reinterpret_cast<T *>(p); }
 
@@ -1004,9 +1011,17 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
 
 // ------------------------------------------------------------------ orthogonality
 // dev[slot] = max |G - I| (one workgroup); info = -1 when above the limit
+// skip (optional): set to 1 when max |G - I| <= skip_limit (the vectors are
+// already orthonormal to rounding, so the Newton-Schulz steps, which take
+// skip as their status word, do nothing) or when the status is not 0;
+// gate (optional): the check does nothing while *gate is nonzero.
 __global__ __launch_bounds__(1024) void k_gram_check(const double *__restrict__ G, int n,
-                                                     double limit, int32_t *info) {
-  if (*info != 0) return;
+                                                     double limit, int32_t *info, int32_t *skip,
+                                                     double skip_limit, const int32_t *gate) {
+  if (*info != 0 || (gate && *gate != 0)) {
+    if (skip && threadIdx.x == 0) *skip = 1;
+    return;
+  }
   __shared__ double red[16];
   double dev = 0.0;
   const int nn = n * n;
@@ -1033,6 +1048,7 @@ __global__ __launch_bounds__(1024) void k_gram_check(const double *__restrict__ 
     double all = 0.0;
     for (int q = 0; q < 16; ++q) all = fmax(all, red[q]);
     if (!(all <= limit)) *info = -1;
+    if (skip) *skip = (all <= skip_limit || !(all <= limit)) ? 1 : 0;
   }
 }
 
@@ -1225,11 +1241,11 @@ int eigh_large_t(const gpaw_sys *s, const T *H, const T *S, int n, double *eps, 
   k_eig_values<<<(n + 3) / 4, 256, values_lds_bytes(n), st>>>(n, w.d, w.e, w.lam, info);
   large_vectors(n, w.d, w.e, w.lam, w.lu, w.Z, info, st);
   k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.Z, w.G, n, info);
-  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 0.5, info);
-  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.G, w.Z2, n, info);
-  k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.Z2, w.G, n, info);
-  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 1e-7, info);
-  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.G, w.Z, n, info);
+  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 0.5, info, w.skip, NS_SKIP, nullptr);
+  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.G, w.Z2, n, w.skip);
+  k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.Z2, w.G, n, w.skip);
+  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 1e-7, info, nullptr, 0.0, w.skip);
+  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.G, w.Z, n, w.skip);
   large_back<T>(n, w.Z, V, tau, w.lam, U, eps, info, st);
   k_small_gemm<T, 1, 0><<<sg_blocks, SG_T, 0, st>>>(Linv, U, C, n, info);
   return GPAW_OK;
@@ -1274,13 +1290,14 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
                                                                                         info);
   // two Newton-Schulz steps Z <- Z (3I - Z^T Z)/2 on the real tridiagonal
   // eigenvectors; the second Gram matrix must be within 1e-7 of I, so the
-  // result is orthonormal to ~1e-14
+  // result is orthonormal to ~1e-14. When the first Gram matrix is already
+  // within NS_SKIP of I the steps are skipped (on the device: no host wait).
   k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.Z, w.G, n, info);
-  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 0.5, info);
-  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.G, w.Z2, n, info);
-  k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.Z2, w.G, n, info);
-  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 1e-7, info);
-  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.G, w.Z, n, info);
+  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 0.5, info, w.skip, NS_SKIP, nullptr);
+  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.G, w.Z2, n, w.skip);
+  k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.Z2, w.G, n, w.skip);
+  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 1e-7, info, nullptr, 0.0, w.skip);
+  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.G, w.Z, n, w.skip);
   // U = Q Z in eigen-order, then C = Linv^H U
   k_eig_back<T><<<(n + 15) / 16, 128, back_lds_bytes<T>(n), st>>>(
       n, w, w.Z, U, eps, info);
