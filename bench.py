@@ -44,8 +44,8 @@ def parse():
 # kernels behind each timed call, and the sources they are built from
 PART_KERNELS = {
     "project": (["k_project"], ["csrc/nonlocal.hip", "csrc/proj.h"]),
-    # H~psi and S~psi in one pass: Delta H.P and Delta S.P, then the stencil
-    "apply_HS": (["k_dmat", "k_dmat", "k_stencil"],
+    # H~psi and S~psi in one pass: Delta H.P and Delta S.P (one launch), then the stencil
+    "apply_HS": (["k_dmat2", "k_stencil"],
                  ["csrc/stencil.hip", "csrc/nonlocal.hip", "csrc/proj.h"]),
     "subspace": (["k_subspace", "k_subspace_reduce"], ["csrc/gemm.hip"]),
     # the block and its projections

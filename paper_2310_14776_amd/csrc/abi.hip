@@ -291,8 +291,7 @@ int gpaw_fd_apply_HS(gpaw_sys *s, const void *psi, int32_t nb, const void *P, vo
       if ((rc = launch_project(s, psi, nb, s->ws.P, st)) != GPAW_OK) return rc;
       P = s->ws.P;
     }
-    if ((rc = launch_dmat(s, s->dH, P, nb, s->ws.X, st)) != GPAW_OK) return rc;
-    if ((rc = launch_dmat(s, s->dS, P, nb, s->ws.XS, st)) != GPAW_OK) return rc;
+    if ((rc = launch_dmat2(s, P, nb, s->ws.X, s->ws.XS, st)) != GPAW_OK) return rc;
     X = s->ws.X;
     XS = s->ws.XS;
   }

@@ -101,8 +101,7 @@ int chain(const gpaw_batch *b, size_t i, const gpaw_batch_io &io, int32_t *info,
   int rc;
   if (s->np > 0) {
     if ((rc = launch_project(s, io.psi, nb, w.P, st)) != GPAW_OK) return rc;
-    if ((rc = launch_dmat(s, s->dH, w.P, nb, s->ws.X, st)) != GPAW_OK) return rc;
-    if ((rc = launch_dmat(s, s->dS, w.P, nb, s->ws.XS, st)) != GPAW_OK) return rc;
+    if ((rc = launch_dmat2(s, w.P, nb, s->ws.X, s->ws.XS, st)) != GPAW_OK) return rc;
   }
   // H~psi and S~psi in one pass
   if ((rc = launch_stencil(s, io.psi, nb, X, w.Hpsi, st, XS, w.Spsi)) != GPAW_OK) return rc;
@@ -267,13 +266,11 @@ int tune_system(gpaw_batch *b, size_t i, const gpaw_batch_io &io, int32_t *info,
   const void *X = s->np > 0 ? s->ws.X : nullptr;
   const void *XS = s->np > 0 ? s->ws.XS : nullptr;
   if (s->np > 0)
-    if ((rc = pick(&s->tune.prj_nbg, cplx ? std::vector<int>{1, 2} : std::vector<int>{2, 4},
+    if ((rc = pick(&s->tune.prj_nbg, cplx ? std::vector<int>{1, 2} : std::vector<int>{2, 4, 8},
                    [&] { return launch_project(s, io.psi, nb, w.P, st); }, st)) != GPAW_OK)
       return rc;
-  if (s->np > 0) {
-    if ((rc = launch_dmat(s, s->dH, w.P, nb, s->ws.X, st)) != GPAW_OK) return rc;
-    if ((rc = launch_dmat(s, s->dS, w.P, nb, s->ws.XS, st)) != GPAW_OK) return rc;
-  }
+  if (s->np > 0)
+    if ((rc = launch_dmat2(s, w.P, nb, s->ws.X, s->ws.XS, st)) != GPAW_OK) return rc;
   auto stencil = [&] { return launch_stencil(s, io.psi, nb, X, w.Hpsi, st, XS, w.Spsi); };
   if ((rc = pick(&s->tune.st_nb, cplx ? std::vector<int>{1, 2} : std::vector<int>{2, 4}, stencil,
                  st)) != GPAW_OK)

@@ -171,7 +171,7 @@ struct Tune {
   int st_nseg = 0;  // x segments of the stencil grid (>= 1)
   int sub_wgs = 0;  // target workgroup count of the split-K subspace product (<= 1024)
   int rot_rb = 0;   // 16-row tiles per rotation workgroup: real 4 or 8, complex 2 or 4
-  int prj_nbg = 0;  // bands per projection workgroup: real 2 or 4, complex 1 or 2
+  int prj_nbg = 0;  // bands per projection workgroup: real 2, 4 or 8, complex 1 or 2
 };
 }  // namespace gfd
 
@@ -227,6 +227,8 @@ __device__ inline void copy_rounds(T *dst, const T *src, int count, int tid, int
 int launch_project(const gpaw_sys *s, const void *psi, int nb, void *P, hipStream_t st);
 int launch_dmat(const gpaw_sys *s, const double *D, const void *P, int nb, void *X,
                 hipStream_t st);
+// X = Delta H . P and XS = Delta S . P in one launch
+int launch_dmat2(const gpaw_sys *s, const void *P, int nb, void *X, void *XS, hipStream_t st);
 // outS (optional): S~psi formed in the same pass, XS = Delta S.P (null
 // without projectors)
 int launch_stencil(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,

@@ -144,8 +144,52 @@ int launch_project(const gpaw_sys *s, const void *psi, int nb, void *P, hipStrea
       break;
     default:
       if (std13 && s->tune.prj_nbg == 2) project_t<double, 13, 2>(s, psi, nb, P, st);
+      else if (std13 && s->tune.prj_nbg == 8) project_t<double, 13, 8>(s, psi, nb, P, st);
       else if (std13) project_t<double, 13, 4>(s, psi, nb, P, st);
       else project_t<double, 32, 1>(s, psi, nb, P, st);
+  }
+  return GPAW_OK;
+}
+
+// X = Delta H . P and XS = Delta S . P in one launch (one read of P)
+template <typename T>
+__global__ __launch_bounds__(256) void k_dmat2(const double *__restrict__ DH,
+                                               const double *__restrict__ DS,
+                                               const T *__restrict__ P, T *__restrict__ X,
+                                               T *__restrict__ XS, int64_t total, int ni, int np) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= total) return;
+  const int64_t n = idx / np;
+  const int ai = static_cast<int>(idx - n * np);
+  const int a = ai / ni, i = ai - a * ni;
+  const int64_t drow = (static_cast<int64_t>(a) * ni + i) * ni;
+  const T *Pa = P + n * np + a * ni;
+  using A = typename St<T>::Acc;
+  A h = St<A>::zero(), sv = St<A>::zero();
+  for (int j = 0; j < ni; ++j) {
+    const A pj = St<T>::widen(Pa[j]);
+    h = h + St<A>::scale(DH[drow + j], pj);
+    sv = sv + St<A>::scale(DS[drow + j], pj);
+  }
+  X[idx] = St<T>::narrow(h);
+  XS[idx] = St<T>::narrow(sv);
+}
+
+template <typename T>
+void dmat2_t(const gpaw_sys *s, const void *P, int nb, void *X, void *XS, hipStream_t st) {
+  const int64_t total = static_cast<int64_t>(nb) * s->np;
+  const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
+  k_dmat2<T><<<blocks, 256, 0, st>>>(s->dH, s->dS, static_cast<const T *>(P), static_cast<T *>(X),
+                                     static_cast<T *>(XS), total, s->ni, s->np);
+}
+
+int launch_dmat2(const gpaw_sys *s, const void *P, int nb, void *X, void *XS, hipStream_t st) {
+  if (s->np == 0) return GPAW_OK;
+  switch (s->dtype) {
+    case GPAW_C128: dmat2_t<z64>(s, P, nb, X, XS, st); break;
+    case GPAW_F32: dmat2_t<float>(s, P, nb, X, XS, st); break;
+    case GPAW_C64: dmat2_t<z32>(s, P, nb, X, XS, st); break;
+    default: dmat2_t<double>(s, P, nb, X, XS, st);
   }
   return GPAW_OK;
 }
