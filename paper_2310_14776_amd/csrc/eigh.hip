@@ -228,8 +228,13 @@ __device__ inline int diag_factor_inverse(T *D, int lda) {
   for (int j = 0; j < 16; ++j) {
     const double d = rl(re_of(row[j]), j);
     if (!(d > 0.0)) return j + 1;
-    const double sd = sqrt(d);
-    dinv[j] = 1.0 / sd;
+    // 1/sqrt(d) from the hardware estimate and two Newton steps, sqrt(d) as
+    // d/sqrt(d): no division or square-root sequence on the chain
+    double rs = __builtin_amdgcn_rsq(d);
+    rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
+    rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
+    const double sd = d * rs;
+    dinv[j] = rs;
     const T lrj = r > j ? row[j] * dinv[j] : (r == j ? realv<T>(sd) : T{});
     row[j] = lrj;
 #pragma unroll
