@@ -148,6 +148,13 @@ __device__ inline double group8_sum(double v) {
 }
 __device__ inline z64 group8_sum(z64 v) { return z64{group8_sum(v.x), group8_sum(v.y)}; }
 
+// 1/x from the hardware estimate and two Newton steps (x != 0, finite)
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // real / complex helpers
 __device__ inline double re_of(double a) { return a; }
 __device__ inline double re_of(z64 a) { return a.x; }
@@ -535,11 +542,17 @@ __device__ inline void tri_reflector(int n, int k, T x0, T x1, T *vout, TriLds<T
     tn = T{};
     scl = T{};
   } else {
-    beta = -copysign(sqrt(abs2(alpha) + xn2), ar);
-    // tau = (beta - alpha)/beta, scl = 1/(alpha - beta)
+    // beta = -sign(ar) sqrt(s2) and -1/beta from one reciprocal square root
+    // (hardware estimate and two Newton steps); tau = (beta - alpha)/beta,
+    // scl = 1/(alpha - beta)
+    const double s2 = abs2(alpha) + xn2;
+    double rs = __builtin_amdgcn_rsq(s2);
+    rs = fma(0.5 * rs, fma(-s2 * rs, rs, 1.0), rs);
+    rs = fma(0.5 * rs, fma(-s2 * rs, rs, 1.0), rs);
+    beta = -copysign(s2 * rs, ar);
     const T amb = alpha - realv<T>(beta);
-    tn = St<T>::scale(-1.0 / beta, amb);
-    scl = cj(amb) * (1.0 / abs2(amb));
+    tn = St<T>::scale(copysign(rs, ar), amb);
+    scl = cj(amb) * rcp_nr(abs2(amb));
   }
   const T y0 = lane == 1 ? realv<T>(1.0) : (lane >= 2 && r0 < n ? x0 * scl : T{});
   const T y1 = r1 < n ? x1 * scl : T{};
@@ -813,12 +826,6 @@ __device__ inline double rv_value(unsigned q) {
   return static_cast<double>(h >> 8) * (1.0 / 8388608.0) - 1.0;
 }
 
-// 1/x from the hardware estimate and two Newton steps (x != 0, finite)
-__device__ inline double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return fma(r, fma(-x, r, 1.0), r);
-}
 
 // LDS doubles of k_eig_vectors: d, e, lam, row sums, split words, the start
 // table, then six per-lane arrays of n (interleaved by lane)
