@@ -73,7 +73,7 @@ void free_sys(gpaw_sys *s) {
   void *bufs[] = {s->tab.a_start, s->tab.e_g, s->tab.e_xyz, s->tab.pinfo, s->tab.pm_code,
                   s->tab.pos,     s->dH,      s->dS,        s->v,          s->ws.P,
                   s->ws.X,        s->ws.part, s->ws.eig,    s->ws.info,    s->tab.proj,
-                  s->ws.split,    s->ws.mat,  s->ws.XS};
+                  s->ws.split,    s->ws.mat,  s->ws.XS,     s->ws.flag};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   delete s;
@@ -179,6 +179,7 @@ int gpaw_sys_create(const gpaw_sys_desc *d, gpaw_sys **out) {
     s->ws.eig_elems = eig_ws_elems(s->max_bands, is_complex(s->dtype));
     if ((rc = dev_alloc(&s->ws.eig, s->ws.eig_elems)) != GPAW_OK) break;
     if ((rc = dev_alloc(&s->ws.info, 1)) != GPAW_OK) break;
+    if ((rc = dev_alloc(&s->ws.flag, 1)) != GPAW_OK) break;
     if ((rc = dev_alloc(reinterpret_cast<char **>(&s->ws.mat),
                         2 * static_cast<size_t>(s->max_bands) * s->max_bands *
                             mat_elem_size(s->dtype))) != GPAW_OK)
@@ -364,10 +365,11 @@ int gpaw_orthonormalize(gpaw_sys *s, const void *psi, const void *Spsi, int32_t 
   int32_t *dinfo = info ? info : s->ws.info;
   if ((rc = launch_subspace(s, psi, Spsi, nullptr, nb, Sm, nullptr, st)) != GPAW_OK) return rc;
   if ((rc = launch_chol_inv(s, Sm, nb, Cm, dinfo, st)) != GPAW_OK) return rc;
-  // L^-H is upper triangular: the rotations skip the zero half
-  if ((rc = launch_rotate(s, Cm, psi, nb, s->ng, psi_out, st, true)) != GPAW_OK) return rc;
+  // L^-H is upper triangular (the rotations skip the zero half) and, for a
+  // nearly orthonormal block, close to the identity
+  if ((rc = launch_rotate(s, Cm, psi, nb, s->ng, psi_out, st, true, true)) != GPAW_OK) return rc;
   if (P && s->np > 0)
-    if ((rc = launch_rotate(s, Cm, P, nb, s->np, P_out, st, true)) != GPAW_OK) return rc;
+    if ((rc = launch_rotate(s, Cm, P, nb, s->np, P_out, st, true, true)) != GPAW_OK) return rc;
   if ((rc = after_launch("gpaw_orthonormalize")) != GPAW_OK) return rc;
   if (info) return GPAW_OK;
   int32_t h_info = 0;

@@ -506,10 +506,10 @@ int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const 
 }
 
 int launch_rotate(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
-                  void *dst, hipStream_t st, bool upper) {
+                  void *dst, hipStream_t st, bool upper, bool near_id) {
   if (cols == 0) return GPAW_OK;
   if (s->dtype == GPAW_F32 || s->dtype == GPAW_C64)
-    return launch_rotate_split(s, C, src, nb, cols, dst, st, upper);
+    return launch_rotate_split(s, C, src, nb, cols, dst, st, upper, near_id);
   // short rows (projections): too few columns to fill the chip by column
   // tiles, so one wavefront per 16 x 16 output tile instead
   if (cols <= 4096) {

@@ -327,11 +327,35 @@ __global__ __launch_bounds__(256) void k_split_reduce(const double *__restrict__
   if (r / tile < q / tile) M[(static_cast<int64_t>(q) * nb + r) * NP + c] = c ? -dV * acc : dV * acc;
 }
 
+// flag = 1 when max |C - I| <= 2^-21: the rotation by C = I + E then needs only
+// the high BF16 parts of E (their product error, about 2^-8 |E| per term, stays
+// below the FP32 resolution of the result), else 0
+template <int NP>
+__global__ __launch_bounds__(1024) void k_offid_small(const double *__restrict__ C, int nb,
+                                                      int32_t *__restrict__ flag) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  const int64_t nn = static_cast<int64_t>(nb) * nb;
+  bool big = false;
+  for (int64_t idx = threadIdx.x; idx < nn; idx += 1024) {
+    const int m = static_cast<int>(idx / nb), n = static_cast<int>(idx - static_cast<int64_t>(m) * nb);
+#pragma unroll
+    for (int c = 0; c < NP; ++c) {
+      const double e = C[idx * NP + c] - (c == 0 && m == n ? 1.0 : 0.0);
+      big |= !(fabs(e) <= 0x1p-21);
+    }
+  }
+  if (big) bad = 1;  // any lane; a plain LDS store of the same value
+  __syncthreads();
+  if (threadIdx.x == 0) *flag = bad ? 0 : 1;
+}
+
 // C (double / complex double, [nb][nb]) -> transposed BF16 planes
 // Ct[p][n][m] for p = hi, mid, lo (and the imaginary part in planes 3..5)
 template <int NP>
 __global__ __launch_bounds__(256) void k_split_c(const double *__restrict__ C, __bf16 *__restrict__ Ct,
-                                                 int nb) {
+                                                 int nb, int minus_id) {
   const int64_t nn = static_cast<int64_t>(nb) * nb;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (idx >= nn) return;
@@ -340,7 +364,8 @@ __global__ __launch_bounds__(256) void k_split_c(const double *__restrict__ C, _
   for (int c = 0; c < NP; ++c) {
     // three BF16 parts of the FP64 coefficient, each rounded to nearest from
     // the remainder in FP64 (the remainders are exact)
-    const double x = C[idx * NP + c];
+    // minus_id: the planes of C - I (the rotation then adds the source back)
+    const double x = C[idx * NP + c] - (minus_id && c == 0 && m == n ? 1.0 : 0.0);
     const uint32_t uh = bf16_rne(__float_as_uint(static_cast<float>(x)));
     const double r1 = x - static_cast<double>(__uint_as_float(uh));
     const uint32_t um = bf16_rne(__float_as_uint(static_cast<float>(r1)));
@@ -358,11 +383,15 @@ __global__ __launch_bounds__(256) void k_split_c(const double *__restrict__ C, _
 // columns g) is split once and stored column-major in LDS, so that the B
 // fragment B[k=m][j=g] of a lane is eight consecutive values. FP32 tiles are
 // added into FP64 accumulators every 8 steps.
-template <typename T, int WT>
+// ADDSRC: Ct holds C - I and the result is src + (C - I)^T src; when *fewer
+// is nonzero (|C - I| small, see k_offid_small) only the high BF16 parts are
+// multiplied (one product instead of six).
+template <typename T, int WT, bool ADDSRC>
 __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
                                                  const T *__restrict__ src, T *__restrict__ dst,
                                                  int nb, int64_t cols, int ntiles_n,
-                                                 int64_t gtiles, int upper) {
+                                                 int64_t gtiles, int upper,
+                                                 const int32_t *__restrict__ fewer) {
   constexpr int NP = Parts<T>::n;
   constexpr int TM = 32 * WT;
   constexpr int PS = TM * LROW;
@@ -437,6 +466,7 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
 
   const int wr = wave >> 1, wc = wave & 1;
   const int fr = lane & 15, fk = (lane >> 4) * 8;
+  const bool one = ADDSRC && fewer && *fewer != 0;
   d4 dacc[NP][WT][WT];
   f4 facc[NP][WT][WT];
 #pragma unroll
@@ -469,11 +499,20 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
 #pragma unroll
       for (int i = 0; i < WT; ++i) {
         // C psi: re = Cr pr - Ci pi, im = Cr pi + Ci pr
-        facc[0][i][j] = mm6(fa[0][i], fb[0], facc[0][i][j]);
-        if constexpr (NP == 2) {
-          facc[0][i][j] = mm6(neg(fa[1][i]), fb[1], facc[0][i][j]);
-          facc[1][i][j] = mm6(fa[0][i], fb[1], facc[1][i][j]);
-          facc[1][i][j] = mm6(fa[1][i], fb[0], facc[1][i][j]);
+        if (ADDSRC && one) {
+          facc[0][i][j] = mm(fa[0][i].h, fb[0].h, facc[0][i][j]);
+          if constexpr (NP == 2) {
+            facc[0][i][j] = mm(neg(fa[1][i]).h, fb[1].h, facc[0][i][j]);
+            facc[1][i][j] = mm(fa[0][i].h, fb[1].h, facc[1][i][j]);
+            facc[1][i][j] = mm(fa[1][i].h, fb[0].h, facc[1][i][j]);
+          }
+        } else {
+          facc[0][i][j] = mm6(fa[0][i], fb[0], facc[0][i][j]);
+          if constexpr (NP == 2) {
+            facc[0][i][j] = mm6(neg(fa[1][i]), fb[1], facc[0][i][j]);
+            facc[1][i][j] = mm6(fa[0][i], fb[1], facc[1][i][j]);
+            facc[1][i][j] = mm6(fa[1][i], fb[0], facc[1][i][j]);
+          }
         }
       }
     }
@@ -500,9 +539,15 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
       for (int e = 0; e < 4; ++e) {
         const int n = n0 + wr * 16 * WT + i * 16 + 4 * (lane >> 4) + e;
         if (n >= nb) continue;
+        double vr = dacc[0][i][j][e], vi = dacc[NP - 1][i][j][e];
+        if (ADDSRC) {
+          const T sv = src[static_cast<int64_t>(n) * cols + g];
+          vr += Parts<T>::re(sv);
+          if constexpr (NP == 2) vi += Parts<T>::im(sv);
+        }
         T o;
-        if constexpr (NP == 2) o = T{static_cast<float>(dacc[0][i][j][e]), static_cast<float>(dacc[1][i][j][e])};
-        else o = static_cast<float>(dacc[0][i][j][e]);
+        if constexpr (NP == 2) o = T{static_cast<float>(vr), static_cast<float>(vi)};
+        else o = static_cast<float>(vr);
         dst[static_cast<int64_t>(n) * cols + g] = o;
       }
     }
@@ -554,19 +599,27 @@ int subspace_split_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const
 
 template <typename T, int WT>
 int rotate_split_t(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
-                   void *dst, hipStream_t st, bool upper) {
+                   void *dst, hipStream_t st, bool upper, bool near_id) {
   constexpr int NP = Parts<T>::n;
   constexpr int TM = 32 * WT;
   __bf16 *Ct = reinterpret_cast<__bf16 *>(s->ws.split);
   const int64_t nn = static_cast<int64_t>(nb) * nb;
-  k_split_c<NP><<<static_cast<unsigned>((nn + 255) / 256), 256, 0, st>>>(
-      static_cast<const double *>(C), Ct, nb);
+  const double *Cd = static_cast<const double *>(C);
+  // near the identity: rotate by C - I and add the source back, with one
+  // BF16 product per pair when |C - I| is small enough (decided on the device)
+  if (near_id) k_offid_small<NP><<<1, 1024, 0, st>>>(Cd, nb, s->ws.flag);
+  k_split_c<NP><<<static_cast<unsigned>((nn + 255) / 256), 256, 0, st>>>(Cd, Ct, nb, near_id ? 1 : 0);
   const int ntiles_n = (nb + TM - 1) / TM;
   const int64_t gtiles = (cols + TM - 1) / TM;
   const int64_t wgs = (gtiles + 7) / 8 * 8 * ntiles_n;
-  k_rot_lds<T, WT><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
-      Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, cols, ntiles_n, gtiles,
-      upper ? 1 : 0);
+  if (near_id)
+    k_rot_lds<T, WT, true><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
+        Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, cols, ntiles_n, gtiles,
+        upper ? 1 : 0, s->ws.flag);
+  else
+    k_rot_lds<T, WT, false><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
+        Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, cols, ntiles_n, gtiles,
+        upper ? 1 : 0, nullptr);
   return GPAW_OK;
 }
 
@@ -591,10 +644,11 @@ int launch_subspace_split(const gpaw_sys *s, const void *psi, const void *Hpsi, 
 }
 
 int launch_rotate_split(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
-                        void *dst, hipStream_t st, bool upper) {
+                        void *dst, hipStream_t st, bool upper, bool near_id) {
   if (cols == 0) return GPAW_OK;
-  if (s->dtype == GPAW_C64) return rotate_split_t<z32, 2>(s, C, src, nb, cols, dst, st, upper);
-  return rotate_split_t<float, 4>(s, C, src, nb, cols, dst, st, upper);
+  if (s->dtype == GPAW_C64)
+    return rotate_split_t<z32, 2>(s, C, src, nb, cols, dst, st, upper, near_id);
+  return rotate_split_t<float, 4>(s, C, src, nb, cols, dst, st, upper, near_id);
 }
 
 }  // namespace gfd

@@ -157,6 +157,7 @@ struct Workspace {
   double *eig = nullptr;   // dense eigensolver scratch
   size_t eig_elems = 0;
   int32_t *info = nullptr; // device status word for synchronous diag
+  int32_t *flag = nullptr; // device word: the near-identity rotation may use one product
   void *mat = nullptr;     // [2][max_bands][max_bands] subspace-sized scratch
 };
 
@@ -238,15 +239,17 @@ int launch_apply_S(const gpaw_sys *s, const void *psi, int nb, const void *X, vo
 int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
                     int nb, void *H, void *S, hipStream_t st);
 size_t subspace_part_elems(const gpaw_sys *s, int nb);
+// upper: C is upper triangular; near_id: C is close to the identity (the
+// single-precision form then rotates by C - I, see the split kernels)
 int launch_rotate(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
-                  void *dst, hipStream_t st, bool upper = false);
+                  void *dst, hipStream_t st, bool upper = false, bool near_id = false);
 // precision form (gemm_split.hip)
 size_t split_part_elems(int nb, bool cplx);
 size_t split_c_bytes(int nb, bool cplx);
 int launch_subspace_split(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
                           int nb, void *H, void *S, hipStream_t st);
 int launch_rotate_split(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
-                        void *dst, hipStream_t st, bool upper = false);
+                        void *dst, hipStream_t st, bool upper = false, bool near_id = false);
 size_t eig_ws_elems(int nmax, bool cplx);
 int launch_eigh(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps, void *C,
                 int32_t *info, hipStream_t st);

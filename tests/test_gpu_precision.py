@@ -82,3 +82,27 @@ def test_precision_form_against_fp64_oracle(name):
     assert errs["eps_max_abs"] <= 1e-6
     assert errs["final_S_minus_I"] <= 1e-6
     g.close()
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_orthonormalize_far_from_orthonormal(cplx):
+    """The single-precision correction on a block far from S~-orthonormal:
+    L^-H is then far from I, so the rotation takes all six split products;
+    the result must be S~-orthonormal at FP32 resolution (FP64 oracle)."""
+    cfg = dict(n=(16, 14, 18), h=0.2, nb=24, natoms=3, rc=1.8, seed=51)
+    if cplx:
+        cfg["k"] = (0.25, 0.0, 0.5)
+    s = fp32_system(cfg)
+    say(f"[orthonormalize] far case complex={cplx}")
+    ops = oracle.Operators.from_system(s)
+    g = gfd.System.from_synth(s, precision="single")
+    psi = to_dev(s.psi.reshape(s.nb, -1).astype(np.complex64 if cplx else np.float32))
+    Spsi = g.apply_S(psi)
+    fin, _ = g.orthonormalize(psi, Spsi)
+    torch.cuda.synchronize()
+    pf = host(fin).astype(np.complex128 if cplx else np.float64)
+    S1 = oracle.subspace_matrices(pf, ops.apply_H(pf), ops.apply_S(pf), ops.dV)[1]
+    dev = np.abs(S1 - np.eye(s.nb)).max()
+    say(f"  max |S' - I| = {dev:.2e}")
+    assert dev <= 1e-5
+    g.close()
