@@ -3,10 +3,9 @@
 // the same method as eigh.hip (Cholesky and diagonalisation of the subspace
 // matrices, Sec. "Parallelization"), with the matrices in global memory
 // (L2/MALL resident) and every sequential step spread over the whole chip:
-//   Cholesky       one launch per column (right-looking, lower), pivots
-//                  recorded, columns scaled in one pass at the end;
-//   Linv           one wavefront per column (forward substitution, the
-//                  column held in registers, rows of L read from L2);
+//   Cholesky       blocked, right-looking, lower, two launches per panel
+//                  of 32 columns, with L^-1 built block row by block row in
+//                  the same launches;
 //   A = Linv H Linv^H, Newton-Schulz, C = Linv^H U: MFMA small-GEMM kernel;
 //   tridiagonal    two launches per column: p = tau A v (one wavefront per
 //                  row), then the rank-2 update of the trailing block with,
@@ -60,77 +59,252 @@ __device__ inline T block_sum(T v, T *red) {
 }
 
 // ------------------------------------------------------------------ Cholesky
-// Step j: pivot d_j = A[j][j] (final after step j-1); trailing lower block
-// A[r][c] -= A[r][j] conj(A[c][j]) / d_j for j < c <= r. Column j stays
-// unscaled until k_lchol_scale.
+// Blocked right-looking Cholesky S = L L^H (lower) with the inverse L^-1
+// formed block row by block row alongside, in panels of CB columns:
+//   diagonal block  factored in LDS by one workgroup, which also writes its
+//                   inverse D (forward substitution, one lane per column),
+//                   zeros the upper parts of its rows in L and L^-1 and
+//                   records the pivots (the squared diagonal of L);
+//   panel rows      L21 = A21 L11^-H, one thread per row (k_lchol_solve);
+//   trailing block  A22 -= L21 L21^H on the lower tiles; the workgroup of
+//                   the top-left tile factors that tile (the next diagonal
+//                   block) straight from LDS (k_lchol_update);
+//   L^-1 block row  (L^-1)_IJ = -D_I sum_{J <= K < I} L_IK (L^-1)_KJ, one
+//                   workgroup per J < I, in the same launch as the trailing
+//                   update (they touch disjoint parts of both matrices).
+// Two launches per panel instead of one per column.
+constexpr int CB = 32;       // panel width
+constexpr int CBP = CB + 1;  // LDS row pitch
+
+struct CholLds {
+  double rdiag[CB];  // 1 / L_cc
+  double pd[CB];     // pivots d_c = L_cc^2
+};
+
+// Factor the wb x wb block held in a (lower part) in place: columns are
+// eliminated unscaled (a_rk -= a_rc conj(a_kc) / d_c; only entries right of
+// column c change in step c, so one barrier per column) and scaled by
+// 1 / sqrt(d_c) at the end. Returns the first failing column + 1 (pivot not
+// positive, or NaN), else 0; uniform across the workgroup. The caller has
+// synchronised after filling a.
 template <typename T>
-__global__ __launch_bounds__(256) void k_lchol_step(T *__restrict__ A, int n, int j,
-                                                    double *__restrict__ piv, int32_t *info) {
-  if (*info != 0) return;
-  const double dj = re_l(A[static_cast<int64_t>(j) * n + j]);
-  if (!(dj > 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *info = j + 1;
+__device__ int chol_block_lds(T *a, int wb, CholLds &cl) {
+  const int tid = threadIdx.x;
+  for (int c = 0; c < wb; ++c) {
+    const double d = re_l(a[c * CBP + c]);
+    if (!(d > 0.0)) return c + 1;
+    const double inv = 1.0 / d;
+    if (tid == 0) cl.pd[c] = d;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + 256 * q, r = idx / CB, k = idx - (idx / CB) * CB;
+      if (k > c && k <= r && r < wb)
+        a[r * CBP + k] = a[r * CBP + k] - mulr(a[r * CBP + c] * cj_l(a[k * CBP + c]), inv);
+    }
+    __syncthreads();
+  }
+  if (tid < wb) cl.rdiag[tid] = 1.0 / sqrt(cl.pd[tid]);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = tid + 256 * q, r = idx / CB, k = idx - (idx / CB) * CB;
+    if (k <= r && r < wb)
+      a[r * CBP + k] = k == r ? rv<T>(sqrt(cl.pd[k])) : mulr(a[r * CBP + k], cl.rdiag[k]);
+  }
+  __syncthreads();
+  return 0;
+}
+
+// The diagonal block at row/column jb (width wb) sits in LDS a (lower part,
+// trailing updates applied, zeros elsewhere): factor it, write L_bb, its
+// inverse D_b (built in dm), the zeros right of the block in both matrices,
+// the pivots, and info on failure.
+template <typename T>
+__device__ void chol_diag_finish(T *a, T *dm, CholLds &cl, T *__restrict__ A, T *__restrict__ Linv, int n,
+                                 int jb, int wb, double *__restrict__ piv, int32_t *info) {
+  const int tid = threadIdx.x;
+  const int bad = chol_block_lds<T>(a, wb, cl);
+  if (bad) {
+    if (tid == 0) *info = jb + bad;
     return;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) piv[j] = dj;
-  const double inv = 1.0 / dj;
-  const int m = n - j - 1;
-  // 2-D tiles of 16 x 16 over the m x m trailing block, lower part only
-  const int tiles = (m + 15) / 16;
-  const int tile = blockIdx.x;
-  const int ti = tile / tiles, tj = tile - (tile / tiles) * tiles;
-  if (tj > ti) return;
-  const int r = j + 1 + ti * 16 + (threadIdx.x >> 4), c = j + 1 + tj * 16 + (threadIdx.x & 15);
-  if (r >= n || c > r) return;
-  const T lr = A[static_cast<int64_t>(r) * n + j];
-  const T lc = cj_l(A[static_cast<int64_t>(c) * n + j]);
-  T &a = A[static_cast<int64_t>(r) * n + c];
-  a = a - mulr(lr * lc, inv);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = tid + 256 * q, r = idx / CB, c = idx - (idx / CB) * CB;
+    if (r < wb && c < wb) A[static_cast<int64_t>(jb + r) * n + jb + c] = c <= r ? a[r * CBP + c] : T{};
+  }
+  const int right = n - jb - wb;
+  for (int r = 0; r < wb; ++r)
+    for (int c = tid; c < right; c += 256) {
+      const int64_t o = static_cast<int64_t>(jb + r) * n + jb + wb + c;
+      A[o] = T{};
+      Linv[o] = T{};
+    }
+  if (tid < wb) piv[jb + tid] = cl.pd[tid];
+  // D = L_bb^-1, column c by lane c (two partial sums for ILP):
+  // D_ic = (delta_ic - sum_{c <= k < i} L_ik D_kc) / L_ii, zero for i < c
+  if (tid < wb) {
+    const int c = tid;
+    for (int i = 0; i < wb; ++i) {
+      T s0{}, s1{};
+      int k = c;
+      for (; k + 1 < i; k += 2) {
+        s0 = s0 + a[i * CBP + k] * dm[k * CBP + c];
+        s1 = s1 + a[i * CBP + k + 1] * dm[(k + 1) * CBP + c];
+      }
+      if (k < i) s0 = s0 + a[i * CBP + k] * dm[k * CBP + c];
+      const T v = (i == c ? rv<T>(1.0) : T{}) - (s0 + s1);
+      dm[i * CBP + c] = i < c ? T{} : mulr(v, cl.rdiag[i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = tid + 256 * q, r = idx / CB, c = idx - (idx / CB) * CB;
+    if (r < wb && c < wb) Linv[static_cast<int64_t>(jb + r) * n + jb + c] = dm[r * CBP + c];
+  }
 }
 
-// L[r][j] = A[r][j] / sqrt(d_j) (r > j), L[j][j] = sqrt(d_j), upper part 0
+// first diagonal block
 template <typename T>
-__global__ __launch_bounds__(256) void k_lchol_scale(T *__restrict__ A, int n,
-                                                     const double *__restrict__ piv,
+__global__ __launch_bounds__(256) void k_lchol_first(T *__restrict__ A, T *__restrict__ Linv, int n,
+                                                     double *__restrict__ piv, int32_t *info) {
+  if (*info != 0) return;
+  __shared__ T a[CB * CBP], dm[CB * CBP];
+  __shared__ CholLds cl;
+  const int wb = min(CB, n);
+  for (int idx = threadIdx.x; idx < CB * CB; idx += 256) {
+    const int r = idx / CB, c = idx - (idx / CB) * CB;
+    a[r * CBP + c] = (r < wb && c <= r) ? A[static_cast<int64_t>(r) * n + c] : T{};
+  }
+  __syncthreads();
+  chol_diag_finish<T>(a, dm, cl, A, Linv, n, 0, wb, piv, info);
+}
+
+// L21 = A21 L11^-H for the rows below the panel at j0 (width CB): one row
+// per thread, x_c = (a_c - sum_{k<c} x_k conj(L_ck)) / L_cc
+template <typename T>
+__global__ __launch_bounds__(256) void k_lchol_solve(T *__restrict__ A, int n, int j0,
                                                      const int32_t *info) {
   if (*info != 0) return;
-  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (idx >= static_cast<int64_t>(n) * n) return;
-  const int r = static_cast<int>(idx / n), c = static_cast<int>(idx - static_cast<int64_t>(idx / n) * n);
-  if (c > r) A[idx] = T{};
-  else if (c == r) A[idx] = rv<T>(sqrt(piv[c]));
-  else A[idx] = mulr(A[idx], 1.0 / sqrt(piv[c]));
-}
-
-// Linv column col = L^-1 e_col: one wavefront, lane s keeps rows 64t+s
-template <typename T>
-__global__ __launch_bounds__(64) void k_linv_col(const T *__restrict__ L, T *__restrict__ Linv,
-                                                 int n, const int32_t *info) {
-  if (*info != 0) return;
-  const int col = blockIdx.x, s = threadIdx.x;
-  constexpr int R = LNMAX / 64;
-  T xr[R];
+  __shared__ T l[CB * CBP];
+  __shared__ double rd[CB];
+  for (int idx = threadIdx.x; idx < CB * CB; idx += 256) {
+    const int r = idx / CB, c = idx - (idx / CB) * CB;
+    l[r * CBP + c] = c <= r ? A[static_cast<int64_t>(j0 + r) * n + j0 + c] : T{};
+  }
+  __syncthreads();
+  if (threadIdx.x < CB) rd[threadIdx.x] = 1.0 / re_l(l[threadIdx.x * CBP + threadIdx.x]);
+  __syncthreads();
+  const int r = j0 + CB + static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);
+  if (r >= n) return;
+  T *Ar = A + static_cast<int64_t>(r) * n + j0;
+  T x[CB];
 #pragma unroll
-  for (int t = 0; t < R; ++t) xr[t] = T{};
-  for (int i = col; i < n; ++i) {
-    const T *Li = L + static_cast<int64_t>(i) * n;
-    T part = T{};
+  for (int c = 0; c < CB; ++c) x[c] = Ar[c];
 #pragma unroll
-    for (int t = 0; t < R; ++t) {
-      const int k = 64 * t + s;
-      if (k >= col && k < i) part = part + Li[k] * xr[t];
-    }
-    part = wsum(part);
-    const double dinv = 1.0 / re_l(Li[i]);
-    const T xi = (i == col) ? rv<T>(dinv) : mulr(part, -dinv);
+  for (int c = 0; c < CB; ++c) {
+    T v = x[c];
 #pragma unroll
-    for (int t = 0; t < R; ++t)
-      if (64 * t + s == i) xr[t] = xi;
+    for (int k = 0; k < c; ++k) v = v - x[k] * cj_l(l[c * CBP + k]);
+    x[c] = mulr(v, rd[c]);
   }
 #pragma unroll
-  for (int t = 0; t < R; ++t) {
-    const int row = 64 * t + s;
-    if (row < n) Linv[static_cast<int64_t>(row) * n + col] = xr[t];
+  for (int c = 0; c < CB; ++c) Ar[c] = x[c];
+}
+
+// Workgroups [0, tt(tt+1)/2): lower tiles of the trailing block below the
+// panel at j0 (tile 0 then factors the next diagonal block); the rest: block
+// row I = j0 / CB of L^-1, one workgroup per block column J < I.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lchol_update(T *__restrict__ A, T *__restrict__ Linv, int n,
+                                                      int j0, int tt, double *__restrict__ piv,
+                                                      int32_t *info) {
+  if (*info != 0) return;
+  __shared__ T ta[CB * CBP], tb[CB * CBP];
+  __shared__ CholLds cl;
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  const int w = min(CB, n - j0), j1 = j0 + w;
+  const int ntri = tt * (tt + 1) / 2;
+  const int bid = static_cast<int>(blockIdx.x);
+  T acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = T{};
+  if (bid < ntri) {
+    int ti = 0, rest = bid;
+    while (rest > ti) {
+      rest -= ti + 1;
+      ++ti;
+    }
+    const int tj = rest;
+    const int r0 = j1 + ti * CB, c0 = j1 + tj * CB;
+    for (int idx = tid; idx < CB * CB; idx += 256) {
+      const int r = idx / CB, k = idx - (idx / CB) * CB;
+      ta[r * CBP + k] = r0 + r < n ? A[static_cast<int64_t>(r0 + r) * n + j0 + k] : T{};
+      tb[r * CBP + k] = c0 + r < n ? A[static_cast<int64_t>(c0 + r) * n + j0 + k] : T{};
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int k = 0; k < CB; ++k) {
+      const T bk = cj_l(tb[tx * CBP + k]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = acc[q] + ta[(ty + 8 * q) * CBP + k] * bk;
+    }
+    const int c = c0 + tx;
+    if (bid == 0) {
+      // top-left tile = next diagonal block: update into LDS, factor there
+      const int wb = min(CB, n - j1);
+      __syncthreads();  // ta is reused
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rl = ty + 8 * q, r = r0 + rl;
+        ta[rl * CBP + tx] = (r < n && c < n && tx <= rl) ? A[static_cast<int64_t>(r) * n + c] - acc[q] : T{};
+      }
+      __syncthreads();
+      chol_diag_finish<T>(ta, tb, cl, A, Linv, n, j1, wb, piv, info);
+      return;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + ty + 8 * q;
+      if (r < n && c < n && c <= r) {
+        T &dst = A[static_cast<int64_t>(r) * n + c];
+        dst = dst - acc[q];
+      }
+    }
+    return;
+  }
+  const int I = j0 / CB, J = bid - ntri, cJ = J * CB;
+  for (int K = J; K < I; ++K) {
+    __syncthreads();
+    for (int idx = tid; idx < CB * CB; idx += 256) {
+      const int r = idx / CB, k = idx - (idx / CB) * CB;
+      ta[r * CBP + k] = r < w ? A[static_cast<int64_t>(j0 + r) * n + K * CB + k] : T{};
+      tb[r * CBP + k] = Linv[static_cast<int64_t>(K * CB + r) * n + cJ + k];
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int k = 0; k < CB; ++k) {
+      const T bk = tb[k * CBP + tx];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = acc[q] + ta[(ty + 8 * q) * CBP + k] * bk;
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < CB * CB; idx += 256) {
+    const int r = idx / CB, k = idx - (idx / CB) * CB;
+    ta[r * CBP + k] = (r < w && k < w) ? Linv[static_cast<int64_t>(j0 + r) * n + j0 + k] : T{};
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) tb[(ty + 8 * q) * CBP + tx] = acc[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int rl = ty + 8 * q;
+    T v{};
+#pragma unroll 8
+    for (int k = 0; k < CB; ++k) v = v + ta[rl * CBP + k] * tb[k * CBP + tx];
+    if (rl < w) Linv[static_cast<int64_t>(j0 + rl) * n + cJ + tx] = T{} - v;
   }
 }
 
@@ -421,14 +595,14 @@ __global__ __launch_bounds__(64) void k_lback(int n, const double *__restrict__ 
 // entry points used by eigh.hip
 template <typename T>
 int large_chol_linv(T *Sw, T *Linv, int n, double *piv, int32_t *info, hipStream_t st) {
-  for (int j = 0; j < n; ++j) {
-    const int m = n - j - 1;
-    const int tiles = (m + 15) / 16;
-    k_lchol_step<T><<<std::max(1, tiles * tiles), 256, 0, st>>>(Sw, n, j, piv, info);
+  k_lchol_first<T><<<1, 256, 0, st>>>(Sw, Linv, n, piv, info);
+  for (int j0 = 0; j0 < n; j0 += CB) {
+    const int below = n - j0 - CB;
+    if (below > 0) k_lchol_solve<T><<<(below + 255) / 256, 256, 0, st>>>(Sw, n, j0, info);
+    const int tt = below > 0 ? (below + CB - 1) / CB : 0;
+    const int wgs = tt * (tt + 1) / 2 + j0 / CB;
+    if (wgs > 0) k_lchol_update<T><<<wgs, 256, 0, st>>>(Sw, Linv, n, j0, tt, piv, info);
   }
-  const int64_t nn = static_cast<int64_t>(n) * n;
-  k_lchol_scale<T><<<static_cast<unsigned>((nn + 255) / 256), 256, 0, st>>>(Sw, n, piv, info);
-  k_linv_col<T><<<n, 64, 0, st>>>(Sw, Linv, n, info);
   return GPAW_OK;
 }
 
