@@ -352,49 +352,60 @@ __global__ __launch_bounds__(1024) void k_offid_small(const double *__restrict__
 }
 
 // C (double / complex double, [nb][nb]) -> transposed BF16 planes
-// Ct[p][n][m] for p = hi, mid, lo (and the imaginary part in planes 3..5)
+// Ct[p][n][m] for p = hi, mid, lo (and the imaginary part in planes 3..5),
+// rows padded with zeros to nbp = nb rounded up to the 64-wide K step, so
+// that every 16-byte row fragment a rotation step reads is in bounds
 template <int NP>
 __global__ __launch_bounds__(256) void k_split_c(const double *__restrict__ C, __bf16 *__restrict__ Ct,
-                                                 int nb, int minus_id) {
-  const int64_t nn = static_cast<int64_t>(nb) * nb;
+                                                 int nb, int nbp, int minus_id) {
+  const int64_t np = static_cast<int64_t>(nb) * nbp;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (idx >= nn) return;
+  if (idx >= np) return;
+  // idx = m nb + n, the element C[m][n] for m < nb
   const int m = static_cast<int>(idx / nb), n = static_cast<int>(idx - static_cast<int64_t>(m) * nb);
 #pragma unroll
   for (int c = 0; c < NP; ++c) {
     // three BF16 parts of the FP64 coefficient, each rounded to nearest from
     // the remainder in FP64 (the remainders are exact)
     // minus_id: the planes of C - I (the rotation then adds the source back)
-    const double x = C[idx * NP + c] - (minus_id && c == 0 && m == n ? 1.0 : 0.0);
+    const double x = m < nb ? C[idx * NP + c] - (minus_id && c == 0 && m == n ? 1.0 : 0.0) : 0.0;
     const uint32_t uh = bf16_rne(__float_as_uint(static_cast<float>(x)));
     const double r1 = x - static_cast<double>(__uint_as_float(uh));
     const uint32_t um = bf16_rne(__float_as_uint(static_cast<float>(r1)));
     const double r2 = r1 - static_cast<double>(__uint_as_float(um));
     const uint32_t ul = bf16_rne(__float_as_uint(static_cast<float>(r2)));
-    const int64_t t = static_cast<int64_t>(n) * nb + m;
-    Ct[(3 * c + 0) * nn + t] = top_half(uh);
-    Ct[(3 * c + 1) * nn + t] = top_half(um);
-    Ct[(3 * c + 2) * nn + t] = top_half(ul);
+    const int64_t t = static_cast<int64_t>(n) * nbp + m;
+    Ct[(3 * c + 0) * np + t] = top_half(uh);
+    Ct[(3 * c + 1) * np + t] = top_half(um);
+    Ct[(3 * c + 2) * np + t] = top_half(ul);
   }
 }
 
 // out[n][g] = sum_m C[m][n] src[m][g] (no conjugation). A[i=n][k=m] comes
-// from the pre-split transposed planes of C; the src slice (32 rows m x TN
-// columns g) is split once and stored column-major in LDS, so that the B
-// fragment B[k=m][j=g] of a lane is eight consecutive values. FP32 tiles are
-// added into FP64 accumulators every 8 steps.
+// from the pre-split transposed planes of C (rows padded to nbp); the src
+// slice (KR rows m x TN columns g) is split once and stored column-major in
+// LDS, so that the B fragment B[k=m][j=g] of a lane is eight consecutive
+// values. FP32 tiles are added into FP64 accumulators every 4 steps (256
+// terms). A step spans 64 values of m: with one wavefront per SIMD the
+// loads of the next step are in flight during one step of matrix work, so
+// the step is made long enough to keep many bytes in flight. The loads are
+// unconditional (row, column and step indices clamped; clamped src rows meet
+// zero padding in Ct, clamped output rows and columns are not stored).
 // ADDSRC: Ct holds C - I and the result is src + (C - I)^T src; when *fewer
 // is nonzero (|C - I| small, see k_offid_small) only the high BF16 parts are
 // multiplied (one product instead of six).
+constexpr int KR = 64;     // K values per rotation step
+constexpr int LROWR = 72;  // LDS row pitch of the rotation tiles (BF16 values)
+
 template <typename T, int WT, bool ADDSRC>
 __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
                                                  const T *__restrict__ src, T *__restrict__ dst,
-                                                 int nb, int64_t cols, int ntiles_n,
+                                                 int nb, int nbp, int64_t cols, int ntiles_n,
                                                  int64_t gtiles, int upper,
                                                  const int32_t *__restrict__ fewer) {
   constexpr int NP = Parts<T>::n;
   constexpr int TM = 32 * WT;
-  constexpr int PS = TM * LROW;
+  constexpr int PS = TM * LROWR;
   __shared__ __attribute__((aligned(16))) __bf16 sA[3 * NP * PS];
   __shared__ __attribute__((aligned(16))) __bf16 sB[3 * NP * PS];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -403,46 +414,41 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
   const int ntile = static_cast<int>(jj % ntiles_n);
   const int64_t gtile = (jj / ntiles_n) * 8 + x;
   if (gtile >= gtiles) return;
-  const int64_t nn = static_cast<int64_t>(nb) * nb;
+  const int64_t np = static_cast<int64_t>(nb) * nbp;
   const int n0 = ntile * TM;
   const int64_t g0 = gtile * TM;
   // an upper-triangular C (m <= n) needs rows m < n0 + TM only
   const int mend = upper ? std::min(nb, n0 + TM) : nb;
-  const int nsteps = (mend + KS - 1) / KS;
+  const int nsteps = (mend + KR - 1) / KR;
 
-  // A staging: row n = n0 + tid/4 (+64 per pass), 8 values m = 8c..8c+7 per plane
+  // A staging: row n = n0 + tid/4 (+64 per pass), values m = sc..sc+7 and
+  // sc+32..sc+39 per plane
   constexpr int PASSES = TM / 64;
   const int sr = tid >> 2, sc = (tid & 3) * 8;
-  bf8 ca[PASSES][NP][3];
-  // B staging: column g = g0 + (tid % TM), values m = mh*MPT .. +MPT-1
-  constexpr int MPT = KS * TM / 256;  // real 16, complex 8
+  bf8 ca[PASSES][NP][3][2];
+  // B staging: column g = g0 + (tid % TM), values m = bm .. bm+MPT-1
+  constexpr int MPT = KR * TM / 256;  // real 32, complex 16
   const int bg = tid % TM, bm = (tid / TM) * MPT;
   float rb[NP][MPT];
+  const T *srcg = src + std::min<int64_t>(g0 + bg, cols - 1);
   auto fetch = [&](int step) {
-    const int m0 = step * KS;
+    const int m0 = std::min(step, nsteps - 1) * KR;
 #pragma unroll
     for (int ps = 0; ps < PASSES; ++ps) {
-      const int n = n0 + ps * 64 + sr;
+      const int n = std::min(n0 + ps * 64 + sr, nb - 1);
 #pragma unroll
       for (int c = 0; c < NP; ++c)
 #pragma unroll
-        for (int p = 0; p < 3; ++p) {
-          const __bf16 *q = Ct + (3 * c + p) * nn + static_cast<int64_t>(n) * nb + m0 + sc;
-          bf8 v;
-          if (n < nb && m0 + sc + 8 <= nb && (reinterpret_cast<uintptr_t>(q) & 15) == 0) {
-            v = *reinterpret_cast<const bf8 *>(q);
-          } else {
+        for (int p = 0; p < 3; ++p)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = (n < nb && m0 + sc + e < nb) ? q[e] : top_half(0u);
-          }
-          ca[ps][c][p] = v;
-        }
+          for (int h = 0; h < 2; ++h)
+            ca[ps][c][p][h] = *reinterpret_cast<const bf8 *>(
+                Ct + (3 * c + p) * np + static_cast<int64_t>(n) * nbp + m0 + sc + 32 * h);
     }
-    const int64_t g = g0 + bg;
 #pragma unroll
     for (int e = 0; e < MPT; ++e) {
-      const int m = m0 + bm + e;
-      const T v = (g < cols && m < nb) ? src[static_cast<int64_t>(m) * cols + g] : T{};
+      const int m = std::min(m0 + bm + e, nb - 1);
+      const T v = srcg[static_cast<int64_t>(m) * cols];
       rb[0][e] = Parts<T>::re(v);
       if constexpr (NP == 2) rb[NP - 1][e] = Parts<T>::im(v);
     }
@@ -454,12 +460,15 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
       for (int c = 0; c < NP; ++c)
 #pragma unroll
         for (int p = 0; p < 3; ++p)
-          *reinterpret_cast<bf8 *>(sA + (c * 3 + p) * PS + (ps * 64 + sr) * LROW + sc) = ca[ps][c][p];
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            *reinterpret_cast<bf8 *>(sA + (c * 3 + p) * PS + (ps * 64 + sr) * LROWR + sc + 32 * h) =
+                ca[ps][c][p][h];
 #pragma unroll
     for (int c = 0; c < NP; ++c)
 #pragma unroll
       for (int h = 0; h < MPT / 8; ++h) {
-        const int o = (c * 3) * PS + bg * LROW + bm + 8 * h;
+        const int o = (c * 3) * PS + bg * LROWR + bm + 8 * h;
         split_store8(rb[c] + 8 * h, sB + o, sB + o + PS, sB + o + 2 * PS);
       }
   };
@@ -483,40 +492,43 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
     __syncthreads();
     stage();
     __syncthreads();
-    if (step + 1 < nsteps) fetch(step + 1);
-    Split8 fa[NP][WT];
+    fetch(step + 1);  // clamped: the last one re-reads the final step, unused
 #pragma unroll
-    for (int i = 0; i < WT; ++i)
+    for (int kh = 0; kh < 2; ++kh) {
+      Split8 fa[NP][WT];
 #pragma unroll
-      for (int c = 0; c < NP; ++c)
-        fa[c][i] = frag(sA + (c * 3) * PS, PS, (wr * 16 * WT + i * 16 + fr) * LROW + fk);
+      for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < WT; ++j) {
-      Split8 fb[NP];
+        for (int c = 0; c < NP; ++c)
+          fa[c][i] = frag(sA + (c * 3) * PS, PS, (wr * 16 * WT + i * 16 + fr) * LROWR + 32 * kh + fk);
 #pragma unroll
-      for (int c = 0; c < NP; ++c)
-        fb[c] = frag(sB + (c * 3) * PS, PS, (wc * 16 * WT + j * 16 + fr) * LROW + fk);
+      for (int j = 0; j < WT; ++j) {
+        Split8 fb[NP];
 #pragma unroll
-      for (int i = 0; i < WT; ++i) {
-        // C psi: re = Cr pr - Ci pi, im = Cr pi + Ci pr
-        if (ADDSRC && one) {
-          facc[0][i][j] = mm(fa[0][i].h, fb[0].h, facc[0][i][j]);
-          if constexpr (NP == 2) {
-            facc[0][i][j] = mm(neg(fa[1][i]).h, fb[1].h, facc[0][i][j]);
-            facc[1][i][j] = mm(fa[0][i].h, fb[1].h, facc[1][i][j]);
-            facc[1][i][j] = mm(fa[1][i].h, fb[0].h, facc[1][i][j]);
-          }
-        } else {
-          facc[0][i][j] = mm6(fa[0][i], fb[0], facc[0][i][j]);
-          if constexpr (NP == 2) {
-            facc[0][i][j] = mm6(neg(fa[1][i]), fb[1], facc[0][i][j]);
-            facc[1][i][j] = mm6(fa[0][i], fb[1], facc[1][i][j]);
-            facc[1][i][j] = mm6(fa[1][i], fb[0], facc[1][i][j]);
+        for (int c = 0; c < NP; ++c)
+          fb[c] = frag(sB + (c * 3) * PS, PS, (wc * 16 * WT + j * 16 + fr) * LROWR + 32 * kh + fk);
+#pragma unroll
+        for (int i = 0; i < WT; ++i) {
+          // C psi: re = Cr pr - Ci pi, im = Cr pi + Ci pr
+          if (ADDSRC && one) {
+            facc[0][i][j] = mm(fa[0][i].h, fb[0].h, facc[0][i][j]);
+            if constexpr (NP == 2) {
+              facc[0][i][j] = mm(neg(fa[1][i]).h, fb[1].h, facc[0][i][j]);
+              facc[1][i][j] = mm(fa[0][i].h, fb[1].h, facc[1][i][j]);
+              facc[1][i][j] = mm(fa[1][i].h, fb[0].h, facc[1][i][j]);
+            }
+          } else {
+            facc[0][i][j] = mm6(fa[0][i], fb[0], facc[0][i][j]);
+            if constexpr (NP == 2) {
+              facc[0][i][j] = mm6(neg(fa[1][i]), fb[1], facc[0][i][j]);
+              facc[1][i][j] = mm6(fa[0][i], fb[1], facc[1][i][j]);
+              facc[1][i][j] = mm6(fa[1][i], fb[0], facc[1][i][j]);
+            }
           }
         }
       }
     }
-    if ((step & 7) == 7 || step + 1 == nsteps) {
+    if ((step & 3) == 3 || step + 1 == nsteps) {
 #pragma unroll
       for (int c = 0; c < NP; ++c)
 #pragma unroll
@@ -603,22 +615,24 @@ int rotate_split_t(const gpaw_sys *s, const void *C, const void *src, int nb, in
   constexpr int NP = Parts<T>::n;
   constexpr int TM = 32 * WT;
   __bf16 *Ct = reinterpret_cast<__bf16 *>(s->ws.split);
-  const int64_t nn = static_cast<int64_t>(nb) * nb;
+  const int nbp = (nb + KR - 1) / KR * KR;
+  const int64_t np = static_cast<int64_t>(nb) * nbp;
   const double *Cd = static_cast<const double *>(C);
   // near the identity: rotate by C - I and add the source back, with one
   // BF16 product per pair when |C - I| is small enough (decided on the device)
   if (near_id) k_offid_small<NP><<<1, 1024, 0, st>>>(Cd, nb, s->ws.flag);
-  k_split_c<NP><<<static_cast<unsigned>((nn + 255) / 256), 256, 0, st>>>(Cd, Ct, nb, near_id ? 1 : 0);
+  k_split_c<NP><<<static_cast<unsigned>((np + 255) / 256), 256, 0, st>>>(Cd, Ct, nb, nbp,
+                                                                        near_id ? 1 : 0);
   const int ntiles_n = (nb + TM - 1) / TM;
   const int64_t gtiles = (cols + TM - 1) / TM;
   const int64_t wgs = (gtiles + 7) / 8 * 8 * ntiles_n;
   if (near_id)
     k_rot_lds<T, WT, true><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
-        Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, cols, ntiles_n, gtiles,
+        Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, nbp, cols, ntiles_n, gtiles,
         upper ? 1 : 0, s->ws.flag);
   else
     k_rot_lds<T, WT, false><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
-        Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, cols, ntiles_n, gtiles,
+        Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, nbp, cols, ntiles_n, gtiles,
         upper ? 1 : 0, nullptr);
   return GPAW_OK;
 }
@@ -634,7 +648,8 @@ size_t split_part_elems(int nb, bool cplx) {
 }
 
 size_t split_c_bytes(int nb, bool cplx) {
-  return static_cast<size_t>(nb) * nb * 3 * (cplx ? 2 : 1) * sizeof(__bf16);
+  const size_t nbp = static_cast<size_t>((nb + KR - 1) / KR * KR);
+  return static_cast<size_t>(nb) * nbp * 3 * (cplx ? 2 : 1) * sizeof(__bf16);
 }
 
 int launch_subspace_split(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
