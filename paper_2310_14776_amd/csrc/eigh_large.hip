@@ -13,10 +13,12 @@
 //                  vector (that column is left to workgroup 0 alone, so no
 //                  workgroup reads a value another one is rewriting);
 //   eigenvalues    as for small blocks (multisection, d/e in LDS);
-//   eigenvectors   inverse iteration with the LU scratch in global memory;
+//   eigenvectors   inverse iteration, a few eigenvalues per workgroup with
+//                  the LU scratch in LDS;
 //   back-transform one wavefront per column, reflectors read from L2.
 #include <algorithm>
 #include <cfloat>
+#include <mutex>
 #include <string>
 
 #include "internal.h"
@@ -443,17 +445,21 @@ __device__ inline bool split_l(const double *d, const double *e, int i) {
 
 // inverse iteration, one lane per eigenvalue, LU scratch in global memory
 // (lu[q][i][j] for q = u0, u1, u2, y)
-__global__ __launch_bounds__(64) void k_lvectors(int n, const double *__restrict__ d,
+__global__ __launch_bounds__(64) void k_lvectors(int n, int L, const double *__restrict__ d,
                                                  const double *__restrict__ e,
                                                  const double *__restrict__ lam,
-                                                 double *__restrict__ lu, double *__restrict__ Z,
-                                                 const int32_t *info) {
+                                                 double *__restrict__ Z, const int32_t *info) {
   if (*info != 0) return;
-  const int j = blockIdx.x * 64 + threadIdx.x;
-  if (j >= n) return;
-  const int64_t nn = static_cast<int64_t>(n) * n;
-  double *u0 = lu, *u1 = lu + nn, *u2 = lu + 2 * nn, *y = lu + 3 * nn;
-#define AT(p, i) (p)[static_cast<int64_t>(i) * n + j]
+  // L eigenvalues per workgroup (lanes 0..L-1), each with six n-long scratch
+  // columns in LDS, interleaved by lane: the solves are sequential chains, so
+  // their latency is that of LDS rather than of L2
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x;
+  const int j = blockIdx.x * L + lane;
+  if (lane >= L || j >= n) return;
+  const int nl = n * L;
+  double *u0 = lds, *u1 = lds + nl, *u2 = lds + 2 * nl, *y = lds + 3 * nl;
+#define AT(p, i) (p)[(i) * L + lane]
   int lo = j, hi = j;
   while (lo > 0 && !split_l(d, e, lo - 1)) --lo;
   while (hi < n - 1 && !split_l(d, e, hi)) ++hi;
@@ -471,7 +477,7 @@ __global__ __launch_bounds__(64) void k_lvectors(int n, const double *__restrict
   // running y_i kept in a register), forward-eliminating y; multipliers and
   // swap flags kept for the second solve, pivots stored as reciprocals
   // (tiny ones replaced by +-eps ||T||)
-  double *ml = lu + 4 * nn, *ms = lu + 5 * nn;
+  double *ml = lds + 4 * nl, *ms = lds + 5 * nl;
   {
     double c0 = d[lo] - x, c1 = (m > 1) ? e[lo] : 0.0;
     double ycur = AT(y, 0);
@@ -622,7 +628,18 @@ int large_tridiag(T *A, int n, T *V, T *tau, double *d, double *e, T *p, int32_t
 
 int large_vectors(int n, const double *d, const double *e, const double *lam, double *lu,
                   double *Z, const int32_t *info, hipStream_t st) {
-  k_lvectors<<<(n + 63) / 64, 64, 0, st>>>(n, d, e, lam, lu, Z, info);
+  (void)lu;  // the scratch lives in LDS
+  constexpr size_t LDS_MAX = 160 * 1024;
+  static std::once_flag once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(once, [] {
+    attr_err = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_lvectors),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, LDS_MAX);
+  });
+  if (attr_err != hipSuccess) return hip_fail(attr_err, "hipFuncSetAttribute(k_lvectors)");
+  const size_t per_lane = 6 * static_cast<size_t>(n) * sizeof(double);
+  const int L = static_cast<int>(std::max<size_t>(1, std::min<size_t>(64, LDS_MAX / per_lane)));
+  k_lvectors<<<(n + L - 1) / L, 64, per_lane * L, st>>>(n, L, d, e, lam, Z, info);
   return GPAW_OK;
 }
 
