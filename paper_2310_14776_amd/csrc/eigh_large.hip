@@ -15,7 +15,8 @@
 //   eigenvalues    as for small blocks (multisection, d/e in LDS);
 //   eigenvectors   inverse iteration, a few eigenvalues per workgroup with
 //                  the LU scratch in LDS;
-//   back-transform one wavefront per column, reflectors read from L2.
+//   back-transform one wavefront per column, reflectors read from L2 one
+//                  step ahead of their use.
 #include <algorithm>
 #include <cfloat>
 #include <mutex>
@@ -27,8 +28,6 @@ namespace gfd {
 
 namespace {
 
-constexpr int LNMAX = 1024;
-
 __device__ inline double re_l(double a) { return a; }
 __device__ inline double re_l(z64 a) { return a.x; }
 __device__ inline double im_l(double) { return 0.0; }
@@ -39,6 +38,8 @@ __device__ inline double cj_l(double a) { return a; }
 __device__ inline z64 cj_l(z64 a) { return zconj(a); }
 __device__ inline z64 mulr(z64 a, double s) { return z64{a.x * s, a.y * s}; }
 __device__ inline double mulr(double a, double s) { return a * s; }
+__device__ inline double sel_l(bool c, double a, double b) { return c ? a : b; }
+__device__ inline z64 sel_l(bool c, z64 a, z64 b) { return z64{c ? a.x : b.x, c ? a.y : b.y}; }
 template <typename T> __device__ inline T rv(double r);
 template <> __device__ inline double rv<double>(double r) { return r; }
 template <> __device__ inline z64 rv<z64>(double r) { return z64{r, 0.0}; }
@@ -551,35 +552,49 @@ __global__ __launch_bounds__(64) void k_lvectors(int n, int L, const double *__r
 // ------------------------------------------------------------------ back-transform
 // one wavefront per column: u <- u - tau_k v_k (v_k^H u), k = n-2..0;
 // U written to column rank(j), eps[rank] = lam[j]
-template <typename T>
+template <typename T, int RR>
 __global__ __launch_bounds__(64) void k_lback(int n, const double *__restrict__ Z,
                                               const T *__restrict__ V, const T *__restrict__ tau,
                                               const double *__restrict__ lam, T *__restrict__ Uo,
                                               double *__restrict__ eps, const int32_t *info) {
   if (*info != 0) return;
-  constexpr int R = LNMAX / 64;
+  // rows 64 t + s, t < RR (64 RR >= n); rows past n hold u = 0 and are never
+  // updated; v_k is zero on rows <= k, so no row needs masking in the dot
+  // product. The reflector of the next step is loaded while the current one
+  // is applied (clamped, unconditional loads).
   const int col = blockIdx.x, s = threadIdx.x;
-  T u[R];
+  T u[RR];
 #pragma unroll
-  for (int t = 0; t < R; ++t) {
+  for (int t = 0; t < RR; ++t) {
     const int row = 64 * t + s;
     u[t] = rv<T>(row < n ? Z[static_cast<int64_t>(row) * n + col] : 0.0);
   }
-  for (int k = n - 2; k >= 0; --k) {
-    const T *vk = V + static_cast<int64_t>(k) * n;
+  auto load_v = [&](int k, T (&v)[RR], T &tk) {
+    const int kc = k < 0 ? 0 : k;
+    const T *vk = V + static_cast<int64_t>(kc) * n;
+#pragma unroll
+    for (int t = 0; t < RR; ++t) v[t] = vk[std::min(64 * t + s, n - 1)];
+    tk = tau[kc];
+  };
+  auto apply = [&](const T (&v)[RR], T tk) {
     T part = T{};
 #pragma unroll
-    for (int t = 0; t < R; ++t) {
-      const int row = 64 * t + s;
-      if (row > k && row < n) part = part + cj_l(vk[row]) * u[t];
-    }
+    for (int t = 0; t < RR; ++t) part = part + cj_l(v[t]) * u[t];
     part = wsum(part);
-    const T f = tau[k] * part;
+    const T f = tk * part;
 #pragma unroll
-    for (int t = 0; t < R; ++t) {
-      const int row = 64 * t + s;
-      if (row > k && row < n) u[t] = u[t] - f * vk[row];
+    for (int t = 0; t < RR; ++t) {
+      u[t] = sel_l(64 * t + s < n, u[t] - f * v[t], u[t]);
     }
+  };
+  T va[RR], vb[RR], ta, tb;
+  load_v(n - 2, va, ta);
+  for (int k = n - 2; k >= 0; k -= 2) {
+    load_v(k - 1, vb, tb);
+    apply(va, ta);
+    if (k - 1 < 0) break;
+    load_v(k - 2, va, ta);
+    apply(vb, tb);
   }
   const double lj = lam[col];
   int rank = 0;
@@ -589,7 +604,7 @@ __global__ __launch_bounds__(64) void k_lback(int n, const double *__restrict__ 
   }
   for (int off = 32; off >= 1; off >>= 1) rank += __shfl_xor(rank, off);
 #pragma unroll
-  for (int t = 0; t < R; ++t) {
+  for (int t = 0; t < RR; ++t) {
     const int row = 64 * t + s;
     if (row < n) Uo[static_cast<int64_t>(row) * n + rank] = u[t];
   }
@@ -646,7 +661,10 @@ int large_vectors(int n, const double *d, const double *e, const double *lam, do
 template <typename T>
 int large_back(int n, const double *Z, const T *V, const T *tau, const double *lam, T *U,
                double *eps, const int32_t *info, hipStream_t st) {
-  k_lback<T><<<n, 64, 0, st>>>(n, Z, V, tau, lam, U, eps, info);
+  if (n <= 128) k_lback<T, 2><<<n, 64, 0, st>>>(n, Z, V, tau, lam, U, eps, info);
+  else if (n <= 256) k_lback<T, 4><<<n, 64, 0, st>>>(n, Z, V, tau, lam, U, eps, info);
+  else if (n <= 512) k_lback<T, 8><<<n, 64, 0, st>>>(n, Z, V, tau, lam, U, eps, info);
+  else k_lback<T, 16><<<n, 64, 0, st>>>(n, Z, V, tau, lam, U, eps, info);
   return GPAW_OK;
 }
 
