@@ -64,8 +64,8 @@ __device__ inline T block_sum(T v, T *red) {
 // ------------------------------------------------------------------ Cholesky
 // Blocked right-looking Cholesky S = L L^H (lower) with the inverse L^-1
 // formed block row by block row alongside, in panels of CB columns:
-//   diagonal block  factored in LDS by one workgroup, which also writes its
-//                   inverse D (forward substitution, one lane per column),
+//   diagonal block  factored in LDS by one workgroup, which builds its
+//                   inverse D with the same row operations applied to I,
 //                   zeros the upper parts of its rows in L and L^-1 and
 //                   records the pivots (the squared diagonal of L);
 //   panel rows      L21 = A21 L11^-H, one thread per row (k_lchol_solve);
@@ -84,25 +84,50 @@ struct CholLds {
   double pd[CB];     // pivots d_c = L_cc^2
 };
 
-// Factor the wb x wb block held in a (lower part) in place: columns are
-// eliminated unscaled (a_rk -= a_rc conj(a_kc) / d_c; only entries right of
-// column c change in step c, so one barrier per column) and scaled by
-// 1 / sqrt(d_c) at the end. Returns the first failing column + 1 (pivot not
+// Factor the wb x wb block held in a (lower part) in place and build its
+// inverse in m. Columns are eliminated unscaled: step c forms the unit-lower
+// factor's column l_r = a_rc / d_c and applies row r -= l_r row c (r > c) to
+// the trailing part of a (a_rk -= l_r conj(a_kc), k > c) and to m, which
+// starts as the identity and so ends as the inverse of the unit-lower factor.
+// Only rows below c and, in a, columns right of c change in step c, so one
+// barrier per column suffices. At the end L_rk = a_rk / sqrt(d_k) and
+// L^-1 = diag(1 / sqrt(d)) m. Returns the first failing column + 1 (pivot not
 // positive, or NaN), else 0; uniform across the workgroup. The caller has
-// synchronised after filling a.
+// synchronised after filling a (zeros outside the lower wb x wb part).
 template <typename T>
-__device__ int chol_block_lds(T *a, int wb, CholLds &cl) {
-  const int tid = threadIdx.x;
+__device__ int chol_block_lds(T *a, T *m, int wb, CholLds &cl) {
+  const int tid = threadIdx.x, tr = tid / CB, k = tid - (tid / CB) * CB;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = tr + 8 * q;
+    m[r * CBP + k] = r == k ? rv<T>(1.0) : T{};
+  }
+  __syncthreads();
   for (int c = 0; c < wb; ++c) {
     const double d = re_l(a[c * CBP + c]);
     if (!(d > 0.0)) return c + 1;
     const double inv = 1.0 / d;
     if (tid == 0) cl.pd[c] = d;
+    const T akc = cj_l(a[k * CBP + c]), mck = m[c * CBP + k];
+    // every element is read and written back (unchanged where not updated):
+    // with conditional stores the compiler moves each load into its branch
+    // and waits on them one by one; each element has one owner, and a value
+    // written back unchanged is the value other threads may read
+    T lr[4], ar[4], mr[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int idx = tid + 256 * q, r = idx / CB, k = idx - (idx / CB) * CB;
-      if (k > c && k <= r && r < wb)
-        a[r * CBP + k] = a[r * CBP + k] - mulr(a[r * CBP + c] * cj_l(a[k * CBP + c]), inv);
+      const int r = tr + 8 * q;
+      lr[q] = a[r * CBP + c];
+      ar[q] = a[r * CBP + k];
+      mr[q] = m[r * CBP + k];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = tr + 8 * q;
+      const T l = mulr(lr[q], inv);
+      const bool upd = r > c;
+      a[r * CBP + k] = sel_l(upd && k > c, ar[q] - l * akc, ar[q]);
+      m[r * CBP + k] = sel_l(upd && k <= c, mr[q] - l * mck, mr[q]);
     }
     __syncthreads();
   }
@@ -110,9 +135,11 @@ __device__ int chol_block_lds(T *a, int wb, CholLds &cl) {
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int idx = tid + 256 * q, r = idx / CB, k = idx - (idx / CB) * CB;
-    if (k <= r && r < wb)
+    const int r = tr + 8 * q;
+    if (k <= r && r < wb) {
       a[r * CBP + k] = k == r ? rv<T>(sqrt(cl.pd[k])) : mulr(a[r * CBP + k], cl.rdiag[k]);
+      m[r * CBP + k] = mulr(m[r * CBP + k], cl.rdiag[r]);
+    }
   }
   __syncthreads();
   return 0;
@@ -126,7 +153,7 @@ template <typename T>
 __device__ void chol_diag_finish(T *a, T *dm, CholLds &cl, T *__restrict__ A, T *__restrict__ Linv, int n,
                                  int jb, int wb, double *__restrict__ piv, int32_t *info) {
   const int tid = threadIdx.x;
-  const int bad = chol_block_lds<T>(a, wb, cl);
+  const int bad = chol_block_lds<T>(a, dm, wb, cl);
   if (bad) {
     if (tid == 0) *info = jb + bad;
     return;
@@ -134,7 +161,11 @@ __device__ void chol_diag_finish(T *a, T *dm, CholLds &cl, T *__restrict__ A, T 
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int idx = tid + 256 * q, r = idx / CB, c = idx - (idx / CB) * CB;
-    if (r < wb && c < wb) A[static_cast<int64_t>(jb + r) * n + jb + c] = c <= r ? a[r * CBP + c] : T{};
+    if (r < wb && c < wb) {
+      const int64_t o = static_cast<int64_t>(jb + r) * n + jb + c;
+      A[o] = c <= r ? a[r * CBP + c] : T{};
+      Linv[o] = c <= r ? dm[r * CBP + c] : T{};
+    }
   }
   const int right = n - jb - wb;
   for (int r = 0; r < wb; ++r)
@@ -144,28 +175,6 @@ __device__ void chol_diag_finish(T *a, T *dm, CholLds &cl, T *__restrict__ A, T 
       Linv[o] = T{};
     }
   if (tid < wb) piv[jb + tid] = cl.pd[tid];
-  // D = L_bb^-1, column c by lane c (two partial sums for ILP):
-  // D_ic = (delta_ic - sum_{c <= k < i} L_ik D_kc) / L_ii, zero for i < c
-  if (tid < wb) {
-    const int c = tid;
-    for (int i = 0; i < wb; ++i) {
-      T s0{}, s1{};
-      int k = c;
-      for (; k + 1 < i; k += 2) {
-        s0 = s0 + a[i * CBP + k] * dm[k * CBP + c];
-        s1 = s1 + a[i * CBP + k + 1] * dm[(k + 1) * CBP + c];
-      }
-      if (k < i) s0 = s0 + a[i * CBP + k] * dm[k * CBP + c];
-      const T v = (i == c ? rv<T>(1.0) : T{}) - (s0 + s1);
-      dm[i * CBP + c] = i < c ? T{} : mulr(v, cl.rdiag[i]);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int idx = tid + 256 * q, r = idx / CB, c = idx - (idx / CB) * CB;
-    if (r < wb && c < wb) Linv[static_cast<int64_t>(jb + r) * n + jb + c] = dm[r * CBP + c];
-  }
 }
 
 // first diagonal block
