@@ -224,3 +224,41 @@ def test_large_eigensolver_against_scipy(n, cplx):
     assert np.abs(Ch.conj().T @ S @ Ch - np.eye(n)).max() <= 1e-11
     assert np.abs(Ch.conj().T @ H @ Ch - np.diag(want)).max() <= TOL * np.abs(want).max() * 10
     sysg.close()
+
+
+@pytest.mark.parametrize("n,cplx,j", [(320, False, 64), (320, False, 177), (150, True, 31),
+                                       (150, True, 149)])
+def test_large_cholesky_reports_failing_minor(n, cplx, j):
+    """Blocked Cholesky above the LDS limit: S = L0 D L0^H with one negative
+    entry D_jj has positive leading minors up to order j and a negative one of
+    order j+1, so the eigensolve reports j+1 (j inside a 32-column panel and
+    at its edges); a later call with a valid S on the same system succeeds."""
+    say(f"[chol-large-info] n={n} complex={cplx} j={j}")
+    rng = np.random.default_rng(1000 + n + j)
+    def rnd(*shape):
+        x = rng.standard_normal(shape)
+        return x + 1j * rng.standard_normal(shape) if cplx else x
+    L0 = np.tril(rnd(n, n)) / n
+    L0[np.diag_indices(n)] = 1.0 + rng.random(n)
+    D = np.ones(n)
+    D[j] = -1.0
+    S = (L0 * D) @ L0.conj().T
+    H = rnd(n, n)
+    H = H + H.conj().T
+    sysg = gfd.System(n=(4, 4, 4), h=0.2, k=(0.25, 0.0, 0.0) if cplx else (0, 0, 0),
+                      pos=np.zeros((0, 3)), channels=[], dH=np.zeros(0), dS=np.zeros(0),
+                      v=np.zeros(64), max_bands=n, complex_=cplx)
+    info = torch.full((1,), 99, dtype=torch.int32, device="cuda")
+    sysg.subspace_diag(to_dev(H), to_dev(S), info=info)
+    torch.cuda.synchronize()
+    assert int(info.item()) == j + 1
+    with pytest.raises(gfd.GpawError) as e:
+        sysg.subspace_diag(to_dev(H), to_dev(S))
+    assert e.value.status == "GPAW_ENOTPD"
+    S_ok = L0 @ L0.conj().T
+    eps, C = sysg.subspace_diag(to_dev(H), to_dev(S_ok))
+    torch.cuda.synchronize()
+    import scipy.linalg
+    want = scipy.linalg.eigh(H, S_ok, eigvals_only=True)
+    assert np.abs(host(eps) - want).max() <= TOL * np.abs(want).max() * 10
+    sysg.close()
