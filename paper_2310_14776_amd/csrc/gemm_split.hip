@@ -542,7 +542,22 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
     }
   }
 #pragma unroll
-  for (int i = 0; i < WT; ++i)
+  for (int i = 0; i < WT; ++i) {
+    // ADDSRC: the source values of this row band are loaded together, from
+    // clamped positions and without branches (a load inside the store's
+    // bounds test would be waited for on its own)
+    T sv[WT][4];
+    if constexpr (ADDSRC) {
+#pragma unroll
+      for (int j = 0; j < WT; ++j) {
+        const int64_t g = std::min<int64_t>(g0 + wc * 16 * WT + j * 16 + (lane & 15), cols - 1);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int n = std::min(n0 + wr * 16 * WT + i * 16 + 4 * (lane >> 4) + e, nb - 1);
+          sv[j][e] = src[static_cast<int64_t>(n) * cols + g];
+        }
+      }
+    }
 #pragma unroll
     for (int j = 0; j < WT; ++j) {
       const int64_t g = g0 + wc * 16 * WT + j * 16 + (lane & 15);
@@ -552,10 +567,9 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
         const int n = n0 + wr * 16 * WT + i * 16 + 4 * (lane >> 4) + e;
         if (n >= nb) continue;
         double vr = dacc[0][i][j][e], vi = dacc[NP - 1][i][j][e];
-        if (ADDSRC) {
-          const T sv = src[static_cast<int64_t>(n) * cols + g];
-          vr += Parts<T>::re(sv);
-          if constexpr (NP == 2) vi += Parts<T>::im(sv);
+        if constexpr (ADDSRC) {
+          vr += Parts<T>::re(sv[j][e]);
+          if constexpr (NP == 2) vi += Parts<T>::im(sv[j][e]);
         }
         T o;
         if constexpr (NP == 2) o = T{static_cast<float>(vr), static_cast<float>(vi)};
@@ -563,6 +577,7 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
         dst[static_cast<int64_t>(n) * cols + g] = o;
       }
     }
+  }
 }
 struct SplitPlanS {
   int tiles_n, tiles, nsplit;
