@@ -2,7 +2,7 @@
 
 Paper: the PAW Hamiltonian and overlap carry the projectors p~^a_i
 (Sec. "Projector augmented-wave method", Eq. (dh)); real projectors come from
-setup files (Sec. "PAW data sets and pseudopotentials"), which this build
+setup files (Sec. "PAW data sets and pseudopotentials"), which this oracle
 replaces by synthetic channels.
 
 Readings:
