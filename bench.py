@@ -114,6 +114,7 @@ def precision_form(steps, warmup):
     stream = torch.cuda.current_stream()
     out = {}
     results = {}
+    tuned = {}
     for prec in ("double", "single"):
         g = gfd.System(s.n, s.h, s.k, s.pos, s.channels, s.dH, s.dS, s.v, nb, complex_=False,
                        precision=prec)
@@ -127,6 +128,14 @@ def precision_form(steps, warmup):
         eps = torch.empty(nb, dtype=torch.float64, device=dev)
         P_rot, P_fin = torch.empty_like(P), torch.empty_like(P)
         info = torch.zeros(1, dtype=torch.int32, device=dev)
+        # both forms run with the launch shapes the library's autotuner picks
+        tb = gfd.Batch([g])
+        tb.tune(tb.io([psi], [psi_rot], [eps]), info)
+        t = tb.tuning()[1][0]
+        # single-precision systems have fixed launch shapes (all knobs report 0)
+        tuned[prec] = t if any(t.values()) else "fixed"
+        tb.close()
+        torch.cuda.synchronize()
 
         def step():
             g.project(psi, out=P, stream=stream)
@@ -145,7 +154,8 @@ def precision_form(steps, warmup):
             raise RuntimeError(f"precision form: eigensolver status {int(info.item())}")
         results[prec] = dict(ms=ms, eps=eps.cpu().numpy(), H=H.cpu().numpy(), S=S.cpu().numpy(),
                              psi_fin=psi_fin if prec == "single" else None, g=g)
-        out[prec] = dict(ms_per_step=round(ms, 3), value=nb * ng / (ms * 1e-3))
+        out[prec] = dict(ms_per_step=round(ms, 3), value=nb * ng / (ms * 1e-3),
+                         launch_tuning=tuned[prec])
         del Hpsi, Spsi, psi_rot, Spsi_rot, P, P_rot, P_fin
         if prec == "single":
             del psi
