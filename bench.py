@@ -1,14 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark: one FD-PAW block eigensolver step per iteration on one MI355X.
 
-Step = projections, H~psi, S~psi, subspace matrices H_nm/S_nm, FP64
-Cholesky + generalised eigensolve, rotation of the block and its projections.
-Workload: periodic 48^3 grid, h = 0.18 bohr, 128 bands, 16 atoms with 13
-projectors each (rc = 2.2 bohr), FP64 real; seeded synthetic inputs already
+Step = projections, H~psi and S~psi (one pass), subspace matrices H_nm and
+S_nm, FP64 Cholesky + generalised eigensolve, rotation of the block and of
+its projections. Default workload: the largest single-GPU case, a Bloch
+120x120x160 grid (h = 0.2 bohr, k = (0.25, 0, 0.5)), 1024 bands, 128 atoms
+with 13 projectors each, complex128. Seeded synthetic inputs, already
 resident in HBM when the timed region starts.
 
-Prints one JSON line with the throughput (band*gridpoints/s), per-part times,
-the roofline of the dominant kernel and the CPU oracle timed on this host.
+Prints one JSON line: throughput (band*gridpoints/s), per-part times, the
+roofline of the dominant kernel, the precision form (complex64 storage,
+split-BF16 matrix-core products, FP64 eigensolve, Cholesky orthonormality
+correction) and the batched form beside the FP64 step, the 48^3 and 96^3
+real workloads as extra lines, and the CPU oracle timed on this host.
 """
 import argparse
 import json
@@ -28,13 +32,15 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="B")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="D", choices=["A", "B", "C", "D"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision-form and batched-form measurements")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the extra workload lines (48^3 and 96^3 real)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed steps, run a plain 256 MiB device copy three times "
                          "(reference kernel for hardware byte counters)")
@@ -98,103 +104,240 @@ def timed(fn, stream, steps, warmup):
     return a.elapsed_time(b) / steps
 
 
-def precision_form(steps, warmup):
-    """FP64 step vs the precision form (single-precision storage, split-BF16
-    products, FP64 eigensolve, Cholesky orthonormality correction of the
-    stored rotated block) on the same FP32-rounded 96^3, 512-band, 64-atom
-    block."""
+def say(*msg):
+    print(*msg, file=sys.stderr, flush=True)
+
+
+def workload_label(s):
+    kind = (f"Bloch k=({s.k[0]:g},{s.k[1]:g},{s.k[2]:g})" if s.is_complex else "periodic")
+    return (f"FD-PAW block step, {kind} {s.n[0]}x{s.n[1]}x{s.n[2]} grid h={s.h[0]:g} bohr, "
+            f"{s.nb} bands, {s.natoms} atoms x 13 projectors")
+
+
+class Step:
+    """Buffers and the call sequence of one block step on one system."""
+
+    def __init__(self, g, psi, stream):
+        import torch
+        self.g, self.psi, self.stream = g, psi, stream
+        nb, dev = psi.shape[0], psi.device
+        self.nb = nb
+        self.P = torch.empty((nb, g.np), dtype=g.dtype, device=dev)
+        self.Hpsi = torch.empty_like(psi)
+        self.Spsi = torch.empty_like(psi)
+        self.H = torch.empty((nb, nb), dtype=g.mat_dtype, device=dev)
+        self.S = torch.empty_like(self.H)
+        self.C = torch.empty_like(self.H)
+        self.eps = torch.empty(nb, dtype=torch.float64, device=dev)
+        self.psi_rot = torch.empty_like(psi)
+        self.P_rot = torch.empty_like(self.P)
+        self.info = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.single = g.precision == "single"
+        if self.single:
+            self.Spsi_rot = torch.empty_like(psi)
+            self.psi_fin = torch.empty_like(psi)
+            self.P_fin = torch.empty_like(self.P)
+
+    def parts(self):
+        g, st = self.g, self.stream
+        out = [
+            ("project", lambda: g.project(self.psi, out=self.P, stream=st)),
+            ("apply_HS", lambda: g.apply_HS(self.psi, self.P, Hpsi=self.Hpsi, Spsi=self.Spsi,
+                                            stream=st)),
+            ("subspace", lambda: g.subspace_matrices(self.psi, self.Hpsi, self.Spsi, H=self.H,
+                                                     S=self.S, stream=st)),
+            ("diag", lambda: g.subspace_diag(self.H, self.S, eps=self.eps, C=self.C,
+                                             info=self.info, stream=st)),
+            ("rotate", lambda: g.rotate(self.psi, self.C, out=self.psi_rot, P=self.P,
+                                        P_out=self.P_rot, stream=st)),
+        ]
+        if self.single:
+            # S~ of the stored rotated block (its projections are the rotated
+            # P), then the Cholesky orthonormality correction
+            out.append(("apply_S_rot", lambda: g.apply_S(self.psi_rot, self.P_rot,
+                                                         out=self.Spsi_rot, stream=st)))
+            out.append(("orthonormalize", lambda: g.orthonormalize(
+                self.psi_rot, self.Spsi_rot, out=self.psi_fin, P=self.P_rot, P_out=self.P_fin,
+                info=self.info, stream=st)))
+        return out
+
+    def run(self):
+        for _, fn in self.parts():
+            fn()
+
+    def check(self):
+        if int(self.info.item()) != 0:
+            raise RuntimeError(f"eigensolver status {int(self.info.item())}")
+
+
+def time_parts(step, steps, warmup):
+    """Whole-step time (HIP events around the timed steps on the launch
+    stream) and per-part mean times (events around each call)."""
+    import torch
+    parts = step.parts()
+    for _ in range(warmup):
+        step.run()
+    torch.cuda.synchronize()
+    ev = {name: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                 for _ in range(steps)] for name, _ in parts}
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    start.record(step.stream)
+    for k in range(steps):
+        for name, fn in parts:
+            a, b = ev[name][k]
+            a.record(step.stream)
+            fn()
+            b.record(step.stream)
+    stop.record(step.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    step.check()
+    ms_step = start.elapsed_time(stop) / steps
+    part_ms = {name: float(np.mean([a.elapsed_time(b) for a, b in ev[name]])) for name, _ in parts}
+    return ms_step, part_ms, wall
+
+
+def tune(g, psi, stream):
+    """Launch shapes from the library's autotuner (kept in the system; every
+    choice computes the same results)."""
+    import torch
+    import paper_2310_14776_amd as gfd
+    out = torch.empty_like(psi)
+    eps = torch.empty(psi.shape[0], dtype=torch.float64, device=psi.device)
+    info = torch.zeros(1, dtype=torch.int32, device=psi.device)
+    tb = gfd.Batch([g])
+    tb.tune(tb.io([psi], [out], [eps]), info)
+    t = tb.tuning()[1][0]
+    tb.close()
+    torch.cuda.synchronize()
+    return t
+
+
+def part_costs(s, info, es):
+    """Algorithmic bytes and flops per launch of each part (es = bytes per
+    element of the block; complex flops are four real ones per product)."""
+    nb, ng, npj, ni = s.nb, s.ng, info["np"], info["ni"]
+    ent = info["entries"]
+    cf = 4 if s.is_complex else 1
+    return {
+        # gather psi at every sphere entry, read the entry table once, write P
+        "project": dict(bytes=ent * nb * es + ent * 12 + nb * npj * es,
+                        flops=2 * ent * ni * nb * cf),
+        # read psi, write H~psi and S~psi, read v and the add-back tables once
+        "apply_HS": dict(bytes=3 * nb * ng * es + ng * 8 + ng * 16 + ent * 4, flops=0),
+        # read psi, H~psi, S~psi; two Hermitian nb x nb products over Ng, of
+        # which the nb (nb + 1) / 2 entries on and above the diagonal are
+        # needed (2 flops per multiply-add)
+        "subspace": dict(bytes=3 * nb * ng * es, flops=2 * nb * (nb + 1) * ng * cf),
+        "diag": dict(bytes=0, flops=0),
+        # read psi, write psi'; nb x nb times nb x (Ng + Np)
+        "rotate": dict(bytes=2 * nb * (ng + npj) * es, flops=2 * nb * nb * (ng + npj) * cf),
+    }
+
+
+def roofline(part_ms, costs, tag):
+    """Roofline object of the costliest part with a bandwidth or matrix-core
+    bound (FP64 MFMA for the contractions, HBM otherwise)."""
+    dom = max((n for n in part_ms if n in costs and (costs[n]["bytes"] or costs[n]["flops"])),
+              key=part_ms.get)
+    c = costs[dom]
+    t = part_ms[dom] * 1e-3
+    intensity = c["flops"] / c["bytes"] if c["bytes"] else float("inf")
+    ridge = FP64_MFMA_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if c["flops"] and intensity >= ridge:
+        achieved = c["flops"] / t / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4)}
+    else:
+        achieved = c["bytes"] / t / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    roof["kernel"] = " + ".join(PART_KERNELS[dom][0])
+    roof["traffic"] = measured_traffic(dom, tag)
+    return roof
+
+
+def part_rows(part_ms, costs):
+    rows = {}
+    for name, ms in part_ms.items():
+        c = costs.get(name, dict(bytes=0, flops=0))
+        t = ms * 1e-3
+        rows[name] = dict(ms=round(ms, 4),
+                          GBs=round(c["bytes"] / t / 1e9, 1) if c["bytes"] else None,
+                          TFLOPs=round(c["flops"] / t / 1e12, 2) if c["flops"] else None)
+    return rows
+
+
+def run_config(name, steps, warmup, dev, stream, single_inputs=False, do_tune=None):
+    """FP64 step of one workload. Returns (result dict, system, step)."""
     import torch
     import synth
     import paper_2310_14776_amd as gfd
-    s = synth.config_system("C")
-    nb, ng = s.nb, s.ng
-    psi32_h = s.psi.reshape(nb, ng).astype(np.float32)
-    s.psi = None
-    dev = torch.device("cuda", 0)
-    stream = torch.cuda.current_stream()
-    out = {}
-    results = {}
-    tuned = {}
-    for prec in ("double", "single"):
-        g = gfd.System(s.n, s.h, s.k, s.pos, s.channels, s.dH, s.dS, s.v, nb, complex_=False,
-                       precision=prec)
-        psi = torch.from_numpy(psi32_h).to(dev)
-        if prec == "double":
-            psi = psi.double()
-        P = torch.empty((nb, g.np), dtype=g.dtype, device=dev)
-        Hpsi, Spsi, psi_rot, Spsi_rot, psi_fin = (torch.empty_like(psi) for _ in range(5))
-        H = torch.empty((nb, nb), dtype=g.mat_dtype, device=dev)
-        S, C = torch.empty_like(H), torch.empty_like(H)
-        eps = torch.empty(nb, dtype=torch.float64, device=dev)
-        P_rot, P_fin = torch.empty_like(P), torch.empty_like(P)
-        info = torch.zeros(1, dtype=torch.int32, device=dev)
-        # both forms run with the launch shapes the library's autotuner picks
-        tb = gfd.Batch([g])
-        tb.tune(tb.io([psi], [psi_rot], [eps]), info)
-        t = tb.tuning()[1][0]
-        # single-precision systems have fixed launch shapes (all knobs report 0)
-        tuned[prec] = t if any(t.values()) else "fixed"
-        tb.close()
-        torch.cuda.synchronize()
+    s = synth.config_system(name, lazy=True)
+    say(f"[bench] {name}: {workload_label(s)}; generating and uploading the block")
+    g = gfd.System.from_synth(s)
+    if single_inputs:
+        # values rounded to single precision (widened exactly on the device),
+        # so that the precision form later sees the same inputs
+        low = synth.block_to_device(s, dev, dtype=torch.complex64 if s.is_complex
+                                    else torch.float32)
+        psi = low.to(g.dtype)
+    else:
+        low = None
+        psi = synth.block_to_device(s, dev, dtype=g.dtype)
+    es = psi.element_size()
+    if do_tune is None:
+        do_tune = s.nb * s.ng * es < (8 << 30)
+    tuning = tune(g, psi, stream) if do_tune else "heuristic (the tuner runs below 8 GiB blocks)"
+    step = Step(g, psi, stream)
+    say(f"[bench] {name}: timing {steps} steps")
+    ms, part_ms, wall = time_parts(step, steps, warmup)
+    costs = part_costs(s, g.info, es)
+    res = dict(ms_per_step=ms, value=s.nb * s.ng / (ms * 1e-3), wall_s=wall,
+               workload=workload_label(s), dtype="c128" if s.is_complex else "f64",
+               parts=part_rows(part_ms, costs), launch_tuning=tuning,
+               roofline=roofline(part_ms, costs, f"{s.n[0]}x{s.n[1]}x{s.n[2]}_nb{s.nb}"))
+    return res, s, step, low
 
-        def step():
-            g.project(psi, out=P, stream=stream)
-            g.apply_HS(psi, P, Hpsi=Hpsi, Spsi=Spsi, stream=stream)
-            g.subspace_matrices(psi, Hpsi, Spsi, H=H, S=S, stream=stream)
-            g.subspace_diag(H, S, eps=eps, C=C, info=info, stream=stream)
-            g.rotate(psi, C, out=psi_rot, P=P, P_out=P_rot, stream=stream)
-            if prec == "single":
-                # S~ applied to the stored rotated block (its projections are
-                # the rotated P), then the Cholesky correction
-                g.apply_S(psi_rot, P_rot, out=Spsi_rot, stream=stream)
-                g.orthonormalize(psi_rot, Spsi_rot, out=psi_fin, P=P_rot, P_out=P_fin,
-                                 info=info, stream=stream)
-        ms = timed(step, stream, steps, warmup)
-        if int(info.item()) != 0:
-            raise RuntimeError(f"precision form: eigensolver status {int(info.item())}")
-        results[prec] = dict(ms=ms, eps=eps.cpu().numpy(), H=H.cpu().numpy(), S=S.cpu().numpy(),
-                             psi_fin=psi_fin if prec == "single" else None, g=g)
-        out[prec] = dict(ms_per_step=round(ms, 3), value=nb * ng / (ms * 1e-3),
-                         launch_tuning=tuned[prec])
-        del Hpsi, Spsi, psi_rot, Spsi_rot, P, P_rot, P_fin
-        if prec == "single":
-            del psi
-        torch.cuda.empty_cache()
-    # overlap of the corrected single-precision block, measured with the FP64 operators
-    g64 = results["double"]["g"]
-    pf = results["single"]["psi_fin"].double()
-    Sf = g64.apply_S(pf)
-    Hf = g64.apply_H(pf)
-    H1, S1 = g64.subspace_matrices(pf, Hf, Sf)
-    torch.cuda.synchronize()
-    e64, e32 = results["double"]["eps"], results["single"]["eps"]
-    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+def precision_form(s, low, fp64_step, fp64_ms, steps, warmup, dev, stream):
+    """The precision form on the same (rounded) block as the FP64 step:
+    single-precision storage, split-BF16 products, FP64 eigensolve, Cholesky
+    orthonormality correction of the stored rotated block."""
+    import torch
+    import paper_2310_14776_amd as gfd
+    g = gfd.System.from_synth(s, precision="single")
+    step = Step(g, low, stream)
+    say(f"[bench] precision form: timing {steps} steps")
+    ms, part_ms, _ = time_parts(step, steps, warmup)
+    e64 = fp64_step.eps.cpu().numpy()
+    e32 = step.eps.cpu().numpy()
+    rel = lambda a, b: float(torch.linalg.norm(a.to(b.dtype) - b) / torch.linalg.norm(b))
     res = {
-        "workload": f"periodic {s.n[0]}x{s.n[1]}x{s.n[2]} grid h={s.h[0]} bohr, {nb} bands, "
-                    f"{s.natoms} atoms x 13 projectors, real, inputs rounded to FP32",
-        "fp64": out["double"], "single_split_bf16": out["single"],
-        "speedup": round(results["double"]["ms"] / results["single"]["ms"], 3),
+        "workload": workload_label(s) + f", {'complex64' if s.is_complex else 'FP32'} storage",
+        "ms_per_step": round(ms, 3), "value": s.nb * s.ng / (ms * 1e-3),
+        "fp64_ms_per_step": round(fp64_ms, 3),
+        "speedup_vs_fp64": round(fp64_ms / ms, 3),
+        "parts_ms": {k: round(v, 4) for k, v in part_ms.items()},
         "max_abs_d_eps_Ha": float(np.abs(e32 - e64).max()),
         "max_abs_eps_Ha": float(np.abs(e64).max()),
-        "H_rel": rel(results["single"]["H"], results["double"]["H"]),
-        "S_rel": rel(results["single"]["S"], results["double"]["S"]),
-        "final_S_minus_I": float((S1.cpu() - torch.eye(nb, dtype=torch.float64)).abs().max()),
-        "error_reference": "FP64 GPU path on the same rounded inputs (parity-tested to 1e-12)",
+        "H_rel": rel(step.H, fp64_step.H), "S_rel": rel(step.S, fp64_step.S),
+        "error_reference": "the FP64 step on the same rounded inputs (both paths are "
+                           "parity-tested against the oracle; this is their difference)",
     }
-    for r in results.values():
-        r["g"].close()
+    g.close()
     return res
 
 
-def batched_form(steps, warmup):
+def batched_form(steps, warmup, dev, stream):
     """64 uneven systems (grids 16..48 per axis, 8..96 bands, 2..16 atoms, half
     complex): one tuned graph launch vs the same systems as per-system calls."""
     import torch
     import synth
     import paper_2310_14776_amd as gfd
     systems = [synth.make_system(**c) for c in synth.batched_systems()]
-    dev = torch.device("cuda", 0)
-    stream = torch.cuda.current_stream()
     gs = [gfd.System.from_synth(s) for s in systems]
     psi = [torch.from_numpy(s.psi.reshape(s.nb, -1)).to(dev) for s in systems]
     for s in systems:
@@ -212,28 +355,12 @@ def batched_form(steps, warmup):
     graph_ms = timed(lambda: batch.step(io, info, stream=stream), stream, steps, warmup)
     if int(info.abs().sum().item()) != 0:
         raise RuntimeError("batched form: eigensolver status")
-    # the same work as separate calls, one system after another on one stream
-    work = []
-    for g, p in zip(gs, psi):
-        nb = p.shape[0]
-        work.append(dict(g=g, psi=p, P=torch.empty((nb, g.np), dtype=g.dtype, device=dev),
-                         Hpsi=torch.empty_like(p), Spsi=torch.empty_like(p),
-                         H=torch.empty((nb, nb), dtype=g.mat_dtype, device=dev),
-                         S=torch.empty((nb, nb), dtype=g.mat_dtype, device=dev),
-                         C=torch.empty((nb, nb), dtype=g.mat_dtype, device=dev),
-                         eps=torch.empty(nb, dtype=torch.float64, device=dev),
-                         out=torch.empty_like(p),
-                         Pr=torch.empty((nb, g.np), dtype=g.dtype, device=dev)))
+    work = [Step(g, p, stream) for g, p in zip(gs, psi)]
 
     def eager():
         for w in work:
-            g = w["g"]
-            g.project(w["psi"], out=w["P"], stream=stream)
-            g.apply_H(w["psi"], w["P"], out=w["Hpsi"], stream=stream)
-            g.apply_S(w["psi"], w["P"], out=w["Spsi"], stream=stream)
-            g.subspace_matrices(w["psi"], w["Hpsi"], w["Spsi"], H=w["H"], S=w["S"], stream=stream)
-            g.subspace_diag(w["H"], w["S"], eps=w["eps"], C=w["C"], info=info, stream=stream)
-            g.rotate(w["psi"], w["C"], out=w["out"], P=w["P"], P_out=w["Pr"], stream=stream)
+            for name, fn in w.parts():
+                fn()
     eager_ms = timed(eager, stream, max(1, steps // 2), 1)
     work_units = sum(int(p.shape[0]) * int(p.shape[1]) for p in psi)
     res = {
@@ -254,39 +381,20 @@ def batched_form(steps, warmup):
     return res
 
 
-def part_costs(s, info):
-    """Algorithmic bytes and flops per launch of each part (FP64, 8 B)."""
-    nb, ng, npj, ni = s.nb, s.ng, info["np"], info["ni"]
-    ent = info["entries"]
-    es = 16 if s.is_complex else 8
-    return {
-        # gather psi at every sphere entry, read the projector table once, write P
-        "project": dict(bytes=ent * nb * es + ent * (ni * es + 4) + nb * npj * es,
-                        flops=2 * ent * ni * nb),
-        # read psi, write H~psi and S~psi, read v and the add-back tables once
-        "apply_HS": dict(bytes=3 * nb * ng * es + ng * 8 + info["covered"] * 8
-                         + ent * (ni * es + 4), flops=0),
-        # read psi, H~psi, S~psi; two Hermitian nb x nb products over Ng, of
-        # which the nb (nb + 1) / 2 entries on and above the diagonal are
-        # needed (real FP64 flops: 2 per multiply-add, 4 times that complex)
-        "subspace": dict(bytes=3 * nb * ng * es, flops=2 * nb * (nb + 1) * ng * (4 if s.is_complex else 1)),
-        "diag": dict(bytes=0, flops=0),
-        # read psi, write psi'; nb x nb times nb x (Ng + Np)
-        "rotate": dict(bytes=2 * nb * (ng + npj) * es,
-                       flops=2 * nb * nb * (ng + npj) * (4 if s.is_complex else 1)),
-    }
-
-
-def cpu_baseline(s, budget_s):
+def cpu_baseline(name, budget_s, nb_sample):
+    """The oracle (sparse projector matrix) on the first nb_sample bands of
+    the same system: full oracle steps, timed on this host."""
     import oracle
+    import synth
     try:
         from threadpoolctl import threadpool_info
         threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     except Exception:
         threads = 1
     cores = min(threads, len(os.sched_getaffinity(0)))
+    s = synth.config_system(name, nb=nb_sample)
     t0 = time.perf_counter()
-    ops = oracle.Operators.from_system(s)
+    ops = oracle.Operators.from_system(s, sparse=True)
     t_setup = time.perf_counter() - t0
     reps, t_steps = 0, 0.0
     while reps == 0 or (t_steps < budget_s and reps < 50):
@@ -297,9 +405,9 @@ def cpu_baseline(s, budget_s):
     per_step = t_steps / reps
     return {"value": s.nb * s.ng / per_step, "unit": "band*gridpoints/s", "cores": cores,
             "kind": "oracle",
-            "sample": f"{reps} full oracle steps of the same {s.n[0]}x{s.n[1]}x{s.n[2]} "
-                      f"{s.nb}-band system (projector matrix build {t_setup:.1f}s excluded), "
-                      f"{per_step * 1e3:.0f} ms/step"}
+            "sample": f"{reps} full oracle steps on bands 0..{s.nb - 1} of the same "
+                      f"{s.n[0]}x{s.n[1]}x{s.n[2]} system (sparse projector matrix, built in "
+                      f"{t_setup:.1f}s, excluded), {per_step * 1e3:.0f} ms/step"}
 
 
 def main():
@@ -311,123 +419,45 @@ def main():
         sys.exit(2)
 
     import torch
-    import synth
     import paper_2310_14776_amd as gfd
 
     if not os.path.exists(gfd.library_path()):
         from paper_2310_14776_amd.build import build
         build()
-    s = synth.config_system(args.config)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    sysg = gfd.System.from_synth(s)
-    nb, ng, npj = s.nb, s.ng, sysg.np
-    dt = sysg.dtype
-    psi = torch.from_numpy(s.psi.reshape(nb, ng)).to(dev)
-    P = torch.empty((nb, npj), dtype=dt, device=dev)
-    Hpsi = torch.empty_like(psi)
-    Spsi = torch.empty_like(psi)
-    H = torch.empty((nb, nb), dtype=dt, device=dev)
-    S = torch.empty_like(H)
-    eps = torch.empty(nb, dtype=torch.float64, device=dev)
-    C = torch.empty_like(H)
-    psi_rot = torch.empty_like(psi)
-    P_rot = torch.empty_like(P)
-    info = torch.zeros(1, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
-    # launch shapes from the library's autotuner (kept in the system; every
-    # choice computes the same results)
-    tb = gfd.Batch([sysg])
-    tio = tb.io([psi], [psi_rot], [eps])
-    tb.tune(tio, info)
-    tuning = tb.tuning()
-    tb.close()
-    torch.cuda.synchronize()
+    forms = not args.no_forms
 
-    parts = [
-        ("project", lambda: sysg.project(psi, out=P, stream=stream)),
-        ("apply_HS", lambda: sysg.apply_HS(psi, P, Hpsi=Hpsi, Spsi=Spsi, stream=stream)),
-        ("subspace", lambda: sysg.subspace_matrices(psi, Hpsi, Spsi, H=H, S=S, stream=stream)),
-        ("diag", lambda: sysg.subspace_diag(H, S, eps=eps, C=C, info=info, stream=stream)),
-        ("rotate", lambda: sysg.rotate(psi, C, out=psi_rot, P=P, P_out=P_rot, stream=stream)),
-    ]
-
-    for _ in range(args.warmup):
-        for _, fn in parts:
-            fn()
-    torch.cuda.synchronize()
-
-    ev = {name: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                 for _ in range(args.steps)] for name, _ in parts}
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    start.record(stream)
-    for k in range(args.steps):
-        for name, fn in parts:
-            a, b = ev[name][k]
-            a.record(stream)
-            fn()
-            b.record(stream)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    if int(info.item()) != 0:
-        raise RuntimeError(f"eigensolver status {int(info.item())}")
-
-    ms_step = start.elapsed_time(stop) / args.steps
-    part_ms = {name: float(np.mean([a.elapsed_time(b) for a, b in ev[name]])) for name, _ in parts}
-    value = nb * ng / (ms_step * 1e-3)
-
-    costs = part_costs(s, sysg.info)
-    rows = {}
-    for name, ms in part_ms.items():
-        c = costs[name]
-        t = ms * 1e-3
-        rows[name] = dict(ms=round(ms, 4),
-                          GBs=round(c["bytes"] / t / 1e9, 1) if c["bytes"] else None,
-                          TFLOPs=round(c["flops"] / t / 1e12, 2) if c["flops"] else None)
-    # dominant kernel: the costliest part with a bandwidth or matrix-core roofline
-    dom = max((n for n in part_ms if costs[n]["bytes"] or costs[n]["flops"]), key=part_ms.get)
-    c = costs[dom]
-    t = part_ms[dom] * 1e-3
-    intensity = c["flops"] / c["bytes"] if c["bytes"] else float("inf")
-    ridge = FP64_MFMA_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
-    if c["flops"] and intensity >= ridge:
-        achieved = c["flops"] / t / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4)}
-    else:
-        achieved = c["bytes"] / t / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
-    roof["kernel"] = " + ".join(PART_KERNELS[dom][0])
-    roof["traffic"] = measured_traffic(dom, f"{s.n[0]}x{s.n[1]}x{s.n[2]}_nb{nb}")
-
+    res, s, step, low = run_config(args.config, args.steps, args.warmup, dev, stream,
+                                   single_inputs=forms)
     out = {
         "metric": "band*gridpoints/s for H|psi>+subspace step",
-        "value": value,
+        "value": res["value"],
         "unit": "band*gridpoints/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "wall_s": wall,
+        "ms_per_step": res["ms_per_step"],
+        "wall_s": res["wall_s"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"FD-PAW block step, periodic {s.n[0]}x{s.n[1]}x{s.n[2]} grid "
-                               f"h={s.h[0]} bohr, {nb} bands, {s.natoms} atoms x 13 projectors, "
-                               f"FP64 real",
-                   "grid": list(s.n), "bands": nb, "atoms": s.natoms, "parallelism": "single GPU"},
-        "parts": rows,
-        "launch_tuning": tuning[1][0] if tuning else None,
-        "roofline": roof,
+        "dtype": res["dtype"],
+        "data": "synthetic (seeded; values rounded to single precision so that the "
+                "precision form sees the same block)" if forms else "synthetic (seeded)",
+        "config": {"workload": res["workload"], "grid": list(s.n), "bands": s.nb,
+                   "atoms": s.natoms, "k": list(s.k), "parallelism": "single GPU"},
+        "parts": res["parts"],
+        "launch_tuning": res["launch_tuning"],
+        "roofline": res["roofline"],
     }
-    sysg.close()
-    del psi, Hpsi, Spsi, psi_rot, P, P_rot
+    fp64_ms = res["ms_per_step"]
+    # the FP64 step ran on the rounded block: its eps, H and S are the error
+    # reference of the precision form; its grid buffers are freed first
+    for attr in ("psi", "Hpsi", "Spsi", "psi_rot"):
+        setattr(step, attr, None)
+    step.g.close()
     torch.cuda.empty_cache()
     if args.calib_copy:
         xa = torch.empty(32 << 20, dtype=torch.float64, device=dev)
@@ -436,12 +466,30 @@ def main():
             xb.copy_(xa)
         torch.cuda.synchronize()
         del xa, xb
-    if not args.no_forms:
-        forms_steps = max(3, min(args.steps, 10))
-        out["forms"] = {"precision": precision_form(forms_steps, 2),
-                        "batched": batched_form(forms_steps, 2)}
+    if forms:
+        out["forms"] = {"precision": precision_form(s, low, step, fp64_ms,
+                                                    max(2, min(args.steps, 10)), 1, dev, stream)}
+        del low
+        torch.cuda.empty_cache()
+        out["forms"]["batched"] = batched_form(max(3, min(args.steps, 10)), 2, dev, stream)
+    del step
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        extra = {}
+        for name in ("B", "C"):
+            if name == args.config:
+                continue
+            r, _, st, _ = run_config(name, max(5, args.steps), 2, dev, stream)
+            st.g.close()
+            del st
+            torch.cuda.empty_cache()
+            extra[name] = {k: r[k] for k in ("workload", "dtype", "ms_per_step", "value",
+                                             "parts", "roofline", "launch_tuning")}
+        out["extra_workloads"] = extra
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+        say("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_seconds,
+                                           nb_sample=8 if s.nb >= 512 else s.nb)
     print(json.dumps(out), flush=True)
 
 

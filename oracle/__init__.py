@@ -23,7 +23,7 @@ from .projectors import (radial_norm, solid_harmonics, projector_values,
                          projector_matrix, projector_matrix_sparse)
 from .paw import project, addback, apply_H, apply_S, block_diag_atoms
 from .subspace import (subspace_matrices, hermiticity_defect, diagonalize,
-                       rotate)
+                       rotate, orthonormalize)
 from .step import Operators, fd_step
 
 __all__ = ["WEIGHTS", "laplacian", "kinetic", "symbol_1d", "radial_norm",
@@ -31,4 +31,5 @@ __all__ = ["WEIGHTS", "laplacian", "kinetic", "symbol_1d", "radial_norm",
            "projector_matrix_sparse",
            "project", "addback", "apply_H", "apply_S", "block_diag_atoms",
            "subspace_matrices", "hermiticity_defect", "diagonalize", "rotate",
+           "orthonormalize",
            "Operators", "fd_step"]

@@ -131,11 +131,7 @@ int gpaw_sys_create(const gpaw_sys_desc *d, gpaw_sys **out) {
     for (int a = 0; a < 3 * d->natoms; ++a)
       if (!std::isfinite(d->pos[a])) return fail(GPAW_EINVAL, "atom positions must be finite");
   }
-  int dev = 0;
-  GFD_HIP(hipGetDevice(&dev));
-
   gpaw_sys *s = new gpaw_sys();
-  s->device = dev;
   for (int c = 0; c < 3; ++c) {
     s->n[c] = d->n[c];
     s->h[c] = d->h[c];
@@ -153,9 +149,22 @@ int gpaw_sys_create(const gpaw_sys_desc *d, gpaw_sys **out) {
 
   int rc = GPAW_OK;
   const size_t es = elem_size(s->dtype);
+  // the projector geometry is built and checked on the host before the
+  // first device call
+  HostTables ht;
+  if (s->natoms > 0 && (rc = build_tables_host(d, s, ht)) != GPAW_OK) {
+    delete s;
+    return rc;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    delete s;
+    return fail(GPAW_EHIP, "hipGetDevice failed: no usable HIP device");
+  }
+  s->device = dev;
   do {
     if (s->natoms > 0) {
-      if ((rc = build_tables(d, s)) != GPAW_OK) break;
+      if ((rc = upload_tables(s, ht)) != GPAW_OK) break;
       const size_t nd = static_cast<size_t>(s->natoms) * s->ni * s->ni;
       if ((rc = dev_alloc(&s->dH, nd)) != GPAW_OK) break;
       if ((rc = dev_alloc(&s->dS, nd)) != GPAW_OK) break;

@@ -14,6 +14,8 @@
 //   k_eig_vectors  (one lane per eigenvalue) inverse iteration with a pivoted
 //                  tridiagonal LU; shifts closer than 10 eps ||T|| are pulled
 //                  apart by that amount;
+//   k_cluster_orth modified Gram-Schmidt (twice) inside clusters of
+//                  eigenvalues closer than 1e-7 ||T||;
 //   Newton-Schulz  two steps Z <- Z (3I - Z^T Z)/2 (each squares the
 //                  orthogonality defect; the second Gram matrix must be
 //                  within 1e-7 of I);
@@ -1064,6 +1066,94 @@ __global__ __launch_bounds__(1024) void k_gram_check(const double *__restrict__ 
   }
 }
 
+// ------------------------------------------------------------------ clusters
+// Inverse iteration separates the eigenvectors of one unreduced block of T
+// only as far as the eigenvalue gaps allow: vectors whose eigenvalues lie
+// within a few rounding units of ||T|| of each other (degenerate shells of a
+// symmetric system, the close pairs of a Wilkinson matrix) come out nearly
+// parallel. Slots of one block whose consecutive eigenvalue gaps are at most
+// CL_TOL ||T|| form a cluster, and each cluster is orthonormalised by modified
+// Gram-Schmidt in slot order, applied twice. Outside the clusters the vectors
+// overlap by at most ~1e-8, which the Newton-Schulz steps that follow remove.
+// One workgroup; each wavefront takes whole clusters (lane r owns rows
+// r + 64q of every column it touches, so its own stores are what it reads
+// back).
+constexpr double CL_TOL = 1e-7;
+constexpr int CL_T = 256;
+constexpr int CL_RPL = EIG_LARGE_MAX / 64;  // rows per lane
+__global__ __launch_bounds__(CL_T) void k_cluster_orth(int n, const double *__restrict__ d,
+                                                       const double *__restrict__ e,
+                                                       const double *__restrict__ lam,
+                                                       double *__restrict__ Z,
+                                                       const int32_t *__restrict__ info) {
+  if (*info != 0) return;
+  __shared__ unsigned char brk[EIG_LARGE_MAX];  // 1: slot j opens a new cluster
+  __shared__ int list[EIG_LARGE_MAX / 2];       // clusters of >= 2 slots: first | last << 16
+  __shared__ int nlist;
+  __shared__ double red[CL_T / 64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  double g = 0.0;
+  for (int i = t; i < n; i += CL_T)
+    g = fmax(g, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0));
+  g = wave_max(g);
+  if (lane == 0) red[wv] = g;
+  if (t == 0) nlist = 0;
+  __syncthreads();
+  double tn = red[0];
+#pragma unroll
+  for (int q = 1; q < CL_T / 64; ++q) tn = fmax(tn, red[q]);
+  const double tol = CL_TOL * tn;
+  for (int j = t; j < n; j += CL_T)
+    brk[j] = (j == 0 || split_at(d, e, j - 1) || !(lam[j] - lam[j - 1] <= tol)) ? 1 : 0;
+  __syncthreads();
+  for (int j = t; j < n; j += CL_T) {
+    if (brk[j] == 0 && (j + 1 == n || brk[j + 1] == 1)) {
+      int b = j;
+      while (brk[b] == 0) --b;  // brk[0] == 1 ends the walk
+      list[atomicAdd(&nlist, 1)] = b | (j << 16);
+    }
+  }
+  __syncthreads();
+  const int ncl = nlist;
+  for (int c = wv; c < ncl; c += CL_T / 64) {  // wavefront-uniform
+    const int b = list[c] & 0xFFFF, last = list[c] >> 16;
+    for (int j = b; j <= last; ++j) {
+      double zj[CL_RPL];
+#pragma unroll
+      for (int q = 0; q < CL_RPL; ++q) {
+        const int r = lane + 64 * q;
+        zj[q] = r < n ? Z[static_cast<int64_t>(r) * n + j] : 0.0;
+      }
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int i = b; i < j; ++i) {
+          double zi[CL_RPL], s = 0.0;
+#pragma unroll
+          for (int q = 0; q < CL_RPL; ++q) {
+            const int r = lane + 64 * q;
+            zi[q] = r < n ? Z[static_cast<int64_t>(r) * n + i] : 0.0;
+            s = fma(zi[q], zj[q], s);
+          }
+          s = wave_sum(s);
+#pragma unroll
+          for (int q = 0; q < CL_RPL; ++q) zj[q] = fma(-s, zi[q], zj[q]);
+        }
+      }
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < CL_RPL; ++q) s = fma(zj[q], zj[q], s);
+      s = wave_sum(s);
+      // a vector lost to cancellation stays as it is; the Gram check after
+      // the Newton-Schulz steps then reports the failure
+      const double sc = s > 1e-200 ? 1.0 / sqrt(s) : 1.0;
+#pragma unroll
+      for (int q = 0; q < CL_RPL; ++q) {
+        const int r = lane + 64 * q;
+        if (r < n) Z[static_cast<int64_t>(r) * n + j] = zj[q] * sc;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ back-transform
 // U = Q Z with Q = H_0 H_1 ... H_n-2, in blocks of KB reflectors in compact
 // WY form: H_k0 ... H_k0+KB-1 = I - V_b T_b V_b^H with T_b upper triangular
@@ -1252,6 +1342,7 @@ int eigh_large_t(const gpaw_sys *s, const T *H, const T *S, int n, double *eps, 
   large_tridiag<T>(Am, n, V, tau, w.d, w.e, p, info, st);
   k_eig_values<<<(n + 3) / 4, 256, values_lds_bytes(n), st>>>(n, w.d, w.e, w.lam, info);
   large_vectors(n, w.d, w.e, w.lam, w.lu, w.Z, info, st);
+  k_cluster_orth<<<1, CL_T, 0, st>>>(n, w.d, w.e, w.lam, w.Z, info);
   k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.Z, w.G, n, info);
   k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 0.5, info, w.skip, NS_SKIP, nullptr);
   k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.G, w.Z2, n, w.skip);
@@ -1300,6 +1391,7 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
   k_eig_values<<<(n + 3) / 4, 256, values_lds_bytes(n), st>>>(n, w.d, w.e, w.lam, info);
   k_eig_vectors<<<(n + VEC_T - 1) / VEC_T, VEC_T, vec_lds_doubles(n) * sizeof(double), st>>>(n, w,
                                                                                         info);
+  k_cluster_orth<<<1, CL_T, 0, st>>>(n, w.d, w.e, w.lam, w.Z, info);
   // two Newton-Schulz steps Z <- Z (3I - Z^T Z)/2 on the real tridiagonal
   // eigenvectors; the second Gram matrix must be within 1e-7 of I, so the
   // result is orthonormal to ~1e-14. When the first Gram matrix is already

@@ -7,6 +7,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "gpaw_fd.h"
 
@@ -201,8 +202,17 @@ size_t elem_size(int32_t dtype);
 size_t mat_elem_size(int32_t dtype);
 bool is_complex(int32_t dtype);
 
-// Host construction of the projector geometry (tables.hip).
-int build_tables(const gpaw_sys_desc *d, gpaw_sys *s);
+// Host construction of the projector geometry (tables.hip): the tables are
+// built and checked on the host first (no device call, so a bad geometry is
+// rejected before anything is allocated), then uploaded.
+struct HostTables {
+  std::vector<int32_t> a_start, e_g, pm_code;
+  std::vector<short4> e_xyz;
+  std::vector<int4> pinfo;
+  std::vector<double> pos;
+};
+int build_tables_host(const gpaw_sys_desc *d, gpaw_sys *s, HostTables &ht);
+int upload_tables(gpaw_sys *s, const HostTables &ht);
 
 // Strided copy global -> LDS by nthr threads: eight loads in flight per
 // thread before the stores, so a round costs one memory latency.

@@ -86,7 +86,7 @@ int setup_proj(const gpaw_sys_desc *d, ProjDev &P) {
 
 }  // namespace
 
-int build_tables(const gpaw_sys_desc *d, gpaw_sys *s) {
+int build_tables_host(const gpaw_sys_desc *d, gpaw_sys *s, HostTables &ht) {
   int rc = setup_proj(d, s->proj);
   if (rc != GPAW_OK) return rc;
   const int64_t n[3] = {d->n[0], d->n[1], d->n[2]};
@@ -171,22 +171,34 @@ int build_tables(const gpaw_sys_desc *d, gpaw_sys *s) {
       ++ncov;
       pi = make_int4(pm_code[e], 0, 0, static_cast<int>(e));
     }
-    const int cnt = (pi.w >> 24) + 1;
-    if (cnt > 255) return fail(GPAW_EINVAL, "more than 255 projector entries at one grid point");
-    if (cnt == 2) pi.y = pm_code[e];
-    if (cnt == 3) pi.z = pm_code[e];
-    pi.w = (cnt << 24) | (pi.w & 0xFFFFFF);
+    // the count lives in the top byte: unsigned arithmetic, so counts of
+    // 128..255 survive the round trip and 256 is caught
+    const unsigned cnt = (static_cast<unsigned>(pi.w) >> 24) + 1u;
+    if (cnt > 255u) return fail(GPAW_EINVAL, "more than 255 projector entries at one grid point");
+    if (cnt == 2u) pi.y = pm_code[e];
+    if (cnt == 3u) pi.z = pm_code[e];
+    pi.w = static_cast<int>((cnt << 24) | (static_cast<unsigned>(pi.w) & 0xFFFFFFu));
   }
 
-  std::vector<double> pos(d->pos, d->pos + 3 * d->natoms);
   s->tab.nent = nent;
   s->tab.ncov = ncov;
-  if ((rc = upload(&s->tab.a_start, a_start)) != GPAW_OK) return rc;
-  if ((rc = upload(&s->tab.e_g, e_g)) != GPAW_OK) return rc;
-  if ((rc = upload(&s->tab.e_xyz, e_xyz)) != GPAW_OK) return rc;
-  if ((rc = upload(&s->tab.pinfo, pinfo)) != GPAW_OK) return rc;
-  if ((rc = upload(&s->tab.pm_code, pm_code)) != GPAW_OK) return rc;
-  if ((rc = upload(&s->tab.pos, pos)) != GPAW_OK) return rc;
+  ht.a_start = std::move(a_start);
+  ht.e_g = std::move(e_g);
+  ht.e_xyz = std::move(e_xyz);
+  ht.pinfo = std::move(pinfo);
+  ht.pm_code = std::move(pm_code);
+  ht.pos.assign(d->pos, d->pos + 3 * d->natoms);
+  return GPAW_OK;
+}
+
+int upload_tables(gpaw_sys *s, const HostTables &ht) {
+  int rc;
+  if ((rc = upload(&s->tab.a_start, ht.a_start)) != GPAW_OK) return rc;
+  if ((rc = upload(&s->tab.e_g, ht.e_g)) != GPAW_OK) return rc;
+  if ((rc = upload(&s->tab.e_xyz, ht.e_xyz)) != GPAW_OK) return rc;
+  if ((rc = upload(&s->tab.pinfo, ht.pinfo)) != GPAW_OK) return rc;
+  if ((rc = upload(&s->tab.pm_code, ht.pm_code)) != GPAW_OK) return rc;
+  if ((rc = upload(&s->tab.pos, ht.pos)) != GPAW_OK) return rc;
   if ((rc = upload(&s->tab.proj, std::vector<ProjDev>(1, s->proj))) != GPAW_OK) return rc;
   return GPAW_OK;
 }

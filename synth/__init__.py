@@ -8,7 +8,9 @@ eigensolve and the rotation live in the HIP library and, independently, in
 the CPU oracle. Both sides read the same arrays from here.
 """
 from .systems import (System, make_system, standard_channels, config_system,
-                      CONFIGS, ragged_cases, batched_systems, smooth_bands)
+                      CONFIGS, ragged_cases, batched_systems, noise_band, smooth_band)
+from .device import block_to_device
 
 __all__ = ["System", "make_system", "standard_channels", "config_system",
-           "CONFIGS", "ragged_cases", "batched_systems", "smooth_bands"]
+           "CONFIGS", "ragged_cases", "batched_systems", "noise_band", "smooth_band",
+           "block_to_device"]

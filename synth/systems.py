@@ -13,16 +13,22 @@ Recipe (one system):
     cut-off at rc (the functions themselves are evaluated by the consumers);
   * Delta H^a = (A + A^T)/2 and Delta S^a = s (B + B^T)/2 with A, B drawn
     U[-1,1]^{13x13} per atom (s = 0.1);
-  * the block of wave functions: U[-1,1] per grid value (real), or
-    independent U[-1,1] real and imaginary parts (complex).
+  * the block of wave functions: U[-1,1) per grid value (real), or
+    independent U[-1,1) real and imaginary parts (complex).
 
 Draw order from numpy.random.default_rng(seed): positions, Delta H,
-Delta S, wave functions.
+Delta S. Band b of the block comes from its own stream,
+numpy.random.default_rng([seed, 1, b]) for noise bands and
+default_rng([seed, 2, b]) for smooth bands, so any band can be regenerated
+alone (the oracle checks sampled bands of blocks too large to hold twice)
+and a large block can be generated in parallel and streamed to a device.
 """
 from __future__ import annotations
 
 from dataclasses import dataclass, field
+import concurrent.futures
 import math
+import os
 
 import numpy as np
 
@@ -43,9 +49,11 @@ class System:
     dH: np.ndarray      # [natoms][ni][ni] real symmetric
     dS: np.ndarray      # [natoms][ni][ni] real symmetric
     v: np.ndarray       # [N0][N1][N2] float64
-    psi: np.ndarray     # [nb][N0][N1][N2] float64 or complex128
+    psi: np.ndarray     # [nb][N0][N1][N2] float64 or complex128, or None (lazy)
     name: str = ""
     meta: dict = field(default_factory=dict)
+    nbands: int = 0     # band count of a lazy block (psi None)
+    complex_psi: bool = False
 
     @property
     def natoms(self):
@@ -53,7 +61,20 @@ class System:
 
     @property
     def nb(self):
-        return self.psi.shape[0]
+        return self.psi.shape[0] if self.psi is not None else self.nbands
+
+    def bands(self, lo, hi, threads=None):
+        """Bands lo..hi-1 of the block as [hi-lo][N0][N1][N2] (generated from
+        their own streams when the block is lazy)."""
+        if self.psi is not None:
+            return self.psi[lo:hi]
+        return _gen_bands(self, range(lo, hi), threads)
+
+    def band_list(self, idx, threads=None):
+        """The bands with the given indices, [len(idx)][N0][N1][N2]."""
+        if self.psi is not None:
+            return self.psi[list(idx)]
+        return _gen_bands(self, list(idx), threads)
 
     @property
     def ni(self):
@@ -69,7 +90,7 @@ class System:
 
     @property
     def is_complex(self):
-        return np.iscomplexobj(self.psi)
+        return np.iscomplexobj(self.psi) if self.psi is not None else self.complex_psi
 
 
 def gaussian_potential(n, h, pos, depth=-2.0, width=1.0):
@@ -91,26 +112,39 @@ def gaussian_potential(n, h, pos, depth=-2.0, width=1.0):
     return depth * v
 
 
-def smooth_bands(rng, nb, n, h, k, complex_psi, g0=2.0):
-    """Band-limited random blocks: plane-wave coefficients drawn from a
-    standard normal, damped by exp(-|G + k|^2 / (2 g0^2)) (g0 in 1/bohr), then
-    the Bloch factor exp(i k.r) applied so that psi(r + L_c e_c) equals
-    exp(2 pi i k_c) psi(r). Real blocks (k = 0) take the real part. The
-    amplitude is scaled to an RMS of 1/sqrt(3) per component, that of U[-1, 1].
-    The Rayleigh quotients of such bands lie in the 1-10 Ha range."""
+def noise_band(seed, b, n, complex_psi):
+    """Band b of a noise block: U[-1, 1) per grid value, complex values with
+    independent real and imaginary parts, from default_rng([seed, 1, b])."""
+    ng = int(np.prod(n))
+    rng = np.random.default_rng([seed, 1, b])
+    out = np.empty(2 * ng if complex_psi else ng)
+    rng.random(out=out)
+    out *= 2.0
+    out -= 1.0
+    return (out.view(np.complex128) if complex_psi else out).reshape(n)
+
+
+def smooth_band(seed, b, n, h, k, complex_psi, g0=2.0):
+    """Band b of a band-limited block: plane-wave coefficients drawn from a
+    standard normal (default_rng([seed, 2, b])), damped by
+    exp(-|G + k|^2 / (2 g0^2)) (g0 in 1/bohr), then the Bloch factor
+    exp(i k.r) applied so that psi(r + L_c e_c) equals exp(2 pi i k_c) psi(r).
+    Real blocks (k = 0) take the real part. The band is scaled to an RMS of
+    1/sqrt(3) per component, that of U[-1, 1]. The Rayleigh quotients of such
+    bands lie in the 1-10 Ha range."""
     L = [n[c] * h[c] for c in range(3)]
     G = [2.0 * np.pi * np.fft.fftfreq(n[c], d=h[c]) + 2.0 * np.pi * k[c] / L[c] for c in range(3)]
     G2 = G[0][:, None, None] ** 2 + G[1][None, :, None] ** 2 + G[2][None, None, :] ** 2
     env = np.exp(-G2 / (2.0 * g0 * g0))
-    shape = (nb,) + tuple(n)
-    c = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
-    psi = np.fft.ifftn(c * env[None], axes=(1, 2, 3))
+    rng = np.random.default_rng([seed, 2, b])
+    c = rng.standard_normal(tuple(n)) + 1j * rng.standard_normal(tuple(n))
+    psi = np.fft.ifftn(c * env)
     if complex_psi:
         x = [np.arange(n[c]) * h[c] for c in range(3)]
         kr = (2.0 * np.pi * k[0] / L[0]) * x[0][:, None, None] \
             + (2.0 * np.pi * k[1] / L[1]) * x[1][None, :, None] \
             + (2.0 * np.pi * k[2] / L[2]) * x[2][None, None, :]
-        psi = psi * np.exp(1j * kr)[None]
+        psi = psi * np.exp(1j * kr)
         rms = np.sqrt(np.mean(np.abs(psi) ** 2) / 2.0)
     else:
         psi = psi.real
@@ -118,8 +152,31 @@ def smooth_bands(rng, nb, n, h, k, complex_psi, g0=2.0):
     return psi * (1.0 / (np.sqrt(3.0) * rms))
 
 
+def _one_band(s, b):
+    seed = s.meta["seed"]
+    if s.meta.get("bands", "noise") == "smooth":
+        return smooth_band(seed, b, s.n, s.h, s.k, s.is_complex)
+    return noise_band(seed, b, s.n, s.is_complex)
+
+
+def _gen_bands(s, idx, threads=None):
+    idx = list(idx)
+    out = np.empty((len(idx),) + tuple(s.n), dtype=np.complex128 if s.is_complex else np.float64)
+    if not idx:
+        return out
+    threads = threads or min(16, len(os.sched_getaffinity(0)))
+
+    def fill(i):
+        out[i] = _one_band(s, idx[i])
+    with concurrent.futures.ThreadPoolExecutor(max(1, min(threads, len(idx)))) as ex:
+        list(ex.map(fill, range(len(idx))))
+    return out
+
+
 def make_system(n, h, nb, natoms, rc, seed, k=(0.0, 0.0, 0.0), complex_psi=None,
-                ds_scale=0.1, depth=-2.0, width=1.0, name="", bands="noise"):
+                ds_scale=0.1, depth=-2.0, width=1.0, name="", bands="noise", lazy=False):
+    """One seeded system. lazy: do not hold the block (psi is None); its
+    bands are generated on request by System.bands / System.band_list."""
     n = tuple(int(x) for x in n)
     h = (float(h),) * 3 if np.isscalar(h) else tuple(float(x) for x in h)
     k = tuple(float(x) for x in k)
@@ -134,18 +191,16 @@ def make_system(n, h, nb, natoms, rc, seed, k=(0.0, 0.0, 0.0), complex_psi=None,
     dH = 0.5 * (A + A.transpose(0, 2, 1))
     B = rng.uniform(-1.0, 1.0, (natoms, ni, ni))
     dS = ds_scale * 0.5 * (B + B.transpose(0, 2, 1))
-    shape = (nb,) + n
-    if bands == "smooth":
-        psi = smooth_bands(rng, nb, n, h, k, complex_psi)
-    elif complex_psi:
-        psi = rng.uniform(-1.0, 1.0, shape) + 1j * rng.uniform(-1.0, 1.0, shape)
-    else:
-        psi = rng.uniform(-1.0, 1.0, shape)
+    if bands not in ("noise", "smooth"):
+        raise ValueError("bands must be 'noise' or 'smooth'")
     v = gaussian_potential(n, h, pos, depth, width)
-    return System(n=n, h=h, k=k, pos=pos, channels=channels, dH=dH, dS=dS, v=v,
-                  psi=psi, name=name,
-                  meta=dict(seed=seed, rc=rc, ds_scale=ds_scale, depth=depth, width=width,
-                            bands=bands))
+    s = System(n=n, h=h, k=k, pos=pos, channels=channels, dH=dH, dS=dS, v=v,
+               psi=None, name=name, nbands=int(nb), complex_psi=bool(complex_psi),
+               meta=dict(seed=seed, rc=rc, ds_scale=ds_scale, depth=depth, width=width,
+                         bands=bands))
+    if not lazy:
+        s.psi = s.bands(0, nb)
+    return s
 
 
 # The five workloads: small real case, the single-GPU FP64 case, the precision
@@ -160,12 +215,13 @@ CONFIGS = {
 }
 
 
-def config_system(name, nb=None):
-    """The named workload; nb overrides the band count (for bounded samples)."""
+def config_system(name, nb=None, lazy=False):
+    """The named workload; nb overrides the band count (for bounded samples);
+    lazy leaves the block to be generated band by band."""
     cfg = dict(CONFIGS[name])
     if nb is not None:
         cfg["nb"] = nb
-    return make_system(name=name, **cfg)
+    return make_system(name=name, lazy=lazy, **cfg)
 
 
 def batched_systems(count=64, seed=4):

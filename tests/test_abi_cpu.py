@@ -78,3 +78,52 @@ def test_compute_calls_reject_null_system(lib):
     assert lib.gpaw_fd_apply_H(None, None, 1, None, None, None) == -1
     assert lib.gpaw_rotate(None, None, None, 1, None, None, None, None) == -1
     assert b"NULL" in lib.gpaw_last_error()
+
+
+def _atoms_desc(natoms, n=(12, 12, 12), h=0.2, rc=0.5):
+    """Descriptor of natoms atoms stacked on one site (every point of the
+    sphere then carries natoms entries); keeps its host arrays alive."""
+    import numpy as np
+    from paper_2310_14776_amd._binding import SysDesc, Channel
+    chans = (Channel * 1)(Channel(0, rc / 3.0, rc))
+    pos = np.ascontiguousarray(np.tile([[1.2, 1.2, 1.2]], (natoms, 1)))
+    dH = np.zeros((natoms, 1, 1))
+    dS = np.zeros((natoms, 1, 1))
+    v = np.zeros(n)
+    dp = ctypes.POINTER(ctypes.c_double)
+    d = SysDesc()
+    d.n[:] = n
+    d.h[:] = (h, h, h)
+    d.dtype = 0
+    d.natoms = natoms
+    d.pos = pos.ctypes.data_as(dp)
+    d.nchan = 1
+    d.chan = chans
+    d.dH = dH.ctypes.data_as(dp)
+    d.dS = dS.ctypes.data_as(dp)
+    d.v = v.ctypes.data_as(dp)
+    d.max_bands = 1
+    return d, (chans, pos, dH, dS, v)
+
+
+def test_too_many_entries_at_one_point_is_rejected_on_the_host(lib):
+    # 256 spheres through one grid point exceed the 8-bit per-point count;
+    # the check runs while the tables are built on the host, before any
+    # device call, so it holds without a GPU
+    d, keep = _atoms_desc(256)
+    out = ctypes.c_void_p()
+    assert lib.gpaw_sys_create(ctypes.byref(d), ctypes.byref(out)) == -1
+    assert b"255 projector entries" in lib.gpaw_last_error()
+    assert out.value is None
+
+
+def test_counts_above_127_pass_the_host_table_check(lib):
+    # 200 entries per point used to wrap through a signed shift; the host
+    # check must accept it (with no GPU the call then stops at the device)
+    d, keep = _atoms_desc(200)
+    out = ctypes.c_void_p()
+    rc = lib.gpaw_sys_create(ctypes.byref(d), ctypes.byref(out))
+    if rc != 0:
+        assert b"255 projector entries" not in lib.gpaw_last_error()
+    else:
+        lib.gpaw_sys_destroy(out)

@@ -149,3 +149,31 @@ def test_rotated_block_is_orthonormal_and_diagonal(k):
     assert np.abs(H1 - np.diag(r["eps"])).max() < 1e-12 * np.abs(r["eps"]).max()
     # rotated projections are the projections of the rotated block
     assert np.abs(r["P_rot"] - ops.project(p)).max() < 1e-12 * np.abs(r["P_rot"]).max()
+
+
+def _gram_schmidt_S(psi, ops):
+    """Classical Gram-Schmidt in the S~ inner product, one band at a time
+    (pure Python loop over bands; S~ applied by the oracle operator)."""
+    out = []
+    for n in range(psi.shape[0]):
+        v = psi[n].astype(complex if np.iscomplexobj(psi) else float)
+        for u in out:
+            v = v - ops.dV * np.vdot(u, ops.apply_S(v[None])[0]) * u
+        nrm = np.sqrt(ops.dV * np.vdot(v, ops.apply_S(v[None])[0]).real)
+        out.append(v / nrm)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("k", [(0.0, 0.0, 0.0), (0.25, 0.0, 0.5)])
+def test_orthonormalize_is_gram_schmidt_in_the_overlap(k):
+    """The Cholesky correction equals Gram-Schmidt in the S~ inner product
+    (both give the unique S~-orthonormal block whose band n lies in the span
+    of bands 0..n with a positive coefficient on band n)."""
+    s = synth.make_system(n=(10, 12, 9), h=0.22, nb=7, natoms=2, rc=1.5, seed=77, k=k)
+    ops = oracle.Operators.from_system(s)
+    psi = s.psi.reshape(s.nb, -1)
+    got = oracle.orthonormalize(psi, ops.apply_S(psi), ops.dV)
+    want = _gram_schmidt_S(psi, ops)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    S1 = oracle.subspace_matrices(got, ops.apply_H(got), ops.apply_S(got), ops.dV)[1]
+    assert np.abs(S1 - np.eye(s.nb)).max() <= 1e-12

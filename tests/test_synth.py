@@ -46,13 +46,36 @@ def test_smooth_bands_satisfy_bloch_condition(k):
 def test_smooth_bands_scale_and_ritz_range():
     s = synth.make_system(n=(20, 20, 20), h=0.2, nb=8, natoms=2, rc=2.0, seed=3, bands="smooth")
     assert np.isrealobj(s.psi)
-    assert abs(np.sqrt(np.mean(s.psi ** 2)) - 1 / np.sqrt(3)) < 1e-12
+    for b in s.psi:
+        assert abs(np.sqrt(np.mean(b ** 2)) - 1 / np.sqrt(3)) < 1e-12
     ref = oracle.fd_step(s)
     assert ref["eps"].max() < 10.0 and ref["eps"].min() > -10.0
 
 
-def test_noise_bands_unchanged_by_default():
-    a = synth.make_system(n=(8, 8, 8), h=0.2, nb=2, natoms=1, rc=1.0, seed=5)
-    rng = np.random.default_rng(5)
-    rng.random((1, 3)); rng.uniform(-1, 1, (1, 13, 13)); rng.uniform(-1, 1, (1, 13, 13))
-    assert np.array_equal(a.psi, rng.uniform(-1.0, 1.0, (2, 8, 8, 8)))
+@pytest.mark.parametrize("k,bands", [((0.0, 0.0, 0.0), "noise"), ((0.25, 0.0, 0.5), "noise"),
+                                     ((0.25, 0.0, 0.5), "smooth")])
+def test_bands_regenerate_alone_and_lazily(k, bands):
+    """Every band comes from its own stream: the materialised block, a lazy
+    block's band ranges and single bands regenerated out of order agree
+    exactly, whatever the thread count."""
+    cfg = dict(n=(9, 8, 10), h=0.2, nb=7, natoms=2, rc=1.0, seed=11, k=k, bands=bands)
+    full = synth.make_system(**cfg)
+    lazy = synth.make_system(lazy=True, **cfg)
+    assert lazy.psi is None and lazy.nb == 7 and lazy.is_complex == full.is_complex
+    assert np.array_equal(lazy.bands(0, 7, threads=1), full.psi)
+    assert np.array_equal(lazy.bands(2, 5, threads=3), full.psi[2:5])
+    assert np.array_equal(lazy.band_list([6, 0, 3]), full.psi[[6, 0, 3]])
+    # positions, corrections and potential do not depend on how bands are made
+    assert np.array_equal(lazy.pos, full.pos) and np.array_equal(lazy.dH, full.dH)
+    assert np.array_equal(lazy.v, full.v)
+
+
+def test_noise_bands_are_uniform_and_independent():
+    s = synth.make_system(n=(16, 16, 16), h=0.2, nb=4, natoms=0, rc=1.0, seed=5,
+                          k=(0.25, 0.0, 0.0))
+    x = s.psi.reshape(4, -1)
+    for part in (x.real, x.imag):
+        assert part.min() >= -1.0 and part.max() < 1.0
+        assert abs(part.mean()) < 0.02 and abs(part.var() - 1.0 / 3.0) < 0.01
+    c = np.corrcoef(np.vstack([x.real, x.imag]))
+    assert np.abs(c - np.eye(8)).max() < 0.07  # ~4.5 sigma for 4096 samples
