@@ -26,6 +26,7 @@ from .subspace import (subspace_matrices, hermiticity_defect, diagonalize,
                        rotate, orthonormalize)
 from .step import Operators, fd_step
 from .density import pseudo_density, atomic_density_matrices, paw_norm
+from .davidson import kinetic_diagonal, precondition, davidson_step
 
 __all__ = ["WEIGHTS", "laplacian", "kinetic", "symbol_1d", "radial_norm",
            "solid_harmonics", "projector_values", "projector_matrix",
@@ -33,4 +34,5 @@ __all__ = ["WEIGHTS", "laplacian", "kinetic", "symbol_1d", "radial_norm",
            "project", "addback", "apply_H", "apply_S", "block_diag_atoms",
            "subspace_matrices", "hermiticity_defect", "diagonalize", "rotate",
            "orthonormalize",
-           "Operators", "fd_step", "pseudo_density", "atomic_density_matrices", "paw_norm"]
+           "Operators", "fd_step", "pseudo_density", "atomic_density_matrices", "paw_norm",
+           "kinetic_diagonal", "precondition", "davidson_step"]
