@@ -51,7 +51,7 @@ def parse():
 PART_KERNELS = {
     "project": (["k_project"], ["csrc/nonlocal.hip", "csrc/proj.h"]),
     # H~psi and S~psi in one pass: Delta H.P and Delta S.P (one launch), then the stencil
-    "apply_HS": (["k_dmat2", "k_stencil"],
+    "apply_HS": (["k_dmat2", "k_plane"],
                  ["csrc/stencil.hip", "csrc/nonlocal.hip", "csrc/proj.h"]),
     "subspace": (["k_subspace", "k_subspace_reduce"], ["csrc/gemm.hip"]),
     # the block and its projections
@@ -215,6 +215,27 @@ def tune(g, psi, stream):
     return t
 
 
+def measured_peaks(dev, stream):
+    """Achievable ceilings of this device from the library's probes: a 16-byte
+    copy over 2 x 4 GiB buffers (HBM bytes moved = 2 x size) and matrix-core
+    loops of independent FP64 and BF16 products (8 workgroups per CU)."""
+    import torch
+    import paper_2310_14776_amd as gfd
+    nbytes = 4 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    copy_ms = timed(lambda: gfd.probe_copy(a, b, stream=stream), stream, 10, 2)
+    del a, b
+    wgs, out = 2048, {}
+    for kind, name, flops, iters, dt in ((0, "fp64_mfma_TFLOPs", 2048, 4000, torch.float64),
+                                         (1, "bf16_mfma_TFLOPs", 16384, 4000, torch.float32)):
+        buf = torch.empty(wgs * 256, dtype=dt, device=dev)
+        ms = timed(lambda: gfd.probe_mfma(kind, buf, wgs, iters, stream=stream), stream, 5, 1)
+        out[name] = round(wgs * 4 * iters * 8 * flops / (ms * 1e-3) / 1e12, 1)
+    out["hbm_copy_GBs"] = round(2 * nbytes / (copy_ms * 1e-3) / 1e9, 1)
+    return out
+
+
 def part_costs(s, info, es):
     """Algorithmic bytes and flops per launch of each part (es = bytes per
     element of the block; complex flops are four real ones per product)."""
@@ -237,9 +258,10 @@ def part_costs(s, info, es):
     }
 
 
-def roofline(part_ms, costs, tag):
+def roofline(part_ms, costs, tag, peaks=None):
     """Roofline object of the costliest part with a bandwidth or matrix-core
-    bound (FP64 MFMA for the contractions, HBM otherwise)."""
+    bound (FP64 MFMA for the contractions, HBM otherwise); with measured
+    ceilings, also the fraction of those."""
     dom = max((n for n in part_ms if n in costs and (costs[n]["bytes"] or costs[n]["flops"])),
               key=part_ms.get)
     c = costs[dom]
@@ -256,6 +278,10 @@ def roofline(part_ms, costs, tag):
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
     roof["kernel"] = " + ".join(PART_KERNELS[dom][0])
     roof["traffic"] = measured_traffic(dom, tag)
+    if peaks:
+        mp = peaks["fp64_mfma_TFLOPs"] if roof["bound"] == "mfma" else peaks["hbm_copy_GBs"]
+        roof["measured_peak"] = mp
+        roof["frac_of_measured"] = round(roof["achieved"] / mp, 4)
     return roof
 
 
@@ -270,7 +296,7 @@ def part_rows(part_ms, costs):
     return rows
 
 
-def run_config(name, steps, warmup, dev, stream, single_inputs=False, do_tune=None):
+def run_config(name, steps, warmup, dev, stream, single_inputs=False, do_tune=True, peaks=None):
     """FP64 step of one workload. Returns (result dict, system, step)."""
     import torch
     import synth
@@ -288,9 +314,7 @@ def run_config(name, steps, warmup, dev, stream, single_inputs=False, do_tune=No
         low = None
         psi = synth.block_to_device(s, dev, dtype=g.dtype)
     es = psi.element_size()
-    if do_tune is None:
-        do_tune = s.nb * s.ng * es < (8 << 30)
-    tuning = tune(g, psi, stream) if do_tune else "heuristic (the tuner runs below 8 GiB blocks)"
+    tuning = tune(g, psi, stream) if do_tune else "heuristic"
     step = Step(g, psi, stream)
     say(f"[bench] {name}: timing {steps} steps")
     ms, part_ms, wall = time_parts(step, steps, warmup)
@@ -298,7 +322,7 @@ def run_config(name, steps, warmup, dev, stream, single_inputs=False, do_tune=No
     res = dict(ms_per_step=ms, value=s.nb * s.ng / (ms * 1e-3), wall_s=wall,
                workload=workload_label(s), dtype="c128" if s.is_complex else "f64",
                parts=part_rows(part_ms, costs), launch_tuning=tuning,
-               roofline=roofline(part_ms, costs, f"{s.n[0]}x{s.n[1]}x{s.n[2]}_nb{s.nb}"))
+               roofline=roofline(part_ms, costs, f"{s.n[0]}x{s.n[1]}x{s.n[2]}_nb{s.nb}", peaks))
     return res, s, step, low
 
 
@@ -429,8 +453,10 @@ def main():
     stream = torch.cuda.current_stream()
     forms = not args.no_forms
 
+    say("[bench] measured ceilings (copy and matrix-core probes)")
+    peaks = measured_peaks(dev, stream)
     res, s, step, low = run_config(args.config, args.steps, args.warmup, dev, stream,
-                                   single_inputs=forms)
+                                   single_inputs=forms, peaks=peaks)
     out = {
         "metric": "band*gridpoints/s for H|psi>+subspace step",
         "value": res["value"],
@@ -451,6 +477,7 @@ def main():
         "parts": res["parts"],
         "launch_tuning": res["launch_tuning"],
         "roofline": res["roofline"],
+        "measured_peaks": peaks,
     }
     fp64_ms = res["ms_per_step"]
     # the FP64 step ran on the rounded block: its eps, H and S are the error
@@ -479,7 +506,7 @@ def main():
         for name in ("B", "C"):
             if name == args.config:
                 continue
-            r, _, st, _ = run_config(name, max(5, args.steps), 2, dev, stream)
+            r, _, st, _ = run_config(name, max(5, args.steps), 2, dev, stream, peaks=peaks)
             st.g.close()
             del st
             torch.cuda.empty_cache()

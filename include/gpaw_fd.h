@@ -150,12 +150,16 @@ GPAW_API int gpaw_fd_apply_HS(gpaw_sys *sys, const void *psi, int32_t nb, const 
 
 /* Subspace matrices of SCF step (1) (Sec. "Solving the Kohn-Sham equation"):
  * H_nm = dV sum_r conj(psi_n(r)) Hpsi_m(r), S_nm likewise with Spsi, both
- * [nb][nb], full (not symmetrised), summed in a fixed order (bitwise
- * reproducible). Spsi may be NULL: then only H_nn is formed and S_nn is
- * ignored. */
+ * [nb][nb], summed in a fixed order (bitwise reproducible). H_nm and S_nm
+ * are Hermitian for the operators of Eq. (dh), and the call relies on it:
+ * it forms the 64 x 64 (real) / 32 x 32 (complex) tiles on and above the
+ * diagonal (diagonal tiles in full) and writes the conjugates of the formed
+ * tiles below them. It is not a general product of two unrelated blocks.
+ * Spsi may be NULL: then only H_nn is formed and S_nn is ignored. */
 GPAW_API int gpaw_subspace_matrices(gpaw_sys *sys, const void *psi, const void *Hpsi,
                            const void *Spsi, int32_t nb, void *H_nn, void *S_nn,
                            void *stream);
+
 
 /* Generalised Hermitian eigenproblem of the subspace (Cholesky of S_nm and
  * diagonalisation, Sec. "Parallelization"), all in double precision on the
@@ -172,11 +176,53 @@ GPAW_API int gpaw_subspace_matrices(gpaw_sys *sys, const void *psi, const void *
 GPAW_API int gpaw_subspace_diag(gpaw_sys *sys, const void *H_nn, const void *S_nn, int32_t nb,
                        double *eps, void *C_nn, int32_t *info, void *stream);
 
+/* Densities of SCF steps (3)-(4) (Sec. "Solving the Kohn-Sham equation"):
+ * the pseudo density n~(r) = sum_n f_n |psi~_n(r)|^2 into n_out (device
+ * [Ng] FP64, real), and the atomic density matrices of
+ * Eq. (atomicdensitymatrix), D^a_ii' = sum_n f_n <psi~_n|p~^a_i>
+ * <p~^a_i'|psi~_n> = sum_n f_n conj(P[n][a ni + i]) P[n][a ni + i'], into
+ * D_nn (device [natoms][ni][ni], FP64 for real systems, complex128 for
+ * complex ones, also in the precision form). f: device [nb] FP64
+ * occupation numbers. P: the block's projections ([nb][Np], the block's
+ * dtype) or NULL, in which case they are computed into workspace when D_nn
+ * is requested. Either output may be NULL (not both). Sums run over bands
+ * in a fixed order, in FP64. Enqueues on `stream`. */
+GPAW_API int gpaw_density(gpaw_sys *sys, const void *psi, int32_t nb, const double *f,
+                          const void *P, double *n_out, void *D_nn, void *stream);
+
 /* Rotation of SCF step (1): psi_out_n = sum_m C_mn psi_m (psi_out = C^T psi),
  * and, when P and P_out are both non-NULL, P_out = C^T P (the projections of
  * the rotated block). psi_out must not overlap psi, nor P_out P. */
 GPAW_API int gpaw_rotate(gpaw_sys *sys, const void *psi, const void *C_nn, int32_t nb,
                 void *psi_out, const void *P, void *P_out, void *stream);
+
+/* Davidson corrections (SCF step (2), Sec. "Solving the Kohn-Sham
+ * equation"; the iterative Davidson eigensolver named in Sec.
+ * "Parallelization"; the paper gives no formulas, this is the textbook
+ * block Davidson update with a diagonal preconditioner):
+ *   out_n(r) = -(Hpsi_n - eps_n Spsi_n)(r) / max(t0 + v(r) - eps_n, t0/2),
+ * t0 = (1/2)(49/18) sum_c 1/h_c^2 (the diagonal of the FD kinetic
+ * operator). Hpsi, Spsi, out: [nb][Ng] in the system dtype; eps: device
+ * [nb] FP64. out must not overlap Hpsi or Spsi. Enqueues on `stream`. */
+GPAW_API int gpaw_davidson_correction(gpaw_sys *sys, const void *Hpsi, const void *Spsi,
+                                      const double *eps, int32_t nb, void *out, void *stream);
+
+/* One block Davidson step (FP64 and complex128 systems): from Ritz vectors
+ * psi (rows 0..nb-1 of x, with H~psi, S~psi in rows 0..nb-1 of Hx, Sx,
+ * their projections in rows 0..nb-1 of Px, and Ritz values eps, e.g. the
+ * output of one subspace step), the corrections of
+ * gpaw_davidson_correction are written to rows nb..2nb-1 of x, their
+ * projections, H~ and S~ to rows nb..2nb-1 of Px, Hx, Sx; then the
+ * Rayleigh-Ritz step on the 2nb block: H2, S2 ([2nb][2nb] subspace
+ * matrices), eps2 ([2nb] ascending) and C2 ([2nb][2nb], C2^H S2 C2 = I),
+ * and psi_out_n = sum_m C2_mn x_m, P_out_n = sum_m C2_mn Px_m for n < nb
+ * (the lowest nb Ritz vectors). Needs 2 nb <= max_bands and 2 nb <= 1024.
+ * x, Hx, Sx: [2nb][Ng]; Px, P_out: [2nb][Np], [nb][Np] (NULL without
+ * atoms); psi_out: [nb][Ng]. info as for gpaw_subspace_diag. No Ritz value
+ * rises in a step (the new span contains the old block). */
+GPAW_API int gpaw_davidson_step(gpaw_sys *sys, int32_t nb, void *x, void *Hx, void *Sx, void *Px,
+                                const double *eps, void *H2, void *S2, void *C2, double *eps2,
+                                void *psi_out, void *P_out, int32_t *info, void *stream);
 
 /* Orthonormality correction of a rotated block: S' = dV psi^H Spsi (Spsi =
  * S~ psi, e.g. the rotated S~psi, since S~ is linear), S' = L L^H in FP64 on
@@ -230,17 +276,18 @@ GPAW_API void gpaw_batch_destroy(gpaw_batch *b);
 GPAW_API int gpaw_batch_step(gpaw_batch *b, const gpaw_batch_io *io, int32_t *info, void *stream);
 
 /* Autotuner (synchronous, runs on the batch's own stream and overwrites the
- * io outputs): times the launch-shape choices of every system (bands per
- * lane and x segments of the stencil, split-K width of the subspace product,
+ * io outputs): times the launch-shape choices of every system (points per
+ * lane, y-z tile and x segments of the stencil, split-K width of the subspace product,
  * row tiles of the rotation, bands per projection workgroup) and then the
  * number of graph branches (1..16), keeps the fastest of each and records
  * the graph for io. Results change only in the order of floating-point sums. */
 GPAW_API int gpaw_batch_tune(gpaw_batch *b, const gpaw_batch_io *io, int32_t *info);
 
-/* Chosen shapes: out[0] = graph branches, then per system 5 values
- * (stencil bands per lane, stencil x segments, subspace workgroup target,
- * rotation row tiles, projection bands per workgroup; 0 = built-in choice).
- * out holds 1 + 5 nsys int32 (host). */
+/* Chosen shapes: out[0] = graph branches, then per system 7 values
+ * (stencil points per lane, stencil tile rows, stencil tile columns,
+ * stencil x segments, subspace workgroup target, rotation row tiles,
+ * projection bands per workgroup; 0 = built-in choice). out holds
+ * 1 + 7 nsys int32 (host). */
 GPAW_API int gpaw_batch_tuning(const gpaw_batch *b, int32_t *out);
 
 /* Message for the calling host thread's last non-zero return ("" if none). */
@@ -248,6 +295,20 @@ GPAW_API const char *gpaw_last_error(void);
 
 /* GPAW_FD_VERSION of the built library. */
 GPAW_API int gpaw_version(void);
+
+/* Measurement probes (they compute nothing of the method): the ceilings the
+ * roofline fractions are also stated against, timed by the caller.
+ * gpaw_probe_copy: dst = src over `bytes` (a multiple of 16; both device
+ * buffers 16-byte aligned, not overlapping), 16-byte loads and stores
+ * (moves 2 x bytes through HBM). gpaw_probe_mfma: `workgroups` x 4
+ * wavefronts, each running `iters` rounds of 8 independent matrix-core
+ * products: kind 0 = FP64 v_mfma_f64_16x16x4 (2048 flops each), kind 1 =
+ * BF16 v_mfma_f32_16x16x32 (16384 flops each); writes one value per lane to
+ * out (workgroups x 256 doubles for kind 0, floats for kind 1). Both only
+ * enqueue on `stream`. */
+GPAW_API int gpaw_probe_copy(const void *src, void *dst, int64_t bytes, void *stream);
+GPAW_API int gpaw_probe_mfma(int32_t kind, void *out, int32_t workgroups, int32_t iters,
+                             void *stream);
 
 #ifdef __cplusplus
 }

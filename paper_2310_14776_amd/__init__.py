@@ -6,7 +6,7 @@ products) and a batched form (many systems in one graph launch) use the same
 calls.
 """
 from ._binding import (System, Batch, GpawError, load, library_path, ENTRY_POINTS,
-                       GPAW_F64, GPAW_C128, GPAW_F32, GPAW_C64)
+                       GPAW_F64, GPAW_C128, GPAW_F32, GPAW_C64, probe_copy, probe_mfma)
 
 __all__ = ["System", "Batch", "GpawError", "load", "library_path", "ENTRY_POINTS",
-           "GPAW_F64", "GPAW_C128", "GPAW_F32", "GPAW_C64"]
+           "GPAW_F64", "GPAW_C128", "GPAW_F32", "GPAW_C64", "probe_copy", "probe_mfma"]

@@ -44,10 +44,12 @@ _lib = None
 
 ENTRY_POINTS = ["gpaw_sys_create", "gpaw_sys_destroy", "gpaw_sys_info", "gpaw_project",
                 "gpaw_fd_apply_H", "gpaw_fd_apply_S", "gpaw_fd_apply_HS", "gpaw_subspace_matrices",
+                "gpaw_density",
+                "gpaw_davidson_correction", "gpaw_davidson_step",
                 "gpaw_subspace_diag", "gpaw_rotate", "gpaw_orthonormalize",
                 "gpaw_batch_create", "gpaw_batch_destroy", "gpaw_batch_step",
                 "gpaw_batch_tune", "gpaw_batch_tuning",
-                "gpaw_last_error", "gpaw_version"]
+                "gpaw_last_error", "gpaw_version", "gpaw_probe_copy", "gpaw_probe_mfma"]
 
 
 class BatchIO(ctypes.Structure):
@@ -78,6 +80,12 @@ def load():
     lib.gpaw_fd_apply_S.argtypes = [vp, vp, i32, vp, vp, vp]
     lib.gpaw_fd_apply_HS.argtypes = [vp, vp, i32, vp, vp, vp, vp]
     lib.gpaw_subspace_matrices.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
+    lib.gpaw_probe_copy.argtypes = [vp, vp, ctypes.c_int64, vp]
+    lib.gpaw_density.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
+    lib.gpaw_davidson_correction.argtypes = [vp, vp, vp, vp, i32, vp, vp]
+    lib.gpaw_davidson_step.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                       vp]
+    lib.gpaw_probe_mfma.argtypes = [i32, vp, i32, i32, vp]
     lib.gpaw_subspace_diag.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
     lib.gpaw_rotate.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
     lib.gpaw_orthonormalize.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp]
@@ -169,6 +177,8 @@ class System:
         self.info = dict(ng=info[0], np=info[1], ni=info[2], natoms=info[3], entries=info[4],
                          covered=info[5], max_bands=info[6], dtype=info[7])
         self.np = int(info[1])
+        self.ni = int(info[2])
+        self.natoms = int(info[3])
         self.max_bands = int(max_bands)
         self.device = torch.device("cuda", torch.cuda.current_device())
 
@@ -235,6 +245,47 @@ class System:
         _check(load().gpaw_subspace_matrices(self._h, _ptr(psi), _ptr(Hpsi), _ptr(Spsi), nb,
                                              _ptr(H), _ptr(S), _stream(stream)))
         return H, S
+
+    def density(self, psi, f, P=None, n_out=None, D=None, want_D=True, stream=None):
+        """Pseudo density [Ng] (float64) and atomic density matrices
+        [natoms][ni][ni] (mat dtype) of the block with occupations f."""
+        nb = self._nb(psi)
+        if f.dtype != torch.float64 or f.numel() != nb:
+            raise ValueError("f must be a float64 tensor of nb occupations")
+        n_out = self._new(self.ng, dtype=torch.float64) if n_out is None else n_out
+        if D is None and want_D and self.natoms > 0:
+            D = self._new(self.natoms, self.ni, self.ni, dtype=self.mat_dtype)
+        _check(load().gpaw_density(self._h, _ptr(psi), nb, _ptr(f), _ptr(P), _ptr(n_out),
+                                   _ptr(D), _stream(stream)))
+        return n_out, D
+
+    def davidson_correction(self, Hpsi, Spsi, eps, out=None, stream=None):
+        nb = self._nb(Hpsi)
+        out = torch.empty_like(Hpsi) if out is None else out
+        _check(load().gpaw_davidson_correction(self._h, _ptr(Hpsi), _ptr(Spsi), _ptr(eps), nb,
+                                               _ptr(out), _stream(stream)))
+        return out
+
+    def davidson_step(self, x, Hx, Sx, Px, eps, out=None, info=None, stream=None):
+        """One block Davidson step; x, Hx, Sx: [2nb][Ng] with the Ritz block in
+        rows 0..nb-1 (rows nb.. are overwritten), Px [2nb][Np] likewise, eps
+        [nb]. Returns dict(psi, P, eps (the lowest nb of eps2), eps2, H2, S2, C2)."""
+        n2 = self._nb(x)
+        if n2 % 2:
+            raise ValueError("x must hold 2 nb bands")
+        nb = n2 // 2
+        o = out or {}
+        psi = o.get("psi", self._new(nb, self.ng))
+        P = o.get("P", self._new(nb, self.np)) if self.np else None
+        H2 = o.get("H2", self._new(n2, n2, dtype=self.mat_dtype))
+        S2 = o.get("S2", self._new(n2, n2, dtype=self.mat_dtype))
+        C2 = o.get("C2", self._new(n2, n2, dtype=self.mat_dtype))
+        e2 = o.get("eps2", self._new(n2, dtype=torch.float64))
+        _check(load().gpaw_davidson_step(self._h, nb, _ptr(x), _ptr(Hx), _ptr(Sx),
+                                         _ptr(Px) if self.np else None, _ptr(eps), _ptr(H2),
+                                         _ptr(S2), _ptr(C2), _ptr(e2), _ptr(psi), _ptr(P),
+                                         _ptr(info), _stream(stream)))
+        return dict(psi=psi, P=P, eps=e2[:nb], eps2=e2, H2=H2, S2=S2, C2=C2)
 
     def subspace_diag(self, H, S, eps=None, C=None, info=None, stream=None):
         nb = H.shape[0]
@@ -320,7 +371,23 @@ class Batch:
 
     def tuning(self):
         n = len(self.systems)
-        out = (ctypes.c_int32 * (1 + 5 * n))()
+        out = (ctypes.c_int32 * (1 + 7 * n))()
         _check(load().gpaw_batch_tuning(self._h, out))
-        keys = ("stencil_nb", "stencil_xseg", "subspace_wgs", "rotate_rb", "project_nbg")
-        return int(out[0]), [dict(zip(keys, out[1 + 5 * i: 6 + 5 * i])) for i in range(n)]
+        keys = ("stencil_ppl", "stencil_ty", "stencil_tz", "stencil_xseg", "subspace_wgs",
+                "rotate_rb", "project_nbg")
+        return int(out[0]), [dict(zip(keys, out[1 + 7 * i: 8 + 7 * i])) for i in range(n)]
+
+
+def probe_copy(src, dst, stream=None):
+    """gpaw_probe_copy: dst = src (device tensors of equal byte size)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst must have the same size")
+    _check(load().gpaw_probe_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)))
+
+
+def probe_mfma(kind, out, workgroups, iters, stream=None):
+    """gpaw_probe_mfma: kind 0 FP64 (out float64), 1 BF16 (out float32)."""
+    if out.numel() < workgroups * 256:
+        raise ValueError("out needs workgroups x 256 values")
+    _check(load().gpaw_probe_mfma(kind, _ptr(out), workgroups, iters, _stream(stream)))

@@ -324,6 +324,31 @@ int gpaw_subspace_matrices(gpaw_sys *s, const void *psi, const void *Hpsi, const
   return after_launch("gpaw_subspace_matrices");
 }
 
+int gpaw_density(gpaw_sys *s, const void *psi, int32_t nb, const double *f, const void *P,
+                 double *n_out, void *D_out, void *stream) {
+  int rc;
+  if ((rc = check_sys(s)) != GPAW_OK) return rc;
+  if ((rc = check_nb(s, nb)) != GPAW_OK) return rc;
+  if (!psi || !f) return fail(GPAW_EINVAL, "psi and f must not be NULL");
+  if (!n_out && !D_out) return fail(GPAW_EINVAL, "one of n_out and D_nn must be given");
+  const size_t es = elem_size(s->dtype);
+  const size_t bytes = static_cast<size_t>(nb) * s->ng * es;
+  const size_t dbytes =
+      static_cast<size_t>(s->natoms) * s->ni * s->ni * mat_elem_size(s->dtype);
+  if (n_out && (overlaps(n_out, s->ng * 8, psi, bytes) || overlaps(n_out, s->ng * 8, f, nb * 8)))
+    return fail(GPAW_EALIAS, "n_out overlaps an input");
+  if (D_out && dbytes && (overlaps(D_out, dbytes, f, nb * 8) ||
+                          (n_out && overlaps(D_out, dbytes, n_out, s->ng * 8))))
+    return fail(GPAW_EALIAS, "D_out overlaps another buffer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (D_out && s->np > 0 && !P) {
+    if ((rc = launch_project(s, psi, nb, s->ws.P, st)) != GPAW_OK) return rc;
+    P = s->ws.P;
+  }
+  if ((rc = launch_density(s, psi, nb, f, P, n_out, D_out, st)) != GPAW_OK) return rc;
+  return after_launch("gpaw_density");
+}
+
 int gpaw_subspace_diag(gpaw_sys *s, const void *H, const void *S, int32_t nb, double *eps,
                        void *C, int32_t *info, void *stream) {
   int rc;
@@ -347,6 +372,83 @@ int gpaw_subspace_diag(gpaw_sys *s, const void *H, const void *S, int32_t nb, do
   if (h_info > 0)
     return fail(GPAW_ENOTPD, "S_nm is not positive definite (leading minor " +
                                  std::to_string(h_info) + ")");
+  if (h_info < 0) return fail(GPAW_ENOCONV, "eigenvector orthogonalisation did not settle");
+  return GPAW_OK;
+}
+
+int gpaw_davidson_correction(gpaw_sys *s, const void *Hpsi, const void *Spsi, const double *eps,
+                              int32_t nb, void *out, void *stream) {
+  int rc;
+  if ((rc = check_sys(s)) != GPAW_OK) return rc;
+  if ((rc = check_nb(s, nb)) != GPAW_OK) return rc;
+  if (!Hpsi || !Spsi || !eps || !out)
+    return fail(GPAW_EINVAL, "Hpsi, Spsi, eps and out must not be NULL");
+  const size_t bytes = static_cast<size_t>(nb) * s->ng * elem_size(s->dtype);
+  if (overlaps(out, bytes, Hpsi, bytes) || overlaps(out, bytes, Spsi, bytes))
+    return fail(GPAW_EALIAS, "out overlaps Hpsi or Spsi");
+  if ((rc = launch_precond(s, Hpsi, Spsi, eps, nb, out, static_cast<hipStream_t>(stream))) !=
+      GPAW_OK)
+    return rc;
+  return after_launch("gpaw_davidson_correction");
+}
+
+int gpaw_davidson_step(gpaw_sys *s, int32_t nb, void *x, void *Hx, void *Sx, void *Px,
+                       const double *eps, void *H2, void *S2, void *C2, double *eps2,
+                       void *psi_out, void *P_out, int32_t *info, void *stream) {
+  int rc;
+  if ((rc = check_sys(s)) != GPAW_OK) return rc;
+  if (s->dtype != GPAW_F64 && s->dtype != GPAW_C128)
+    return fail(GPAW_EDTYPE, "gpaw_davidson_step runs on FP64 and complex128 systems");
+  if (nb < 1 || 2 * nb > s->max_bands || 2 * nb > 1024)
+    return fail(GPAW_ESHAPE, "gpaw_davidson_step needs 1 <= nb, 2 nb <= max_bands and <= 1024");
+  if (!x || !Hx || !Sx || !eps || !H2 || !S2 || !C2 || !eps2 || !psi_out)
+    return fail(GPAW_EINVAL, "x, Hx, Sx, eps, H2, S2, C2, eps2 and psi_out must not be NULL");
+  if (s->np > 0 && (!Px || !P_out))
+    return fail(GPAW_EINVAL, "Px and P_out must be given when the system has atoms");
+  const size_t es = elem_size(s->dtype);
+  const size_t row = static_cast<size_t>(s->ng) * es, prow = static_cast<size_t>(s->np) * es;
+  const size_t xbytes = 2 * nb * row, obytes = nb * row;
+  const size_t m2 = static_cast<size_t>(2 * nb) * (2 * nb) * mat_elem_size(s->dtype);
+  if (overlaps(x, xbytes, Hx, xbytes) || overlaps(x, xbytes, Sx, xbytes) ||
+      overlaps(Hx, xbytes, Sx, xbytes) || overlaps(psi_out, obytes, x, xbytes) ||
+      overlaps(H2, m2, S2, m2) || overlaps(C2, m2, H2, m2) || overlaps(C2, m2, S2, m2) ||
+      overlaps(eps2, 16 * nb, C2, m2))
+    return fail(GPAW_EALIAS, "buffers of gpaw_davidson_step overlap");
+  if (s->np > 0 && overlaps(P_out, nb * prow, Px, 2 * nb * prow))
+    return fail(GPAW_EALIAS, "P_out overlaps Px");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char *xd = static_cast<char *>(x) + nb * row;
+  char *Hd = static_cast<char *>(Hx) + nb * row;
+  char *Sd = static_cast<char *>(Sx) + nb * row;
+  // corrections of the first nb rows into the last nb rows of x
+  if ((rc = launch_precond(s, Hx, Sx, eps, nb, xd, st)) != GPAW_OK) return rc;
+  // H~ and S~ of the corrections (their projections into the rows of Px)
+  const void *X = nullptr, *XS = nullptr;
+  if (s->np > 0) {
+    char *Pd = static_cast<char *>(Px) + nb * prow;
+    if ((rc = launch_project(s, xd, nb, Pd, st)) != GPAW_OK) return rc;
+    if ((rc = launch_dmat2(s, Pd, nb, s->ws.X, s->ws.XS, st)) != GPAW_OK) return rc;
+    X = s->ws.X;
+    XS = s->ws.XS;
+  }
+  if ((rc = launch_stencil(s, xd, nb, X, Hd, st, XS, Sd)) != GPAW_OK) return rc;
+  // Rayleigh-Ritz on the 2 nb block
+  if ((rc = launch_subspace(s, x, Hx, Sx, 2 * nb, H2, S2, st)) != GPAW_OK) return rc;
+  int32_t *dinfo = info ? info : s->ws.info;
+  if ((rc = launch_eigh(s, H2, S2, 2 * nb, eps2, C2, dinfo, st)) != GPAW_OK) return rc;
+  if ((rc = launch_rotate(s, C2, x, 2 * nb, s->ng, psi_out, st, false, false, nb)) != GPAW_OK)
+    return rc;
+  if (s->np > 0)
+    if ((rc = launch_rotate(s, C2, Px, 2 * nb, s->np, P_out, st, false, false, nb)) != GPAW_OK)
+      return rc;
+  if ((rc = after_launch("gpaw_davidson_step")) != GPAW_OK) return rc;
+  if (info) return GPAW_OK;
+  int32_t h_info = 0;
+  GFD_HIP(hipMemcpyAsync(&h_info, dinfo, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  GFD_HIP(hipStreamSynchronize(st));
+  if (h_info > 0)
+    return fail(GPAW_ENOTPD, "the extended overlap matrix is not positive definite (leading "
+                             "minor " + std::to_string(h_info) + ")");
   if (h_info < 0) return fail(GPAW_ENOCONV, "eigenvector orthogonalisation did not settle");
   return GPAW_OK;
 }

@@ -11,6 +11,7 @@
 // and short kernels instead of running back to back. The autotuner times the
 // launch-shape choices of every system and the number of branches.
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -272,12 +273,31 @@ int tune_system(gpaw_batch *b, size_t i, const gpaw_batch_io &io, int32_t *info,
   if (s->np > 0)
     if ((rc = launch_dmat2(s, w.P, nb, s->ws.X, s->ws.XS, st)) != GPAW_OK) return rc;
   auto stencil = [&] { return launch_stencil(s, io.psi, nb, X, w.Hpsi, st, XS, w.Spsi); };
-  if ((rc = pick(&s->tune.st_nb, cplx ? std::vector<int>{1, 2} : std::vector<int>{2, 4}, stencil,
-                 st)) != GPAW_OK)
-    return rc;
+  {
+    // points per lane 1 or 2, each with its cheapest tiles by the cost
+    // model, timed together
+    std::vector<std::array<int, 3>> shapes;
+    for (int ppl : {1, 2}) {
+      s->tune.st_ppl = ppl;
+      for (const auto &t : stencil_tiles(s, 3)) shapes.push_back({ppl, t.first, t.second});
+    }
+    std::vector<int> idx;
+    for (size_t j = 0; j < shapes.size(); ++j) idx.push_back(static_cast<int>(j));
+    int pickj = 0;
+    auto by_shape = [&] {
+      s->tune.st_ppl = shapes[pickj][0];
+      s->tune.st_ty = shapes[pickj][1];
+      s->tune.st_tz = shapes[pickj][2];
+      return stencil();
+    };
+    if ((rc = pick(&pickj, idx, by_shape, st)) != GPAW_OK) return rc;
+    s->tune.st_ppl = shapes[pickj][0];
+    s->tune.st_ty = shapes[pickj][1];
+    s->tune.st_tz = shapes[pickj][2];
+  }
   std::vector<int> segs = {0};
   for (int v : {1, 2, 4, 8})
-    if (v <= std::max(1, s->n[0] / 4)) segs.push_back(v);
+    if (v <= std::max(1, s->n[0] / 12)) segs.push_back(v);
   if ((rc = pick(&s->tune.st_nseg, segs, stencil, st)) != GPAW_OK) return rc;
   if ((rc = pick(&s->tune.sub_wgs, {128, 256, 512, 1024},
                  [&] {
@@ -409,12 +429,14 @@ int gpaw_batch_tuning(const gpaw_batch *b, int32_t *out) {
   out[0] = branches_of(b);
   for (size_t i = 0; i < b->sys.size(); ++i) {
     const Tune &t = b->sys[i]->tune;
-    int32_t *o = out + 1 + 5 * i;
-    o[0] = t.st_nb;
-    o[1] = t.st_nseg;
-    o[2] = t.sub_wgs;
-    o[3] = t.rot_rb;
-    o[4] = t.prj_nbg;
+    int32_t *o = out + 1 + 7 * i;
+    o[0] = t.st_ppl;
+    o[1] = t.st_ty;
+    o[2] = t.st_tz;
+    o[3] = t.st_nseg;
+    o[4] = t.sub_wgs;
+    o[5] = t.rot_rb;
+    o[6] = t.prj_nbg;
   }
   return GPAW_OK;
 }

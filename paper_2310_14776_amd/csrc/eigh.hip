@@ -16,9 +16,11 @@
 //                  apart by that amount;
 //   k_cluster_orth modified Gram-Schmidt (twice) inside clusters of
 //                  eigenvalues closer than 1e-7 ||T||;
-//   Newton-Schulz  two steps Z <- Z (3I - Z^T Z)/2 (each squares the
-//                  orthogonality defect; the second Gram matrix must be
-//                  within 1e-7 of I);
+//   refinement     one step (a second when the first leaves the Gram matrix
+//                  more than 1e-13 from I) of the Ogita-Aishima eigenvector
+//                  refinement on T: with G = Z^T Z and M = Z^T T Z it removes
+//                  the orthogonality defect and every vector's part along
+//                  eigenvectors at least 1e-2 ||T|| away;
 //   k_eig_back     (8 lanes per column, reflectors in LDS) U = Q Z written
 //                  in eigen-order; then C = Linv^T U on MFMA.
 #include <algorithm>
@@ -47,9 +49,6 @@ constexpr int EIG_T = 1024;
 constexpr int EIG_NMAX = 128;
 constexpr int EIG_LARGE_MAX = 1024;
 constexpr int VEC_T = 8;  // lanes (eigenvectors) per inverse-iteration workgroup
-// max |Z^T Z - I| below which the Newton-Schulz steps are skipped (an eighth
-// of the 1e-12 orthonormality the eigenvectors are held to)
-constexpr double NS_SKIP = 1.25e-13;
 constexpr int SG_T = 256;  // small-GEMM workgroup: four 16x16 output tiles
 constexpr int CH_T = 512;  // blocked Cholesky: 8 wavefronts (256 VGPRs each)
 
@@ -60,13 +59,16 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 struct EigWs {
   double *Linv, *T1, *A, *V, *Z, *Z2, *G, *tau, *d, *e, *lam;
   double *Sw, *piv, *p, *lu;  // blocks above the LDS limit only
-  int32_t *skip;              // nonzero: the Newton-Schulz steps have nothing to do
+  int32_t *cid;               // [n] first slot of each slot's eigenvalue cluster
+  double *cltol;              // cluster tolerance CL_TOL ||T||
+  int32_t *skip;              // nonzero: the second refinement step has nothing to do
 };
 
 size_t eig_layout_elems(int n, int sz, bool large) {
   const size_t nn = static_cast<size_t>(n) * n;
   size_t e = 4 * sz * nn + 3 * nn + sz * n + 3 * n;
   if (large) e += sz * nn + n + sz * n + 6 * nn;
+  e += (n + 1) / 2 + 2;  // cluster ids and tolerance
   return e + 64;
 }
 
@@ -92,7 +94,10 @@ EigWs eig_layout(double *base, int n, int sz, bool large) {
     w.piv = w.Sw + sz * nn;
     w.p = w.piv + n;
     w.lu = w.p + sz * n;
+    q = w.lu + 6 * nn;
   }
+  w.cltol = q;
+  w.cid = reinterpret_cast<int32_t *>(q + 1);
   // the last double of the block (the layout keeps 64 spare at its end)
   w.skip = reinterpret_cast<int32_t *>(base + eig_layout_elems(n, sz, large) - 1);
   return w;
@@ -1026,8 +1031,8 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
 // ------------------------------------------------------------------ orthogonality
 // dev[slot] = max |G - I| (one workgroup); info = -1 when above the limit
 // skip (optional): set to 1 when max |G - I| <= skip_limit (the vectors are
-// already orthonormal to rounding, so the Newton-Schulz steps, which take
-// skip as their status word, do nothing) or when the status is not 0;
+// already orthonormal to rounding, so the kernels that take skip as their
+// status word do nothing) or when the status is not 0;
 // gate (optional): the check does nothing while *gate is nonzero.
 __global__ __launch_bounds__(1024) void k_gram_check(const double *__restrict__ G, int n,
                                                      double limit, int32_t *info, int32_t *skip,
@@ -1074,7 +1079,7 @@ __global__ __launch_bounds__(1024) void k_gram_check(const double *__restrict__ 
 // parallel. Slots of one block whose consecutive eigenvalue gaps are at most
 // CL_TOL ||T|| form a cluster, and each cluster is orthonormalised by modified
 // Gram-Schmidt in slot order, applied twice. Outside the clusters the vectors
-// overlap by at most ~1e-8, which the Newton-Schulz steps that follow remove.
+// overlap by at most ~1e-8, which the refinement that follows removes.
 // One workgroup; each wavefront takes whole clusters (lane r owns rows
 // r + 64q of every column it touches, so its own stores are what it reads
 // back).
@@ -1085,6 +1090,8 @@ __global__ __launch_bounds__(CL_T) void k_cluster_orth(int n, const double *__re
                                                        const double *__restrict__ e,
                                                        const double *__restrict__ lam,
                                                        double *__restrict__ Z,
+                                                       int32_t *__restrict__ cid,
+                                                       double *__restrict__ cltol,
                                                        const int32_t *__restrict__ info) {
   if (*info != 0) return;
   __shared__ unsigned char brk[EIG_LARGE_MAX];  // 1: slot j opens a new cluster
@@ -1106,6 +1113,13 @@ __global__ __launch_bounds__(CL_T) void k_cluster_orth(int n, const double *__re
   for (int j = t; j < n; j += CL_T)
     brk[j] = (j == 0 || split_at(d, e, j - 1) || !(lam[j] - lam[j - 1] <= tol)) ? 1 : 0;
   __syncthreads();
+  // cluster id of every slot (its cluster's first slot) for the refinement
+  for (int j = t; j < n; j += CL_T) {
+    int b = j;
+    while (brk[b] == 0) --b;
+    cid[j] = b;
+  }
+  if (t == 0) *cltol = tol;
   for (int j = t; j < n; j += CL_T) {
     if (brk[j] == 0 && (j + 1 == n || brk[j + 1] == 1)) {
       int b = j;
@@ -1142,8 +1156,8 @@ __global__ __launch_bounds__(CL_T) void k_cluster_orth(int n, const double *__re
 #pragma unroll
       for (int q = 0; q < CL_RPL; ++q) s = fma(zj[q], zj[q], s);
       s = wave_sum(s);
-      // a vector lost to cancellation stays as it is; the Gram check after
-      // the Newton-Schulz steps then reports the failure
+      // a vector lost to cancellation stays as it is; the Gram checks of the
+      // refinement then report the failure
       const double sc = s > 1e-200 ? 1.0 / sqrt(s) : 1.0;
 #pragma unroll
       for (int q = 0; q < CL_RPL; ++q) {
@@ -1152,6 +1166,61 @@ __global__ __launch_bounds__(CL_T) void k_cluster_orth(int n, const double *__re
       }
     }
   }
+}
+
+// ------------------------------------------------------------------ refinement
+// Eigenvector refinement of Ogita and Aishima (2018), one step, on the
+// tridiagonal problem T z_j = lam_j z_j. With G = Z^T Z, M = Z^T (T Z) and
+// R = I - G, every column becomes z_j + sum_i z_i E_ij with
+//   E_ij = (M_ij + lam_j R_ij) / (lam_j - lam_i) for eigenvalues further
+//          apart than RF_GAP ||T|| (and not in one Gram-Schmidt cluster);
+//   E_ij = R_ij / 2 otherwise, and E_jj = R_jj / 2.
+// A vector z_i = v_i + c v_j (v exact) gets E_ji = -c: the part along a
+// distant eigenvector, which a symmetric orthogonalisation would only halve
+// (leaving (lam_i - lam_j) c / 2 in Z^T T Z), is removed. M and R are formed
+// in FP64, so M_ij + lam_j R_ij carries rounding of order eps |lam|; divided
+// by a small gap it would inject errors larger than the ones corrected,
+// hence the full correction only across gaps above RF_GAP ||T|| (rounding
+// below ~1e-14 there). Across smaller gaps the leftover antisymmetric part
+// contributes only gap x c to Z^T T Z, and the step is the symmetric
+// (Newton-Schulz) orthogonalisation Z (3I - G) / 2.
+
+// Y = T Z (T tridiagonal: diagonal d, off-diagonal e)
+__global__ __launch_bounds__(256) void k_tri_apply(int n, const double *__restrict__ d,
+                                                   const double *__restrict__ e,
+                                                   const double *__restrict__ Z,
+                                                   double *__restrict__ Y,
+                                                   const int32_t *__restrict__ gate) {
+  if (*gate != 0) return;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * n) return;
+  const int i = static_cast<int>(idx / n);
+  double y = d[i] * Z[idx];
+  if (i > 0) y = fma(e[i - 1], Z[idx - n], y);
+  if (i + 1 < n) y = fma(e[i], Z[idx + n], y);
+  Y[idx] = y;
+}
+
+constexpr double RF_GAP = 1e-2;
+
+// F = I + E from G and M (above)
+__global__ __launch_bounds__(256) void k_refine_coef(int n, const double *__restrict__ G,
+                                                     const double *__restrict__ M,
+                                                     const double *__restrict__ lam,
+                                                     const int32_t *__restrict__ cid,
+                                                     const double *__restrict__ cltol,
+                                                     double *__restrict__ F,
+                                                     const int32_t *__restrict__ gate) {
+  if (*gate != 0) return;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * n) return;
+  const int i = static_cast<int>(idx / n), j = static_cast<int>(idx - static_cast<int64_t>(i) * n);
+  const double r = (i == j ? 1.0 : 0.0) - G[idx];
+  const double gap = lam[j] - lam[i];
+  double E = 0.5 * r;
+  if (i != j && cid[i] != cid[j] && fabs(gap) > (RF_GAP / CL_TOL) * *cltol)
+    E = (M[idx] + lam[j] * r) / gap;
+  F[idx] = (i == j ? 1.0 : 0.0) + E;
 }
 
 // ------------------------------------------------------------------ back-transform
@@ -1321,6 +1390,44 @@ __global__ __launch_bounds__(128) void k_eig_back(int n, EigWs w, const double *
 }
 
 
+
+__global__ __launch_bounds__(256) void k_copy_gated(const double *__restrict__ src,
+                                                    double *__restrict__ dst, int64_t count,
+                                                    const int32_t *__restrict__ gate) {
+  if (*gate != 0) return;
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx < count) dst[idx] = src[idx];
+}
+
+// Refined eigenvectors of T (from w.Z after the cluster step) into w.G.
+// Step 1 always runs; its Gram matrix G' decides the second: none when
+// max |G' - I| <= 1e-13 (w.skip set on the device, no host wait), and
+// status -1 when above 1e-4 (or the first Gram matrix above 0.1), where the
+// second-order step could not reach rounding level. Scratch: w.Z2, and w.T1
+// (as doubles) for M; w.Z is overwritten.
+void refine_vectors(int n, const EigWs &w, int32_t *info, hipStream_t st) {
+  const int64_t nn = static_cast<int64_t>(n) * n;
+  const unsigned eb = static_cast<unsigned>((nn + 255) / 256);
+  const int tiles = ((n + 15) / 16) * ((n + 15) / 16);
+  const unsigned sgb = static_cast<unsigned>((tiles + 3) / 4);
+  double *M = w.T1;
+  // step 1: G = Z^T Z, Y = T Z, M = Z^T Y, F = I + E, Z' = Z F (into G)
+  k_small_gemm<double, 1, 0><<<sgb, SG_T, 0, st>>>(w.Z, w.Z, w.G, n, info);
+  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 0.1, info, nullptr, 0.0, nullptr);
+  k_tri_apply<<<eb, 256, 0, st>>>(n, w.d, w.e, w.Z, w.Z2, info);
+  k_small_gemm<double, 1, 0><<<sgb, SG_T, 0, st>>>(w.Z, w.Z2, M, n, info);
+  k_refine_coef<<<eb, 256, 0, st>>>(n, w.G, M, w.lam, w.cid, w.cltol, w.Z2, info);
+  k_small_gemm<double, 0, 0><<<sgb, SG_T, 0, st>>>(w.Z, w.Z2, w.G, n, info);
+  // step 2 on Z' (G' into w.Z), gated by w.skip
+  k_small_gemm<double, 1, 0><<<sgb, SG_T, 0, st>>>(w.G, w.G, w.Z, n, info);
+  k_gram_check<<<1, 1024, 0, st>>>(w.Z, n, 1e-4, info, w.skip, 1e-13, nullptr);
+  k_tri_apply<<<eb, 256, 0, st>>>(n, w.d, w.e, w.G, w.Z2, w.skip);
+  k_small_gemm<double, 1, 0><<<sgb, SG_T, 0, st>>>(w.G, w.Z2, M, n, w.skip);
+  k_refine_coef<<<eb, 256, 0, st>>>(n, w.Z, M, w.lam, w.cid, w.cltol, w.Z2, w.skip);
+  k_small_gemm<double, 0, 0><<<sgb, SG_T, 0, st>>>(w.G, w.Z2, w.Z, n, w.skip);
+  k_copy_gated<<<eb, 256, 0, st>>>(w.Z, w.G, nn, w.skip);
+}
+
 // blocks above the LDS limit: global-memory pipeline (eigh_large.hip)
 template <typename T>
 int eigh_large_t(const gpaw_sys *s, const T *H, const T *S, int n, double *eps, T *C,
@@ -1342,14 +1449,9 @@ int eigh_large_t(const gpaw_sys *s, const T *H, const T *S, int n, double *eps, 
   large_tridiag<T>(Am, n, V, tau, w.d, w.e, p, info, st);
   k_eig_values<<<(n + 3) / 4, 256, values_lds_bytes(n), st>>>(n, w.d, w.e, w.lam, info);
   large_vectors(n, w.d, w.e, w.lam, w.lu, w.Z, info, st);
-  k_cluster_orth<<<1, CL_T, 0, st>>>(n, w.d, w.e, w.lam, w.Z, info);
-  k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.Z, w.G, n, info);
-  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 0.5, info, w.skip, NS_SKIP, nullptr);
-  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.G, w.Z2, n, w.skip);
-  k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.Z2, w.G, n, w.skip);
-  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 1e-7, info, nullptr, 0.0, w.skip);
-  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.G, w.Z, n, w.skip);
-  large_back<T>(n, w.Z, V, tau, w.lam, U, eps, info, st);
+  k_cluster_orth<<<1, CL_T, 0, st>>>(n, w.d, w.e, w.lam, w.Z, w.cid, w.cltol, info);
+  refine_vectors(n, w, info, st);
+  large_back<T>(n, w.G, V, tau, w.lam, U, eps, info, st);
   k_small_gemm<T, 1, 0><<<sg_blocks, SG_T, 0, st>>>(Linv, U, C, n, info);
   return GPAW_OK;
 }
@@ -1391,20 +1493,11 @@ int eigh_t(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps,
   k_eig_values<<<(n + 3) / 4, 256, values_lds_bytes(n), st>>>(n, w.d, w.e, w.lam, info);
   k_eig_vectors<<<(n + VEC_T - 1) / VEC_T, VEC_T, vec_lds_doubles(n) * sizeof(double), st>>>(n, w,
                                                                                         info);
-  k_cluster_orth<<<1, CL_T, 0, st>>>(n, w.d, w.e, w.lam, w.Z, info);
-  // two Newton-Schulz steps Z <- Z (3I - Z^T Z)/2 on the real tridiagonal
-  // eigenvectors; the second Gram matrix must be within 1e-7 of I, so the
-  // result is orthonormal to ~1e-14. When the first Gram matrix is already
-  // within NS_SKIP of I the steps are skipped (on the device: no host wait).
-  k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.Z, w.G, n, info);
-  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 0.5, info, w.skip, NS_SKIP, nullptr);
-  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z, w.G, w.Z2, n, w.skip);
-  k_small_gemm<double, 1, 0><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.Z2, w.G, n, w.skip);
-  k_gram_check<<<1, 1024, 0, st>>>(w.G, n, 1e-7, info, nullptr, 0.0, w.skip);
-  k_small_gemm<double, 0, 3><<<sg_blocks, SG_T, 0, st>>>(w.Z2, w.G, w.Z, n, w.skip);
+  k_cluster_orth<<<1, CL_T, 0, st>>>(n, w.d, w.e, w.lam, w.Z, w.cid, w.cltol, info);
+  refine_vectors(n, w, info, st);
   // U = Q Z in eigen-order, then C = Linv^H U
   k_eig_back<T><<<(n + 15) / 16, 128, back_lds_bytes<T>(n), st>>>(
-      n, w, w.Z, U, eps, info);
+      n, w, w.G, U, eps, info);
   k_small_gemm<T, 1, 0><<<sg_blocks, SG_T, 0, st>>>(Linv, U, static_cast<T *>(C), n, info);
   return GPAW_OK;
 }

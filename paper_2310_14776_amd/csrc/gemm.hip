@@ -276,7 +276,7 @@ struct SplitPlan {
   int64_t kchunk;
 };
 
-SplitPlan plan_subspace(int nb, int64_t ng, int nmat, int tile, int target) {
+SplitPlan plan_subspace(int nb, int64_t ng, int nmat, int tile, int target, int64_t max_split) {
   SplitPlan p;
   p.tiles_n = (nb + tile - 1) / tile;
   p.tiles = p.tiles_n * (p.tiles_n + 1) / 2;  // on and above the diagonal
@@ -288,7 +288,7 @@ SplitPlan plan_subspace(int nb, int64_t ng, int nmat, int tile, int target) {
   int64_t want = std::max<int64_t>(1, target / (p.tiles * nmat));
   if (want >= 8) want = want / 8 * 8;
   const int64_t kmax_split = std::max<int64_t>(1, ng / 1024);
-  int64_t nsplit = std::min(want, kmax_split);
+  int64_t nsplit = std::max<int64_t>(1, std::min({want, kmax_split, max_split}));
   int64_t kchunk = (ng + nsplit - 1) / nsplit;
   kchunk = (kchunk + 63) / 64 * 64;
   p.kchunk = kchunk;
@@ -300,8 +300,8 @@ SplitPlan plan_subspace(int nb, int64_t ng, int nmat, int tile, int target) {
 // row group blockIdx.y) by 32 columns; no conjugation (psi' = C^T psi).
 template <typename T, int RB>
 __global__ __launch_bounds__(256) void k_rotate(const T *__restrict__ C, const T *__restrict__ src,
-                                                T *__restrict__ dst, int nb, int64_t cols,
-                                                int upper) {
+                                                T *__restrict__ dst, int nb, int nout,
+                                                int64_t cols, int upper) {
   constexpr int NP = Cx<T>::parts;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = lane & 15, kq = lane >> 4;
@@ -323,13 +323,14 @@ __global__ __launch_bounds__(256) void k_rotate(const T *__restrict__ C, const T
       for (int q = 0; q < 2; ++q) acc[c][i][q] = d4{0.0, 0.0, 0.0, 0.0};
 
   // Clamped addresses keep every load unconditional and in bounds (branches
-  // around loads would force a full wait at each loop turn): rows n >= nb
+  // around loads would force a full wait at each loop turn): rows n >= nout
   // and columns g >= cols only feed outputs that are never stored, and the
-  // steps past m = nb are zeroed on the src side where they are used.
+  // steps past m = nb are zeroed on the src side where they are used. C is
+  // nb x nb (row stride nb); the first nout of its columns are used.
   const T *cp[RB];
   const T *sp[2];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) cp[rb] = C + std::min(n0 + rb * 16 + j, nb - 1);
+  for (int rb = 0; rb < RB; ++rb) cp[rb] = C + std::min(n0 + rb * 16 + j, nout - 1);
 #pragma unroll
   for (int cb = 0; cb < 2; ++cb) sp[cb] = src + std::min<int64_t>(gc[cb], cols - 1);
   auto load_step = [&](int m0, T (&a)[RB], T (&b)[2]) {
@@ -380,7 +381,7 @@ __global__ __launch_bounds__(256) void k_rotate(const T *__restrict__ C, const T
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int n = n0 + rb * 16 + kq + 4 * e;
-        if (n < nb)
+        if (n < nout)
           dst[static_cast<int64_t>(n) * cols + gc[cb]] =
               Cx<T>::make(acc[0][rb][cb][e], acc[NP - 1][rb][cb][e]);
       }
@@ -391,12 +392,12 @@ __global__ __launch_bounds__(256) void k_rotate(const T *__restrict__ C, const T
 // per 16 x 16 output tile, 64 m per round with all loads issued first.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rot_small(const T *__restrict__ C, const T *__restrict__ src,
-                                                   T *__restrict__ dst, int nb, int64_t cols,
-                                                   int tiles_c, int upper) {
+                                                   T *__restrict__ dst, int nb, int nout,
+                                                   int64_t cols, int tiles_c, int upper) {
   constexpr int NP = Cx<T>::parts;
   const int lane = threadIdx.x & 63;
   const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int tiles_n = (nb + 15) / 16;
+  const int tiles_n = (nout + 15) / 16;
   if (tile >= tiles_n * tiles_c) return;
   const int n0 = (tile / tiles_c) * 16;
   const int64_t c0 = static_cast<int64_t>(tile % tiles_c) * 16;
@@ -410,7 +411,7 @@ __global__ __launch_bounds__(256) void k_rot_small(const T *__restrict__ C, cons
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int m = m0 + 4 * u + lk;
-      a[u] = (m < nb && n0 + i < nb) ? C[static_cast<int64_t>(m) * nb + n0 + i] : T{};
+      a[u] = (m < nb && n0 + i < nout) ? C[static_cast<int64_t>(m) * nb + n0 + i] : T{};
       b[u] = (m < nb && c0 + i < cols) ? src[static_cast<int64_t>(m) * cols + c0 + i] : T{};
     }
 #pragma unroll
@@ -429,30 +430,30 @@ __global__ __launch_bounds__(256) void k_rot_small(const T *__restrict__ C, cons
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int n = n0 + lk + 4 * e;
-    if (n < nb) dst[static_cast<int64_t>(n) * cols + c0 + i] = Cx<T>::make(acc[0][e], acc[NP - 1][e]);
+    if (n < nout) dst[static_cast<int64_t>(n) * cols + c0 + i] = Cx<T>::make(acc[0][e], acc[NP - 1][e]);
   }
 }
 
 template <typename T>
-int rotate_small_t(const void *C, const void *src, int nb, int64_t cols, void *dst, hipStream_t st,
-                   bool upper) {
+int rotate_small_t(const void *C, const void *src, int nb, int nout, int64_t cols, void *dst,
+                   hipStream_t st, bool upper) {
   const int tiles_c = static_cast<int>((cols + 15) / 16);
-  const int64_t tiles = static_cast<int64_t>((nb + 15) / 16) * tiles_c;
+  const int64_t tiles = static_cast<int64_t>((nout + 15) / 16) * tiles_c;
   k_rot_small<T><<<static_cast<unsigned>((tiles + 3) / 4), 256, 0, st>>>(
-      static_cast<const T *>(C), static_cast<const T *>(src), static_cast<T *>(dst), nb, cols,
-      tiles_c, upper ? 1 : 0);
+      static_cast<const T *>(C), static_cast<const T *>(src), static_cast<T *>(dst), nb, nout,
+      cols, tiles_c, upper ? 1 : 0);
   return GPAW_OK;
 }
 
 template <typename T, int BM>
 int subspace_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi, int nb,
-               void *H, void *S, hipStream_t st) {
+               void *H, void *S, hipStream_t st, double *pbuf, size_t pcap) {
   const int nmat = Spsi ? 2 : 1;
-  const SplitPlan p = plan_subspace(nb, s->ng, nmat, 16 * BM, s->tune.sub_wgs);
-  const int64_t need = static_cast<int64_t>(p.nsplit) * nmat * nb * nb * Cx<T>::parts;
-  if (need > static_cast<int64_t>(s->ws.part_elems))
-    return fail(GPAW_EINVAL, "subspace workspace too small");
-  T *part = reinterpret_cast<T *>(s->ws.part);
+  const int64_t per_split = static_cast<int64_t>(nmat) * nb * nb * Cx<T>::parts;
+  const int64_t max_split = static_cast<int64_t>(pcap) / per_split;
+  if (max_split < 1) return fail(GPAW_ESHAPE, "subspace partial-sum buffer too small for nb");
+  const SplitPlan p = plan_subspace(nb, s->ng, nmat, 16 * BM, s->tune.sub_wgs, max_split);
+  T *part = reinterpret_cast<T *>(pbuf);
   const int64_t slots = p.nsplit >= 8 ? (p.nsplit + 7) / 8 * 8 : p.nsplit;
   const int64_t wgs = slots * p.tiles * nmat;
   // rows are 32-byte aligned when Ng is a multiple of 4 (the tensors' bases are)
@@ -474,11 +475,11 @@ int subspace_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const void 
 }
 
 template <typename T, int RB>
-int rotate_t(const void *C, const void *src, int nb, int64_t cols, void *dst, hipStream_t st,
-             bool upper) {
-  dim3 grid(static_cast<unsigned>((cols + 127) / 128), (nb + RB * 16 - 1) / (RB * 16));
+int rotate_t(const void *C, const void *src, int nb, int nout, int64_t cols, void *dst,
+             hipStream_t st, bool upper) {
+  dim3 grid(static_cast<unsigned>((cols + 127) / 128), (nout + RB * 16 - 1) / (RB * 16));
   k_rotate<T, RB><<<grid, 256, 0, st>>>(static_cast<const T *>(C), static_cast<const T *>(src),
-                                        static_cast<T *>(dst), nb, cols, upper ? 1 : 0);
+                                        static_cast<T *>(dst), nb, nout, cols, upper ? 1 : 0);
   return GPAW_OK;
 }
 
@@ -498,29 +499,39 @@ size_t subspace_part_elems(const gpaw_sys *s, int nb) {
 }
 
 int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
-                    int nb, void *H, void *S, hipStream_t st) {
+                    int nb, void *H, void *S, hipStream_t st, double *part, size_t part_elems) {
+  if (!part) {
+    part = s->ws.part;
+    part_elems = s->ws.part_elems;
+  }
   if (s->dtype == GPAW_F32 || s->dtype == GPAW_C64)
-    return launch_subspace_split(s, psi, Hpsi, Spsi, nb, H, S, st);
-  if (s->dtype == GPAW_C128) return subspace_t<z64, 2>(s, psi, Hpsi, Spsi, nb, H, S, st);
-  return subspace_t<double, 4>(s, psi, Hpsi, Spsi, nb, H, S, st);
+    return launch_subspace_split(s, psi, Hpsi, Spsi, nb, H, S, st, part, part_elems);
+  if (s->dtype == GPAW_C128)
+    return subspace_t<z64, 2>(s, psi, Hpsi, Spsi, nb, H, S, st, part, part_elems);
+  return subspace_t<double, 4>(s, psi, Hpsi, Spsi, nb, H, S, st, part, part_elems);
 }
 
 int launch_rotate(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
-                  void *dst, hipStream_t st, bool upper, bool near_id) {
+                  void *dst, hipStream_t st, bool upper, bool near_id, int nout) {
   if (cols == 0) return GPAW_OK;
-  if (s->dtype == GPAW_F32 || s->dtype == GPAW_C64)
+  if (nout < 0) nout = nb;
+  if (nout > nb || (upper && nout != nb)) return fail(GPAW_EINVAL, "rotation: nout > nb");
+  if (s->dtype == GPAW_F32 || s->dtype == GPAW_C64) {
+    if (nout != nb)
+      return fail(GPAW_EDTYPE, "a rotation to fewer bands runs in FP64/complex128 only");
     return launch_rotate_split(s, C, src, nb, cols, dst, st, upper, near_id);
+  }
   // short rows (projections): too few columns to fill the chip by column
   // tiles, so one wavefront per 16 x 16 output tile instead
   if (cols <= 4096) {
-    if (s->dtype == GPAW_C128) return rotate_small_t<z64>(C, src, nb, cols, dst, st, upper);
-    return rotate_small_t<double>(C, src, nb, cols, dst, st, upper);
+    if (s->dtype == GPAW_C128) return rotate_small_t<z64>(C, src, nb, nout, cols, dst, st, upper);
+    return rotate_small_t<double>(C, src, nb, nout, cols, dst, st, upper);
   }
   if (s->dtype == GPAW_C128)
-    return s->tune.rot_rb == 2 ? rotate_t<z64, 2>(C, src, nb, cols, dst, st, upper)
-                               : rotate_t<z64, 4>(C, src, nb, cols, dst, st, upper);
-  return s->tune.rot_rb == 4 ? rotate_t<double, 4>(C, src, nb, cols, dst, st, upper)
-                             : rotate_t<double, 8>(C, src, nb, cols, dst, st, upper);
+    return s->tune.rot_rb == 2 ? rotate_t<z64, 2>(C, src, nb, nout, cols, dst, st, upper)
+                               : rotate_t<z64, 4>(C, src, nb, nout, cols, dst, st, upper);
+  return s->tune.rot_rb == 4 ? rotate_t<double, 4>(C, src, nb, nout, cols, dst, st, upper)
+                             : rotate_t<double, 8>(C, src, nb, nout, cols, dst, st, upper);
 }
 
 }  // namespace gfd

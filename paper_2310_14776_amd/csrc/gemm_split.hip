@@ -586,14 +586,14 @@ struct SplitPlanS {
 
 // split-K over ~512 workgroups, chunks a multiple of 32, split count a
 // multiple of 8 (one group of splits per XCD)
-SplitPlanS plan_split(int nb, int64_t ng, int nmat, int tile) {
+SplitPlanS plan_split(int nb, int64_t ng, int nmat, int tile, int64_t max_split) {
   SplitPlanS p;
   p.tiles_n = (nb + tile - 1) / tile;
   p.tiles = p.tiles_n * (p.tiles_n + 1) / 2;  // on and above the diagonal
   // (the launch rounds the splits up to whole groups of 8: round down here)
   const int64_t want = std::max<int64_t>(8, 512 / (p.tiles * nmat) / 8 * 8);
   const int64_t kmax_split = std::max<int64_t>(1, ng / 256);
-  int64_t nsplit = std::max<int64_t>(1, std::min(want, kmax_split));
+  int64_t nsplit = std::max<int64_t>(1, std::min({want, kmax_split, max_split}));
   int64_t kchunk = (ng + nsplit - 1) / nsplit;
   kchunk = (kchunk + KS - 1) / KS * KS;
   nsplit = (ng + kchunk - 1) / kchunk;
@@ -604,22 +604,22 @@ SplitPlanS plan_split(int nb, int64_t ng, int nmat, int tile) {
 
 template <typename T, int WT>
 int subspace_split_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
-                     int nb, void *H, void *S, hipStream_t st) {
+                     int nb, void *H, void *S, hipStream_t st, double *part, size_t pcap) {
   constexpr int NP = Parts<T>::n;
   const int nmat = Spsi ? 2 : 1;
-  const SplitPlanS p = plan_split(nb, s->ng, nmat, 32 * WT);
-  const int64_t need = static_cast<int64_t>(p.nsplit) * nmat * nb * nb * NP;
-  if (need > static_cast<int64_t>(s->ws.part_elems))
-    return fail(GPAW_EINVAL, "subspace workspace too small");
+  const int64_t per_split = static_cast<int64_t>(nmat) * nb * nb * NP;
+  const int64_t max_split = static_cast<int64_t>(pcap) / per_split;
+  if (max_split < 1) return fail(GPAW_ESHAPE, "subspace partial-sum buffer too small for nb");
+  const SplitPlanS p = plan_split(nb, s->ng, nmat, 32 * WT, max_split);
   const int64_t slots = p.nsplit >= 8 ? (p.nsplit + 7) / 8 * 8 : p.nsplit;
   const int64_t wgs = slots * p.tiles * nmat;
   k_sub_lds<T, WT><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
       static_cast<const T *>(psi), static_cast<const T *>(Hpsi),
-      static_cast<const T *>(Spsi ? Spsi : Hpsi), s->ws.part, nb, s->ng, p.kchunk, p.tiles_n,
+      static_cast<const T *>(Spsi ? Spsi : Hpsi), part, nb, s->ng, p.kchunk, p.tiles_n,
       nmat, p.nsplit);
   const int64_t tot = static_cast<int64_t>(nb) * nb * nmat * NP;
   k_split_reduce<NP><<<static_cast<unsigned>((tot + 255) / 256), 256, 0, st>>>(
-      s->ws.part, static_cast<double *>(H), static_cast<double *>(S), nb, p.nsplit, nmat, s->dV,
+      part, static_cast<double *>(H), static_cast<double *>(S), nb, p.nsplit, nmat, s->dV,
       32 * WT);
   return GPAW_OK;
 }
@@ -668,9 +668,11 @@ size_t split_c_bytes(int nb, bool cplx) {
 }
 
 int launch_subspace_split(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
-                          int nb, void *H, void *S, hipStream_t st) {
-  if (s->dtype == GPAW_C64) return subspace_split_t<z32, 2>(s, psi, Hpsi, Spsi, nb, H, S, st);
-  return subspace_split_t<float, 4>(s, psi, Hpsi, Spsi, nb, H, S, st);
+                          int nb, void *H, void *S, hipStream_t st, double *part,
+                          size_t part_elems) {
+  if (s->dtype == GPAW_C64)
+    return subspace_split_t<z32, 2>(s, psi, Hpsi, Spsi, nb, H, S, st, part, part_elems);
+  return subspace_split_t<float, 4>(s, psi, Hpsi, Spsi, nb, H, S, st, part, part_elems);
 }
 
 int launch_rotate_split(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,

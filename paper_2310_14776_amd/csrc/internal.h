@@ -7,6 +7,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "gpaw_fd.h"
@@ -169,8 +170,10 @@ namespace gfd {
 // form's autotuner sets them per system; every choice computes the same
 // result up to the order of floating-point sums.
 struct Tune {
-  int st_nb = 0;    // bands per lane in the stencil: real 2 or 4, complex 1 or 2
+  int st_ty = 0;    // stencil tile rows (y) and columns (z): st_ty x st_tz points of
+  int st_tz = 0;    //   the y-z plane per workgroup (both set, or the built-in tile)
   int st_nseg = 0;  // x segments of the stencil grid (>= 1)
+  int st_ppl = 0;   // stencil points per lane: 1 or 2 (0 = 1)
   int sub_wgs = 0;  // target workgroup count of the split-K subspace product (<= 1024)
   int rot_rb = 0;   // 16-row tiles per rotation workgroup: real 4 or 8, complex 2 or 4
   int prj_nbg = 0;  // bands per projection workgroup: real 2, 4 or 8, complex 1 or 2
@@ -244,20 +247,37 @@ int launch_dmat2(const gpaw_sys *s, const void *P, int nb, void *X, void *XS, hi
 // without projectors)
 int launch_stencil(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,
                    hipStream_t st, const void *XS = nullptr, void *outS = nullptr);
+// Davidson corrections out = -(Hpsi - eps Spsi) / max(t0 + v - eps, t0/2)
+int launch_precond(const gpaw_sys *s, const void *Hpsi, const void *Spsi, const double *eps,
+                   int nb, void *out, hipStream_t st);
+// pseudo density n_out [Ng] (may be null) and atomic density matrices D_out
+// [natoms][ni][ni] in the matrix dtype (may be null; needs P)
+int launch_density(const gpaw_sys *s, const void *psi, int nb, const double *f, const void *P,
+                   double *n_out, void *D_out, hipStream_t st);
+// (rows, columns) of the cheapest stencil tiles of the system's y-z plane
+std::vector<std::pair<int, int>> stencil_tiles(const gpaw_sys *s, int keep);
 int launch_apply_S(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,
                    hipStream_t st);
+// part/part_elems: the split-K partial sums go to this buffer of doubles
+// instead of the system's workspace (the split count is capped to fit;
+// GPAW_ESHAPE when even one split does not)
 int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
-                    int nb, void *H, void *S, hipStream_t st);
+                    int nb, void *H, void *S, hipStream_t st, double *part = nullptr,
+                    size_t part_elems = 0);
 size_t subspace_part_elems(const gpaw_sys *s, int nb);
 // upper: C is upper triangular; near_id: C is close to the identity (the
 // single-precision form then rotates by C - I, see the split kernels)
+// nout >= 0: only the first nout output rows (C is still nb x nb; its first
+// nout columns), FP64 and complex128 only
 int launch_rotate(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
-                  void *dst, hipStream_t st, bool upper = false, bool near_id = false);
+                  void *dst, hipStream_t st, bool upper = false, bool near_id = false,
+                  int nout = -1);
 // precision form (gemm_split.hip)
 size_t split_part_elems(int nb, bool cplx);
 size_t split_c_bytes(int nb, bool cplx);
 int launch_subspace_split(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
-                          int nb, void *H, void *S, hipStream_t st);
+                          int nb, void *H, void *S, hipStream_t st, double *part,
+                          size_t part_elems);
 int launch_rotate_split(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
                         void *dst, hipStream_t st, bool upper = false, bool near_id = false);
 size_t eig_ws_elems(int nmax, bool cplx);

@@ -102,7 +102,12 @@ def test_step_parity(name):
     assert rel(host(out["psi_rot"]), oracle.rotate(psi_h, C)) <= TOL
     if s.natoms:
         assert rel(host(out["P_rot"]), oracle.rotate(ref["P"], C)) <= TOL
-    # the rotated block is S~-orthonormal and diagonalises H~ (oracle operators)
+    # the rotated block is S~-orthonormal and diagonalises H~ (oracle
+    # operators). These products are formed from the stored rotated block, so
+    # besides the eigensolver they carry the rounding of the rotation itself,
+    # sum_m C_mn psi_m, whose relative size grows with max |C| (C = L^-H U is
+    # as large as S_nm^-1/2): on these blocks up to ~1e-12, so the bound here
+    # is 1e-11. C itself is held to 1e-12 just above.
     pr = host(out["psi_rot"])
     H1, S1 = oracle.subspace_matrices(pr, ops.apply_H(pr), ops.apply_S(pr), ops.dV)
     assert np.abs(S1 - np.eye(s.nb)).max() <= 1e-11
@@ -221,8 +226,8 @@ def test_large_eigensolver_against_scipy(n, cplx):
     want = scipy.linalg.eigh(H, S, eigvals_only=True)
     assert np.abs(host(eps) - want).max() <= TOL * np.abs(want).max()
     Ch = host(C)
-    assert np.abs(Ch.conj().T @ S @ Ch - np.eye(n)).max() <= 1e-11
-    assert np.abs(Ch.conj().T @ H @ Ch - np.diag(want)).max() <= TOL * np.abs(want).max() * 10
+    assert np.abs(Ch.conj().T @ S @ Ch - np.eye(n)).max() <= TOL
+    assert np.abs(Ch.conj().T @ H @ Ch - np.diag(want)).max() <= TOL * np.abs(want).max()
     sysg.close()
 
 
@@ -260,5 +265,5 @@ def test_large_cholesky_reports_failing_minor(n, cplx, j):
     torch.cuda.synchronize()
     import scipy.linalg
     want = scipy.linalg.eigh(H, S_ok, eigvals_only=True)
-    assert np.abs(host(eps) - want).max() <= TOL * np.abs(want).max() * 10
+    assert np.abs(host(eps) - want).max() <= TOL * np.abs(want).max()
     sysg.close()
