@@ -160,6 +160,18 @@ GPAW_API int gpaw_subspace_matrices(gpaw_sys *sys, const void *psi, const void *
                            const void *Spsi, int32_t nb, void *H_nn, void *S_nn,
                            void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * results as gpaw_subspace_matrices, with the split-K partial sums in a
+ * static device array of the library (64 MiB per GPU, held until the
+ * process ends) instead of the system's workspace; the call allocates
+ * nothing. nb must satisfy nmat * nb^2 * (2 if complex else 1) * 8 bytes
+ * <= 64 MiB (nmat = 2 with Spsi, 1 without), else GPAW_ESHAPE. Every call
+ * on one GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (other streams, other threads) race and must not be issued. */
+GPAW_API int gpaw_subspace_matrices_noalloc(gpaw_sys *sys, const void *psi, const void *Hpsi,
+                                           const void *Spsi, int32_t nb, void *H_nn,
+                                           void *S_nn, void *stream);
 
 /* Generalised Hermitian eigenproblem of the subspace (Cholesky of S_nm and
  * diagonalisation, Sec. "Parallelization"), all in double precision on the

@@ -44,7 +44,7 @@ _lib = None
 
 ENTRY_POINTS = ["gpaw_sys_create", "gpaw_sys_destroy", "gpaw_sys_info", "gpaw_project",
                 "gpaw_fd_apply_H", "gpaw_fd_apply_S", "gpaw_fd_apply_HS", "gpaw_subspace_matrices",
-                "gpaw_density",
+                "gpaw_subspace_matrices_noalloc", "gpaw_density",
                 "gpaw_davidson_correction", "gpaw_davidson_step",
                 "gpaw_subspace_diag", "gpaw_rotate", "gpaw_orthonormalize",
                 "gpaw_batch_create", "gpaw_batch_destroy", "gpaw_batch_step",
@@ -80,6 +80,7 @@ def load():
     lib.gpaw_fd_apply_S.argtypes = [vp, vp, i32, vp, vp, vp]
     lib.gpaw_fd_apply_HS.argtypes = [vp, vp, i32, vp, vp, vp, vp]
     lib.gpaw_subspace_matrices.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
+    lib.gpaw_subspace_matrices_noalloc.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp]
     lib.gpaw_probe_copy.argtypes = [vp, vp, ctypes.c_int64, vp]
     lib.gpaw_density.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
     lib.gpaw_davidson_correction.argtypes = [vp, vp, vp, vp, i32, vp, vp]
@@ -244,6 +245,14 @@ class System:
             S = self._new(nb, nb, dtype=self.mat_dtype)
         _check(load().gpaw_subspace_matrices(self._h, _ptr(psi), _ptr(Hpsi), _ptr(Spsi), nb,
                                              _ptr(H), _ptr(S), _stream(stream)))
+        return H, S
+
+    def subspace_matrices_noalloc(self, psi, Hpsi, Spsi, H, S, stream=None):
+        """gpaw_subspace_matrices_noalloc: caller-provided outputs, nothing
+        allocated by the library (partial sums in its static device array)."""
+        nb = self._nb(psi)
+        _check(load().gpaw_subspace_matrices_noalloc(self._h, _ptr(psi), _ptr(Hpsi), _ptr(Spsi),
+                                                     nb, _ptr(H), _ptr(S), _stream(stream)))
         return H, S
 
     def density(self, psi, f, P=None, n_out=None, D=None, want_D=True, stream=None):

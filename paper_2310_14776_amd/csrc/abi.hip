@@ -2,6 +2,7 @@
 // the device kernels. No arithmetic of the method happens here.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "internal.h"
@@ -65,6 +66,34 @@ int check_nb(const gpaw_sys *s, int32_t nb) {
 int after_launch(const char *what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, what);
+  return GPAW_OK;
+}
+
+// Partial-sum scratch of gpaw_subspace_matrices_noalloc: a file-scope device
+// array (each GPU the library runs on holds its own copy for the life of the
+// process). Host code never uses its name as an address: the device address
+// comes from hipGetSymbolAddress, once per device, and is kept per device.
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = size_t(8) << 20;  // 64 MiB
+__device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_addr[MAX_DEVICES] = {};
+
+// device address of scratch on the current device (set up on first use)
+int scratch_address(double **out) {
+  int dev = -1;
+  GFD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(GPAW_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(GPAW_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_addr[dev] = static_cast<double *>(ptr);
+  }
+  *out = g_scratch_addr[dev];
   return GPAW_OK;
 }
 
@@ -322,6 +351,32 @@ int gpaw_subspace_matrices(gpaw_sys *s, const void *psi, const void *Hpsi, const
                             static_cast<hipStream_t>(stream))) != GPAW_OK)
     return rc;
   return after_launch("gpaw_subspace_matrices");
+}
+
+int gpaw_subspace_matrices_noalloc(gpaw_sys *s, const void *psi, const void *Hpsi,
+                                   const void *Spsi, int32_t nb, void *H, void *S, void *stream) {
+  int rc;
+  if ((rc = check_sys(s)) != GPAW_OK) return rc;
+  if ((rc = check_nb(s, nb)) != GPAW_OK) return rc;
+  if (!psi || !Hpsi || !H) return fail(GPAW_EINVAL, "psi, Hpsi and H_nn must not be NULL");
+  if (Spsi && !S) return fail(GPAW_EINVAL, "S_nn must not be NULL when Spsi is given");
+  const size_t mbytes = static_cast<size_t>(nb) * nb * mat_elem_size(s->dtype);
+  if (Spsi && overlaps(H, mbytes, S, mbytes)) return fail(GPAW_EALIAS, "H_nn overlaps S_nn");
+  // one split-K slice of partial sums must fit the scratch array
+  const size_t per_split =
+      static_cast<size_t>(Spsi ? 2 : 1) * nb * nb * (is_complex(s->dtype) ? 2 : 1);
+  if (per_split > NOALLOC_SCRATCH_DOUBLES)
+    return fail(GPAW_ESHAPE, "gpaw_subspace_matrices_noalloc: nb=" + std::to_string(nb) +
+                                 " needs " + std::to_string(per_split * 8) +
+                                 " bytes of partial sums, above the " +
+                                 std::to_string(NOALLOC_SCRATCH_DOUBLES * 8) + "-byte scratch");
+  double *part = nullptr;
+  if ((rc = scratch_address(&part)) != GPAW_OK) return rc;
+  if ((rc = launch_subspace(s, psi, Hpsi, Spsi, nb, H, Spsi ? S : nullptr,
+                            static_cast<hipStream_t>(stream), part, NOALLOC_SCRATCH_DOUBLES)) !=
+      GPAW_OK)
+    return rc;
+  return after_launch("gpaw_subspace_matrices_noalloc");
 }
 
 int gpaw_density(gpaw_sys *s, const void *psi, int32_t nb, const double *f, const void *P,
