@@ -62,6 +62,8 @@ struct AddArgs {
   const ProjDev *pj;
   int np;
   int natoms;
+  double rcmax;  // largest projector cut-off radius
+  int cap;       // k_plane: atoms whose X rows a workgroup stages in LDS
 };
 
 constexpr int POS_LDS_MAX = 1024;  // atoms whose positions are staged in LDS
@@ -78,53 +80,116 @@ __device__ inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + 
 
 __device__ inline int clamp3(int w) { return w < -3 ? -3 : (w > 3 ? 3 : w); }
 
+// Pointers with their address space spelled out, so that the LDS and the
+// global-memory paths of the add-back stay two code paths with their own
+// load instructions (a merged path through a generic pointer uses flat
+// loads, which make every wait cover both counters). The host pass of the
+// compiler sees plain pointers.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T> using lds_cptr = const __attribute__((address_space(3))) T *;
+template <typename T> using glb_cptr = const __attribute__((address_space(1))) T *;
+#else
+template <typename T> using lds_cptr = const T *;
+template <typename T> using glb_cptr = const T *;
+#endif
+
 // Non-local add-back for NB bands at grid point (ix, iy, iz) whose entry
 // summary is pi: acc[b] += sum_entries phase * sum_i p_i(r) X[b][atom*ni + i].
 // The projector values of an entry are evaluated once and reused for every
-// band; X rows of the band group and the atom positions come from LDS when
-// they fit (generic pointers otherwise).
-template <typename T, int NI, int NB, bool S2, typename PJ>
+// band.
+//
+// SLOT: slot[a] >= 0 (LDS) places atom a's position in lpos[3 slot] and its
+// rows in Xl/XSl (row [b][slot][i], band stride ldl); atoms without a slot,
+// or every atom without SLOT, read pos and Xs/XSs (band stride ldx,
+// atom-major inside a band).
+//
+// Values read from global memory on the rare paths (entry codes past the
+// three carried in pi, atoms without a slot) are waited for inside their
+// branch: the empty asm statements take them as operands, so the wait is
+// placed there and not where the paths join, where it would also wait for
+// every prefetched load of the caller.
+template <typename T, int NI, int NB, bool S2, typename PJ, bool SLOT = false, bool XG = false>
 __device__ inline void addback_group(const AddArgs &ab, const PJ &pj, int4 pi, int ix, int iy,
                                      int iz, const double *pos, const z64 *phs, const T *Xs,
                                      const T *XSs, int ldx, int ni, int b0, int nb,
-                                     typename St<T>::Acc *acc, typename St<T>::Acc *accS) {
+                                     typename St<T>::Acc *acc, typename St<T>::Acc *accS,
+                                     const int *slot = nullptr, const double *lpos = nullptr,
+                                     const T *Xl = nullptr, const T *XSl = nullptr,
+                                     int ldl = 0) {
   using A = typename St<T>::Acc;
   constexpr bool FIXED = NI == 13;
-  const int cnt = static_cast<int>(static_cast<unsigned>(pi.w) >> 24);
-  const int first = pi.w & 0xFFFFFF;
-  for (int j = 0; j < cnt; ++j) {
-    const int code = j == 0 ? pi.x : (j == 1 ? pi.y : (j == 2 ? pi.z : ab.pm_code[first + j]));
+  const int stride = FIXED ? 13 : ni;
+  auto entry = [&](int code) {
     const int a = code >> 12;
     const int wx = ((code >> 8) & 15) - 8, wy = ((code >> 4) & 15) - 8, wz = (code & 15) - 8;
-    const double *R = pos + 3 * a;
-    const double dx = (ix + wx * pj.n[0]) * pj.h[0] - R[0];
-    const double dy = (iy + wy * pj.n[1]) * pj.h[1] - R[1];
-    const double dz = (iz + wz * pj.n[2]) * pj.h[2] - R[2];
+    int sl = -1;
+    if constexpr (SLOT) sl = slot[a];
+    double R0, R1, R2;
+    if (sl >= 0) {
+      R0 = lpos[3 * sl];
+      R1 = lpos[3 * sl + 1];
+      R2 = lpos[3 * sl + 2];
+    } else {
+      R0 = pos[3 * a];
+      R1 = pos[3 * a + 1];
+      R2 = pos[3 * a + 2];
+      asm volatile("" : "+v"(R0), "+v"(R1), "+v"(R2));
+    }
+    const double dx = (ix + wx * pj.n[0]) * pj.h[0] - R0;
+    const double dy = (iy + wy * pj.n[1]) * pj.h[1] - R1;
+    const double dz = (iz + wz * pj.n[2]) * pj.h[2] - R2;
     double pv[NI];
     if constexpr (FIXED) eval_proj13(pj, dx, dy, dz, pv);
     else eval_proj<NI>(pj, dx, dy, dz, pv);
     z64 ph = zmake(1.0, 0.0);
     if (St<T>::cplx) ph = phs[wx + 8] * phs[16 + wy + 8] * phs[32 + wz + 8];
-    const T *Xa = Xs + a * (FIXED ? 13 : ni);
+    // rows of the band group for this atom: staged (LDS) or global
+    auto apply = [&](auto Xa, auto XSa, int ld) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      if (b0 + b >= nb) continue;
-      const T *Xb = Xa + static_cast<int64_t>(b) * ldx;
-      A sum = St<A>::zero();
-#pragma unroll
-      for (int i = 0; i < NI; ++i)
-        if (FIXED || i < ni) sum = sum + St<A>::scale(pv[i], St<T>::widen(Xb[i]));
-      acc[b] = acc[b] + St<A>::phase(sum, ph);
-      if constexpr (S2) {
-        // the overlap's add-back from the same projector values
-        const T *XSb = XSs + a * (FIXED ? 13 : ni) + static_cast<int64_t>(b) * ldx;
-        A sumS = St<A>::zero();
+      for (int b = 0; b < NB; ++b) {
+        if (b0 + b >= nb) continue;
+        const auto Xb = Xa + static_cast<int64_t>(b) * ld;
+        A sum = St<A>::zero();
 #pragma unroll
         for (int i = 0; i < NI; ++i)
-          if (FIXED || i < ni) sumS = sumS + St<A>::scale(pv[i], St<T>::widen(XSb[i]));
-        accS[b] = accS[b] + St<A>::phase(sumS, ph);
+          if (FIXED || i < ni) {
+            const T xv = Xb[i];
+            sum = sum + St<A>::scale(pv[i], St<T>::widen(xv));
+          }
+        acc[b] = acc[b] + St<A>::phase(sum, ph);
+        if constexpr (S2) {
+          // the overlap's add-back from the same projector values
+          const auto XSb = XSa + static_cast<int64_t>(b) * ld;
+          A sumS = St<A>::zero();
+#pragma unroll
+          for (int i = 0; i < NI; ++i)
+            if (FIXED || i < ni) {
+              const T xv = XSb[i];
+              sumS = sumS + St<A>::scale(pv[i], St<T>::widen(xv));
+            }
+          accS[b] = accS[b] + St<A>::phase(sumS, ph);
+        }
+      }
+    };
+    if constexpr (SLOT) {
+      if (sl >= 0) {
+        apply((lds_cptr<T>)(Xl + sl * stride), (lds_cptr<T>)(S2 ? XSl + sl * stride : Xl), ldl);
+        return;
       }
     }
+    if constexpr (XG)
+      apply((glb_cptr<T>)(Xs + a * stride), (glb_cptr<T>)(S2 ? XSs + a * stride : Xs), ldx);
+    else
+      apply(Xs + a * stride, S2 ? XSs + a * stride : Xs, ldx);
+  };
+  const int cnt = static_cast<int>(static_cast<unsigned>(pi.w) >> 24);
+  const int first = pi.w & 0xFFFFFF;
+  const int c3 = cnt < 3 ? cnt : 3;
+  for (int j = 0; j < c3; ++j) entry(j == 0 ? pi.x : (j == 1 ? pi.y : pi.z));
+  for (int j = 3; j < cnt; ++j) {
+    int code = ab.pm_code[first + j];
+    asm volatile("" : "+v"(code));
+    entry(code);
   }
 }
 
@@ -224,7 +289,6 @@ __global__ __launch_bounds__(PT_THREADS) void k_plane(const T *__restrict__ psi,
   const T *Xs = static_cast<const T *>(ab.X) + static_cast<int64_t>(b0) * ab.np;
   const T *XSs = SOUT && ADD ? static_cast<const T *>(ab.XS) + static_cast<int64_t>(b0) * ab.np
                              : nullptr;
-  const double *pos = ab.pos;
   const z64 *phs = nullptr;
   Proj13 *pjl = nullptr;
   if (ADD) {
@@ -237,19 +301,6 @@ __global__ __launch_bounds__(PT_THREADS) void k_plane(const T *__restrict__ psi,
       phs = stage_phases(ab, reinterpret_cast<z64 *>(after));
       after += 48 * sizeof(z64);
     }
-    T *xa = reinterpret_cast<T *>(after);
-    if (XLDS) {
-      stage_x<T, NB>(ab, b0, nb, xa, ab.X);
-      Xs = xa;
-      xa += NB * ab.np;
-      if (SOUT) {
-        stage_x<T, NB>(ab, b0, nb, xa, ab.XS);
-        XSs = xa;
-        xa += NB * ab.np;
-      }
-    }
-    pos = stage_pos(ab, ab.natoms <= POS_LDS_MAX ? reinterpret_cast<double *>(xa) : nullptr,
-                    ab.natoms);
   }
   const int ni = NI == 13 ? 13 : ab.pj->ni;
 
@@ -258,6 +309,64 @@ __global__ __launch_bounds__(PT_THREADS) void k_plane(const T *__restrict__ psi,
   const int y0 = ty * G.TY, z0 = tz * G.TZ;
   const int TYe = min(G.TY, n1 - y0), TZe = min(G.TZ, n2 - z0);
   const int LS = G.LS;
+
+  // XLDS: the atoms whose spheres (any periodic image) reach the tile's y-z
+  // footprint get LDS slots (the first ab.cap of them, in any order: a slot
+  // only says where a row is kept); their positions and X rows of this band
+  // group are staged, and the add-back reads the others from global memory
+  int *slot = nullptr;
+  const double *lpos = nullptr;
+  const T *Xl = nullptr, *XSl = nullptr;
+  int ldl = 0;
+  if (ADD && XLDS) {
+    slot = reinterpret_cast<int *>(after);
+    int *list = slot + ab.natoms;
+    int *count = list + ab.cap;
+    double *lp = reinterpret_cast<double *>(
+        after + ((sizeof(int) * (ab.natoms + ab.cap + 1) + 15) / 16) * 16);
+    T *xl = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(lp) +
+                                  ((3 * sizeof(double) * ab.cap + 15) / 16) * 16);
+    if (t == 0) *count = 0;
+    __syncthreads();
+    const double h1 = ab.pj->h[1], h2 = ab.pj->h[2];
+    const double L1 = n1 * h1, L2 = n2 * h2;
+    const double ya = y0 * h1, wy = (TYe - 1) * h1, za = z0 * h2, wz = (TZe - 1) * h2;
+    const double reach = ab.rcmax * (1.0 + 1e-12);
+    for (int a = t; a < ab.natoms; a += PT_THREADS) {
+      // periodic distance from the atom to the footprint, per axis
+      double dy = ab.pos[3 * a + 1] - ya, dz = ab.pos[3 * a + 2] - za;
+      dy -= floor(dy / L1) * L1;
+      dz -= floor(dz / L2) * L2;
+      const double ey = dy <= wy ? 0.0 : fmin(dy - wy, L1 - dy);
+      const double ez = dz <= wz ? 0.0 : fmin(dz - wz, L2 - dz);
+      int sl = -1;
+      if (ey <= reach && ez <= reach) {
+        const int k = atomicAdd(count, 1);
+        if (k < ab.cap) {
+          sl = k;
+          list[k] = a;
+        }
+      }
+      slot[a] = sl;
+    }
+    __syncthreads();
+    const int nl = min(*count, ab.cap);
+    ldl = nl * ni;
+    for (int e = t; e < 3 * nl; e += PT_THREADS) lp[e] = ab.pos[3 * list[e / 3] + e % 3];
+    const int rows = min(NB, nb - b0);
+    const T *Xg = static_cast<const T *>(ab.X) + static_cast<int64_t>(b0) * ab.np;
+    const T *XSg = SOUT ? static_cast<const T *>(ab.XS) + static_cast<int64_t>(b0) * ab.np
+                        : nullptr;
+    for (int e = t; e < rows * ldl; e += PT_THREADS) {
+      const int b = e / ldl, r = e - b * ldl, k = r / ni, i = r - k * ni;
+      const int64_t src = static_cast<int64_t>(b) * ab.np + list[k] * ni + i;
+      xl[e] = Xg[src];
+      if (SOUT) xl[NB * ldl + e] = XSg[src];
+    }
+    lpos = lp;
+    Xl = xl;
+    XSl = xl + NB * ldl;
+  }
 
   // owned points p = t + k * 512 of the tile, row-major over TYe x TZe
   bool own[PPL];
@@ -310,44 +419,62 @@ __global__ __launch_bounds__(PT_THREADS) void k_plane(const T *__restrict__ psi,
 #pragma unroll
   for (int b = 0; b < NB; ++b) brow[b] = static_cast<int64_t>(min(b0 + b, nb - 1)) * bstride;
 
-  // owned values of plane xp (any integer: folded, with the x Bloch phase)
+  // owned values of plane xp (any integer: folded), as loaded; the x Bloch
+  // phase of the fold is applied where a value enters the window, so a
+  // prefetched load is not waited for before its plane is reached
   auto load_own = [&](T (&dst)[NB][PPL], int xp) {
     const int wx = fold_count(xp, n0);
     const int64_t off = static_cast<int64_t>(xp - wx * n0) * plane;
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int k = 0; k < PPL; ++k) {
-        const T val = psi[brow[b] + off + goff[k]];
-        if constexpr (BLOCH) {
-          const z64 ph = G.phx[clamp3(wx) + 3];
-          dst[b][k] = St<T>::narrow(St<A>::phase(St<T>::widen(val), ph));
-        } else {
-          dst[b][k] = val;
-        }
-      }
+      for (int k = 0; k < PPL; ++k) dst[b][k] = psi[brow[b] + off + goff[k]];
   };
-  // halo values of plane xp (inside the grid)
-  auto load_halo = [&](T (&dst)[NB][HPL], int xp) {
+  auto phase_own = [&](T (&dst)[NB][PPL], const T (&src)[NB][PPL], int xp) {
+    if constexpr (BLOCH) {
+      const z64 ph = G.phx[clamp3(fold_count(xp, n0)) + 3];
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int k = 0; k < PPL; ++k)
+          dst[b][k] = St<T>::narrow(St<A>::phase(St<T>::widen(src[b][k]), ph));
+    } else {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) dst[b][k] = src[b][k];
+    }
+  };
+  // halo values of plane xp (inside the grid), as loaded (phases at the
+  // LDS write); with them the potential and, for the add-back, the entry
+  // summaries of the owned points of plane xp
+  auto load_halo = [&](T (&dst)[NB][HPL], double (&vd)[PPL], int4 (&pd)[PPL], int xp) {
     const int64_t off = static_cast<int64_t>(xp) * plane;
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
-      for (int k = 0; k < HPL; ++k) {
-        const T val = psi[brow[b] + off + hoff[k]];
-        dst[b][k] = BLOCH ? St<T>::narrow(St<A>::phase(St<T>::widen(val), hph[k])) : val;
-      }
+      for (int k = 0; k < HPL; ++k) dst[b][k] = psi[brow[b] + off + hoff[k]];
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) {
+      vd[k] = v[off + goff[k]];
+      if (ADD) pd[k] = ab.pinfo[off + goff[k]];
+    }
   };
 
   T q[7][NB][PPL];    // planes x-3 .. x+3 of the owned points at step x
   T pq[HR][NB][PPL];  // owned loads in flight: slot (p - x0) mod HR holds plane p + 3
   T hq[HR][NB][HPL];  // halo loads in flight: slot (p - x0) mod HR holds plane p
+  double vq[HR][PPL]; // potential of plane p, same slots
+  int4 iq[HR][PPL];   // entry summaries of plane p (add-back), same slots
 #pragma unroll
-  for (int s = 0; s < 6; ++s) load_own(q[s + 1], x0 - 3 + s);
+  for (int s = 0; s < 6; ++s) {
+    load_own(pq[0], x0 - 3 + s);
+    phase_own(q[s + 1], pq[0], x0 - 3 + s);
+  }
 #pragma unroll
   for (int s = 0; s < HR - 1; ++s) {
     load_own(pq[s], x0 + 3 + s);
-    load_halo(hq[s], min(x0 + s, n0 - 1));
+    load_halo(hq[s], vq[s], iq[s], min(x0 + s, n0 - 1));
   }
   if (ADD) __syncthreads();  // staged add-back operands
 
@@ -364,14 +491,12 @@ __global__ __launch_bounds__(PT_THREADS) void k_plane(const T *__restrict__ psi,
         for (int b = 0; b < NB; ++b)
 #pragma unroll
           for (int j = 0; j < PPL; ++j) q[s][b][j] = q[s + 1][b][j];
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int j = 0; j < PPL; ++j) q[6][b][j] = pq[k][b][j];
-      if (x + PF < x1) {
-        load_own(pq[(k + PF) % HR], x + 3 + PF);
-        load_halo(hq[(k + PF) % HR], x + PF);
-      }
+      phase_own(q[6], pq[k], x + 3);
+      // issued on every step (past the segment end they read planes that
+      // are never used, clamped into the grid): a load that only some
+      // paths issue makes the compiler wait for every load in flight
+      load_own(pq[(k + PF) % HR], x + 3 + PF);
+      load_halo(hq[(k + PF) % HR], vq[(k + PF) % HR], iq[(k + PF) % HR], min(x + PF, n0 - 1));
       // plane x into LDS buffer (x - x0) & 1
       T *L = lbuf + ((x - x0) & 1) * NB * cells;
 #pragma unroll
@@ -379,7 +504,9 @@ __global__ __launch_bounds__(PT_THREADS) void k_plane(const T *__restrict__ psi,
 #pragma unroll
         for (int j = 0; j < PPL; ++j) L[b * cells + lw[j]] = q[3][b][j];
 #pragma unroll
-        for (int j = 0; j < HPL; ++j) L[b * cells + hl[j]] = hq[k][b][j];
+        for (int j = 0; j < HPL; ++j)
+          L[b * cells + hl[j]] =
+              BLOCH ? St<T>::narrow(St<A>::phase(St<T>::widen(hq[k][b][j]), hph[j])) : hq[k][b][j];
       }
       // one barrier per plane: the buffer written next step was last read
       // before every lane arrived here
@@ -395,15 +522,18 @@ __global__ __launch_bounds__(PT_THREADS) void k_plane(const T *__restrict__ psi,
           accS[b] = St<A>::zero();
         }
         if (ADD) {
-          const int4 pi = own[j] ? ab.pinfo[g] : make_int4(0, 0, 0, 0);
+          int4 pi = iq[k][j];
+          pi.w = own[j] ? pi.w : 0;  // a select, not a branch (see the loads)
           if constexpr (NI == 13)
-            addback_group<T, NI, NB, SOUT>(ab, *pjl, pi, x, py[j], pz[j], pos, phs, Xs, XSs,
-                                           ab.np, ni, b0, nb, acc, accS);
+            addback_group<T, NI, NB, SOUT, Proj13, XLDS, true>(ab, *pjl, pi, x, py[j], pz[j], ab.pos,
+                                                         phs, Xs, XSs, ab.np, ni, b0, nb, acc,
+                                                         accS, slot, lpos, Xl, XSl, ldl);
           else
-            addback_group<T, NI, NB, SOUT>(ab, *ab.pj, pi, x, py[j], pz[j], pos, phs, Xs, XSs,
-                                           ab.np, ni, b0, nb, acc, accS);
+            addback_group<T, NI, NB, SOUT, ProjDev, XLDS, true>(ab, *ab.pj, pi, x, py[j], pz[j],
+                                                          ab.pos, phs, Xs, XSs, ab.np, ni, b0, nb,
+                                                          acc, accS, slot, lpos, Xl, XSl, ldl);
         }
-        const double cv = G.c0 + v[g];
+        const double cv = G.c0 + vq[k][j];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           const T *Lb = L + b * cells + lc[j];
@@ -587,26 +717,39 @@ AddArgs make_add(const gpaw_sys *s, const void *X, const void *XS = nullptr) {
   ab.pj = s->tab.proj;
   ab.np = s->np;
   ab.natoms = s->natoms;
+  ab.rcmax = 0.0;
+  for (int c = 0; c < s->proj.nchan; ++c)
+    ab.rcmax = std::max(ab.rcmax, 1.0 / std::sqrt(s->proj.rc2inv[c]));
+  ab.cap = 0;
   return ab;
 }
 
-constexpr size_t XLDS_MAX = 32 * 1024;
+constexpr size_t XLDS_MAX = 24 * 1024;  // staged X rows of the atoms reaching a tile
+constexpr int SLOT_ATOMS_MAX = 4096;     // atoms with a slot index in LDS
 
 template <typename T, bool BLOCH, int NB, int NI, int PPL>
 int plane_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,
             hipStream_t st, const void *XS = nullptr, void *outS = nullptr) {
   const int ngroups = (nb + NB - 1) / NB;
   const PlaneGeom G = make_geom(s, ngroups, PPL);
-  const AddArgs ab = make_add(s, X, XS);
+  AddArgs ab = make_add(s, X, XS);
   const bool sout = outS != nullptr;
   const size_t tile =
       (2 * static_cast<size_t>(NB) * ((G.TY + 6) * G.LS + 1) * sizeof(T) + 15) / 16 * 16 +
       (X && NI == 13 ? (sizeof(Proj13) + 15) / 16 * 16 : 0);
-  const size_t xbytes = static_cast<size_t>(NB) * s->np * sizeof(T) * (sout ? 2 : 1);
-  const bool xlds = X && xbytes <= XLDS_MAX;
-  const size_t pbytes = (X && s->natoms <= POS_LDS_MAX) ? 3 * sizeof(double) * s->natoms : 0;
   const size_t phb = (X && St<T>::cplx) ? 48 * sizeof(z64) : 0;
-  const size_t lds = tile + phb + (xlds ? xbytes : 0) + pbytes;
+  // LDS slots for the positions and X rows of the atoms that reach a tile
+  // (the rest are read from global memory)
+  const size_t row = static_cast<size_t>(NB) * s->ni * sizeof(T) * (sout ? 2 : 1);
+  const bool slots = X && s->natoms <= SLOT_ATOMS_MAX;
+  const int cap =
+      slots && row ? static_cast<int>(std::min<size_t>(s->natoms, XLDS_MAX / row)) : 0;
+  const bool xlds = cap > 0;
+  ab.cap = cap;
+  const size_t xbytes = xlds ? (sizeof(int) * (s->natoms + cap + 1) + 15) / 16 * 16 +
+                                   (3 * sizeof(double) * cap + 15) / 16 * 16 + row * cap
+                             : 0;
+  const size_t lds = tile + phb + xbytes;
   const int64_t cols = static_cast<int64_t>(G.ngroups) * G.nseg;
   const int64_t blocks = (cols >= 8 ? (cols + 7) / 8 * 8 : cols) * G.tiles;
   if (blocks > 0x7FFFFFFF) return fail(GPAW_ESHAPE, "stencil grid too large");
@@ -640,7 +783,7 @@ int apply_S_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *o
   const AddArgs ab = make_add(s, X);
   dim3 grid(static_cast<unsigned>((s->ng + 255) / 256), (nb + NB - 1) / NB);
   const size_t xbytes = static_cast<size_t>(NB) * s->np * sizeof(T);
-  const bool xlds = X && xbytes <= XLDS_MAX;
+  const bool xlds = X && xbytes <= 32 * 1024;
   const size_t pbytes = (X && s->natoms <= POS_LDS_MAX) ? 3 * sizeof(double) * s->natoms : 0;
   const T *ps = static_cast<const T *>(psi);
   T *po = static_cast<T *>(out);
