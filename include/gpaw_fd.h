@@ -297,7 +297,8 @@ GPAW_API int gpaw_batch_tune(gpaw_batch *b, const gpaw_batch_io *io, int32_t *in
 
 /* Chosen shapes: out[0] = graph branches, then per system 7 values
  * (stencil points per lane, stencil tile rows, stencil tile columns,
- * stencil x segments, subspace workgroup target, rotation row tiles,
+ * stencil x segments, subspace workgroup target (0: split count balanced
+ * over the resident workgroups), rotation row tiles,
  * projection bands per workgroup; 0 = built-in choice). out holds
  * 1 + 7 nsys int32 (host). */
 GPAW_API int gpaw_batch_tuning(const gpaw_batch *b, int32_t *out);

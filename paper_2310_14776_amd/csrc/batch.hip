@@ -299,7 +299,7 @@ int tune_system(gpaw_batch *b, size_t i, const gpaw_batch_io &io, int32_t *info,
   for (int v : {1, 2, 4, 8})
     if (v <= std::max(1, s->n[0] / 12)) segs.push_back(v);
   if ((rc = pick(&s->tune.st_nseg, segs, stencil, st)) != GPAW_OK) return rc;
-  if ((rc = pick(&s->tune.sub_wgs, {128, 256, 512, 1024},
+  if ((rc = pick(&s->tune.sub_wgs, {0, 128, 256, 512, 1024},
                  [&] {
                    return launch_subspace(s, io.psi, w.Hpsi, w.Spsi, nb, w.H, w.S, st);
                  },

@@ -270,25 +270,68 @@ __global__ __launch_bounds__(256) void k_subspace_reduce(const T *__restrict__ p
   if (mirror) M[static_cast<int64_t>(c) * nb + r] = Cx<T>::make(Cx<T>::re(val), -Cx<T>::im(val));
 }
 
+}  // namespace
+
+int64_t balanced_splits(int64_t units, int64_t slots, double tile_s, double part_s,
+                        int64_t max_split, int64_t k, int64_t min_k) {
+  slots = std::max<int64_t>(1, slots);
+  const int64_t hi = std::max<int64_t>(1, std::min({max_split, k / std::max<int64_t>(1, min_k),
+                                                    int64_t{64}}));
+  int64_t best = 1;
+  double best_t = 0.0;
+  for (int64_t ns = 1; ns <= hi; ++ns) {
+    const int64_t w = (ns >= 8 ? (ns + 7) / 8 * 8 : ns) * units;
+    const double rounds = static_cast<double>((w + slots - 1) / slots);
+    const double t = rounds * tile_s / static_cast<double>(ns) + static_cast<double>(ns) * part_s;
+    // a larger count must gain at least 1%
+    if (ns == 1 || t < 0.99 * best_t) {
+      best = ns;
+      best_t = t;
+    }
+  }
+  return best;
+}
+
+int64_t resident_slots(const void *kern, int threads, size_t lds) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess)
+    return 512;
+  return static_cast<int64_t>(std::max(1, cus)) * std::max(1, per_cu);
+}
+
+namespace {
+
 struct SplitPlan {
   int tiles_n, tiles;
   int nsplit;
   int64_t kchunk;
 };
 
-SplitPlan plan_subspace(int nb, int64_t ng, int nmat, int tile, int target, int64_t max_split) {
+// target > 0: about that many workgroups (a tuned launch shape); else the
+// balanced count for the resident slots of the kernel (flops: of one tile
+// over the whole K range; pbytes: partial sums of one split)
+SplitPlan plan_subspace(int nb, int64_t ng, int nmat, int tile, int target, int64_t max_split,
+                        int64_t slots, double tile_flops, double pbytes) {
   SplitPlan p;
   p.tiles_n = (nb + tile - 1) / tile;
   p.tiles = p.tiles_n * (p.tiles_n + 1) / 2;  // on and above the diagonal
-  // aim at ~512 workgroups (two per CU) with at least 1024 K per workgroup
-  if (target <= 0) target = 512;
-  target = std::min(target, 1024);
-  // (with 8 or more splits the launch rounds them up to whole groups of 8,
-  // so round down here to stay within the target)
-  int64_t want = std::max<int64_t>(1, target / (p.tiles * nmat));
-  if (want >= 8) want = want / 8 * 8;
-  const int64_t kmax_split = std::max<int64_t>(1, ng / 1024);
-  int64_t nsplit = std::max<int64_t>(1, std::min({want, kmax_split, max_split}));
+  int64_t nsplit;
+  if (target > 0) {
+    target = std::min(target, 1024);
+    // (with 8 or more splits the launch rounds them up to whole groups of
+    // 8, so round down here to stay within the target)
+    int64_t want = std::max<int64_t>(1, target / (p.tiles * nmat));
+    if (want >= 8) want = want / 8 * 8;
+    const int64_t kmax_split = std::max<int64_t>(1, ng / 1024);
+    nsplit = std::max<int64_t>(1, std::min({want, kmax_split, max_split}));
+  } else {
+    // FP64 matrix cores at about 70% of peak, partial sums at 5 TB/s
+    nsplit = balanced_splits(static_cast<int64_t>(p.tiles) * nmat, slots,
+                             tile_flops * static_cast<double>(slots) / (0.7 * 78.6e12),
+                             2.0 * pbytes / 5e12, max_split, ng, 1024);
+  }
   int64_t kchunk = (ng + nsplit - 1) / nsplit;
   kchunk = (kchunk + 63) / 64 * 64;
   p.kchunk = kchunk;
@@ -452,14 +495,22 @@ int subspace_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const void 
   const int64_t per_split = static_cast<int64_t>(nmat) * nb * nb * Cx<T>::parts;
   const int64_t max_split = static_cast<int64_t>(pcap) / per_split;
   if (max_split < 1) return fail(GPAW_ESHAPE, "subspace partial-sum buffer too small for nb");
-  const SplitPlan p = plan_subspace(nb, s->ng, nmat, 16 * BM, s->tune.sub_wgs, max_split);
-  T *part = reinterpret_cast<T *>(pbuf);
-  const int64_t slots = p.nsplit >= 8 ? (p.nsplit + 7) / 8 * 8 : p.nsplit;
-  const int64_t wgs = slots * p.tiles * nmat;
   // rows are 32-byte aligned when Ng is a multiple of 4 (the tensors' bases are)
   const bool vec = (s->ng % 4) == 0 &&
                    (reinterpret_cast<uintptr_t>(psi) | reinterpret_cast<uintptr_t>(Hpsi) |
                     reinterpret_cast<uintptr_t>(Spsi ? Spsi : Hpsi)) % 32 == 0;
+  const int64_t slots =
+      resident_slots(vec ? reinterpret_cast<const void *>(&k_subspace<T, BM, true>)
+                         : reinterpret_cast<const void *>(&k_subspace<T, BM, false>),
+                     256, 0);
+  const double tile_flops = 2.0 * Cx<T>::parts * Cx<T>::parts * (16.0 * BM) * (16.0 * BM) *
+                            static_cast<double>(s->ng);
+  const SplitPlan p =
+      plan_subspace(nb, s->ng, nmat, 16 * BM, s->tune.sub_wgs, max_split, slots, tile_flops,
+                    static_cast<double>(per_split) * sizeof(double));
+  T *part = reinterpret_cast<T *>(pbuf);
+  const int64_t sgroups = p.nsplit >= 8 ? (p.nsplit + 7) / 8 * 8 : p.nsplit;
+  const int64_t wgs = sgroups * p.tiles * nmat;
   auto go = [&](auto vflag) {
     k_subspace<T, BM, decltype(vflag)::value><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
         static_cast<const T *>(psi), static_cast<const T *>(Hpsi),
@@ -487,15 +538,18 @@ int rotate_t(const void *C, const void *src, int nb, int nout, int64_t cols, voi
 
 size_t subspace_part_elems(const gpaw_sys *s, int nb) {
   if (s->dtype == GPAW_F32 || s->dtype == GPAW_C64) return split_part_elems(nb, s->dtype == GPAW_C64);
-  // nsplit * tiles * nmat <= 1024 (the largest target) whenever that allows
+  // A tuned target keeps nsplit * tiles * nmat <= 1024 whenever that allows
   // one split, else nsplit = 1; the tiles formed are those on and above the
   // diagonal, T (T + 1) / 2 >= T^2 / 2 of them for T tiles a side, so
-  // nsplit * nmat * nb^2 <= 2048 tile^2; complex tiles are 32 x 32 (a quarter
-  // of the real 64 x 64)
+  // nsplit * nmat * nb^2 <= 2048 tile^2 (complex tiles are 32 x 32, a quarter
+  // of the real 64 x 64). The balanced plan takes up to 64 splits of two
+  // matrices, within 64 Mi doubles (512 MiB); past that it is capped to fit.
   const bool cplx = s->dtype == GPAW_C128;
   const int64_t tile = cplx ? 32 : SUB_TILE;
-  const int64_t bound = std::max<int64_t>(2048 * tile * tile, 2 * int64_t(nb) * nb);
-  return static_cast<size_t>(bound) * (cplx ? 2 : 1);
+  const int64_t parts = cplx ? 2 : 1;
+  const int64_t tuned = std::max<int64_t>(2048 * tile * tile, 2 * int64_t(nb) * nb) * parts;
+  const int64_t balanced = std::min<int64_t>(64 * 2 * int64_t(nb) * nb * parts, int64_t{64} << 20);
+  return static_cast<size_t>(std::max(tuned, balanced));
 }
 
 int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,

@@ -586,14 +586,17 @@ struct SplitPlanS {
 
 // split-K over ~512 workgroups, chunks a multiple of 32, split count a
 // multiple of 8 (one group of splits per XCD)
-SplitPlanS plan_split(int nb, int64_t ng, int nmat, int tile, int64_t max_split) {
+// split count balanced over the resident workgroups (tile_flops: one tile
+// over the whole K range, as BF16 products; pbytes: partials of one split)
+SplitPlanS plan_split(int nb, int64_t ng, int nmat, int tile, int64_t max_split, int64_t slots,
+                      double tile_flops, double pbytes) {
   SplitPlanS p;
   p.tiles_n = (nb + tile - 1) / tile;
   p.tiles = p.tiles_n * (p.tiles_n + 1) / 2;  // on and above the diagonal
-  // (the launch rounds the splits up to whole groups of 8: round down here)
-  const int64_t want = std::max<int64_t>(8, 512 / (p.tiles * nmat) / 8 * 8);
-  const int64_t kmax_split = std::max<int64_t>(1, ng / 256);
-  int64_t nsplit = std::max<int64_t>(1, std::min({want, kmax_split, max_split}));
+  // BF16 matrix cores at about 30% of their peak, partial sums at 5 TB/s
+  int64_t nsplit = balanced_splits(static_cast<int64_t>(p.tiles) * nmat, slots,
+                                   tile_flops * static_cast<double>(slots) / (0.3 * 2.5e15),
+                                   2.0 * pbytes / 5e12, max_split, ng, 256);
   int64_t kchunk = (ng + nsplit - 1) / nsplit;
   kchunk = (kchunk + KS - 1) / KS * KS;
   nsplit = (ng + kchunk - 1) / kchunk;
@@ -610,9 +613,15 @@ int subspace_split_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const
   const int64_t per_split = static_cast<int64_t>(nmat) * nb * nb * NP;
   const int64_t max_split = static_cast<int64_t>(pcap) / per_split;
   if (max_split < 1) return fail(GPAW_ESHAPE, "subspace partial-sum buffer too small for nb");
-  const SplitPlanS p = plan_split(nb, s->ng, nmat, 32 * WT, max_split);
-  const int64_t slots = p.nsplit >= 8 ? (p.nsplit + 7) / 8 * 8 : p.nsplit;
-  const int64_t wgs = slots * p.tiles * nmat;
+  const int64_t slots =
+      resident_slots(reinterpret_cast<const void *>(&k_sub_lds<T, WT>), 256, 0);
+  // six BF16 products per real product, four real products per complex one
+  const double tile_flops =
+      6.0 * 2.0 * NP * NP * (32.0 * WT) * (32.0 * WT) * static_cast<double>(s->ng);
+  const SplitPlanS p = plan_split(nb, s->ng, nmat, 32 * WT, max_split, slots, tile_flops,
+                                  static_cast<double>(per_split) * sizeof(double));
+  const int64_t sgroups = p.nsplit >= 8 ? (p.nsplit + 7) / 8 * 8 : p.nsplit;
+  const int64_t wgs = sgroups * p.tiles * nmat;
   k_sub_lds<T, WT><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
       static_cast<const T *>(psi), static_cast<const T *>(Hpsi),
       static_cast<const T *>(Spsi ? Spsi : Hpsi), part, nb, s->ng, p.kchunk, p.tiles_n,
@@ -655,11 +664,13 @@ int rotate_split_t(const gpaw_sys *s, const void *C, const void *src, int nb, in
 }  // namespace
 
 size_t split_part_elems(int nb, bool cplx) {
-  // nsplit * tiles * nmat stays within 512 (rounded up to whole groups of 8
-  // splits) unless a single split is already larger
+  // up to 64 splits of two matrices, within 64 Mi doubles (512 MiB); past
+  // that the split count is capped to fit
   const int64_t tile = cplx ? 64 : 128;
-  const int64_t bound = std::max<int64_t>(1024 * tile * tile, 16 * int64_t(nb) * nb);
-  return static_cast<size_t>(bound) * (cplx ? 2 : 1);
+  const int64_t parts = cplx ? 2 : 1;
+  const int64_t small = std::max<int64_t>(1024 * tile * tile, 16 * int64_t(nb) * nb) * parts;
+  const int64_t balanced = std::min<int64_t>(64 * 2 * int64_t(nb) * nb * parts, int64_t{64} << 20);
+  return static_cast<size_t>(std::max(small, balanced));
 }
 
 size_t split_c_bytes(int nb, bool cplx) {

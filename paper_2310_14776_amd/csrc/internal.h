@@ -265,6 +265,17 @@ int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const 
                     int nb, void *H, void *S, hipStream_t st, double *part = nullptr,
                     size_t part_elems = 0);
 size_t subspace_part_elems(const gpaw_sys *s, int nb);
+// Split-K planning (gemm.hip). A product whose K range is cut into ns
+// pieces launches units workgroups per piece (8 or more pieces are launched
+// in whole groups of 8, one per XCD), slots of them resident at a time. The
+// count returned minimises the modelled time: whole rounds of resident
+// workgroups, each doing 1/ns of a tile's work (tile_s: one tile over the
+// whole K range with every slot busy), plus the partial sums' traffic per
+// piece (part_s); at most max_split, and at least min_k of K per piece.
+int64_t balanced_splits(int64_t units, int64_t slots, double tile_s, double part_s,
+                        int64_t max_split, int64_t k, int64_t min_k);
+// Workgroups of a kernel resident on the whole device at once.
+int64_t resident_slots(const void *kern, int threads, size_t lds);
 // upper: C is upper triangular; near_id: C is close to the identity (the
 // single-precision form then rotates by C - I, see the split kernels)
 // nout >= 0: only the first nout output rows (C is still nb x nb; its first
