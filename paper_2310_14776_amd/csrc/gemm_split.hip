@@ -130,6 +130,15 @@ __device__ inline void split_store8(const float *x, __bf16 *ph, __bf16 *pm, __bf
   *reinterpret_cast<bf8 *>(pl) = l;
 }
 
+// eight consecutive values -> their high BF16 parts only (the one-product
+// rotation near the identity)
+__device__ inline void hi_store8(const float *x, __bf16 *ph) {
+  bf8 h;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) h[e] = top_half(bf16_rne(__float_as_uint(x[e])));
+  *reinterpret_cast<bf8 *>(ph) = h;
+}
+
 // eight consecutive values p[0..7] (zero where e >= avail or !row_ok), as
 // 16-byte loads when the address allows
 template <typename T>
@@ -147,11 +156,15 @@ __device__ inline void load8(const T *p, bool row_ok, int64_t avail, T *v) {
   }
 }
 
-__device__ inline Split8 frag(const __bf16 *plane0, int plane_stride, int off) {
+// hi_only: the high plane alone (the others are left unset)
+__device__ inline Split8 frag(const __bf16 *plane0, int plane_stride, int off,
+                              bool hi_only = false) {
   Split8 f;
   f.h = *reinterpret_cast<const bf8 *>(plane0 + off);
-  f.m = *reinterpret_cast<const bf8 *>(plane0 + plane_stride + off);
-  f.l = *reinterpret_cast<const bf8 *>(plane0 + 2 * plane_stride + off);
+  if (!hi_only) {
+    f.m = *reinterpret_cast<const bf8 *>(plane0 + plane_stride + off);
+    f.l = *reinterpret_cast<const bf8 *>(plane0 + 2 * plane_stride + off);
+  }
   return f;
 }
 
@@ -431,6 +444,7 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
   const int bg = tid % TM, bm = (tid / TM) * MPT;
   float rb[NP][MPT];
   const T *srcg = src + std::min<int64_t>(g0 + bg, cols - 1);
+  const bool one = ADDSRC && fewer && *fewer != 0;
   auto fetch = [&](int step) {
     const int m0 = std::min(step, nsteps - 1) * KR;
 #pragma unroll
@@ -440,10 +454,11 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
       for (int c = 0; c < NP; ++c)
 #pragma unroll
         for (int p = 0; p < 3; ++p)
+          if (p == 0 || !one)  // one product: the high parts only
 #pragma unroll
-          for (int h = 0; h < 2; ++h)
-            ca[ps][c][p][h] = *reinterpret_cast<const bf8 *>(
-                Ct + (3 * c + p) * np + static_cast<int64_t>(n) * nbp + m0 + sc + 32 * h);
+            for (int h = 0; h < 2; ++h)
+              ca[ps][c][p][h] = *reinterpret_cast<const bf8 *>(
+                  Ct + (3 * c + p) * np + static_cast<int64_t>(n) * nbp + m0 + sc + 32 * h);
     }
 #pragma unroll
     for (int e = 0; e < MPT; ++e) {
@@ -460,22 +475,23 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
       for (int c = 0; c < NP; ++c)
 #pragma unroll
         for (int p = 0; p < 3; ++p)
+          if (p == 0 || !one)
 #pragma unroll
-          for (int h = 0; h < 2; ++h)
-            *reinterpret_cast<bf8 *>(sA + (c * 3 + p) * PS + (ps * 64 + sr) * LROWR + sc + 32 * h) =
-                ca[ps][c][p][h];
+            for (int h = 0; h < 2; ++h)
+              *reinterpret_cast<bf8 *>(sA + (c * 3 + p) * PS + (ps * 64 + sr) * LROWR + sc +
+                                       32 * h) = ca[ps][c][p][h];
 #pragma unroll
     for (int c = 0; c < NP; ++c)
 #pragma unroll
       for (int h = 0; h < MPT / 8; ++h) {
         const int o = (c * 3) * PS + bg * LROWR + bm + 8 * h;
-        split_store8(rb[c] + 8 * h, sB + o, sB + o + PS, sB + o + 2 * PS);
+        if (one) hi_store8(rb[c] + 8 * h, sB + o);
+        else split_store8(rb[c] + 8 * h, sB + o, sB + o + PS, sB + o + 2 * PS);
       }
   };
 
   const int wr = wave >> 1, wc = wave & 1;
   const int fr = lane & 15, fk = (lane >> 4) * 8;
-  const bool one = ADDSRC && fewer && *fewer != 0;
   d4 dacc[NP][WT][WT];
   f4 facc[NP][WT][WT];
 #pragma unroll
@@ -500,13 +516,15 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
       for (int i = 0; i < WT; ++i)
 #pragma unroll
         for (int c = 0; c < NP; ++c)
-          fa[c][i] = frag(sA + (c * 3) * PS, PS, (wr * 16 * WT + i * 16 + fr) * LROWR + 32 * kh + fk);
+          fa[c][i] = frag(sA + (c * 3) * PS, PS, (wr * 16 * WT + i * 16 + fr) * LROWR + 32 * kh + fk,
+                          one);
 #pragma unroll
       for (int j = 0; j < WT; ++j) {
         Split8 fb[NP];
 #pragma unroll
         for (int c = 0; c < NP; ++c)
-          fb[c] = frag(sB + (c * 3) * PS, PS, (wc * 16 * WT + j * 16 + fr) * LROWR + 32 * kh + fk);
+          fb[c] = frag(sB + (c * 3) * PS, PS, (wc * 16 * WT + j * 16 + fr) * LROWR + 32 * kh + fk,
+                       one);
 #pragma unroll
         for (int i = 0; i < WT; ++i) {
           // C psi: re = Cr pr - Ci pi, im = Cr pi + Ci pr
