@@ -76,7 +76,8 @@ enum gpaw_status {
   GPAW_EHIP = -5,         /* HIP runtime or launch failure               */
   GPAW_ENOTPD = -6,       /* S_nm is not positive definite               */
   GPAW_ENOMEM = -7,       /* device or host allocation failed            */
-  GPAW_ENOCONV = -8       /* eigenvector orthogonalisation did not settle */
+  GPAW_ENOCONV = -8,      /* eigenvector orthogonalisation did not settle */
+  GPAW_ENONFINITE = -9    /* a non-finite value where a finite one is due */
 };
 
 /* Storage/arithmetic type of the wave functions. GPAW_F32 and GPAW_C64 are
@@ -308,6 +309,60 @@ GPAW_API const char *gpaw_last_error(void);
 
 /* GPAW_FD_VERSION of the built library. */
 GPAW_API int gpaw_version(void);
+
+/* ------------------------------------------------------------------------
+ * Poisson equation of a finite system (Sec. "Solving the Kohn-Sham
+ * equation": iterative multigrid Poisson solvers with Jacobi smoothing; for
+ * finite systems the potential vanishes on the cell boundary) and the grid
+ * transfers between uniform grids it uses (interpolation is one of the C
+ * hot spots, Sec. "Developer's perspective").
+ *
+ * Zero-boundary grid: n[c] interior points per axis at x = i h_c,
+ * i = 1..n[c]; values vanish at i <= 0 and i >= n[c] + 1 (also for the
+ * stencil's reach of three points). Arrays are real FP64 [n0][n1][n2],
+ * device memory owned by the caller. The discrete operator is the 19-point
+ * 6th-order Laplacian of the kinetic term (weights above).
+ * ------------------------------------------------------------------------ */
+typedef struct gpaw_poisson gpaw_poisson;
+
+/* Multigrid hierarchy for an n0 x n1 x n2 zero-boundary grid of spacing h
+ * (host arrays of 3). Levels halve while every axis is odd and >= 3
+ * (N = 2m + 1 -> m; coarse point j on fine point 2j + 1, 0-based); the
+ * library allocates each level's right-hand side and scratch (about 2.3 x
+ * the fine grid in total). GPAW_ESHAPE for grids above 2^31 points,
+ * GPAW_ENOMEM when the device allocations fail. */
+GPAW_API int gpaw_poisson_create(const int32_t *n, const double *h, gpaw_poisson **out);
+GPAW_API void gpaw_poisson_destroy(gpaw_poisson *p);
+/* Number of levels (1 = the grid does not coarsen). */
+GPAW_API int gpaw_poisson_levels(const gpaw_poisson *p, int32_t *levels);
+
+/* Solves nabla^2 phi = -4 pi rho. phi is the initial guess on entry and the
+ * solution on return; V-cycles (two weighted-Jacobi sweeps, omega = 0.8,
+ * before and after each coarse correction; the coarsest level smoothed with
+ * 20 x its largest axis sweeps) run until ||f - A phi|| <= tol ||f||
+ * (f = -4 pi rho, 2-norms) or max_cycles. Synchronous: waits for `stream`
+ * after every cycle to read the residual. cycles / rel_residual (host,
+ * optional) receive the count and the final relative residual. rho and phi
+ * must not alias (GPAW_EALIAS); GPAW_ENONFINITE when the residual is not
+ * finite. Calls on one hierarchy must not overlap (shared scratch). */
+GPAW_API int gpaw_poisson_solve(gpaw_poisson *p, const double *rho, double *phi, double tol,
+                                int32_t max_cycles, int32_t *cycles, double *rel_residual,
+                                void *stream);
+
+/* out = nabla^2 f on the zero-boundary grid (n, h host arrays of 3). */
+GPAW_API int gpaw_laplacian_zero(const int32_t *n, const double *h, const double *f,
+                                 double *out, void *stream);
+
+/* Full-weighting restriction fine (nf) -> coarse ((nf - 1) / 2 per axis):
+ * coarse[j] = sum_d prod_c w(d_c) fine[2j + 1 + d], w = (1/4, 1/2, 1/4).
+ * Every axis of nf odd and >= 3 (GPAW_ESHAPE otherwise). */
+GPAW_API int gpaw_grid_restrict(const int32_t *nf, const double *fine, double *coarse,
+                                void *stream);
+/* Trilinear interpolation coarse ((nf - 1) / 2) -> fine (nf): weight 1 on
+ * the coarse point, 1/2 beside it, zero past the faces; accumulate != 0
+ * adds into fine instead of overwriting it. Same shape rule. */
+GPAW_API int gpaw_grid_interpolate(const int32_t *nf, const double *coarse, double *fine,
+                                   int32_t accumulate, void *stream);
 
 /* Measurement probes (they compute nothing of the method): the ceilings the
  * roofline fractions are also stated against, timed by the caller.

@@ -17,7 +17,7 @@ GPAW_F64, GPAW_C128, GPAW_F32, GPAW_C64 = 0, 1, 2, 3
 
 STATUS = {0: "GPAW_OK", -1: "GPAW_EINVAL", -2: "GPAW_EDTYPE", -3: "GPAW_ESHAPE",
           -4: "GPAW_EALIAS", -5: "GPAW_EHIP", -6: "GPAW_ENOTPD", -7: "GPAW_ENOMEM",
-          -8: "GPAW_ENOCONV"}
+          -8: "GPAW_ENOCONV", -9: "GPAW_ENONFINITE"}
 
 
 class GpawError(RuntimeError):
@@ -49,7 +49,10 @@ ENTRY_POINTS = ["gpaw_sys_create", "gpaw_sys_destroy", "gpaw_sys_info", "gpaw_pr
                 "gpaw_subspace_diag", "gpaw_rotate", "gpaw_orthonormalize",
                 "gpaw_batch_create", "gpaw_batch_destroy", "gpaw_batch_step",
                 "gpaw_batch_tune", "gpaw_batch_tuning",
-                "gpaw_last_error", "gpaw_version", "gpaw_probe_copy", "gpaw_probe_mfma"]
+                "gpaw_last_error", "gpaw_version", "gpaw_probe_copy", "gpaw_probe_mfma",
+                "gpaw_poisson_create", "gpaw_poisson_destroy", "gpaw_poisson_levels",
+                "gpaw_poisson_solve", "gpaw_laplacian_zero", "gpaw_grid_restrict",
+                "gpaw_grid_interpolate"]
 
 
 class BatchIO(ctypes.Structure):
@@ -96,11 +99,21 @@ def load():
     lib.gpaw_batch_step.argtypes = [vp, ctypes.POINTER(BatchIO), vp, vp]
     lib.gpaw_batch_tune.argtypes = [vp, ctypes.POINTER(BatchIO), vp]
     lib.gpaw_batch_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    i32p, f64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
+    lib.gpaw_poisson_create.argtypes = [i32p, f64p, ctypes.POINTER(vp)]
+    lib.gpaw_poisson_destroy.argtypes = [vp]
+    lib.gpaw_poisson_destroy.restype = None
+    lib.gpaw_poisson_levels.argtypes = [vp, i32p]
+    lib.gpaw_poisson_solve.argtypes = [vp, vp, vp, ctypes.c_double, i32, i32p, f64p, vp]
+    lib.gpaw_laplacian_zero.argtypes = [i32p, f64p, vp, vp, vp]
+    lib.gpaw_grid_restrict.argtypes = [i32p, vp, vp, vp]
+    lib.gpaw_grid_interpolate.argtypes = [i32p, vp, vp, i32, vp]
     lib.gpaw_last_error.restype = ctypes.c_char_p
     lib.gpaw_last_error.argtypes = []
     lib.gpaw_version.argtypes = []
     for name in ENTRY_POINTS:
-        if name not in ("gpaw_sys_destroy", "gpaw_batch_destroy", "gpaw_last_error"):
+        if name not in ("gpaw_sys_destroy", "gpaw_batch_destroy", "gpaw_last_error",
+                        "gpaw_poisson_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -400,3 +413,90 @@ def probe_mfma(kind, out, workgroups, iters, stream=None):
     if out.numel() < workgroups * 256:
         raise ValueError("out needs workgroups x 256 values")
     _check(load().gpaw_probe_mfma(kind, _ptr(out), workgroups, iters, _stream(stream)))
+
+
+def _i3(n):
+    return (ctypes.c_int32 * 3)(*[int(x) for x in n])
+
+
+def _d3(h):
+    return (ctypes.c_double * 3)(*[float(x) for x in h])
+
+
+def _grid_f64(t, shape, name):
+    if t.dtype != torch.float64 or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be a float64 tensor of shape {tuple(shape)}")
+
+
+class Poisson:
+    """Multigrid solver of nabla^2 phi = -4 pi rho on a zero-boundary grid
+    (gpaw_poisson_create / _solve / _destroy)."""
+
+    def __init__(self, n, h):
+        self.n = tuple(int(x) for x in n)
+        self.h = tuple(float(x) for x in h)
+        handle = ctypes.c_void_p()
+        _check(load().gpaw_poisson_create(_i3(self.n), _d3(self.h), ctypes.byref(handle)))
+        self._p = handle
+
+    @property
+    def levels(self):
+        v = ctypes.c_int32()
+        _check(load().gpaw_poisson_levels(self._p, ctypes.byref(v)))
+        return v.value
+
+    def solve(self, rho, phi=None, tol=1e-12, max_cycles=100, stream=None):
+        """phi (initial guess, zeros if None) -> (phi, cycles, relative residual)."""
+        _grid_f64(rho, self.n, "rho")
+        if phi is None:
+            phi = torch.zeros_like(rho)
+        _grid_f64(phi, self.n, "phi")
+        cyc, res = ctypes.c_int32(), ctypes.c_double()
+        _check(load().gpaw_poisson_solve(self._p, _ptr(rho), _ptr(phi), float(tol),
+                                         int(max_cycles), ctypes.byref(cyc), ctypes.byref(res),
+                                         _stream(stream)))
+        return phi, cyc.value, res.value
+
+    def close(self):
+        if self._p:
+            load().gpaw_poisson_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def laplacian_zero(f, h, out=None, stream=None):
+    """gpaw_laplacian_zero: nabla^2 f on the zero-boundary grid."""
+    if out is None:
+        out = torch.empty_like(f)
+    _grid_f64(f, f.shape, "f")
+    _grid_f64(out, f.shape, "out")
+    _check(load().gpaw_laplacian_zero(_i3(f.shape), _d3(h), _ptr(f), _ptr(out), _stream(stream)))
+    return out
+
+
+def grid_restrict(fine, out=None, stream=None):
+    """gpaw_grid_restrict: full weighting onto the (n - 1) / 2 grid."""
+    nc = tuple((m - 1) // 2 for m in fine.shape)
+    if out is None:
+        out = torch.empty(nc, dtype=torch.float64, device=fine.device)
+    _grid_f64(fine, fine.shape, "fine")
+    _grid_f64(out, nc, "out")
+    _check(load().gpaw_grid_restrict(_i3(fine.shape), _ptr(fine), _ptr(out), _stream(stream)))
+    return out
+
+
+def grid_interpolate(coarse, nf, out=None, accumulate=False, stream=None):
+    """gpaw_grid_interpolate: trilinear interpolation onto the nf grid."""
+    nf = tuple(int(x) for x in nf)
+    if out is None:
+        out = torch.zeros(nf, dtype=torch.float64, device=coarse.device)
+    _grid_f64(coarse, tuple((m - 1) // 2 for m in nf), "coarse")
+    _grid_f64(out, nf, "out")
+    _check(load().gpaw_grid_interpolate(_i3(nf), _ptr(coarse), _ptr(out), 1 if accumulate else 0,
+                                        _stream(stream)))
+    return out
