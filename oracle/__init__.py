@@ -27,7 +27,7 @@ from .subspace import (subspace_matrices, hermiticity_defect, diagonalize,
 from .step import Operators, fd_step
 from .density import pseudo_density, atomic_density_matrices, paw_norm
 from .davidson import kinetic_diagonal, precondition, davidson_step
-from . import poisson
+from . import poisson, tddft
 
 __all__ = ["WEIGHTS", "laplacian", "kinetic", "symbol_1d", "radial_norm",
            "solid_harmonics", "projector_values", "projector_matrix",
@@ -36,4 +36,4 @@ __all__ = ["WEIGHTS", "laplacian", "kinetic", "symbol_1d", "radial_norm",
            "subspace_matrices", "hermiticity_defect", "diagonalize", "rotate",
            "orthonormalize",
            "Operators", "fd_step", "pseudo_density", "atomic_density_matrices", "paw_norm",
-           "kinetic_diagonal", "precondition", "davidson_step", "poisson"]
+           "kinetic_diagonal", "precondition", "davidson_step", "poisson", "tddft"]
