@@ -20,7 +20,12 @@
  *   (bohr); point (i,j,l) sits at (i h0, j h1, l h2); axis 2 is contiguous.
  *   Ng = n0*n1*n2, dV = h0*h1*h2; integrals are dV times grid sums.
  * Boundary: Bloch, psi(r + L_c e_c) = exp(2 pi i k_c) psi(r), k in reduced
- *   units; k = 0 is the periodic (real) case.
+ *   units; k = 0 is the periodic (real) case. A system created with
+ *   boundary = 1 is finite instead: every value outside the grid is zero
+ *   (for the stencil's reach of three points too) and projector spheres do
+ *   not wrap (Sec. "Solving the Kohn-Sham equation": for 0-D systems the
+ *   potential vanishes on the cell boundary; the time propagation of
+ *   Sec. "Real-time TDDFT" needs such boundaries).
  * Kinetic operator: per axis the 6th-order central second difference,
  *   weights (1/90, -3/20, 3/2, -49/18, 3/2, -3/20, 1/90)/h_c^2 (19-point star).
  * Projectors: every atom carries the same channel list; channel (l, sigma, rc)
@@ -106,6 +111,9 @@ typedef struct {
   const double *dS;         /* host [natoms][ni][ni], Delta S^a (real symmetric) */
   const double *v;          /* host [n0][n1][n2], local potential v~ (Ha) */
   int32_t max_bands;        /* largest nb any call will pass, >= 1 */
+  int32_t boundary;         /* 0: periodic / Bloch (above); 1: zero boundary,
+                               a finite system (values vanish outside the
+                               n0 x n1 x n2 points, no periodic images; k = 0) */
 } gpaw_sys_desc;
 
 typedef struct gpaw_sys gpaw_sys;
@@ -309,6 +317,39 @@ GPAW_API const char *gpaw_last_error(void);
 
 /* GPAW_FD_VERSION of the built library. */
 GPAW_API int gpaw_version(void);
+
+/* ------------------------------------------------------------------------
+ * Real-time propagation (Sec. "Real-time TDDFT", Eq. (td_ks)):
+ * i S~ d psi~_n / dt = H~ psi~_n with S~ fixed; FD propagation needs the
+ * finite (boundary = 1) systems above, and k = 0 in any case. complex128
+ * wave functions only (GPAW_EDTYPE otherwise). Allocates, on first use, a
+ * workspace of 5 x max_bands x Ng complex values kept until the system is
+ * destroyed (GPAW_ENOMEM when that fails).
+ * ------------------------------------------------------------------------ */
+
+/* psi_n <- exp(-i kappa . r) psi_n at r = (i h0, j h1, l h2): the delta kick
+ * of strength |kappa| (kappa: host [3], 1/bohr) on the pseudo wave
+ * functions. Enqueues only. */
+GPAW_API int gpaw_td_kick(gpaw_sys *sys, void *psi, int32_t nb, const double *kappa,
+                          void *stream);
+
+/* d[c] = sum_n f_n dV sum_r r_c |psi_n(r)|^2 (device f [nb], device d [3]):
+ * the dipole of the pseudo density, summed in a fixed order. Enqueues only. */
+GPAW_API int gpaw_td_dipole(gpaw_sys *sys, const void *psi, int32_t nb, const double *f,
+                            double *d, void *stream);
+
+/* One Crank-Nicolson step, in place: (S~ + i dt/2 H~) psi(t + dt) =
+ * (S~ - i dt/2 H~) psi(t) with H~ held fixed over the step, solved per band
+ * by conjugate orthogonal CG (M is complex symmetric for k = 0) from
+ * psi(t), until every band's ||r|| <= tol ||rhs|| or max_iter iterations.
+ * Synchronous: reads the residual norms after each iteration. iters /
+ * rel_residual (host, optional): iterations run and the largest relative
+ * residual. GPAW_ENOCONV when tol was not reached (psi then holds the last
+ * iterate), GPAW_ENONFINITE for a non-finite residual, GPAW_EINVAL for
+ * k != 0. */
+GPAW_API int gpaw_td_propagate(gpaw_sys *sys, void *psi, int32_t nb, double dt, double tol,
+                               int32_t max_iter, int32_t *iters, double *rel_residual,
+                               void *stream);
 
 /* ------------------------------------------------------------------------
  * Poisson equation of a finite system (Sec. "Solving the Kohn-Sham

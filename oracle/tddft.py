@@ -32,12 +32,40 @@ from .projectors import projector_values
 from .paw import block_diag_atoms
 
 
-def projector_matrix_zero(n, h, pos, channels):
+def projector_matrix_zero(n, h, pos, channels, sparse=False):
     """Q[a*ni + i, g] of a finite system: each sphere's own values, no
-    images, points outside the grid dropped."""
+    images, points outside the grid dropped (sparse: CSR, visiting only the
+    box around each sphere)."""
     n = tuple(n)
     ni = sum(2 * l + 1 for (l, _, _) in channels)
     rmax = max(rc for (_, _, rc) in channels)
+    if sparse:
+        from scipy.sparse import coo_matrix
+        rows, cols, vals = [], [], []
+        for a in range(pos.shape[0]):
+            axes = []
+            for c in range(3):
+                lo = max(0, int(np.floor((pos[a, c] - rmax) / h[c])))
+                hi = min(n[c] - 1, int(np.ceil((pos[a, c] + rmax) / h[c])))
+                axes.append(np.arange(lo, hi + 1))
+            if any(len(ax) == 0 for ax in axes):
+                continue
+            I, J, K = np.meshgrid(*axes, indexing="ij")
+            dx = I.ravel() * h[0] - pos[a, 0]
+            dy = J.ravel() * h[1] - pos[a, 1]
+            dz = K.ravel() * h[2] - pos[a, 2]
+            inside = dx * dx + dy * dy + dz * dz < rmax * rmax
+            g = ((I.ravel() * n[1] + J.ravel()) * n[2] + K.ravel())[inside]
+            v = projector_values(channels, dx[inside], dy[inside], dz[inside])
+            for i in range(ni):
+                rows.append(np.full(g.size, a * ni + i))
+                cols.append(g)
+                vals.append(v[i])
+        shape = (pos.shape[0] * ni, int(np.prod(n)))
+        if not rows:
+            return coo_matrix(shape).tocsr()
+        return coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                          shape=shape).tocsr()
     X, Y, Z = np.meshgrid(*[np.arange(n[c]) * h[c] for c in range(3)], indexing="ij")
     X, Y, Z = X.ravel(), Y.ravel(), Z.ravel()
     Q = np.zeros((pos.shape[0] * ni, X.size))
@@ -53,21 +81,25 @@ def projector_matrix_zero(n, h, pos, channels):
 class FiniteOps:
     """H~ and S~ of a finite (zero-boundary, k = 0) system on [nb, Ng] blocks."""
 
-    def __init__(self, n, h, v, pos, channels, dH, dS):
+    def __init__(self, n, h, v, pos, channels, dH, dS, sparse=False):
         self.n, self.h = tuple(n), tuple(h)
         self.v = np.asarray(v, dtype=float).ravel()
-        self.Q = projector_matrix_zero(n, h, np.asarray(pos).reshape(-1, 3), channels) \
+        self.Q = projector_matrix_zero(n, h, np.asarray(pos).reshape(-1, 3), channels, sparse) \
             if len(pos) else np.zeros((0, int(np.prod(n))))
         self.DH = block_diag_atoms(np.asarray(dH))
         self.DS = block_diag_atoms(np.asarray(dS))
         self.dV = float(np.prod(h))
 
     @classmethod
-    def from_system(cls, s):
-        return cls(s.n, s.h, s.v, s.pos, s.channels, s.dH, s.dS)
+    def from_system(cls, s, sparse=False):
+        return cls(s.n, s.h, s.v, s.pos, s.channels, s.dH, s.dS, sparse)
 
     def project(self, psi):
-        return self.dV * (psi @ self.Q.T)
+        return self.dV * (self.Q @ psi.T).T
+
+    def _addback(self, X):
+        """sum_ai Q[ai, g] X[n, ai] for each band n."""
+        return (self.Q.T @ X.T).T
 
     def apply_H(self, psi, P=None):
         nb = psi.shape[0]
@@ -78,14 +110,14 @@ class FiniteOps:
         out = out + self.v[None, :] * psi
         if self.Q.shape[0]:
             P = self.project(psi) if P is None else P
-            out = out + (P @ self.DH.T) @ self.Q
+            out = out + self._addback(P @ self.DH.T)
         return out
 
     def apply_S(self, psi, P=None):
         out = np.array(psi, dtype=np.result_type(psi.dtype, 1.0), copy=True)
         if self.Q.shape[0]:
             P = self.project(psi) if P is None else P
-            out = out + (P @ self.DS.T) @ self.Q
+            out = out + self._addback(P @ self.DS.T)
         return out
 
     def dense(self):

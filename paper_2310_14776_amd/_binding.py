@@ -37,7 +37,7 @@ class SysDesc(ctypes.Structure):
                 ("pos", ctypes.POINTER(ctypes.c_double)), ("nchan", ctypes.c_int32),
                 ("chan", ctypes.POINTER(Channel)), ("dH", ctypes.POINTER(ctypes.c_double)),
                 ("dS", ctypes.POINTER(ctypes.c_double)), ("v", ctypes.POINTER(ctypes.c_double)),
-                ("max_bands", ctypes.c_int32)]
+                ("max_bands", ctypes.c_int32), ("boundary", ctypes.c_int32)]
 
 
 _lib = None
@@ -52,7 +52,7 @@ ENTRY_POINTS = ["gpaw_sys_create", "gpaw_sys_destroy", "gpaw_sys_info", "gpaw_pr
                 "gpaw_last_error", "gpaw_version", "gpaw_probe_copy", "gpaw_probe_mfma",
                 "gpaw_poisson_create", "gpaw_poisson_destroy", "gpaw_poisson_levels",
                 "gpaw_poisson_solve", "gpaw_laplacian_zero", "gpaw_grid_restrict",
-                "gpaw_grid_interpolate"]
+                "gpaw_grid_interpolate", "gpaw_td_kick", "gpaw_td_dipole", "gpaw_td_propagate"]
 
 
 class BatchIO(ctypes.Structure):
@@ -108,6 +108,10 @@ def load():
     lib.gpaw_laplacian_zero.argtypes = [i32p, f64p, vp, vp, vp]
     lib.gpaw_grid_restrict.argtypes = [i32p, vp, vp, vp]
     lib.gpaw_grid_interpolate.argtypes = [i32p, vp, vp, i32, vp]
+    lib.gpaw_td_kick.argtypes = [vp, vp, i32, f64p, vp]
+    lib.gpaw_td_dipole.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.gpaw_td_propagate.argtypes = [vp, vp, i32, ctypes.c_double, ctypes.c_double, i32, i32p,
+                                      f64p, vp]
     lib.gpaw_last_error.restype = ctypes.c_char_p
     lib.gpaw_last_error.argtypes = []
     lib.gpaw_version.argtypes = []
@@ -145,7 +149,7 @@ class System:
     """One FD-PAW system on the current GPU (owns the library's gpaw_sys)."""
 
     def __init__(self, n, h, k, pos, channels, dH, dS, v, max_bands, complex_=None,
-                 precision="double"):
+                 precision="double", boundary="periodic"):
         lib = load()
         k = tuple(float(x) for x in k)
         if complex_ is None:
@@ -183,6 +187,10 @@ class System:
         d.dS = self._keep[2].ctypes.data_as(dp)
         d.v = self._keep[3].ctypes.data_as(dp)
         d.max_bands = int(max_bands)
+        if boundary not in ("periodic", "zero"):
+            raise ValueError("boundary must be 'periodic' or 'zero'")
+        d.boundary = 1 if boundary == "zero" else 0
+        self.boundary = boundary
         handle = ctypes.c_void_p()
         _check(lib.gpaw_sys_create(ctypes.byref(d), ctypes.byref(handle)))
         self._h = handle
@@ -197,9 +205,38 @@ class System:
         self.device = torch.device("cuda", torch.cuda.current_device())
 
     @classmethod
-    def from_synth(cls, s, max_bands=None, precision="double"):
+    def from_synth(cls, s, max_bands=None, precision="double", boundary=None):
+        """boundary: 'periodic' or 'zero' (default: the system's own, if it
+        names one, else periodic)."""
+        boundary = boundary or getattr(s, "meta", {}).get("boundary", "periodic")
         return cls(s.n, s.h, s.k, s.pos, s.channels, s.dH, s.dS, s.v,
-                   max_bands or s.nb, complex_=s.is_complex, precision=precision)
+                   max_bands or s.nb, complex_=s.is_complex, precision=precision,
+                   boundary=boundary)
+
+    # real-time propagation (finite systems, complex128)
+    def td_kick(self, psi, kappa, stream=None):
+        """gpaw_td_kick: psi <- exp(-i kappa . r) psi, in place."""
+        k = (ctypes.c_double * 3)(*[float(x) for x in kappa])
+        _check(load().gpaw_td_kick(self._h, _ptr(psi), psi.shape[0], k, _stream(stream)))
+        return psi
+
+    def td_dipole(self, psi, f, out=None, stream=None):
+        """gpaw_td_dipole: pseudo-density dipole (device tensor of 3)."""
+        if out is None:
+            out = torch.empty(3, dtype=torch.float64, device=psi.device)
+        f = f.to(device=psi.device, dtype=torch.float64).contiguous()
+        _check(load().gpaw_td_dipole(self._h, _ptr(psi), psi.shape[0], _ptr(f), _ptr(out),
+                                     _stream(stream)))
+        return out
+
+    def td_propagate(self, psi, dt, tol=1e-12, max_iter=200, stream=None):
+        """gpaw_td_propagate: one Crank-Nicolson step in place; returns
+        (iterations, largest relative residual)."""
+        it, res = ctypes.c_int32(), ctypes.c_double()
+        _check(load().gpaw_td_propagate(self._h, _ptr(psi), psi.shape[0], float(dt), float(tol),
+                                        int(max_iter), ctypes.byref(it), ctypes.byref(res),
+                                        _stream(stream)))
+        return it.value, res.value
 
     def close(self):
         if getattr(self, "_h", None):

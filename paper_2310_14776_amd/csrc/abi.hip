@@ -105,6 +105,8 @@ void free_sys(gpaw_sys *s) {
                   s->ws.split,    s->ws.mat,  s->ws.XS,     s->ws.flag};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
+  if (s->td) (void)hipFree(s->td);
+  if (s->td_host) (void)hipHostFree(s->td_host);
   delete s;
 }
 
@@ -145,6 +147,10 @@ int gpaw_sys_create(const gpaw_sys_desc *d, gpaw_sys **out) {
   if (d->natoms < 0) return fail(GPAW_EINVAL, "natoms must be >= 0");
   if (!d->v) return fail(GPAW_EINVAL, "v must not be NULL");
   if (d->max_bands < 1) return fail(GPAW_EINVAL, "max_bands must be >= 1");
+  if (d->boundary != 0 && d->boundary != 1)
+    return fail(GPAW_EINVAL, "boundary must be 0 (periodic / Bloch) or 1 (zero)");
+  if (d->boundary == 1 && (d->k[0] != 0.0 || d->k[1] != 0.0 || d->k[2] != 0.0))
+    return fail(GPAW_EINVAL, "a zero-boundary system has no Bloch vector: k must be 0");
   int ni = 0;
   if (d->natoms > 0) {
     if (!d->pos || !d->dH || !d->dS || !d->chan || d->nchan < 1)
@@ -169,6 +175,7 @@ int gpaw_sys_create(const gpaw_sys_desc *d, gpaw_sys **out) {
     s->phase[c] = zmake(std::cos(arg), std::sin(arg));
   }
   s->dV = d->h[0] * d->h[1] * d->h[2];
+  s->zbc = d->boundary;
   s->dtype = d->dtype;
   s->natoms = d->natoms;
   s->ni = d->natoms > 0 ? ni : 0;

@@ -191,6 +191,10 @@ struct gpaw_sys {
   int32_t natoms = 0, ni = 0, np = 0;
   int64_t ng = 0;
   int32_t max_bands = 0;
+  int32_t zbc = 0;  // zero boundary (finite system)
+  void *td = nullptr;       // time-propagation workspace (allocated on first use)
+  void *td_host = nullptr;  // pinned residual norms of the time propagation
+  size_t td_bytes = 0;
   gfd::Tables tab;
   gfd::ProjDev proj;                    // projector parameters (host copy)
   double *dH = nullptr, *dS = nullptr;  // device [natoms][ni][ni]

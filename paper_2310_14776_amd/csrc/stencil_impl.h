@@ -51,6 +51,7 @@ struct PlaneGeom {
   int TY, TZ, LS;             // tile rows (y), columns (z), LDS row stride TZ + 6
   int tiles_z, tiles;         // tiles per plane
   int xseg, nseg, ngroups;    // planes per x segment, x segments, band groups
+  int zbc;                    // zero boundary: values past the faces are zero
 };
 
 struct AddArgs {
@@ -389,6 +390,7 @@ __global__ __launch_bounds__(PT_THREADS) void k_plane(const T *__restrict__ psi,
   const int W = TZe + 6;
   const int nh = 6 * W + 6 * TYe;
   int hoff[HPL], hl[HPL];
+  bool hzero[HPL];  // zero boundary, real kernels: the cell lies past a face
   z64 hph[HPL];
 #pragma unroll
   for (int k = 0; k < HPL; ++k) {
@@ -411,6 +413,7 @@ __global__ __launch_bounds__(PT_THREADS) void k_plane(const T *__restrict__ psi,
     const int wy = fold_count(yg, n1), wz = fold_count(zg, n2);
     hoff[k] = (yg - wy * n1) * n2 + (zg - wz * n2);
     hph[k] = BLOCH ? G.phy[clamp3(wy) + 3] * G.phz[clamp3(wz) + 3] : zmake(1.0, 0.0);
+    hzero[k] = !BLOCH && G.zbc && (wy != 0 || wz != 0);
     hl[k] = h < nh ? r * LS + c : spare;
   }
 
@@ -439,10 +442,13 @@ __global__ __launch_bounds__(PT_THREADS) void k_plane(const T *__restrict__ psi,
         for (int k = 0; k < PPL; ++k)
           dst[b][k] = St<T>::narrow(St<A>::phase(St<T>::widen(src[b][k]), ph));
     } else {
+      // zero boundary: a plane past a face is zero (uniform over the
+      // workgroup: one scalar test per plane)
+      const bool past = G.zbc && (xp < 0 || xp >= n0);
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int k = 0; k < PPL; ++k) dst[b][k] = src[b][k];
+        for (int k = 0; k < PPL; ++k) dst[b][k] = past ? T{} : src[b][k];
     }
   };
   // halo values of plane xp (inside the grid), as loaded (phases at the
@@ -506,7 +512,8 @@ __global__ __launch_bounds__(PT_THREADS) void k_plane(const T *__restrict__ psi,
 #pragma unroll
         for (int j = 0; j < HPL; ++j)
           L[b * cells + hl[j]] =
-              BLOCH ? St<T>::narrow(St<A>::phase(St<T>::widen(hq[k][b][j]), hph[j])) : hq[k][b][j];
+              BLOCH ? St<T>::narrow(St<A>::phase(St<T>::widen(hq[k][b][j]), hph[j]))
+                    : (hzero[j] ? T{} : hq[k][b][j]);
       }
       // one barrier per plane: the buffer written next step was last read
       // before every lane arrived here
@@ -676,10 +683,12 @@ PlaneGeom make_geom(const gpaw_sys *s, int ngroups, int ppl) {
     ph[c][3] = pw;
     for (int w = 1; w <= 3; ++w) {
       pw = pw * p;
-      ph[c][3 + w] = pw;
-      ph[c][3 - w] = zconj(pw);
+      // zero boundary: a neighbour past a face is zero (factor 0)
+      ph[c][3 + w] = s->zbc ? zmake(0.0, 0.0) : pw;
+      ph[c][3 - w] = s->zbc ? zmake(0.0, 0.0) : zconj(pw);
     }
   }
+  G.zbc = s->zbc;
   const int TILE = PT_THREADS * ppl;
   const auto best = tile_candidates(s->n[1], s->n[2], ppl, 1);
   int TY = best[0].first, TZ = best[0].second;

@@ -109,6 +109,11 @@ int build_tables_host(const gpaw_sys_desc *d, gpaw_sys *s, HostTables &ht) {
           const double dz = l * d->h[2] - R[2];
           if (dx * dx + dy * dy + dz * dz >= rmax * rmax) continue;
           const int64_t u[3] = {i, j, l};
+          // a finite system has no images: points outside the grid carry
+          // no projector values
+          if (d->boundary == 1 &&
+              (i < 0 || i >= n[0] || j < 0 || j >= n[1] || l < 0 || l >= n[2]))
+            continue;
           Entry e;
           int64_t f[3];
           for (int c = 0; c < 3; ++c) {

@@ -109,3 +109,12 @@ def test_kick_and_dipole():
     d = T.dipole(kicked, [2.0], n, h)
     norm = 2.0 * np.prod(h) * np.sum(g ** 2)
     assert np.allclose(d, np.array(c) * norm, rtol=1e-6)
+
+
+def test_sparse_projectors_match_dense():
+    s = _system(seed=9, natoms=3)
+    a = T.FiniteOps.from_system(s)
+    b = T.FiniteOps.from_system(s, sparse=True)
+    psi = s.psi.reshape(s.nb, -1)
+    assert np.abs(a.apply_H(psi) - b.apply_H(psi)).max() < 1e-12
+    assert np.abs(a.apply_S(psi) - b.apply_S(psi)).max() < 1e-12
