@@ -12,7 +12,9 @@ Prints one JSON line: throughput (band*gridpoints/s), per-part times, the
 roofline of the dominant kernel, the precision form (complex64 storage,
 split-BF16 matrix-core products, FP64 eigensolve, Cholesky orthonormality
 correction) and the batched form beside the FP64 step, the 48^3 and 96^3
-real workloads as extra lines, and the CPU oracle timed on this host.
+real workloads as extra lines, the paths beside the step (density, Davidson
+correction, zero-boundary multigrid Poisson, Crank-Nicolson propagation),
+and the CPU oracle timed on this host.
 """
 import argparse
 import json
@@ -405,6 +407,98 @@ def batched_form(steps, warmup, dev, stream):
     return res
 
 
+def other_paths(dev, stream):
+    """The rows beside the step, each on a workload of its own: density and
+    atomic density matrices and the Davidson correction at 96^3 / 512 bands
+    (FP64), the zero-boundary multigrid Poisson solve on a 119x119x159 box,
+    and one Crank-Nicolson step of 16 complex bands in a finite 95x95x127
+    box with 32 atoms."""
+    import torch
+    import synth
+    import paper_2310_14776_amd as gfd
+    out = {}
+    s = synth.config_system("C", lazy=True)
+    say(f"[bench] density / Davidson correction: {workload_label(s)}")
+    g = gfd.System.from_synth(s)
+    psi = synth.block_to_device(s, dev, dtype=g.dtype)
+    P = g.project(psi)
+    f = torch.full((s.nb,), 2.0, dtype=torch.float64, device=dev)
+    n_out = torch.empty(s.ng, dtype=torch.float64, device=dev)
+    D = torch.empty((s.natoms, g.ni, g.ni), dtype=g.mat_dtype, device=dev)
+    ms = timed(lambda: g.density(psi, f, P=P, n_out=n_out, D=D, stream=stream), stream, 5, 1)
+    byt = s.nb * s.ng * psi.element_size() + s.ng * 8
+    out["density"] = {"workload": workload_label(s), "ms": round(ms, 3),
+                      "GBs": round(byt / (ms * 1e-3) / 1e9, 1),
+                      "frac_hbm": round(byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
+    Hpsi = torch.empty_like(psi)
+    Spsi = torch.empty_like(psi)
+    g.apply_HS(psi, P, Hpsi=Hpsi, Spsi=Spsi, stream=stream)
+    eps = torch.linspace(-1.0, 1.0, s.nb, dtype=torch.float64, device=dev)
+    corr = torch.empty_like(psi)
+    ms = timed(lambda: g.davidson_correction(Hpsi, Spsi, eps, out=corr, stream=stream), stream, 5, 1)
+    byt = 3 * s.nb * s.ng * psi.element_size()
+    out["davidson_correction"] = {"workload": workload_label(s), "ms": round(ms, 3),
+                                  "GBs": round(byt / (ms * 1e-3) / 1e9, 1),
+                                  "frac_hbm": round(byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)}
+    del psi, Hpsi, Spsi, corr, P
+    g.close()
+    torch.cuda.empty_cache()
+
+    n, h = (119, 119, 159), (0.2, 0.2, 0.2)
+    say(f"[bench] Poisson: zero-boundary {n[0]}x{n[1]}x{n[2]} grid")
+    x = [np.arange(1, n[c] + 1) * h[c] for c in range(3)]
+    rng = np.random.default_rng(7)
+    rho = np.zeros(n)
+    for _ in range(8):
+        c = [(n[i] + 1) * h[i] * rng.uniform(0.3, 0.7) for i in range(3)]
+        w = rng.uniform(0.4, 0.9)
+        gg = [np.exp(-(x[i] - c[i]) ** 2 / (2 * w * w)) for i in range(3)]
+        rho += rng.uniform(-1, 1) * gg[0][:, None, None] * gg[1][None, :, None] * gg[2][None, None, :]
+    rho_d = torch.from_numpy(rho).to(dev)
+    solver = gfd.Poisson(n, h)
+    phi = torch.zeros_like(rho_d)
+    res = {}
+
+    def solve():
+        phi.zero_()
+        res["r"] = solver.solve(rho_d, phi=phi, tol=1e-10, max_cycles=200, stream=stream)
+    ms = timed(solve, stream, 3, 1)
+    cycles = res["r"][1]
+    ng = int(np.prod(n))
+    # per V-cycle on the finest level: 4 Jacobi sweeps + 1 residual, each
+    # reading two arrays and writing one (24 bytes per point)
+    out["poisson"] = {"workload": f"zero-boundary {n[0]}x{n[1]}x{n[2]} grid, h=0.2 bohr, "
+                                  f"{solver.levels} levels, 8 Gaussian charges",
+                      "ms_per_solve": round(ms, 3), "cycles": cycles,
+                      "ms_per_cycle": round(ms / cycles, 4), "rel_residual": res["r"][2],
+                      "fine_level_GBs": round(5 * 24 * ng / (ms / cycles * 1e-3) / 1e9, 1)}
+    solver.close()
+    del rho_d, phi
+    torch.cuda.empty_cache()
+
+    s = synth.make_system(n=(95, 95, 127), h=0.2, nb=16, natoms=32, rc=2.0, seed=42,
+                          complex_psi=True, bands="smooth", lazy=True)
+    say("[bench] Crank-Nicolson step: finite 95x95x127 box, 16 bands, 32 atoms")
+    g = gfd.System.from_synth(s, boundary="zero")
+    psi = synth.block_to_device(s, dev, dtype=g.dtype)
+    g.td_kick(psi, (0.01, 0.0, 0.0), stream=stream)
+    it = {}
+
+    def cn():
+        it["r"] = g.td_propagate(psi, 0.05, tol=1e-10, max_iter=500, stream=stream)
+    ms = timed(cn, stream, 2, 1)
+    P = g.project(psi)
+    Hp, Sp = torch.empty_like(psi), torch.empty_like(psi)
+    ms_hs = timed(lambda: g.apply_HS(psi, P, Hpsi=Hp, Spsi=Sp, stream=stream), stream, 5, 1)
+    out["tddft"] = {"workload": "finite 95x95x127 box, h=0.2 bohr, 16 complex128 bands, "
+                                "32 atoms, dt=0.05 au, tol 1e-10",
+                    "ms_per_step": round(ms, 3), "cocg_iterations": it["r"][0],
+                    "ms_per_iteration": round(ms / max(1, it["r"][0] + 1), 3),
+                    "apply_HS_ms": round(ms_hs, 3)}
+    g.close()
+    return out
+
+
 def cpu_baseline(name, budget_s, nb_sample):
     """The oracle (sparse projector matrix) on the first nb_sample bands of
     the same system: full oracle steps, timed on this host."""
@@ -513,6 +607,7 @@ def main():
             extra[name] = {k: r[k] for k in ("workload", "dtype", "ms_per_step", "value",
                                              "parts", "roofline", "launch_tuning")}
         out["extra_workloads"] = extra
+        out["other_paths"] = other_paths(dev, stream)
     if not args.no_cpu:
         say("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(args.config, args.cpu_seconds,

@@ -5,6 +5,8 @@ A block too large to hold twice on the host (1024 complex bands of a
 and copied into one preallocated device tensor through two pinned staging
 buffers, so that generation of one chunk overlaps the copy of the previous.
 """
+import sys
+
 import numpy as np
 
 
@@ -23,8 +25,12 @@ def block_to_device(s, device, dtype=None, chunk_bytes=1 << 30):
     stream = torch.cuda.Stream(device=device)
     pinned = [torch.empty((chunk, ng), dtype=dtype, pin_memory=True) for _ in range(2)]
     done = [None, None]
+    nchunks = (nb + chunk - 1) // chunk
     for i, lo in enumerate(range(0, nb, chunk)):
         hi = min(nb, lo + chunk)
+        if nchunks >= 8 and i % max(1, nchunks // 8) == 0:
+            # progress on stderr: a large block takes minutes to generate
+            print(f"[synth] bands {lo}..{hi} of {nb}", file=sys.stderr, flush=True)
         slot = i % 2
         if done[slot] is not None:
             done[slot].synchronize()
