@@ -43,6 +43,8 @@ def parse():
                     help="skip the precision-form and batched-form measurements")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the extra workload lines (48^3 and 96^3 real)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the built-in launch shapes (skip the autotuner; for profiler runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed steps, run a plain 256 MiB device copy three times "
                          "(reference kernel for hardware byte counters)")
@@ -316,6 +318,8 @@ def run_config(name, steps, warmup, dev, stream, single_inputs=False, do_tune=Tr
         low = None
         psi = synth.block_to_device(s, dev, dtype=g.dtype)
     es = psi.element_size()
+    if do_tune:
+        say(f"[bench] {name}: autotuning the launch shapes")
     tuning = tune(g, psi, stream) if do_tune else "heuristic"
     step = Step(g, psi, stream)
     say(f"[bench] {name}: timing {steps} steps")
@@ -550,7 +554,7 @@ def main():
     say("[bench] measured ceilings (copy and matrix-core probes)")
     peaks = measured_peaks(dev, stream)
     res, s, step, low = run_config(args.config, args.steps, args.warmup, dev, stream,
-                                   single_inputs=forms, peaks=peaks)
+                                   single_inputs=forms, do_tune=not args.no_tune, peaks=peaks)
     out = {
         "metric": "band*gridpoints/s for H|psi>+subspace step",
         "value": res["value"],

@@ -17,7 +17,9 @@
 // The grids of this solver are small next to the wave-function blocks (one
 // potential per system), and they stay resident in the XCDs' L2 and the
 // Infinity Cache across a sweep; every kernel is one lane per output point
-// with coalesced rows along the contiguous axis.
+// with coalesced rows along the contiguous axis. The coarsest level's many
+// sweeps run in one workgroup with the level in LDS (one barrier per sweep)
+// when it fits, instead of one launch per sweep.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -75,6 +77,37 @@ __global__ __launch_bounds__(256) void k_zlap(const double *__restrict__ f,
   if (mode == 0) out[g] = a;
   else if (mode == 1) out[g] = rhs[g] - a;
   else out[g] = f[g] + w * (rhs[g] - a);
+}
+
+// All sweeps of the coarsest level in one workgroup: phi, the scratch and
+// the right-hand side live in LDS, one barrier per sweep. Each sweep does
+// the same arithmetic as k_zlap's mode 2, so the result equals that of one
+// launch per sweep bit for bit.
+constexpr int COARSE_LDS_POINTS = 6144;  // 3 x 6144 doubles = 144 KiB of LDS
+__global__ __launch_bounds__(1024) void k_coarse_sweeps(double *__restrict__ phi,
+                                                        const double *__restrict__ rhs, Dims d,
+                                                        int sweeps, double w) {
+  extern __shared__ double lds[];
+  const int npts = d.n0 * d.n1 * d.n2;
+  double *a = lds, *b = lds + npts, *f = lds + 2 * npts;
+  for (int g = threadIdx.x; g < npts; g += 1024) {
+    a[g] = phi[g];
+    f[g] = rhs[g];
+  }
+  __syncthreads();
+  for (int s = 0; s < sweeps; ++s) {
+    const double *src = (s & 1) ? b : a;
+    double *dst = (s & 1) ? a : b;
+    for (int g = threadIdx.x; g < npts; g += 1024) {
+      const int z = g % d.n2, r = g / d.n2;
+      const int y = r % d.n1, x = r / d.n1;
+      const double lap = lap_at(src, d, x, y, z);
+      dst[g] = src[g] + w * (f[g] - lap);
+    }
+    __syncthreads();
+  }
+  const double *res = (sweeps & 1) ? b : a;
+  for (int g = threadIdx.x; g < npts; g += 1024) phi[g] = res[g];
 }
 
 // coarse[j] = sum over the 27 fine neighbours of fine point 2 j + 1 of
@@ -231,6 +264,7 @@ struct PoissonLevel {
 
 struct gpaw_poisson {
   std::vector<gfd::PoissonLevel> lv;
+  bool coarse_lds_ok = false;  // the coarsest level's sweeps may run in one workgroup
   double *part = nullptr;   // norm partials [NRM_WGS]
   double *norm = nullptr;   // [2]: |f|^2, |r|^2
   double *host = nullptr;   // pinned [2]
@@ -259,7 +293,15 @@ void vcycle(gpaw_poisson *p, size_t l, double *phi, hipStream_t st) {
   PoissonLevel &L = p->lv[l];
   if (l + 1 == p->lv.size()) {
     const int mx = std::max({L.n[0], L.n[1], L.n[2]});
-    sweeps(L, phi, 20 * mx + (20 * mx) % 2, st);
+    const int count = 20 * mx;  // even
+    if (L.ng <= COARSE_LDS_POINTS && p->coarse_lds_ok) {
+      const Dims d = dims_of(L.n, L.h);
+      const double diag = PW0 * (d.i0 + d.i1 + d.i2);
+      k_coarse_sweeps<<<1, 1024, 3 * L.ng * sizeof(double), st>>>(phi, L.f, d, count,
+                                                                  JACOBI_OMEGA / diag);
+    } else {
+      sweeps(L, phi, count, st);
+    }
     return;
   }
   PoissonLevel &C = p->lv[l + 1];
@@ -329,6 +371,12 @@ int gpaw_poisson_create(const int32_t *n, const double *h, gpaw_poisson **out) {
     if (e == hipSuccess) e = hipMalloc(&L.tmp, sizeof(double) * L.ng);
   }
   if (e == hipSuccess) e = hipMalloc(&p->part, sizeof(double) * NRM_WGS);
+  if (e == hipSuccess)
+    p->coarse_lds_ok =
+        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_coarse_sweeps),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            3 * COARSE_LDS_POINTS * sizeof(double)) == hipSuccess;
+  (void)hipGetLastError();
   if (e == hipSuccess) e = hipMalloc(&p->norm, sizeof(double) * 2);
   if (e == hipSuccess) e = hipHostMalloc(&p->host, sizeof(double) * 2);
   if (e != hipSuccess) {
