@@ -56,10 +56,12 @@ PART_KERNELS = {
     "project": (["k_project"], ["csrc/nonlocal.hip", "csrc/proj.h"]),
     # H~psi and S~psi in one pass: Delta H.P and Delta S.P (one launch), then the stencil
     "apply_HS": (["k_dmat2", "k_plane"],
-                 ["csrc/stencil.hip", "csrc/nonlocal.hip", "csrc/proj.h"]),
-    "subspace": (["k_subspace", "k_subspace_reduce"], ["csrc/gemm.hip"]),
+                 ["csrc/stencil.hip", "csrc/stencil_impl.h", "csrc/stencil_f64.hip",
+                  "csrc/stencil_c128.hip", "csrc/nonlocal.hip", "csrc/proj.h"]),
+    # (k_subspace matches the narrow- and wide-block kernels)
+    "subspace": (["k_subspace", "k_subspace_reduce"], ["csrc/gemm.hip", "csrc/tile_order.h"]),
     # the block and its projections
-    "rotate": (["k_rotate", "k_rot_small"], ["csrc/gemm.hip"]),
+    "rotate": (["k_rotate", "k_rot_small"], ["csrc/gemm.hip", "csrc/tile_order.h"]),
 }
 
 
@@ -242,14 +244,17 @@ def measured_peaks(dev, stream):
 
 def part_costs(s, info, es):
     """Algorithmic bytes and flops per launch of each part (es = bytes per
-    element of the block; complex flops are four real ones per product)."""
+    element of the block). A complex-by-complex product costs three real
+    products (the contractions use the three-multiplication form), a real
+    projector value times a complex value two."""
     nb, ng, npj, ni = s.nb, s.ng, info["np"], info["ni"]
     ent = info["entries"]
-    cf = 4 if s.is_complex else 1
+    cf = 3 if s.is_complex else 1
+    cp = 2 if s.is_complex else 1
     return {
         # gather psi at every sphere entry, read the entry table once, write P
         "project": dict(bytes=ent * nb * es + ent * 12 + nb * npj * es,
-                        flops=2 * ent * ni * nb * cf),
+                        flops=2 * ent * ni * nb * cp),
         # read psi, write H~psi and S~psi, read v and the add-back tables once
         "apply_HS": dict(bytes=3 * nb * ng * es + ng * 8 + ng * 16 + ent * 4, flops=0),
         # read psi, H~psi, S~psi; two Hermitian nb x nb products over Ng, of

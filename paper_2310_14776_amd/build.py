@@ -24,6 +24,15 @@ HIPCC_FLAGS = [
 ]
 
 
+# Per-source additions. The contractions keep their MFMA accumulators in
+# VGPRs (the AGPR form made the compiler copy accumulators between the two
+# register files on every K step).
+EXTRA_FLAGS = {
+    "gemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "gemm_split.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
+
 def _hipcc():
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -37,7 +46,7 @@ def sources():
 
 def _compile(src, verbose):
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [_hipcc(), *HIPCC_FLAGS, "-c", src, "-o", obj]
+    cmd = [_hipcc(), *HIPCC_FLAGS, *EXTRA_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

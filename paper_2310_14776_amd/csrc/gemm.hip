@@ -2,12 +2,21 @@
 // equation") on the FP64 matrix cores of gfx950.
 //
 // H_nm = dV sum_r psi_n(r) Hpsi_m(r) is a tall-skinny contraction (K = Ng up
-// to millions, M = N = nb). Work splits over K across the whole chip; each
-// workgroup (4 wavefronts) owns one 64x64 output tile of one matrix for one
-// K-range, every wavefront accumulates the full tile over a quarter of the
-// range with v_mfma_f64_16x16x4, and the four partial tiles are summed
-// through LDS in a fixed order. A second kernel adds the K-range partials in
-// a fixed order and applies dV, so the result is bitwise reproducible.
+// to millions, M = N = nb). Work splits over K across the whole chip, in
+// K chunks whose count balances whole rounds of resident workgroups against
+// the partial-sum traffic. Two kernels form one K chunk's partial tiles:
+//   * k_subspace (narrow blocks, and real blocks): a workgroup (4 wavefronts)
+//     owns one output tile of one matrix; every wavefront accumulates the
+//     full tile over a quarter of the chunk from registers fed by 16-byte
+//     global loads, and the four partial tiles are summed through LDS in a
+//     fixed order;
+//   * k_subspace_lds (complex blocks of 256 bands or more): a 64 x 64 tile
+//     per workgroup, 2 x 2 wavefronts, operands staged in LDS once for all
+//     four (half the global bytes per MFMA).
+// Work items run K chunk by K chunk, each chunk's tiles in super-blocks, and
+// each XCD takes a contiguous range of them, so the workgroups resident on
+// one XCD read the same rows. A second kernel adds the K-chunk partials in a
+// fixed order and applies dV, so the result is bitwise reproducible.
 //
 // MFMA operand layout (16x16x4, FP64): lane l supplies A[i = l%16][k = l/16]
 // and B[k = l/16][j = l%16]; the accumulator element r of lane l is
@@ -24,6 +33,7 @@
 #include <type_traits>
 
 #include "internal.h"
+#include "tile_order.h"
 
 namespace gfd {
 
@@ -37,8 +47,15 @@ __device__ inline d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Complex operands: conj(a) b = (ax bx + ay by) + i (ax by - ay bx) and
-// a b = (ax bx - ay by) + i (ax by + ay bx), four real MFMAs each.
+// Complex operands take three real MFMAs per complex product (Gauss's
+// three-multiplication form), each into an accumulator of its own:
+//   conj(a) b: T1 = ax bx, T2 = ay by, T3 = (ax - ay)(bx + by);
+//              re = T1 + T2, im = T3 - T1 + T2
+//   a b:       T1 = ax bx, T2 = ay by, T3 = (ax + ay)(bx + by);
+//              re = T1 - T2, im = T3 - T1 - T2
+// The operand sums are one vector add per fragment. The three sums are
+// combined once, after the K loop; the rounding error stays of the order
+// of the unit roundoff times sum |a||b|, as for the four-product form.
 template <typename T> struct Cx;
 template <> struct Cx<double> {
   static constexpr int parts = 1;
@@ -70,34 +87,22 @@ template <typename T, int BM, bool VEC>
 __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const T *__restrict__ B0,
                                                   const T *__restrict__ B1, T *__restrict__ part,
                                                   int nb, int64_t ng, int64_t kchunk, int tiles_n,
-                                                  int nmat, int nsplit) {
+                                                  int nmat, int nsplit, int sb) {
   constexpr int TILE = 16 * BM;
   constexpr int NP = Cx<T>::parts;
+  constexpr int NACC = NP == 2 ? 3 : 1;
   __shared__ d4 red[2][NP][BM][BM][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // workgroups are dealt to the 8 XCDs round-robin by id: give all tiles and
-  // matrices of one K chunk the same id residue so they share that XCD's L2
-  // (with fewer than 8 K chunks the plain order keeps every XCD busy)
   // H and S are Hermitian: only the tiles on and above the diagonal are
-  // formed (the reduction mirrors the rest)
+  // formed (the reduction mirrors the rest). Work items run K chunk by K
+  // chunk, each chunk's tiles in super-block order.
   const int tiles = tiles_n * (tiles_n + 1) / 2, TT = tiles * nmat;
-  int split, tt;
-  if (nsplit >= 8) {
-    const int xcd = blockIdx.x & 7, jj = blockIdx.x >> 3;
-    split = (jj / TT) * 8 + xcd;
-    tt = jj - (jj / TT) * TT;
-  } else {
-    split = blockIdx.x / TT;
-    tt = blockIdx.x - split * TT;
-  }
+  const int64_t item = xcd_item();
+  const int split = static_cast<int>(item / TT);
   if (split >= nsplit) return;
-  const int mat = tt / tiles, tile = tt - mat * tiles;
-  int tm = 0, rest = tile;
-  while (rest >= tiles_n - tm) {
-    rest -= tiles_n - tm;
-    ++tm;
-  }
-  const int tn = tm + rest;
+  int mat, tm, tn;
+  tile_of(static_cast<int>(item - static_cast<int64_t>(split) * TT), tiles_n, nmat, sb, mat, tm,
+          tn);
   const T *B = mat ? B1 : B0;
   const int64_t kb = static_cast<int64_t>(split) * kchunk;
   const int64_t ke = std::min(ng, kb + kchunk);
@@ -113,9 +118,9 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
     bp[q] = B + static_cast<int64_t>(std::min(tn * TILE + q * 16 + r, nb - 1)) * ng;
   }
 
-  d4 acc[NP][BM][BM];
+  d4 acc[NACC][BM][BM];
 #pragma unroll
-  for (int c = 0; c < NP; ++c)
+  for (int c = 0; c < NACC; ++c)
 #pragma unroll
     for (int i = 0; i < BM; ++i)
 #pragma unroll
@@ -123,20 +128,29 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
 
   auto compute = [&](const T (&a)[BM][4], const T (&b)[BM][4]) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 4; ++s) {
+      if constexpr (NP == 2) {
+        double ad[BM], bs[BM];
 #pragma unroll
-      for (int i = 0; i < BM; ++i)
+        for (int i = 0; i < BM; ++i) ad[i] = Cx<T>::re(a[i][s]) - Cx<T>::im(a[i][s]);
 #pragma unroll
-        for (int j = 0; j < BM; ++j) {
-          const double ax = Cx<T>::re(a[i][s]), bx = Cx<T>::re(b[j][s]);
-          acc[0][i][j] = mfma(ax, bx, acc[0][i][j]);
-          if constexpr (NP == 2) {
-            const double ay = Cx<T>::im(a[i][s]), by = Cx<T>::im(b[j][s]);
-            acc[0][i][j] = mfma(ay, by, acc[0][i][j]);
-            acc[NP - 1][i][j] = mfma(ax, by, acc[NP - 1][i][j]);
-            acc[NP - 1][i][j] = mfma(-ay, bx, acc[NP - 1][i][j]);
+        for (int j = 0; j < BM; ++j) bs[j] = Cx<T>::re(b[j][s]) + Cx<T>::im(b[j][s]);
+#pragma unroll
+        for (int i = 0; i < BM; ++i)
+#pragma unroll
+          for (int j = 0; j < BM; ++j) {
+            acc[0][i][j] = mfma(Cx<T>::re(a[i][s]), Cx<T>::re(b[j][s]), acc[0][i][j]);
+            acc[1][i][j] = mfma(Cx<T>::im(a[i][s]), Cx<T>::im(b[j][s]), acc[1][i][j]);
+            acc[2][i][j] = mfma(ad[i], bs[j], acc[2][i][j]);
           }
-        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < BM; ++i)
+#pragma unroll
+          for (int j = 0; j < BM; ++j)
+            acc[0][i][j] = mfma(Cx<T>::re(a[i][s]), Cx<T>::re(b[j][s]), acc[0][i][j]);
+      }
+    }
   };
   // The wavefront's full 16-wide K steps run as a software pipeline: a ring
   // of D register buffers, each step's operands requested D steps before its
@@ -193,6 +207,19 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
     }
   }
 
+  // the wavefront's real and imaginary parts from the three products
+  d4 fin[NP][BM][BM];
+#pragma unroll
+  for (int i = 0; i < BM; ++i)
+#pragma unroll
+    for (int j = 0; j < BM; ++j) {
+      if constexpr (NP == 2) {
+        fin[0][i][j] = acc[0][i][j] + acc[1][i][j];
+        fin[1][i][j] = (acc[2][i][j] - acc[0][i][j]) + acc[1][i][j];
+      } else {
+        fin[0][i][j] = acc[0][i][j];
+      }
+    }
   // fixed-order sum of the four wavefronts' tiles: (w0 + w2) + (w1 + w3)
   if (wave >= 2)
 #pragma unroll
@@ -200,7 +227,7 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
 #pragma unroll
       for (int i = 0; i < BM; ++i)
 #pragma unroll
-        for (int j = 0; j < BM; ++j) red[wave - 2][c][i][j][lane] = acc[c][i][j];
+        for (int j = 0; j < BM; ++j) red[wave - 2][c][i][j][lane] = fin[c][i][j];
   __syncthreads();
   if (wave < 2)
 #pragma unroll
@@ -208,7 +235,7 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
 #pragma unroll
       for (int i = 0; i < BM; ++i)
 #pragma unroll
-        for (int j = 0; j < BM; ++j) acc[c][i][j] += red[wave][c][i][j][lane];
+        for (int j = 0; j < BM; ++j) fin[c][i][j] += red[wave][c][i][j][lane];
   __syncthreads();
   if (wave == 1)
 #pragma unroll
@@ -216,7 +243,7 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
 #pragma unroll
       for (int i = 0; i < BM; ++i)
 #pragma unroll
-        for (int j = 0; j < BM; ++j) red[0][c][i][j][lane] = acc[c][i][j];
+        for (int j = 0; j < BM; ++j) red[0][c][i][j][lane] = fin[c][i][j];
   __syncthreads();
   if (wave == 0) {
     T *out = part + (static_cast<int64_t>(split) * nmat + mat) * nb * nb;
@@ -224,8 +251,8 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
     for (int i = 0; i < BM; ++i)
 #pragma unroll
       for (int j = 0; j < BM; ++j) {
-        const d4 vr = acc[0][i][j] + red[0][0][i][j][lane];
-        const d4 vi = acc[NP - 1][i][j] + red[0][NP - 1][i][j][lane];
+        const d4 vr = fin[0][i][j] + red[0][0][i][j][lane];
+        const d4 vi = fin[NP - 1][i][j] + red[0][NP - 1][i][j][lane];
         const int col = tn * TILE + j * 16 + (lane & 15);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -234,6 +261,180 @@ __global__ __launch_bounds__(256) void k_subspace(const T *__restrict__ A, const
         }
       }
   }
+}
+
+// The same contraction for wide blocks (nb >= 256): a workgroup owns a
+// TILE x TILE output tile (TILE = 32 WM) of one matrix for one K chunk, its
+// four wavefronts in a 2 x 2 layout each own 16WM x 16WM of it, and the
+// A and B rows of each 16-wide K stage are staged once in LDS for all four
+// (each row serves two wavefronts): per MFMA the workgroup reads half the
+// global bytes of the register-only kernel above.
+//
+// Stage pipeline: the next stage's global loads are issued before the
+// current stage is multiplied out of one of two LDS buffers, then written to
+// the other; one barrier per stage. Loads are unconditional: past the end
+// of the chunk a lane reads a row of zeros instead (an address select, no
+// branch), so the last stage needs no separate path.
+//
+// LDS rows hold the stage's 16 values plus 16 bytes of padding, so the
+// fragment reads of eight consecutive rows (one 128-bit LDS phase) and the
+// staging writes hit disjoint banks.
+__device__ __attribute__((aligned(64))) double zero_group[8] = {};  // four complex zeros
+
+template <typename T, int WM, bool VEC>
+__global__ __launch_bounds__(256) void k_subspace_lds(const T *__restrict__ A,
+                                                      const T *__restrict__ B0,
+                                                      const T *__restrict__ B1,
+                                                      T *__restrict__ part, int nb, int64_t ng,
+                                                      int64_t kchunk, int tiles_n, int nmat,
+                                                      int nsplit, int sb) {
+  constexpr int NP = Cx<T>::parts;
+  constexpr int NACC = NP == 2 ? 3 : 1;
+  constexpr int TILE = 32 * WM;
+  constexpr int KS = 16;                                  // K values per stage
+  constexpr int PITCH = KS + static_cast<int>(16 / sizeof(T));  // LDS row pitch (elements)
+  constexpr int TPR = 256 / TILE;                         // staging threads per row
+  constexpr int EPT = KS / TPR;                           // values per thread and row
+  constexpr int GPT = EPT / 4;                            // groups of 4 per thread
+  static_assert(TPR * EPT == KS && GPT * 4 == EPT, "staging layout");
+  __shared__ __attribute__((aligned(16))) T sA[2][TILE * PITCH];
+  __shared__ __attribute__((aligned(16))) T sB[2][TILE * PITCH];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = wave >> 1, wc = wave & 1;
+
+  const int tiles = tiles_n * (tiles_n + 1) / 2, TT = tiles * nmat;
+  const int64_t item = xcd_item();
+  const int split = static_cast<int>(item / TT);
+  if (split >= nsplit) return;  // whole workgroup: no barrier is reached
+  int mat, tm, tn;
+  tile_of(static_cast<int>(item - static_cast<int64_t>(split) * TT), tiles_n, nmat, sb, mat, tm,
+          tn);
+  const T *B = mat ? B1 : B0;
+  const int64_t kb = static_cast<int64_t>(split) * kchunk;
+  const int64_t ke = std::min(ng, kb + kchunk);
+  const int nst = kb < ke ? static_cast<int>((ke - kb + KS - 1) / KS) : 0;
+
+  // staging: thread -> row srow of the tile, values sk .. sk + EPT - 1 of
+  // the stage (rows past nb are clamped: they feed outputs never stored)
+  const int srow = tid / TPR, sk = (tid % TPR) * EPT;
+  const T *ga = A + static_cast<int64_t>(std::min(tm * TILE + srow, nb - 1)) * ng;
+  const T *gb = B + static_cast<int64_t>(std::min(tn * TILE + srow, nb - 1)) * ng;
+  const T *zr = reinterpret_cast<const T *>(zero_group);
+  auto gload = [&](int st, T (&va)[EPT], T (&vb)[EPT]) {
+    const int64_t k0 = kb + static_cast<int64_t>(st) * KS + sk;
+    if constexpr (VEC) {
+      // groups of four values start at multiples of 4 and ke is one, so a
+      // group is either inside the chunk or past it
+#pragma unroll
+      for (int g = 0; g < GPT; ++g) {
+        const int64_t k = k0 + 4 * g;
+        const bool in = k < ke;
+        load4(in ? ga + k : zr, va + 4 * g);
+        load4(in ? gb + k : zr, vb + 4 * g);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int64_t k = k0 + e;
+        const bool in = k < ke;
+        va[e] = *(in ? ga + k : zr);
+        vb[e] = *(in ? gb + k : zr);
+      }
+    }
+  };
+  auto lstore = [&](int buf, const T (&va)[EPT], const T (&vb)[EPT]) {
+    T *pa = &sA[buf][srow * PITCH + sk];
+    T *pb = &sB[buf][srow * PITCH + sk];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      pa[e] = va[e];
+      pb[e] = vb[e];
+    }
+  };
+
+  d4 acc[NACC][WM][WM];
+#pragma unroll
+  for (int c = 0; c < NACC; ++c)
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WM; ++j) acc[c][i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  // fragment reads: lane l takes row l % 16 of each 16-row block and the
+  // four consecutive stage values 4 (l / 16) .. 4 (l / 16) + 3, the s-th of
+  // which feeds the s-th MFMA (the same K permutation on both operands)
+  const int fr = lane & 15, fk = 4 * (lane >> 4);
+  auto compute = [&](int buf) {  // buf: LDS buffer, a run-time index
+    T a[WM][4], b[WM][4];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      const T *pa = &sA[buf][(wr * 16 * WM + i * 16 + fr) * PITCH + fk];
+      const T *pb = &sB[buf][(wc * 16 * WM + i * 16 + fr) * PITCH + fk];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        a[i][e] = pa[e];
+        b[i][e] = pb[e];
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      if constexpr (NP == 2) {
+        double ad[WM], bs[WM];
+#pragma unroll
+        for (int i = 0; i < WM; ++i) ad[i] = Cx<T>::re(a[i][s]) - Cx<T>::im(a[i][s]);
+#pragma unroll
+        for (int j = 0; j < WM; ++j) bs[j] = Cx<T>::re(b[j][s]) + Cx<T>::im(b[j][s]);
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WM; ++j) {
+            acc[0][i][j] = mfma(Cx<T>::re(a[i][s]), Cx<T>::re(b[j][s]), acc[0][i][j]);
+            acc[1][i][j] = mfma(Cx<T>::im(a[i][s]), Cx<T>::im(b[j][s]), acc[1][i][j]);
+            acc[2][i][j] = mfma(ad[i], bs[j], acc[2][i][j]);
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+          for (int j = 0; j < WM; ++j)
+            acc[0][i][j] = mfma(Cx<T>::re(a[i][s]), Cx<T>::re(b[j][s]), acc[0][i][j]);
+      }
+    }
+  };
+
+  if (nst > 0) {
+    T ra[EPT], rb[EPT];
+    gload(0, ra, rb);
+    lstore(0, ra, rb);
+    __syncthreads();
+    for (int t = 0; t < nst; ++t) {
+      // the next stage's loads are in flight while this one is multiplied
+      gload(t + 1, ra, rb);
+      compute(t & 1);
+      // keep the products ahead of the LDS writes, which wait for the loads
+      __builtin_amdgcn_sched_barrier(0);
+      lstore((t + 1) & 1, ra, rb);
+      __syncthreads();
+    }
+  }
+
+  T *out = part + (static_cast<int64_t>(split) * nmat + mat) * nb * nb;
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WM; ++j) {
+      const int col = tn * TILE + wc * 16 * WM + j * 16 + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = tm * TILE + wr * 16 * WM + i * 16 + (lane >> 4) + 4 * e;
+        double re = acc[0][i][j][e], im = 0.0;
+        if constexpr (NP == 2) {
+          re = acc[0][i][j][e] + acc[1][i][j][e];
+          im = (acc[2][i][j][e] - acc[0][i][j][e]) + acc[1][i][j][e];
+        }
+        if (row < nb && col < nb) out[static_cast<int64_t>(row) * nb + col] = Cx<T>::make(re, im);
+      }
+    }
 }
 
 template <typename T>
@@ -339,17 +540,26 @@ SplitPlan plan_subspace(int nb, int64_t ng, int nmat, int tile, int target, int6
   return p;
 }
 
-// out[n][g] = sum_m C[m][n] src[m][g]; each wavefront owns RB*16 rows (the
-// row group blockIdx.y) by 32 columns; no conjugation (psi' = C^T psi).
+// out[n][g] = sum_m C[m][n] src[m][g]; a workgroup owns RB*16 rows (a row
+// group) by 128 columns (a column block), each wavefront 32 of the columns;
+// no conjugation (psi' = C^T psi). Work items run column block by column
+// block, the row groups of one block consecutively, so the workgroups that
+// read the same src columns are resident on one XCD together and src comes
+// from HBM about once.
 template <typename T, int RB>
 __global__ __launch_bounds__(256) void k_rotate(const T *__restrict__ C, const T *__restrict__ src,
                                                 T *__restrict__ dst, int nb, int nout,
-                                                int64_t cols, int upper) {
+                                                int64_t cols, int upper, int rgroups,
+                                                int64_t items) {
   constexpr int NP = Cx<T>::parts;
+  constexpr int NACC = NP == 2 ? 3 : 1;
+  const int64_t item = xcd_item();
+  if (item >= items) return;
+  const int64_t cblock = item / rgroups;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = lane & 15, kq = lane >> 4;
-  const int64_t g0 = static_cast<int64_t>(blockIdx.x) * 128 + wave * 32;
-  const int n0 = blockIdx.y * RB * 16;
+  const int64_t g0 = cblock * 128 + wave * 32;
+  const int n0 = static_cast<int>(item - cblock * rgroups) * RB * 16;
   int64_t gc[2];
   bool gv[2];
 #pragma unroll
@@ -357,9 +567,9 @@ __global__ __launch_bounds__(256) void k_rotate(const T *__restrict__ C, const T
     gc[cb] = g0 + cb * 16 + j;
     gv[cb] = gc[cb] < cols;
   }
-  d4 acc[NP][RB][2];
+  d4 acc[NACC][RB][2];
 #pragma unroll
-  for (int c = 0; c < NP; ++c)
+  for (int c = 0; c < NACC; ++c)
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -399,19 +609,27 @@ __global__ __launch_bounds__(256) void k_rotate(const T *__restrict__ C, const T
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb)
           if (!mv) b[d][cb] = T{};
+        if constexpr (NP == 2) {
+          double as[RB], bs[2];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+          for (int rb = 0; rb < RB; ++rb) as[rb] = Cx<T>::re(a[d][rb]) + Cx<T>::im(a[d][rb]);
 #pragma unroll
-          for (int cb = 0; cb < 2; ++cb) {
-            const double ax = Cx<T>::re(a[d][rb]), bx = Cx<T>::re(b[d][cb]);
-            acc[0][rb][cb] = mfma(ax, bx, acc[0][rb][cb]);
-            if constexpr (NP == 2) {
-              const double ay = Cx<T>::im(a[d][rb]), by = Cx<T>::im(b[d][cb]);
-              acc[0][rb][cb] = mfma(-ay, by, acc[0][rb][cb]);
-              acc[NP - 1][rb][cb] = mfma(ax, by, acc[NP - 1][rb][cb]);
-              acc[NP - 1][rb][cb] = mfma(ay, bx, acc[NP - 1][rb][cb]);
+          for (int cb = 0; cb < 2; ++cb) bs[cb] = Cx<T>::re(b[d][cb]) + Cx<T>::im(b[d][cb]);
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+              acc[0][rb][cb] = mfma(Cx<T>::re(a[d][rb]), Cx<T>::re(b[d][cb]), acc[0][rb][cb]);
+              acc[1][rb][cb] = mfma(Cx<T>::im(a[d][rb]), Cx<T>::im(b[d][cb]), acc[1][rb][cb]);
+              acc[2][rb][cb] = mfma(as[rb], bs[cb], acc[2][rb][cb]);
             }
-          }
+        } else {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+              acc[0][rb][cb] = mfma(Cx<T>::re(a[d][rb]), Cx<T>::re(b[d][cb]), acc[0][rb][cb]);
+        }
       }
       load_step(m0 + 4 * (d + D), a[d], b[d]);
     }
@@ -424,9 +642,13 @@ __global__ __launch_bounds__(256) void k_rotate(const T *__restrict__ C, const T
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int n = n0 + rb * 16 + kq + 4 * e;
-        if (n < nout)
-          dst[static_cast<int64_t>(n) * cols + gc[cb]] =
-              Cx<T>::make(acc[0][rb][cb][e], acc[NP - 1][rb][cb][e]);
+        if (n >= nout) continue;
+        double re = acc[0][rb][cb][e], im = 0.0;
+        if constexpr (NP == 2) {
+          re = acc[0][rb][cb][e] - acc[1][rb][cb][e];
+          im = (acc[2][rb][cb][e] - acc[0][rb][cb][e]) - acc[1][rb][cb][e];
+        }
+        dst[static_cast<int64_t>(n) * cols + gc[cb]] = Cx<T>::make(re, im);
       }
     }
 }
@@ -488,7 +710,10 @@ int rotate_small_t(const void *C, const void *src, int nb, int nout, int64_t col
   return GPAW_OK;
 }
 
-template <typename T, int BM>
+// BM: wavefront blocks of the register-only kernel; WM > 0: wavefront
+// blocks of the LDS-staged kernel, used from nb >= 256 on (complex blocks:
+// for real ones the register-only kernel measured faster)
+template <typename T, int BM, int WM>
 int subspace_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi, int nb,
                void *H, void *S, hipStream_t st, double *pbuf, size_t pcap) {
   const int nmat = Spsi ? 2 : 1;
@@ -499,38 +724,50 @@ int subspace_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const void 
   const bool vec = (s->ng % 4) == 0 &&
                    (reinterpret_cast<uintptr_t>(psi) | reinterpret_cast<uintptr_t>(Hpsi) |
                     reinterpret_cast<uintptr_t>(Spsi ? Spsi : Hpsi)) % 32 == 0;
-  const int64_t slots =
-      resident_slots(vec ? reinterpret_cast<const void *>(&k_subspace<T, BM, true>)
-                         : reinterpret_cast<const void *>(&k_subspace<T, BM, false>),
-                     256, 0);
-  const double tile_flops = 2.0 * Cx<T>::parts * Cx<T>::parts * (16.0 * BM) * (16.0 * BM) *
+  using Kern = void (*)(const T *, const T *, const T *, T *, int, int64_t, int64_t, int, int, int,
+                        int);
+  Kern kern = vec ? &k_subspace<T, BM, true> : &k_subspace<T, BM, false>;
+  int tile = 16 * BM;
+  if constexpr (WM > 0) {
+    if (nb >= 256) {
+      kern = vec ? &k_subspace_lds<T, WM, true> : &k_subspace_lds<T, WM, false>;
+      tile = 32 * WM;
+    }
+  }
+  const int64_t slots = resident_slots(reinterpret_cast<const void *>(kern), 256, 0);
+  // real MFMA flops of one tile over the whole K range (three real
+  // products per complex one)
+  const double tile_flops = 2.0 * (Cx<T>::parts == 2 ? 3.0 : 1.0) * tile * tile *
                             static_cast<double>(s->ng);
   const SplitPlan p =
-      plan_subspace(nb, s->ng, nmat, 16 * BM, s->tune.sub_wgs, max_split, slots, tile_flops,
+      plan_subspace(nb, s->ng, nmat, tile, s->tune.sub_wgs, max_split, slots, tile_flops,
                     static_cast<double>(per_split) * sizeof(double));
   T *part = reinterpret_cast<T *>(pbuf);
-  const int64_t sgroups = p.nsplit >= 8 ? (p.nsplit + 7) / 8 * 8 : p.nsplit;
-  const int64_t wgs = sgroups * p.tiles * nmat;
-  auto go = [&](auto vflag) {
-    k_subspace<T, BM, decltype(vflag)::value><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
-        static_cast<const T *>(psi), static_cast<const T *>(Hpsi),
-        static_cast<const T *>(Spsi ? Spsi : Hpsi), part, nb, s->ng, p.kchunk, p.tiles_n, nmat,
-        p.nsplit);
-  };
-  if (vec) go(std::true_type{});
-  else go(std::false_type{});
+  // one work item per (K chunk, tile, matrix); the grid is rounded up to
+  // whole groups of 8 (one workgroup per XCD)
+  const int64_t items = static_cast<int64_t>(p.nsplit) * p.tiles * nmat;
+  const int64_t wgs = (items + 7) / 8 * 8;
+  // super-blocks of about the workgroups one XCD holds at a time
+  const int sb = super_block(slots, p.tiles_n);
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(wgs)), dim3(256), 0, st,
+                     static_cast<const T *>(psi), static_cast<const T *>(Hpsi),
+                     static_cast<const T *>(Spsi ? Spsi : Hpsi), part, nb, s->ng, p.kchunk,
+                     p.tiles_n, nmat, p.nsplit, sb);
   const int64_t tot = static_cast<int64_t>(nb) * nb * nmat;
   k_subspace_reduce<T><<<static_cast<unsigned>((tot + 255) / 256), 256, 0, st>>>(
-      part, static_cast<T *>(H), static_cast<T *>(S), nb, p.nsplit, nmat, s->dV, 16 * BM);
+      part, static_cast<T *>(H), static_cast<T *>(S), nb, p.nsplit, nmat, s->dV, tile);
   return GPAW_OK;
 }
 
 template <typename T, int RB>
 int rotate_t(const void *C, const void *src, int nb, int nout, int64_t cols, void *dst,
              hipStream_t st, bool upper) {
-  dim3 grid(static_cast<unsigned>((cols + 127) / 128), (nout + RB * 16 - 1) / (RB * 16));
-  k_rotate<T, RB><<<grid, 256, 0, st>>>(static_cast<const T *>(C), static_cast<const T *>(src),
-                                        static_cast<T *>(dst), nb, nout, cols, upper ? 1 : 0);
+  const int rgroups = (nout + RB * 16 - 1) / (RB * 16);
+  const int64_t items = (cols + 127) / 128 * rgroups;
+  const int64_t wgs = (items + 7) / 8 * 8;
+  k_rotate<T, RB><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
+      static_cast<const T *>(C), static_cast<const T *>(src), static_cast<T *>(dst), nb, nout,
+      cols, upper ? 1 : 0, rgroups, items);
   return GPAW_OK;
 }
 
@@ -561,8 +798,8 @@ int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const 
   if (s->dtype == GPAW_F32 || s->dtype == GPAW_C64)
     return launch_subspace_split(s, psi, Hpsi, Spsi, nb, H, S, st, part, part_elems);
   if (s->dtype == GPAW_C128)
-    return subspace_t<z64, 2>(s, psi, Hpsi, Spsi, nb, H, S, st, part, part_elems);
-  return subspace_t<double, 4>(s, psi, Hpsi, Spsi, nb, H, S, st, part, part_elems);
+    return subspace_t<z64, 2, 2>(s, psi, Hpsi, Spsi, nb, H, S, st, part, part_elems);
+  return subspace_t<double, 4, 0>(s, psi, Hpsi, Spsi, nb, H, S, st, part, part_elems);
 }
 
 int launch_rotate(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,

@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include "internal.h"
+#include "tile_order.h"
 
 namespace gfd {
 
@@ -184,7 +185,7 @@ template <typename T, int WT>
 __global__ __launch_bounds__(256) void k_sub_lds(const T *__restrict__ A, const T *__restrict__ B0,
                                                  const T *__restrict__ B1, double *__restrict__ part,
                                                  int nb, int64_t ng, int64_t kchunk, int tiles_n,
-                                                 int nmat, int nsplit) {
+                                                 int nmat, int nsplit, int sb) {
   constexpr int NP = Parts<T>::n;
   constexpr int TM = 32 * WT;
   constexpr int PS = TM * LROW;  // plane stride (bf16)
@@ -193,25 +194,15 @@ __global__ __launch_bounds__(256) void k_sub_lds(const T *__restrict__ A, const 
   __shared__ __attribute__((aligned(16))) __bf16 sB[3 * NP * PS];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   // H and S are Hermitian: only the tiles on and above the diagonal are
-  // formed (the reduction mirrors the rest)
+  // formed (the reduction mirrors the rest). Work items run K chunk by K
+  // chunk, each chunk's tiles in super-block order.
   const int tiles = tiles_n * (tiles_n + 1) / 2, TT = tiles * nmat;
-  int split, tt;
-  if (nsplit >= 8) {
-    const int x = blockIdx.x & 7, jj = blockIdx.x >> 3;
-    split = (jj / TT) * 8 + x;
-    tt = jj - (jj / TT) * TT;
-  } else {  // fewer chunks than XCDs: plain order keeps every XCD busy
-    split = blockIdx.x / TT;
-    tt = blockIdx.x - split * TT;
-  }
+  const int64_t item = xcd_item();
+  const int split = static_cast<int>(item / TT);
   if (split >= nsplit) return;
-  const int mat = tt / tiles, tile = tt - mat * tiles;
-  int tm = 0, rest = tile;
-  while (rest >= tiles_n - tm) {
-    rest -= tiles_n - tm;
-    ++tm;
-  }
-  const int tn = tm + rest;
+  int mat, tm, tn;
+  tile_of(static_cast<int>(item - static_cast<int64_t>(split) * TT), tiles_n, nmat, sb, mat, tm,
+          tn);
   const T *B = mat ? B1 : B0;
   const int64_t kb = static_cast<int64_t>(split) * kchunk;
   const int64_t ke = std::min(ng, kb + kchunk);
@@ -638,12 +629,14 @@ int subspace_split_t(const gpaw_sys *s, const void *psi, const void *Hpsi, const
       6.0 * 2.0 * NP * NP * (32.0 * WT) * (32.0 * WT) * static_cast<double>(s->ng);
   const SplitPlanS p = plan_split(nb, s->ng, nmat, 32 * WT, max_split, slots, tile_flops,
                                   static_cast<double>(per_split) * sizeof(double));
-  const int64_t sgroups = p.nsplit >= 8 ? (p.nsplit + 7) / 8 * 8 : p.nsplit;
-  const int64_t wgs = sgroups * p.tiles * nmat;
+  // one work item per (K chunk, tile, matrix), the grid rounded up to whole
+  // groups of 8 (one workgroup per XCD)
+  const int64_t items = static_cast<int64_t>(p.nsplit) * p.tiles * nmat;
+  const int64_t wgs = (items + 7) / 8 * 8;
   k_sub_lds<T, WT><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
       static_cast<const T *>(psi), static_cast<const T *>(Hpsi),
       static_cast<const T *>(Spsi ? Spsi : Hpsi), part, nb, s->ng, p.kchunk, p.tiles_n,
-      nmat, p.nsplit);
+      nmat, p.nsplit, super_block(slots, p.tiles_n));
   const int64_t tot = static_cast<int64_t>(nb) * nb * nmat * NP;
   k_split_reduce<NP><<<static_cast<unsigned>((tot + 255) / 256), 256, 0, st>>>(
       part, static_cast<double *>(H), static_cast<double *>(S), nb, p.nsplit, nmat, s->dV,
