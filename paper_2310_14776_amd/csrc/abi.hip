@@ -102,7 +102,7 @@ void free_sys(gpaw_sys *s) {
   void *bufs[] = {s->tab.a_start, s->tab.e_g, s->tab.e_xyz, s->tab.pinfo, s->tab.pm_code,
                   s->tab.pos,     s->dH,      s->dS,        s->v,          s->ws.P,
                   s->ws.X,        s->ws.part, s->ws.eig,    s->ws.info,    s->tab.proj,
-                  s->ws.split,    s->ws.mat,  s->ws.XS,     s->ws.flag};
+                  s->ws.split,    s->ws.mat,  s->ws.XS,     s->ws.flag,    s->tab.cov};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   if (s->td) (void)hipFree(s->td);

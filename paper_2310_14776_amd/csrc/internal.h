@@ -145,6 +145,7 @@ struct Tables {
   int4 *pinfo = nullptr;       // [Ng] {codes of the point's first three
                                //       entries, count << 24 | index of the first}
   int32_t *pm_code = nullptr;  // [nent] atom << 12 | image code (point-major)
+  int32_t *cov = nullptr;      // [ncov] covered grid points in increasing order
   double *pos = nullptr;       // [natoms][3] atom positions
   ProjDev *proj = nullptr;     // device copy of the projector parameters
 };
@@ -213,7 +214,7 @@ bool is_complex(int32_t dtype);
 // built and checked on the host first (no device call, so a bad geometry is
 // rejected before anything is allocated), then uploaded.
 struct HostTables {
-  std::vector<int32_t> a_start, e_g, pm_code;
+  std::vector<int32_t> a_start, e_g, pm_code, cov;
   std::vector<short4> e_xyz;
   std::vector<int4> pinfo;
   std::vector<double> pos;

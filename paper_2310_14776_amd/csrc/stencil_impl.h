@@ -584,7 +584,11 @@ __global__ __launch_bounds__(PT_THREADS) void k_plane(const T *__restrict__ psi,
   }
 }
 
-// S~psi: one lane per grid point, NB bands per workgroup
+// S~psi: one lane per grid point, NB bands per workgroup; a workgroup walks
+// AS_CHUNKS consecutive runs of 256 points, so the atom positions and phases
+// it stages in LDS serve all of them
+constexpr int AS_CHUNKS = 8;
+
 template <typename T, bool ADD, bool XLDS, int NI, int NB>
 __global__ __launch_bounds__(256) void k_apply_S(const T *__restrict__ psi, T *__restrict__ out,
                                                  int64_t ng, int nb, AddArgs ab) {
@@ -610,27 +614,87 @@ __global__ __launch_bounds__(256) void k_apply_S(const T *__restrict__ psi, T *_
   }
   typename PJSel<NI>::type pj = PJSel<NI>::get(ab.pj);
   const int ni = NI == 13 ? 13 : ab.pj->ni;
-  const int64_t g = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (g >= ng) return;
   using A = typename St<T>::Acc;
-  A acc[NB];
+  for (int c = 0; c < AS_CHUNKS; ++c) {
+    const int64_t g = (static_cast<int64_t>(blockIdx.x) * AS_CHUNKS + c) * 256 + threadIdx.x;
+    if (g >= ng) return;  // no barrier follows
+    A acc[NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) acc[b] = St<A>::zero();
-  if (ADD) {
-    const int n1 = pj.n[1], n2 = pj.n[2];
-    const int plane = n1 * n2;
+    for (int b = 0; b < NB; ++b) acc[b] = St<A>::zero();
+    if (ADD) {
+      const int n1 = pj.n[1], n2 = pj.n[2];
+      const int plane = n1 * n2;
+      const int ix = static_cast<int>(g / plane);
+      const int r = static_cast<int>(g - static_cast<int64_t>(ix) * plane);
+      const int iy = r / n2, iz = r - iy * n2;
+      addback_group<T, NI, NB, false>(ab, pj, ab.pinfo[g], ix, iy, iz, pos, phs, Xs, nullptr,
+                                      ab.np, ni, b0, nb, acc, nullptr);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      if (b0 + b < nb) {
+        const int64_t idx = static_cast<int64_t>(b0 + b) * ng + g;
+        out[idx] = St<T>::narrow(St<T>::widen(psi[idx]) + acc[b]);
+      }
+  }
+}
+
+// Non-local add-back as a pass of its own over the covered grid points (the
+// points some projector sphere reaches), used for large blocks: the stencil
+// kernel then runs without atoms (H~psi = (T + v) psi, S~psi = psi) at the
+// occupancy and instruction count of the atom-free case, and here one lane
+// per covered point adds sum_entries q (Delta H P) and q (Delta S P) to NB
+// bands, the projector values of an entry evaluated once for the NB bands.
+// Covered points are listed in increasing order, so a wavefront's lanes
+// mostly touch consecutive points. A workgroup walks AB_CHUNKS runs of 256
+// covered points, so its staged phases and atom positions serve all of them.
+constexpr int AB_CHUNKS = 4;
+
+template <typename T, int NI, int NB, bool S2>
+__global__ __launch_bounds__(256) void k_addback(T *__restrict__ out, T *__restrict__ outS,
+                                                 const int32_t *__restrict__ cov, int64_t ncov,
+                                                 int64_t ng, int nb, AddArgs ab) {
+  extern __shared__ unsigned char smem[];
+  const int b0 = blockIdx.y * NB;
+  const z64 *phs = nullptr;
+  unsigned char *after = smem;
+  if (St<T>::cplx) {
+    phs = stage_phases(ab, reinterpret_cast<z64 *>(smem));
+    after = smem + 48 * sizeof(z64);
+  }
+  const double *pos = stage_pos(
+      ab, ab.natoms <= POS_LDS_MAX ? reinterpret_cast<double *>(after) : nullptr, ab.natoms);
+  __syncthreads();
+  typename PJSel<NI>::type pj = PJSel<NI>::get(ab.pj);
+  const int ni = NI == 13 ? 13 : ab.pj->ni;
+  const T *Xs = static_cast<const T *>(ab.X) + static_cast<int64_t>(b0) * ab.np;
+  const T *XSs = S2 ? static_cast<const T *>(ab.XS) + static_cast<int64_t>(b0) * ab.np : Xs;
+  using A = typename St<T>::Acc;
+  const int n1 = pj.n[1], n2 = pj.n[2];
+  const int plane = n1 * n2;
+  for (int c = 0; c < AB_CHUNKS; ++c) {
+    const int64_t ci = (static_cast<int64_t>(blockIdx.x) * AB_CHUNKS + c) * 256 + threadIdx.x;
+    if (ci >= ncov) return;  // no barrier follows
+    const int64_t g = cov[ci];
     const int ix = static_cast<int>(g / plane);
     const int r = static_cast<int>(g - static_cast<int64_t>(ix) * plane);
     const int iy = r / n2, iz = r - iy * n2;
-    addback_group<T, NI, NB, false>(ab, pj, ab.pinfo[g], ix, iy, iz, pos, phs, Xs, nullptr,
-                                    ab.np, ni, b0, nb, acc, nullptr);
-  }
+    A acc[NB], accS[NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b)
-    if (b0 + b < nb) {
-      const int64_t idx = static_cast<int64_t>(b0 + b) * ng + g;
-      out[idx] = St<T>::narrow(St<T>::widen(psi[idx]) + acc[b]);
+    for (int b = 0; b < NB; ++b) {
+      acc[b] = St<A>::zero();
+      accS[b] = St<A>::zero();
     }
+    addback_group<T, NI, NB, S2, typename PJSel<NI>::type, false, true>(
+        ab, pj, ab.pinfo[g], ix, iy, iz, pos, phs, Xs, XSs, ab.np, ni, b0, nb, acc, accS);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      if (b0 + b < nb) {
+        const int64_t idx = static_cast<int64_t>(b0 + b) * ng + g;
+        out[idx] = St<T>::narrow(St<T>::widen(out[idx]) + acc[b]);
+        if (S2) outS[idx] = St<T>::narrow(St<T>::widen(outS[idx]) + accS[b]);
+      }
+  }
 }
 
 // 6th-order central second-difference weights (h^2 d^2/dx^2)
@@ -733,12 +797,46 @@ AddArgs make_add(const gpaw_sys *s, const void *X, const void *XS = nullptr) {
   return ab;
 }
 
+// Bands per lane of the separate add-back
+template <typename T> struct AddbackNB { static constexpr int value = St<T>::cplx ? 8 : 16; };
+
+template <typename T, int NI>
+int addback_t(const gpaw_sys *s, int nb, const void *X, const void *XS, void *out, void *outS,
+              hipStream_t st) {
+  constexpr int NB = AddbackNB<T>::value;
+  const AddArgs ab = make_add(s, X, XS);
+  const int64_t ncov = s->tab.ncov;
+  if (ncov == 0) return GPAW_OK;
+  dim3 grid(static_cast<unsigned>((ncov + 256 * AB_CHUNKS - 1) / (256 * AB_CHUNKS)),
+            (nb + NB - 1) / NB);
+  const size_t lds = (St<T>::cplx ? 48 * sizeof(z64) : 0) +
+                     (s->natoms <= POS_LDS_MAX ? 3 * sizeof(double) * s->natoms : 0);
+  T *po = static_cast<T *>(out);
+  T *pso = static_cast<T *>(outS);
+  if (outS)
+    k_addback<T, NI, NB, true><<<grid, 256, lds, st>>>(po, pso, s->tab.cov, ncov, s->ng, nb, ab);
+  else
+    k_addback<T, NI, NB, false><<<grid, 256, lds, st>>>(po, pso, s->tab.cov, ncov, s->ng, nb, ab);
+  return GPAW_OK;
+}
+
+// The add-back runs as its own pass for blocks of at least 2^24
+// band-points (below that the fused kernel is cheaper than a second launch)
+inline bool separate_addback(const gpaw_sys *s, int nb) {
+  return s->tab.ncov > 0 && static_cast<int64_t>(nb) * s->ng >= (int64_t{1} << 24);
+}
+
 constexpr size_t XLDS_MAX = 24 * 1024;  // staged X rows of the atoms reaching a tile
 constexpr int SLOT_ATOMS_MAX = 4096;     // atoms with a slot index in LDS
 
 template <typename T, bool BLOCH, int NB, int NI, int PPL>
 int plane_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,
             hipStream_t st, const void *XS = nullptr, void *outS = nullptr) {
+  if (X && separate_addback(s, nb)) {
+    const int rc = plane_t<T, BLOCH, NB, NI, PPL>(s, psi, nb, nullptr, out, st, nullptr, outS);
+    if (rc != GPAW_OK) return rc;
+    return addback_t<T, NI>(s, nb, X, XS, out, outS, st);
+  }
   const int ngroups = (nb + NB - 1) / NB;
   const PlaneGeom G = make_geom(s, ngroups, PPL);
   AddArgs ab = make_add(s, X, XS);
@@ -790,7 +888,8 @@ template <typename T, int NB, int NI>
 int apply_S_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,
               hipStream_t st) {
   const AddArgs ab = make_add(s, X);
-  dim3 grid(static_cast<unsigned>((s->ng + 255) / 256), (nb + NB - 1) / NB);
+  dim3 grid(static_cast<unsigned>((s->ng + 256 * AS_CHUNKS - 1) / (256 * AS_CHUNKS)),
+            (nb + NB - 1) / NB);
   const size_t xbytes = static_cast<size_t>(NB) * s->np * sizeof(T);
   const bool xlds = X && xbytes <= 32 * 1024;
   const size_t pbytes = (X && s->natoms <= POS_LDS_MAX) ? 3 * sizeof(double) * s->natoms : 0;

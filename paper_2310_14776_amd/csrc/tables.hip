@@ -167,6 +167,7 @@ int build_tables_host(const gpaw_sys_desc *d, gpaw_sys *s, HostTables &ht) {
   // three), the count and the index of the first entry in pm_code
   std::vector<int32_t> pm_code(nent);
   std::vector<int4> pinfo(s->ng, make_int4(0, 0, 0, 0));
+  std::vector<int32_t> cov;
   int64_t ncov = 0;
   for (int64_t e = 0; e < nent; ++e) {
     const Entry &x = ent[e];
@@ -174,6 +175,7 @@ int build_tables_host(const gpaw_sys_desc *d, gpaw_sys *s, HostTables &ht) {
     int4 &pi = pinfo[x.g];
     if (e == 0 || ent[e - 1].g != x.g) {
       ++ncov;
+      cov.push_back(static_cast<int32_t>(x.g));
       pi = make_int4(pm_code[e], 0, 0, static_cast<int>(e));
     }
     // the count lives in the top byte: unsigned arithmetic, so counts of
@@ -192,6 +194,7 @@ int build_tables_host(const gpaw_sys_desc *d, gpaw_sys *s, HostTables &ht) {
   ht.e_xyz = std::move(e_xyz);
   ht.pinfo = std::move(pinfo);
   ht.pm_code = std::move(pm_code);
+  ht.cov = std::move(cov);
   ht.pos.assign(d->pos, d->pos + 3 * d->natoms);
   return GPAW_OK;
 }
@@ -203,6 +206,7 @@ int upload_tables(gpaw_sys *s, const HostTables &ht) {
   if ((rc = upload(&s->tab.e_xyz, ht.e_xyz)) != GPAW_OK) return rc;
   if ((rc = upload(&s->tab.pinfo, ht.pinfo)) != GPAW_OK) return rc;
   if ((rc = upload(&s->tab.pm_code, ht.pm_code)) != GPAW_OK) return rc;
+  if ((rc = upload(&s->tab.cov, ht.cov)) != GPAW_OK) return rc;
   if ((rc = upload(&s->tab.pos, ht.pos)) != GPAW_OK) return rc;
   if ((rc = upload(&s->tab.proj, std::vector<ProjDev>(1, s->proj))) != GPAW_OK) return rc;
   return GPAW_OK;
