@@ -395,13 +395,17 @@ __global__ __launch_bounds__(256) void k_split_c(const double *__restrict__ C, _
 // the step is made long enough to keep many bytes in flight. The loads are
 // unconditional (row, column and step indices clamped; clamped src rows meet
 // zero padding in Ct, clamped output rows and columns are not stored).
-// ADDSRC: Ct holds C - I and the result is src + (C - I)^T src; when *fewer
-// is nonzero (|C - I| small, see k_offid_small) only the high BF16 parts are
-// multiplied (one product instead of six).
+// ADDSRC: Ct holds C - I and the result is src + (C - I)^T src. Two kernels
+// are launched for it and the device decides which one works: when *fewer
+// is nonzero (|C - I| small, see k_offid_small) the ONEP one multiplies the
+// high BF16 parts only (one product instead of six; its LDS holds one plane
+// per part, so four workgroups fit a CU), else the six-product one. Both are
+// persistent (a resident-sized grid walks the output tiles, each XCD a
+// contiguous range of them), so the one that exits costs one launch.
 constexpr int KR = 64;     // K values per rotation step
 constexpr int LROWR = 72;  // LDS row pitch of the rotation tiles (BF16 values)
 
-template <typename T, int WT, bool ADDSRC>
+template <typename T, int WT, bool ADDSRC, bool ONEP>
 __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
                                                  const T *__restrict__ src, T *__restrict__ dst,
                                                  int nb, int nbp, int64_t cols, int ntiles_n,
@@ -410,14 +414,31 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
   constexpr int NP = Parts<T>::n;
   constexpr int TM = 32 * WT;
   constexpr int PS = TM * LROWR;
-  __shared__ __attribute__((aligned(16))) __bf16 sA[3 * NP * PS];
-  __shared__ __attribute__((aligned(16))) __bf16 sB[3 * NP * PS];
+  constexpr int NPL = ONEP ? 1 : 3;  // BF16 planes staged per part
+  static_assert(ADDSRC || !ONEP, "one product only near the identity");
+  __shared__ __attribute__((aligned(16))) __bf16 sA[NPL * NP * PS];
+  __shared__ __attribute__((aligned(16))) __bf16 sB[NPL * NP * PS];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (ADDSRC && ((*fewer != 0) != ONEP)) return;  // the other kernel's case
+  // output tiles (column block gtile, row tile ntile), the row tiles of one
+  // column block consecutive
   const int x = blockIdx.x & 7;
-  const int64_t jj = blockIdx.x >> 3;
-  const int ntile = static_cast<int>(jj % ntiles_n);
-  const int64_t gtile = (jj / ntiles_n) * 8 + x;
-  if (gtile >= gtiles) return;
+  int64_t it, it_end, it_step;
+  if constexpr (ADDSRC) {
+    const int64_t items = gtiles * ntiles_n, per = (items + 7) / 8;
+    it = x * per + (blockIdx.x >> 3);
+    it_end = std::min(items, (x + 1) * per);
+    it_step = gridDim.x >> 3;
+  } else {
+    const int64_t jj = blockIdx.x >> 3;
+    const int64_t gt = (jj / ntiles_n) * 8 + x;
+    it = gt * ntiles_n + jj % ntiles_n;
+    it_end = gt < gtiles ? it + 1 : it;
+    it_step = 1;
+  }
+  for (; it < it_end; it += it_step) {
+  const int ntile = static_cast<int>(it % ntiles_n);
+  const int64_t gtile = it / ntiles_n;
   const int64_t np = static_cast<int64_t>(nb) * nbp;
   const int n0 = ntile * TM;
   const int64_t g0 = gtile * TM;
@@ -435,7 +456,7 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
   const int bg = tid % TM, bm = (tid / TM) * MPT;
   float rb[NP][MPT];
   const T *srcg = src + std::min<int64_t>(g0 + bg, cols - 1);
-  const bool one = ADDSRC && fewer && *fewer != 0;
+  constexpr bool one = ONEP;
   auto fetch = [&](int step) {
     const int m0 = std::min(step, nsteps - 1) * KR;
 #pragma unroll
@@ -469,14 +490,14 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
           if (p == 0 || !one)
 #pragma unroll
             for (int h = 0; h < 2; ++h)
-              *reinterpret_cast<bf8 *>(sA + (c * 3 + p) * PS + (ps * 64 + sr) * LROWR + sc +
+              *reinterpret_cast<bf8 *>(sA + (c * NPL + p) * PS + (ps * 64 + sr) * LROWR + sc +
                                        32 * h) = ca[ps][c][p][h];
 #pragma unroll
     for (int c = 0; c < NP; ++c)
 #pragma unroll
       for (int h = 0; h < MPT / 8; ++h) {
-        const int o = (c * 3) * PS + bg * LROWR + bm + 8 * h;
-        if (one) hi_store8(rb[c] + 8 * h, sB + o);
+        const int o = (c * NPL) * PS + bg * LROWR + bm + 8 * h;
+        if constexpr (ONEP) hi_store8(rb[c] + 8 * h, sB + o);
         else split_store8(rb[c] + 8 * h, sB + o, sB + o + PS, sB + o + 2 * PS);
       }
   };
@@ -507,14 +528,14 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
       for (int i = 0; i < WT; ++i)
 #pragma unroll
         for (int c = 0; c < NP; ++c)
-          fa[c][i] = frag(sA + (c * 3) * PS, PS, (wr * 16 * WT + i * 16 + fr) * LROWR + 32 * kh + fk,
+          fa[c][i] = frag(sA + (c * NPL) * PS, PS, (wr * 16 * WT + i * 16 + fr) * LROWR + 32 * kh + fk,
                           one);
 #pragma unroll
       for (int j = 0; j < WT; ++j) {
         Split8 fb[NP];
 #pragma unroll
         for (int c = 0; c < NP; ++c)
-          fb[c] = frag(sB + (c * 3) * PS, PS, (wc * 16 * WT + j * 16 + fr) * LROWR + 32 * kh + fk,
+          fb[c] = frag(sB + (c * NPL) * PS, PS, (wc * 16 * WT + j * 16 + fr) * LROWR + 32 * kh + fk,
                        one);
 #pragma unroll
         for (int i = 0; i < WT; ++i) {
@@ -587,6 +608,7 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
       }
     }
   }
+  }  // output tiles
 }
 struct SplitPlanS {
   int tiles_n, tiles, nsplit;
@@ -661,14 +683,27 @@ int rotate_split_t(const gpaw_sys *s, const void *C, const void *src, int nb, in
   const int ntiles_n = (nb + TM - 1) / TM;
   const int64_t gtiles = (cols + TM - 1) / TM;
   const int64_t wgs = (gtiles + 7) / 8 * 8 * ntiles_n;
-  if (near_id)
-    k_rot_lds<T, WT, true><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
+  if (near_id) {
+    // both persistent kernels, resident-sized grids (whole groups of 8); the
+    // device's flag lets exactly one of them work
+    const int64_t items = gtiles * ntiles_n;
+    auto grid_of = [&](const void *k) {
+      const int64_t r = std::max<int64_t>(8, resident_slots(k, 256, 0) / 8 * 8);
+      return static_cast<unsigned>(std::min(r, (items + 7) / 8 * 8));
+    };
+    auto *k1 = &k_rot_lds<T, WT, true, true>;
+    auto *k6 = &k_rot_lds<T, WT, true, false>;
+    k1<<<grid_of(reinterpret_cast<const void *>(k1)), 256, 0, st>>>(
         Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, nbp, cols, ntiles_n, gtiles,
         upper ? 1 : 0, s->ws.flag);
-  else
-    k_rot_lds<T, WT, false><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
+    k6<<<grid_of(reinterpret_cast<const void *>(k6)), 256, 0, st>>>(
+        Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, nbp, cols, ntiles_n, gtiles,
+        upper ? 1 : 0, s->ws.flag);
+  } else {
+    k_rot_lds<T, WT, false, false><<<static_cast<unsigned>(wgs), 256, 0, st>>>(
         Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, nbp, cols, ntiles_n, gtiles,
         upper ? 1 : 0, nullptr);
+  }
   return GPAW_OK;
 }
 

@@ -82,8 +82,11 @@ __global__ __launch_bounds__(256) void k_zlap(const double *__restrict__ f,
 // All sweeps of the coarsest level in one workgroup: phi, the scratch and
 // the right-hand side live in LDS, one barrier per sweep. Each sweep does
 // the same arithmetic as k_zlap's mode 2, so the result equals that of one
-// launch per sweep bit for bit.
-constexpr int COARSE_LDS_POINTS = 6144;  // 3 x 6144 doubles = 144 KiB of LDS
+// launch per sweep bit for bit. Used up to one point per lane: past that a
+// sweep in one workgroup costs more than a launch over the whole chip
+// (measured: a 14 x 14 x 19 coarsest level took 2.9 ms per V-cycle this way
+// against 1.7 ms with a launch per sweep).
+constexpr int COARSE_LDS_POINTS = 1024;  // 3 x 1024 doubles = 24 KiB of LDS
 __global__ __launch_bounds__(1024) void k_coarse_sweeps(double *__restrict__ phi,
                                                         const double *__restrict__ rhs, Dims d,
                                                         int sweeps, double w) {

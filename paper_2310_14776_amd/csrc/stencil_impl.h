@@ -647,14 +647,21 @@ __global__ __launch_bounds__(256) void k_apply_S(const T *__restrict__ psi, T *_
 // bands, the projector values of an entry evaluated once for the NB bands.
 // Covered points are listed in increasing order, so a wavefront's lanes
 // mostly touch consecutive points. A workgroup walks AB_CHUNKS runs of 256
-// covered points, so its staged phases and atom positions serve all of them.
-constexpr int AB_CHUNKS = 4;
+// covered points: it first marks the atoms their entries name, gives the
+// first ab.cap of them LDS slots and stages their positions and X rows of
+// the band group there (the add-back reads the others from global memory),
+// then adds. Its staged phases and slots serve all of its points.
+constexpr int AB_CHUNKS = 2;
+constexpr size_t AB_LDS = 60 * 1024;     // LDS of one add-back workgroup
+constexpr size_t XLDS_MAX = 24 * 1024;  // k_plane: staged X rows of the atoms reaching a tile
+constexpr int SLOT_ATOMS_MAX = 4096;     // atoms with a slot index in LDS
 
 template <typename T, int NI, int NB, bool S2>
 __global__ __launch_bounds__(256) void k_addback(T *__restrict__ out, T *__restrict__ outS,
                                                  const int32_t *__restrict__ cov, int64_t ncov,
                                                  int64_t ng, int nb, AddArgs ab) {
-  extern __shared__ unsigned char smem[];
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int t = threadIdx.x;
   const int b0 = blockIdx.y * NB;
   const z64 *phs = nullptr;
   unsigned char *after = smem;
@@ -662,18 +669,65 @@ __global__ __launch_bounds__(256) void k_addback(T *__restrict__ out, T *__restr
     phs = stage_phases(ab, reinterpret_cast<z64 *>(smem));
     after = smem + 48 * sizeof(z64);
   }
-  const double *pos = stage_pos(
-      ab, ab.natoms <= POS_LDS_MAX ? reinterpret_cast<double *>(after) : nullptr, ab.natoms);
+  const bool pos_lds = ab.natoms <= POS_LDS_MAX;
+  const double *pos = stage_pos(ab, pos_lds ? reinterpret_cast<double *>(after) : nullptr,
+                                ab.natoms);
+  if (pos_lds) after += ((3 * sizeof(double) * ab.natoms + 15) / 16) * 16;
+  // slots: slot[natoms], list[cap], count, then positions and X rows
+  int *slot = reinterpret_cast<int *>(after);
+  int *list = slot + ab.natoms;
+  int *count = list + ab.cap;
+  double *lp = reinterpret_cast<double *>(
+      after + ((sizeof(int) * (ab.natoms + ab.cap + 1) + 15) / 16) * 16);
+  T *xl = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(lp) +
+                                ((3 * sizeof(double) * ab.cap + 15) / 16) * 16);
+  if (t == 0) *count = 0;
+  for (int a = t; a < ab.natoms; a += 256) slot[a] = -1;
+  __syncthreads();
+  const int64_t cbase = static_cast<int64_t>(blockIdx.x) * AB_CHUNKS * 256;
+  // mark the atoms named by the entries of this workgroup's points (every
+  // writer stores the same value)
+  for (int c = 0; c < AB_CHUNKS; ++c) {
+    const int64_t ci = cbase + c * 256 + t;
+    if (ci >= ncov) break;
+    const int4 pi = ab.pinfo[cov[ci]];
+    const int cnt = static_cast<int>(static_cast<unsigned>(pi.w) >> 24);
+    const int first = pi.w & 0xFFFFFF;
+    for (int j = 0; j < cnt; ++j) {
+      const int code = j == 0 ? pi.x : (j == 1 ? pi.y : (j == 2 ? pi.z : ab.pm_code[first + j]));
+      slot[code >> 12] = -2;
+    }
+  }
+  __syncthreads();
+  for (int a = t; a < ab.natoms; a += 256) {
+    if (slot[a] != -2) continue;
+    const int k = atomicAdd(count, 1);
+    slot[a] = k < ab.cap ? k : -1;
+    if (k < ab.cap) list[k] = a;
+  }
+  __syncthreads();
+  const int nl = min(*count, ab.cap);
+  const int ni = NI == 13 ? 13 : ab.pj->ni;
+  const int ldl = nl * ni;
+  for (int e = t; e < 3 * nl; e += 256) lp[e] = ab.pos[3 * list[e / 3] + e % 3];
+  const int rows = min(NB, nb - b0);
+  const T *Xg = static_cast<const T *>(ab.X) + static_cast<int64_t>(b0) * ab.np;
+  const T *XSg = S2 ? static_cast<const T *>(ab.XS) + static_cast<int64_t>(b0) * ab.np : nullptr;
+  for (int e = t; e < rows * ldl; e += 256) {
+    const int b = e / ldl, r = e - b * ldl, k = r / ni, i = r - k * ni;
+    const int64_t src = static_cast<int64_t>(b) * ab.np + list[k] * ni + i;
+    xl[e] = Xg[src];
+    if (S2) xl[NB * ldl + e] = XSg[src];
+  }
   __syncthreads();
   typename PJSel<NI>::type pj = PJSel<NI>::get(ab.pj);
-  const int ni = NI == 13 ? 13 : ab.pj->ni;
-  const T *Xs = static_cast<const T *>(ab.X) + static_cast<int64_t>(b0) * ab.np;
-  const T *XSs = S2 ? static_cast<const T *>(ab.XS) + static_cast<int64_t>(b0) * ab.np : Xs;
+  const T *Xs = Xg;
+  const T *XSs = S2 ? XSg : Xg;
   using A = typename St<T>::Acc;
   const int n1 = pj.n[1], n2 = pj.n[2];
   const int plane = n1 * n2;
   for (int c = 0; c < AB_CHUNKS; ++c) {
-    const int64_t ci = (static_cast<int64_t>(blockIdx.x) * AB_CHUNKS + c) * 256 + threadIdx.x;
+    const int64_t ci = cbase + c * 256 + t;
     if (ci >= ncov) return;  // no barrier follows
     const int64_t g = cov[ci];
     const int ix = static_cast<int>(g / plane);
@@ -685,8 +739,9 @@ __global__ __launch_bounds__(256) void k_addback(T *__restrict__ out, T *__restr
       acc[b] = St<A>::zero();
       accS[b] = St<A>::zero();
     }
-    addback_group<T, NI, NB, S2, typename PJSel<NI>::type, false, true>(
-        ab, pj, ab.pinfo[g], ix, iy, iz, pos, phs, Xs, XSs, ab.np, ni, b0, nb, acc, accS);
+    addback_group<T, NI, NB, S2, typename PJSel<NI>::type, true, true>(
+        ab, pj, ab.pinfo[g], ix, iy, iz, pos, phs, Xs, XSs, ab.np, ni, b0, nb, acc, accS, slot,
+        lp, xl, S2 ? xl + NB * ldl : xl, ldl);
 #pragma unroll
     for (int b = 0; b < NB; ++b)
       if (b0 + b < nb) {
@@ -804,13 +859,27 @@ template <typename T, int NI>
 int addback_t(const gpaw_sys *s, int nb, const void *X, const void *XS, void *out, void *outS,
               hipStream_t st) {
   constexpr int NB = AddbackNB<T>::value;
-  const AddArgs ab = make_add(s, X, XS);
+  AddArgs ab = make_add(s, X, XS);
   const int64_t ncov = s->tab.ncov;
   if (ncov == 0) return GPAW_OK;
   dim3 grid(static_cast<unsigned>((ncov + 256 * AB_CHUNKS - 1) / (256 * AB_CHUNKS)),
             (nb + NB - 1) / NB);
+  // phases, positions and the slot table first; the rest of AB_LDS holds
+  // as many atoms' positions and X rows as fit (at least one)
+  const size_t row = static_cast<size_t>(NB) * s->ni * sizeof(T) * (outS ? 2 : 1);
+  const size_t fixed = (St<T>::cplx ? 48 * sizeof(z64) : 0) +
+                       (s->natoms <= POS_LDS_MAX ? (3 * sizeof(double) * s->natoms + 15) / 16 * 16
+                                                 : 0) +
+                       (sizeof(int) * (s->natoms + 1) + 15) / 16 * 16 + 16;
+  const size_t per_atom = row + 3 * sizeof(double) + sizeof(int);
+  const size_t fit = fixed < AB_LDS ? (AB_LDS - fixed) / per_atom : 0;
+  ab.cap = static_cast<int>(std::max<size_t>(1, std::min<size_t>(s->natoms, fit)));
   const size_t lds = (St<T>::cplx ? 48 * sizeof(z64) : 0) +
-                     (s->natoms <= POS_LDS_MAX ? 3 * sizeof(double) * s->natoms : 0);
+                     (s->natoms <= POS_LDS_MAX ? (3 * sizeof(double) * s->natoms + 15) / 16 * 16
+                                               : 0) +
+                     (sizeof(int) * (s->natoms + ab.cap + 1) + 15) / 16 * 16 +
+                     (3 * sizeof(double) * ab.cap + 15) / 16 * 16 + row * ab.cap;
+  if (lds > 64 * 1024) return fail(GPAW_ESHAPE, "add-back: LDS layout exceeds 64 KiB");
   T *po = static_cast<T *>(out);
   T *pso = static_cast<T *>(outS);
   if (outS)
@@ -823,11 +892,10 @@ int addback_t(const gpaw_sys *s, int nb, const void *X, const void *XS, void *ou
 // The add-back runs as its own pass for blocks of at least 2^24
 // band-points (below that the fused kernel is cheaper than a second launch)
 inline bool separate_addback(const gpaw_sys *s, int nb) {
-  return s->tab.ncov > 0 && static_cast<int64_t>(nb) * s->ng >= (int64_t{1} << 24);
+  return s->tab.ncov > 0 && s->natoms <= SLOT_ATOMS_MAX &&
+         static_cast<int64_t>(nb) * s->ng >= (int64_t{1} << 24);
 }
 
-constexpr size_t XLDS_MAX = 24 * 1024;  // staged X rows of the atoms reaching a tile
-constexpr int SLOT_ATOMS_MAX = 4096;     // atoms with a slot index in LDS
 
 template <typename T, bool BLOCH, int NB, int NI, int PPL>
 int plane_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,
