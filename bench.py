@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision-form and batched-form measurements")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-form measurement (profiler runs)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the extra workload lines (48^3 and 96^3 real)")
     ap.add_argument("--no-tune", action="store_true",
@@ -54,8 +56,9 @@ def parse():
 # kernels behind each timed call, and the sources they are built from
 PART_KERNELS = {
     "project": (["k_project"], ["csrc/nonlocal.hip", "csrc/proj.h"]),
-    # H~psi and S~psi in one pass: Delta H.P and Delta S.P (one launch), then the stencil
-    "apply_HS": (["k_dmat2", "k_plane"],
+    # H~psi and S~psi: Delta H.P and Delta S.P (one launch), then the stencil (with the
+    # add-back fused, or for large blocks followed by the add-back pass)
+    "apply_HS": (["k_dmat2", "k_plane", "k_addback"],
                  ["csrc/stencil.hip", "csrc/stencil_impl.h", "csrc/stencil_f64.hip",
                   "csrc/stencil_c128.hip", "csrc/nonlocal.hip", "csrc/proj.h"]),
     # (k_subspace matches the narrow- and wide-block kernels)
@@ -601,7 +604,8 @@ def main():
                                                     max(2, min(args.steps, 10)), 1, dev, stream)}
         del low
         torch.cuda.empty_cache()
-        out["forms"]["batched"] = batched_form(max(3, min(args.steps, 10)), 2, dev, stream)
+        if not args.no_batched:
+            out["forms"]["batched"] = batched_form(max(3, min(args.steps, 10)), 2, dev, stream)
     del step
     torch.cuda.empty_cache()
     if not args.no_extra:

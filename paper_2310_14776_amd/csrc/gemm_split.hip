@@ -558,7 +558,9 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
         }
       }
     }
-    if ((step & 3) == 3 || step + 1 == nsteps) {
+    // (the one-product rotation sums terms of size 2^-21 |psi| and keeps its
+    // FP32 tile: its rounding is far below that of the FP32 result)
+    if (!ONEP && ((step & 3) == 3 || step + 1 == nsteps)) {
 #pragma unroll
       for (int c = 0; c < NP; ++c)
 #pragma unroll
@@ -596,7 +598,8 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
       for (int e = 0; e < 4; ++e) {
         const int n = n0 + wr * 16 * WT + i * 16 + 4 * (lane >> 4) + e;
         if (n >= nb) continue;
-        double vr = dacc[0][i][j][e], vi = dacc[NP - 1][i][j][e];
+        double vr = ONEP ? facc[0][i][j][e] : dacc[0][i][j][e];
+        double vi = ONEP ? facc[NP - 1][i][j][e] : dacc[NP - 1][i][j][e];
         if constexpr (ADDSRC) {
           vr += Parts<T>::re(sv[j][e]);
           if constexpr (NP == 2) vi += Parts<T>::im(sv[j][e]);
@@ -685,18 +688,23 @@ int rotate_split_t(const gpaw_sys *s, const void *C, const void *src, int nb, in
   const int64_t wgs = (gtiles + 7) / 8 * 8 * ntiles_n;
   if (near_id) {
     // both persistent kernels, resident-sized grids (whole groups of 8); the
-    // device's flag lets exactly one of them work
-    const int64_t items = gtiles * ntiles_n;
-    auto grid_of = [&](const void *k) {
+    // device's flag lets exactly one of them work. The one-product kernel
+    // takes 128 x 128 tiles (complex too: it keeps no FP64 accumulators),
+    // so each staged source column serves twice the rows.
+    constexpr int WT1 = WT < 4 ? 4 : WT;
+    constexpr int TM1 = 32 * WT1;
+    auto grid_of = [&](const void *k, int64_t items) {
       const int64_t r = std::max<int64_t>(8, resident_slots(k, 256, 0) / 8 * 8);
       return static_cast<unsigned>(std::min(r, (items + 7) / 8 * 8));
     };
-    auto *k1 = &k_rot_lds<T, WT, true, true>;
+    const int nt1 = (nb + TM1 - 1) / TM1;
+    const int64_t gt1 = (cols + TM1 - 1) / TM1;
+    auto *k1 = &k_rot_lds<T, WT1, true, true>;
     auto *k6 = &k_rot_lds<T, WT, true, false>;
-    k1<<<grid_of(reinterpret_cast<const void *>(k1)), 256, 0, st>>>(
-        Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, nbp, cols, ntiles_n, gtiles,
+    k1<<<grid_of(reinterpret_cast<const void *>(k1), gt1 * nt1), 256, 0, st>>>(
+        Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, nbp, cols, nt1, gt1,
         upper ? 1 : 0, s->ws.flag);
-    k6<<<grid_of(reinterpret_cast<const void *>(k6)), 256, 0, st>>>(
+    k6<<<grid_of(reinterpret_cast<const void *>(k6), gtiles * ntiles_n), 256, 0, st>>>(
         Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, nbp, cols, ntiles_n, gtiles,
         upper ? 1 : 0, s->ws.flag);
   } else {
