@@ -172,3 +172,76 @@ def test_batch_full_workload_sampled():
         assert np.abs(C.conj().T @ Ss @ C - np.eye(s.nb)).max() <= 1e-12
         assert np.abs(C.conj().T @ Hs @ C - np.diag(eps)).max() <= 1e-12 * np.abs(eps).max()
     r.close()
+
+
+def test_batch_mixed_precision():
+    """Single-precision systems (FP32 and complex64 storage, split-BF16
+    products) in one batch with FP64 and complex128 ones: the FP64 systems
+    meet the 1e-12 bar, the single-precision ones the precision form's
+    (eigenvalues within 1e-6 Ha of the oracle on the same rounded inputs, or
+    2e-8 of the largest |eps| where that is larger: FP32 storage of H~psi
+    resolves 6e-8 of a value, and these noise bands reach ~100 Ha; H and S
+    within 1e-7 relative) and equal their own per-system step; the autotuner
+    leaves the single-precision shapes fixed and the results hold."""
+    cfgs = [SMALL[0], SMALL[1], SMALL[2], SMALL[3], SMALL[5]]
+    prec = ["double", "single", "single", "double", "single"]
+    systems = []
+    for i, (c, p) in enumerate(zip(cfgs, prec)):
+        s = synth.make_system(name=f"mixed{i}", **c)
+        if p == "single":
+            s.psi = s.psi.astype(np.complex64 if s.is_complex else np.float32).astype(s.psi.dtype)
+        systems.append(s)
+    say(f"[batch] mixed precision batch: {prec}")
+    gs = [gfd.System.from_synth(s, precision=p) for s, p in zip(systems, prec)]
+    psi = []
+    for s, g in zip(systems, gs):
+        x = s.psi.reshape(s.nb, -1)
+        psi.append(to_dev(x).to(g.dtype))
+    out = [torch.empty_like(p) for p in psi]
+    eps = [torch.empty(s.nb, dtype=torch.float64, device="cuda") for s in systems]
+    P = [torch.empty((s.nb, g.np), dtype=g.dtype, device="cuda") for s, g in zip(systems, gs)]
+    H = [torch.empty((s.nb, s.nb), dtype=g.mat_dtype, device="cuda") for s, g in zip(systems, gs)]
+    S = [torch.empty_like(h) for h in H]
+    C = [torch.empty_like(h) for h in H]
+    info = torch.full((len(systems),), -7, dtype=torch.int32, device="cuda")
+    batch = gfd.Batch(gs)
+    io = batch.io(psi, out, eps, P, H, S, C)
+    refs = [oracle.fd_step(s) for s in systems]
+
+    def check():
+        torch.cuda.synchronize()
+        assert host(info).tolist() == [0] * len(systems)
+        for i, (s, p, ref) in enumerate(zip(systems, prec, refs)):
+            e = host(eps[i])
+            if p == "double":
+                assert rel(host(H[i]), ref["H"]) <= TOL and rel(host(S[i]), ref["S"]) <= TOL
+                assert np.abs(e - ref["eps"]).max() <= TOL * np.abs(ref["eps"]).max()
+            else:
+                assert rel(host(H[i]), ref["H"]) <= 1e-7 and rel(host(S[i]), ref["S"]) <= 1e-7
+                err = np.abs(e - ref["eps"]).max()
+                bound = max(1e-6, 2e-8 * np.abs(ref["eps"]).max())
+                say(f"  system {i} ({'complex64' if s.is_complex else 'FP32'}): max |d eps| "
+                    f"{err:.2e} Ha (bound {bound:.1e}, max |eps| {np.abs(ref['eps']).max():.1f})")
+                assert err <= bound
+
+    batch.step(io, info)
+    check()
+    # the single-precision systems equal their own per-system step
+    for i, p in enumerate(prec):
+        if p == "single":
+            own = gs[i].step(psi[i])
+            torch.cuda.synchronize()
+            assert np.array_equal(host(own["eps"]), host(eps[i])), i
+            assert np.array_equal(host(own["psi_rot"]), host(out[i])), i
+    batch.tune(io, info)
+    torch.cuda.synchronize()
+    nbr, shapes = batch.tuning()
+    say(f"  tuned branches={nbr} shapes={shapes}")
+    for i, p in enumerate(prec):
+        if p == "single":
+            assert all(v == 0 for v in shapes[i].values()), i
+    batch.step(io, info)
+    check()
+    batch.close()
+    for g in gs:
+        g.close()
