@@ -7,9 +7,13 @@
 // matrices -> Cholesky + eigensolve -> rotation; the chains share nothing, so
 // they are dealt onto several capture streams (largest first, to the least
 // loaded stream) and recorded once into a HIP graph whose branches run
-// concurrently. Small systems then overlap their latency-bound eigensolver
-// and short kernels instead of running back to back. The autotuner times the
-// launch-shape choices of every system and the number of branches.
+// concurrently. The subspace eigensolves of all systems small enough for the
+// one-workgroup solver run between two such phases as one chain of batched
+// launches per scalar type (every system in each launch), so their
+// latency-bound stages overlap across systems instead of queueing on a few
+// hardware queues; larger systems keep their eigensolve in their branch.
+// The autotuner times the launch-shape choices of every system and the
+// number of branches.
 #include <algorithm>
 #include <array>
 #include <cstring>
@@ -31,7 +35,9 @@ struct gpaw_batch {
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> joins;
   hipStream_t cap = nullptr;
-  hipEvent_t fork = nullptr;
+  hipEvent_t fork = nullptr, fork2 = nullptr;
+  std::vector<hipEvent_t> joins2;
+  void *jobs[2] = {nullptr, nullptr};  // batched eigensolver job tables (real, complex)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<gpaw_batch_io> key;  // io the graph was recorded with
@@ -89,8 +95,16 @@ int check_io(const gpaw_batch *b, const gpaw_batch_io *io, const int32_t *info) 
   return GPAW_OK;
 }
 
-// The whole step of system i on one stream.
-int chain(const gpaw_batch *b, size_t i, const gpaw_batch_io &io, int32_t *info, hipStream_t st) {
+// Whether system i's eigensolve runs in the batched launches.
+bool batched_eig(const gpaw_batch *b, size_t i, const gpaw_batch_io &io) {
+  return io.nb <= eig_small_max(is_complex(b->sys[i]->dtype));
+}
+
+// Part of system i's step on one stream: phase 0 up to the subspace matrices
+// (and, for a system outside the batched eigensolve, the rest of the step);
+// phase 1 the rotations after the batched eigensolve.
+int chain(const gpaw_batch *b, size_t i, const gpaw_batch_io &io, int32_t *info, hipStream_t st,
+          int phase) {
   gpaw_sys *s = b->sys[i];
   const gpaw_batch::Buf &w = b->buf[i];
   const int nb = io.nb;
@@ -100,18 +114,39 @@ int chain(const gpaw_batch *b, size_t i, const gpaw_batch_io &io, int32_t *info,
   const void *X = s->np > 0 ? s->ws.X : nullptr;
   const void *XS = s->np > 0 ? s->ws.XS : nullptr;
   int rc;
-  if (s->np > 0) {
-    if ((rc = launch_project(s, io.psi, nb, w.P, st)) != GPAW_OK) return rc;
-    if ((rc = launch_dmat2(s, w.P, nb, s->ws.X, s->ws.XS, st)) != GPAW_OK) return rc;
+  const bool batched = batched_eig(b, i, io);
+  if (phase == 0) {
+    if (s->np > 0) {
+      if ((rc = launch_project(s, io.psi, nb, w.P, st)) != GPAW_OK) return rc;
+      if ((rc = launch_dmat2(s, w.P, nb, s->ws.X, s->ws.XS, st)) != GPAW_OK) return rc;
+    }
+    // H~psi and S~psi in one pass
+    if ((rc = launch_stencil(s, io.psi, nb, X, w.Hpsi, st, XS, w.Spsi)) != GPAW_OK) return rc;
+    if ((rc = launch_subspace(s, io.psi, w.Hpsi, w.Spsi, nb, H, S, st)) != GPAW_OK) return rc;
+    if (batched) return GPAW_OK;
+    if ((rc = launch_eigh(s, H, S, nb, io.eps, C, info + i, st)) != GPAW_OK) return rc;
+  } else if (!batched) {
+    return GPAW_OK;
   }
-  // H~psi and S~psi in one pass
-  if ((rc = launch_stencil(s, io.psi, nb, X, w.Hpsi, st, XS, w.Spsi)) != GPAW_OK) return rc;
-  if ((rc = launch_subspace(s, io.psi, w.Hpsi, w.Spsi, nb, H, S, st)) != GPAW_OK) return rc;
-  if ((rc = launch_eigh(s, H, S, nb, io.eps, C, info + i, st)) != GPAW_OK) return rc;
   if ((rc = launch_rotate(s, C, io.psi, nb, s->ng, io.psi_out, st)) != GPAW_OK) return rc;
   if (s->np > 0 && io.P_out)
     if ((rc = launch_rotate(s, C, w.P, nb, s->np, io.P_out, st)) != GPAW_OK) return rc;
   return GPAW_OK;
+}
+
+// The whole step of system i on one stream (its eigensolve unbatched).
+int full_chain(const gpaw_batch *b, size_t i, const gpaw_batch_io &io, int32_t *info,
+               hipStream_t st) {
+  int rc;
+  if ((rc = chain(b, i, io, info, st, 0)) != GPAW_OK) return rc;
+  if (batched_eig(b, i, io)) {
+    gpaw_sys *s = b->sys[i];
+    const gpaw_batch::Buf &w = b->buf[i];
+    if ((rc = launch_eigh(s, io.H_nn ? io.H_nn : w.H, io.S_nn ? io.S_nn : w.S, io.nb, io.eps,
+                          io.C_nn ? io.C_nn : w.C, info + i, st)) != GPAW_OK)
+      return rc;
+  }
+  return chain(b, i, io, info, st, 1);
 }
 
 // relative cost of one system's step (grid work, contractions, eigensolver latency)
@@ -146,20 +181,50 @@ int record(gpaw_batch *b, const gpaw_batch_io *io, int32_t *info, int branches) 
     lanes[l].push_back(i);
     load[l] += cost(b->sys[i], io[i].nb);
   }
+  // job tables of the batched eigensolves (a synchronous upload, before
+  // the capture; a graph recorded earlier may still read the old tables)
+  std::vector<EigBatchItem> items[2];
+  for (size_t i = 0; i < n; ++i) {
+    if (!batched_eig(b, i, io[i])) continue;
+    gpaw_sys *s = b->sys[i];
+    const gpaw_batch::Buf &w = b->buf[i];
+    items[is_complex(s->dtype) ? 1 : 0].push_back(
+        EigBatchItem{s, io[i].H_nn ? io[i].H_nn : w.H, io[i].S_nn ? io[i].S_nn : w.S, io[i].nb,
+                     io[i].eps, io[i].C_nn ? io[i].C_nn : w.C, info + i});
+  }
+  GFD_HIP(hipDeviceSynchronize());
+  for (int c = 0; c < 2; ++c) {
+    if (b->jobs[c]) (void)hipFree(b->jobs[c]);
+    b->jobs[c] = nullptr;
+    if (items[c].empty()) continue;
+    GFD_HIP(hipMalloc(&b->jobs[c], items[c].size() * eig_job_bytes()));
+    int rc0 = eigh_batched_prepare(items[c].data(), static_cast<int>(items[c].size()), b->jobs[c]);
+    if (rc0 != GPAW_OK) return rc0;
+  }
   GFD_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
   int rc = GPAW_OK;
-  hipError_t e = hipEventRecord(b->fork, b->cap);
-  for (int l = 0; l < branches && e == hipSuccess; ++l) e = hipStreamWaitEvent(b->streams[l], b->fork, 0);
-  if (e != hipSuccess) rc = hip_fail(e, "graph fork");
-  for (int l = 0; l < branches && rc == GPAW_OK; ++l)
-    for (size_t i : lanes[l])
-      if ((rc = chain(b, i, io[i], info, b->streams[l])) != GPAW_OK) break;
-  // join every branch, also after a failed launch, so that no stream is
-  // left in capture mode
-  for (int l = 0; l < branches; ++l) {
-    e = hipEventRecord(b->joins[l], b->streams[l]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->joins[l], 0);
-    if (e != hipSuccess && rc == GPAW_OK) rc = hip_fail(e, "graph join");
+  hipError_t e = hipSuccess;
+  // phase 0 on the branches, the batched eigensolves on the capture stream,
+  // phase 1 on the branches again; every fork and join is recorded, also
+  // after a failed launch, so that no stream is left in capture mode
+  for (int phase = 0; phase < 2; ++phase) {
+    hipEvent_t fk = phase == 0 ? b->fork : b->fork2;
+    e = hipEventRecord(fk, b->cap);
+    for (int l = 0; l < branches && e == hipSuccess; ++l) e = hipStreamWaitEvent(b->streams[l], fk, 0);
+    if (e != hipSuccess && rc == GPAW_OK) rc = hip_fail(e, "graph fork");
+    for (int l = 0; l < branches && rc == GPAW_OK; ++l)
+      for (size_t i : lanes[l])
+        if ((rc = chain(b, i, io[i], info, b->streams[l], phase)) != GPAW_OK) break;
+    std::vector<hipEvent_t> &jn = phase == 0 ? b->joins : b->joins2;
+    for (int l = 0; l < branches; ++l) {
+      e = hipEventRecord(jn[l], b->streams[l]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, jn[l], 0);
+      if (e != hipSuccess && rc == GPAW_OK) rc = hip_fail(e, "graph join");
+    }
+    if (phase == 0 && rc == GPAW_OK)
+      for (int c = 0; c < 2 && rc == GPAW_OK; ++c)
+        rc = launch_eigh_batched(items[c].data(), static_cast<int>(items[c].size()), c == 1,
+                                 b->jobs[c], b->cap);
   }
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(b->cap, &g);
@@ -204,7 +269,11 @@ void free_batch(gpaw_batch *b) {
   }
   for (hipStream_t st : b->streams) (void)hipStreamDestroy(st);
   for (hipEvent_t ev : b->joins) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : b->joins2) (void)hipEventDestroy(ev);
   if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->fork2) (void)hipEventDestroy(b->fork2);
+  for (void *j : b->jobs)
+    if (j) (void)hipFree(j);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   delete b;
 }
@@ -262,7 +331,7 @@ int tune_system(gpaw_batch *b, size_t i, const gpaw_batch_io &io, int32_t *info,
   s->tune = Tune{};
   int rc;
   // one full chain so P, X, Hpsi, Spsi, C hold valid data for the part timings
-  if ((rc = chain(b, i, io, info, st)) != GPAW_OK) return rc;
+  if ((rc = full_chain(b, i, io, info, st)) != GPAW_OK) return rc;
   void *C = io.C_nn ? io.C_nn : w.C;
   const void *X = s->np > 0 ? s->ws.X : nullptr;
   const void *XS = s->np > 0 ? s->ws.XS : nullptr;
@@ -356,6 +425,7 @@ int gpaw_batch_create(gpaw_sys *const *systems, int32_t nsys, gpaw_batch **out) 
   hipError_t e = hipSuccess;
   if (rc == GPAW_OK) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (rc == GPAW_OK && e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  if (rc == GPAW_OK && e == hipSuccess) e = hipEventCreateWithFlags(&b->fork2, hipEventDisableTiming);
   for (int l = 0; l < kMaxBranches && rc == GPAW_OK && e == hipSuccess; ++l) {
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
@@ -363,6 +433,9 @@ int gpaw_batch_create(gpaw_sys *const *systems, int32_t nsys, gpaw_batch **out) 
     if (e == hipSuccess) b->streams.push_back(st);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e == hipSuccess) b->joins.push_back(ev);
+    hipEvent_t ev2 = nullptr;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev2, hipEventDisableTiming);
+    if (e == hipSuccess) b->joins2.push_back(ev2);
   }
   if (rc == GPAW_OK && e != hipSuccess) rc = hip_fail(e, "batch streams");
   if (rc != GPAW_OK) {

@@ -285,7 +285,7 @@ __device__ inline int diag_factor_inverse(T *D, int lda) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(CH_T) void k_eig_chol(const T *__restrict__ S, int n, EigWs w,
+__device__ __forceinline__ void d_eig_chol(const T *__restrict__ S, int n, EigWs w,
                                                     int32_t *info) {
   extern __shared__ double sm[];
   const int NT = (n + 15) / 16, N = 16 * NT, lda = N + 1;
@@ -400,6 +400,12 @@ __global__ __launch_bounds__(CH_T) void k_eig_chol(const T *__restrict__ S, int 
   if (tid == 0) *info = 0;
 }
 
+template <typename T>
+__global__ __launch_bounds__(CH_T) void k_eig_chol(const T *__restrict__ S, int n, EigWs w,
+                                                    int32_t *info) {
+  d_eig_chol<T>(S, n, w, info);
+}
+
 // LDS bytes of k_eig_chol for an n x n block
 template <typename T>
 size_t chol_lds_bytes(int n) {
@@ -437,7 +443,7 @@ __device__ inline T opval(const T *M, int r, int c, int n) {
 }
 
 template <typename T, int AM, int BM>
-__global__ __launch_bounds__(SG_T) void k_small_gemm(const T *__restrict__ A,
+__device__ __forceinline__ void d_small_gemm(const T *__restrict__ A,
                                                      const T *__restrict__ B,
                                                      T *__restrict__ C, int n,
                                                      const int32_t *info) {
@@ -481,6 +487,14 @@ __global__ __launch_bounds__(SG_T) void k_small_gemm(const T *__restrict__ A,
       else C[rr * n + cc] = accr[e];
     }
   }
+}
+
+template <typename T, int AM, int BM>
+__global__ __launch_bounds__(SG_T) void k_small_gemm(const T *__restrict__ A,
+                                                     const T *__restrict__ B,
+                                                     T *__restrict__ C, int n,
+                                                     const int32_t *info) {
+  d_small_gemm<T, AM, BM>(A, B, C, n, info);
 }
 
 // ------------------------------------------------------------------ tridiagonal
@@ -577,7 +591,7 @@ __device__ inline void tri_reflector(int n, int k, T x0, T x1, T *vout, TriLds<T
 }
 
 template <typename T>
-__global__ __launch_bounds__(TRI_T) void k_eig_tridiag(int n, EigWs w, const int32_t *info) {
+__device__ __forceinline__ void d_eig_tridiag(int n, EigWs w, const int32_t *info) {
   if (*info != 0) return;
   constexpr int NM = EigMax<T>::n, RR = NM / 32, RC = NM / 8;
   __shared__ TriLds<T> L;
@@ -697,13 +711,18 @@ __global__ __launch_bounds__(TRI_T) void k_eig_tridiag(int n, EigWs w, const int
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(TRI_T) void k_eig_tridiag(int n, EigWs w, const int32_t *info) {
+  d_eig_tridiag<T>(n, w, info);
+}
+
 // ------------------------------------------------------------------ values
 // The workgroup stages T once: split points as ballot bit masks, and
 // (d_i s, e_i-1^2 s^2) pairs for the Sturm recurrence, with s a power of two
 // (exact) that brings the Gershgorin bound of the whole matrix below 1.
 inline size_t values_lds_bytes(int n) { return (5 * static_cast<size_t>(n) + 1) * sizeof(double); }
 
-__global__ __launch_bounds__(256) void k_eig_values(int n, const double *__restrict__ dg,
+__device__ __forceinline__ void d_eig_values(int n, const double *__restrict__ dg,
                                                     const double *__restrict__ eg,
                                                     double *__restrict__ lam_out,
                                                     const int32_t *__restrict__ info) {
@@ -818,6 +837,13 @@ __global__ __launch_bounds__(256) void k_eig_values(int n, const double *__restr
   if (lane == 0) lam_out[j] = 0.5 * (a + b);
 }
 
+__global__ __launch_bounds__(256) void k_eig_values(int n, const double *__restrict__ dg,
+                                                    const double *__restrict__ eg,
+                                                    double *__restrict__ lam_out,
+                                                    const int32_t *__restrict__ info) {
+  d_eig_values(n, dg, eg, lam_out, info);
+}
+
 // ------------------------------------------------------------------ vectors
 // Start vectors of inverse iteration: windows of one table of pseudo-random
 // values in [-1, 1) (MurmurHash3's 32-bit finaliser of the index), window j
@@ -840,7 +866,7 @@ inline size_t vec_lds_doubles(int n) {
   return 4 * static_cast<size_t>(n) + 8 + RV_N + 6 * static_cast<size_t>(n) * VEC_T;
 }
 
-__global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int32_t *info) {
+__device__ __forceinline__ void d_eig_vectors(int n, EigWs w, const int32_t *info) {
   if (*info != 0) return;
   extern __shared__ double sv[];
   double *d = sv, *e = sv + n, *lam = sv + 2 * n, *rs = sv + 3 * n;
@@ -1028,13 +1054,17 @@ __global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int
 #undef AT
 }
 
+__global__ __launch_bounds__(VEC_T) void k_eig_vectors(int n, EigWs w, const int32_t *info) {
+  d_eig_vectors(n, w, info);
+}
+
 // ------------------------------------------------------------------ orthogonality
 // dev[slot] = max |G - I| (one workgroup); info = -1 when above the limit
 // skip (optional): set to 1 when max |G - I| <= skip_limit (the vectors are
 // already orthonormal to rounding, so the kernels that take skip as their
 // status word do nothing) or when the status is not 0;
 // gate (optional): the check does nothing while *gate is nonzero.
-__global__ __launch_bounds__(1024) void k_gram_check(const double *__restrict__ G, int n,
+__device__ __forceinline__ void d_gram_check(const double *__restrict__ G, int n,
                                                      double limit, int32_t *info, int32_t *skip,
                                                      double skip_limit, const int32_t *gate) {
   if (*info != 0 || (gate && *gate != 0)) {
@@ -1071,6 +1101,12 @@ __global__ __launch_bounds__(1024) void k_gram_check(const double *__restrict__ 
   }
 }
 
+__global__ __launch_bounds__(1024) void k_gram_check(const double *__restrict__ G, int n,
+                                                     double limit, int32_t *info, int32_t *skip,
+                                                     double skip_limit, const int32_t *gate) {
+  d_gram_check(G, n, limit, info, skip, skip_limit, gate);
+}
+
 // ------------------------------------------------------------------ clusters
 // Inverse iteration separates the eigenvectors of one unreduced block of T
 // only as far as the eigenvalue gaps allow: vectors whose eigenvalues lie
@@ -1086,7 +1122,7 @@ __global__ __launch_bounds__(1024) void k_gram_check(const double *__restrict__ 
 constexpr double CL_TOL = 1e-7;
 constexpr int CL_T = 256;
 constexpr int CL_RPL = EIG_LARGE_MAX / 64;  // rows per lane
-__global__ __launch_bounds__(CL_T) void k_cluster_orth(int n, const double *__restrict__ d,
+__device__ __forceinline__ void d_cluster_orth(int n, const double *__restrict__ d,
                                                        const double *__restrict__ e,
                                                        const double *__restrict__ lam,
                                                        double *__restrict__ Z,
@@ -1168,6 +1204,16 @@ __global__ __launch_bounds__(CL_T) void k_cluster_orth(int n, const double *__re
   }
 }
 
+__global__ __launch_bounds__(CL_T) void k_cluster_orth(int n, const double *__restrict__ d,
+                                                       const double *__restrict__ e,
+                                                       const double *__restrict__ lam,
+                                                       double *__restrict__ Z,
+                                                       int32_t *__restrict__ cid,
+                                                       double *__restrict__ cltol,
+                                                       const int32_t *__restrict__ info) {
+  d_cluster_orth(n, d, e, lam, Z, cid, cltol, info);
+}
+
 // ------------------------------------------------------------------ refinement
 // Eigenvector refinement of Ogita and Aishima (2018), one step, on the
 // tridiagonal problem T z_j = lam_j z_j. With G = Z^T Z, M = Z^T (T Z) and
@@ -1186,7 +1232,7 @@ __global__ __launch_bounds__(CL_T) void k_cluster_orth(int n, const double *__re
 // (Newton-Schulz) orthogonalisation Z (3I - G) / 2.
 
 // Y = T Z (T tridiagonal: diagonal d, off-diagonal e)
-__global__ __launch_bounds__(256) void k_tri_apply(int n, const double *__restrict__ d,
+__device__ __forceinline__ void d_tri_apply(int n, const double *__restrict__ d,
                                                    const double *__restrict__ e,
                                                    const double *__restrict__ Z,
                                                    double *__restrict__ Y,
@@ -1201,10 +1247,18 @@ __global__ __launch_bounds__(256) void k_tri_apply(int n, const double *__restri
   Y[idx] = y;
 }
 
+__global__ __launch_bounds__(256) void k_tri_apply(int n, const double *__restrict__ d,
+                                                   const double *__restrict__ e,
+                                                   const double *__restrict__ Z,
+                                                   double *__restrict__ Y,
+                                                   const int32_t *__restrict__ gate) {
+  d_tri_apply(n, d, e, Z, Y, gate);
+}
+
 constexpr double RF_GAP = 1e-2;
 
 // F = I + E from G and M (above)
-__global__ __launch_bounds__(256) void k_refine_coef(int n, const double *__restrict__ G,
+__device__ __forceinline__ void d_refine_coef(int n, const double *__restrict__ G,
                                                      const double *__restrict__ M,
                                                      const double *__restrict__ lam,
                                                      const int32_t *__restrict__ cid,
@@ -1221,6 +1275,16 @@ __global__ __launch_bounds__(256) void k_refine_coef(int n, const double *__rest
   if (i != j && cid[i] != cid[j] && fabs(gap) > (RF_GAP / CL_TOL) * *cltol)
     E = (M[idx] + lam[j] * r) / gap;
   F[idx] = (i == j ? 1.0 : 0.0) + E;
+}
+
+__global__ __launch_bounds__(256) void k_refine_coef(int n, const double *__restrict__ G,
+                                                     const double *__restrict__ M,
+                                                     const double *__restrict__ lam,
+                                                     const int32_t *__restrict__ cid,
+                                                     const double *__restrict__ cltol,
+                                                     double *__restrict__ F,
+                                                     const int32_t *__restrict__ gate) {
+  d_refine_coef(n, G, M, lam, cid, cltol, F, gate);
 }
 
 // ------------------------------------------------------------------ back-transform
@@ -1245,7 +1309,7 @@ size_t back_lds_bytes(int n) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(128) void k_eig_back(int n, EigWs w, const double *__restrict__ Z,
+__device__ __forceinline__ void d_eig_back(int n, EigWs w, const double *__restrict__ Z,
                                                   T *__restrict__ Uo, double *__restrict__ eps,
                                                   const int32_t *info) {
   if (*info != 0) return;
@@ -1389,14 +1453,27 @@ __global__ __launch_bounds__(128) void k_eig_back(int n, EigWs w, const double *
   if (s == 0) eps[rank] = lj;
 }
 
+template <typename T>
+__global__ __launch_bounds__(128) void k_eig_back(int n, EigWs w, const double *__restrict__ Z,
+                                                  T *__restrict__ Uo, double *__restrict__ eps,
+                                                  const int32_t *info) {
+  d_eig_back<T>(n, w, Z, Uo, eps, info);
+}
 
 
-__global__ __launch_bounds__(256) void k_copy_gated(const double *__restrict__ src,
+
+__device__ __forceinline__ void d_copy_gated(const double *__restrict__ src,
                                                     double *__restrict__ dst, int64_t count,
                                                     const int32_t *__restrict__ gate) {
   if (*gate != 0) return;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (idx < count) dst[idx] = src[idx];
+}
+
+__global__ __launch_bounds__(256) void k_copy_gated(const double *__restrict__ src,
+                                                    double *__restrict__ dst, int64_t count,
+                                                    const int32_t *__restrict__ gate) {
+  d_copy_gated(src, dst, count, gate);
 }
 
 // Refined eigenvectors of T (from w.Z after the cluster step) into w.G.
@@ -1542,6 +1619,165 @@ int chol_inv_t(const gpaw_sys *s, const void *S, int n, void *Cout, int32_t *inf
   return GPAW_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Batched small eigensolves: the one-workgroup pipeline above for several
+// systems of one scalar type in one chain of launches. Launch k covers every
+// system (blockIdx.y = system) with the grid of the largest; a system's
+// workgroups past its own grid for that stage leave at once, so each system
+// runs exactly the single-system launches, in the same order, and its results
+// equal those of its own call bit for bit. Independent systems then share
+// one launch per stage instead of queueing one-workgroup launches behind
+// each other.
+struct EigJob {
+  int n;
+  EigWs w;
+  const void *H, *S;
+  double *eps;
+  void *C;
+  int32_t *info;
+};
+
+__device__ inline unsigned sg_grid(int n) {
+  const int t = (n + 15) / 16;
+  return static_cast<unsigned>((t * t + 3) / 4);
+}
+__device__ inline unsigned elem_grid(int n) {
+  return static_cast<unsigned>((static_cast<int64_t>(n) * n + 255) / 256);
+}
+
+template <typename T>
+__global__ __launch_bounds__(CH_T) void kb_eig_chol(const EigJob *J) {
+  const EigJob &j = J[blockIdx.y];
+  d_eig_chol<T>(static_cast<const T *>(j.S), j.n, j.w, j.info);
+}
+
+// SEL picks the operands of one of the pipeline's small products (see
+// eigh_t and refine_vectors for the single-system order)
+template <typename T, int AM, int BM, int SEL>
+__global__ __launch_bounds__(SG_T) void kb_small_gemm(const EigJob *J) {
+  const EigJob &j = J[blockIdx.y];
+  if (blockIdx.x >= sg_grid(j.n)) return;
+  const EigWs &w = j.w;
+  if constexpr (SEL == 0) d_small_gemm<T, AM, BM>(static_cast<const T *>(j.H), as<T>(w.Linv), as<T>(w.T1), j.n, j.info);
+  if constexpr (SEL == 1) d_small_gemm<T, AM, BM>(as<T>(w.Linv), as<T>(w.T1), as<T>(w.A), j.n, j.info);
+  if constexpr (SEL == 2) d_small_gemm<T, AM, BM>(as<T>(w.Linv), as<T>(w.T1), static_cast<T *>(j.C), j.n, j.info);
+  if constexpr (SEL == 3) d_small_gemm<T, AM, BM>(w.Z, w.Z, w.G, j.n, j.info);
+  if constexpr (SEL == 4) d_small_gemm<T, AM, BM>(w.Z, w.Z2, w.T1, j.n, j.info);
+  if constexpr (SEL == 5) d_small_gemm<T, AM, BM>(w.Z, w.Z2, w.G, j.n, j.info);
+  if constexpr (SEL == 6) d_small_gemm<T, AM, BM>(w.G, w.G, w.Z, j.n, j.info);
+  if constexpr (SEL == 7) d_small_gemm<T, AM, BM>(w.G, w.Z2, w.T1, j.n, w.skip);
+  if constexpr (SEL == 8) d_small_gemm<T, AM, BM>(w.G, w.Z2, w.Z, j.n, w.skip);
+}
+
+template <typename T>
+__global__ __launch_bounds__(TRI_T) void kb_eig_tridiag(const EigJob *J) {
+  const EigJob &j = J[blockIdx.y];
+  d_eig_tridiag<T>(j.n, j.w, j.info);
+}
+
+__global__ __launch_bounds__(256) void kb_eig_values(const EigJob *J) {
+  const EigJob &j = J[blockIdx.y];
+  if (blockIdx.x >= static_cast<unsigned>((j.n + 3) / 4)) return;
+  d_eig_values(j.n, j.w.d, j.w.e, j.w.lam, j.info);
+}
+
+__global__ __launch_bounds__(VEC_T) void kb_eig_vectors(const EigJob *J) {
+  const EigJob &j = J[blockIdx.y];
+  if (blockIdx.x >= static_cast<unsigned>((j.n + VEC_T - 1) / VEC_T)) return;
+  d_eig_vectors(j.n, j.w, j.info);
+}
+
+__global__ __launch_bounds__(CL_T) void kb_cluster_orth(const EigJob *J) {
+  const EigJob &j = J[blockIdx.y];
+  d_cluster_orth(j.n, j.w.d, j.w.e, j.w.lam, j.w.Z, j.w.cid, j.w.cltol, j.info);
+}
+
+template <int STEP>
+__global__ __launch_bounds__(1024) void kb_gram_check(const EigJob *J) {
+  const EigJob &j = J[blockIdx.y];
+  if constexpr (STEP == 0) d_gram_check(j.w.G, j.n, 0.1, j.info, nullptr, 0.0, nullptr);
+  else d_gram_check(j.w.Z, j.n, 1e-4, j.info, j.w.skip, 1e-13, nullptr);
+}
+
+template <int STEP>
+__global__ __launch_bounds__(256) void kb_tri_apply(const EigJob *J) {
+  const EigJob &j = J[blockIdx.y];
+  if (blockIdx.x >= elem_grid(j.n)) return;
+  if constexpr (STEP == 0) d_tri_apply(j.n, j.w.d, j.w.e, j.w.Z, j.w.Z2, j.info);
+  else d_tri_apply(j.n, j.w.d, j.w.e, j.w.G, j.w.Z2, j.w.skip);
+}
+
+template <int STEP>
+__global__ __launch_bounds__(256) void kb_refine_coef(const EigJob *J) {
+  const EigJob &j = J[blockIdx.y];
+  if (blockIdx.x >= elem_grid(j.n)) return;
+  const EigWs &w = j.w;
+  if constexpr (STEP == 0) d_refine_coef(j.n, w.G, w.T1, w.lam, w.cid, w.cltol, w.Z2, j.info);
+  else d_refine_coef(j.n, w.Z, w.T1, w.lam, w.cid, w.cltol, w.Z2, w.skip);
+}
+
+__global__ __launch_bounds__(256) void kb_copy_gated(const EigJob *J) {
+  const EigJob &j = J[blockIdx.y];
+  if (blockIdx.x >= elem_grid(j.n)) return;
+  d_copy_gated(j.w.Z, j.w.G, static_cast<int64_t>(j.n) * j.n, j.w.skip);
+}
+
+template <typename T>
+__global__ __launch_bounds__(128) void kb_eig_back(const EigJob *J) {
+  const EigJob &j = J[blockIdx.y];
+  if (blockIdx.x >= static_cast<unsigned>((j.n + 15) / 16)) return;
+  d_eig_back<T>(j.n, j.w, j.w.G, as<T>(j.w.T1), j.eps, j.info);
+}
+
+template <typename T>
+int eigh_batched_t(const EigBatchItem *items, int count, const void *jobs, hipStream_t st) {
+  static std::once_flag once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(once, [] {
+    const void *fns[] = {reinterpret_cast<const void *>(&kb_eig_chol<T>),
+                         reinterpret_cast<const void *>(&kb_eig_back<T>)};
+    for (const void *f : fns)
+      if (attr_err == hipSuccess)
+        attr_err = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  });
+  if (attr_err != hipSuccess) return hip_fail(attr_err, "hipFuncSetAttribute(batched eigensolver)");
+  int nmax = 1;
+  for (int i = 0; i < count; ++i) nmax = std::max(nmax, items[i].nb);
+  if (nmax > EigMax<T>::n) return fail(GPAW_ESHAPE, "batched eigensolver: nb above the one-workgroup limit");
+  const EigJob *J = static_cast<const EigJob *>(jobs);
+  const unsigned ny = static_cast<unsigned>(count);
+  const int64_t nn = static_cast<int64_t>(nmax) * nmax;
+  const unsigned eb = static_cast<unsigned>((nn + 255) / 256);
+  const int tiles = ((nmax + 15) / 16) * ((nmax + 15) / 16);
+  const unsigned sgb = static_cast<unsigned>((tiles + 3) / 4);
+  kb_eig_chol<T><<<dim3(1, ny), CH_T, chol_lds_bytes<T>(nmax), st>>>(J);
+  kb_small_gemm<T, 2, 1, 0><<<dim3(sgb, ny), SG_T, 0, st>>>(J);
+  kb_small_gemm<T, 0, 0, 1><<<dim3(sgb, ny), SG_T, 0, st>>>(J);
+  kb_eig_tridiag<T><<<dim3(1, ny), TRI_T, 0, st>>>(J);
+  kb_eig_values<<<dim3((nmax + 3) / 4, ny), 256, values_lds_bytes(nmax), st>>>(J);
+  kb_eig_vectors<<<dim3((nmax + VEC_T - 1) / VEC_T, ny), VEC_T,
+                   vec_lds_doubles(nmax) * sizeof(double), st>>>(J);
+  kb_cluster_orth<<<dim3(1, ny), CL_T, 0, st>>>(J);
+  // eigenvector refinement, as refine_vectors
+  kb_small_gemm<double, 1, 0, 3><<<dim3(sgb, ny), SG_T, 0, st>>>(J);
+  kb_gram_check<0><<<dim3(1, ny), 1024, 0, st>>>(J);
+  kb_tri_apply<0><<<dim3(eb, ny), 256, 0, st>>>(J);
+  kb_small_gemm<double, 1, 0, 4><<<dim3(sgb, ny), SG_T, 0, st>>>(J);
+  kb_refine_coef<0><<<dim3(eb, ny), 256, 0, st>>>(J);
+  kb_small_gemm<double, 0, 0, 5><<<dim3(sgb, ny), SG_T, 0, st>>>(J);
+  kb_small_gemm<double, 1, 0, 6><<<dim3(sgb, ny), SG_T, 0, st>>>(J);
+  kb_gram_check<1><<<dim3(1, ny), 1024, 0, st>>>(J);
+  kb_tri_apply<1><<<dim3(eb, ny), 256, 0, st>>>(J);
+  kb_small_gemm<double, 1, 0, 7><<<dim3(sgb, ny), SG_T, 0, st>>>(J);
+  kb_refine_coef<1><<<dim3(eb, ny), 256, 0, st>>>(J);
+  kb_small_gemm<double, 0, 0, 8><<<dim3(sgb, ny), SG_T, 0, st>>>(J);
+  kb_copy_gated<<<dim3(eb, ny), 256, 0, st>>>(J);
+  // U = Q Z in eigen-order, then C = Linv^H U
+  kb_eig_back<T><<<dim3((nmax + 15) / 16, ny), 128, back_lds_bytes<T>(nmax), st>>>(J);
+  kb_small_gemm<T, 1, 0, 2><<<dim3(sgb, ny), SG_T, 0, st>>>(J);
+  return GPAW_OK;
+}
+
 }  // namespace
 
 int launch_chol_inv(const gpaw_sys *s, const void *S, int nb, void *Cout, int32_t *info,
@@ -1554,6 +1790,37 @@ size_t eig_ws_elems(int nmax, bool cplx) {
   const int small = cplx ? EigMax<z64>::n : EigMax<double>::n;
   const int n = std::min(nmax, EIG_LARGE_MAX);
   return eig_layout_elems(n, cplx ? 2 : 1, n > small);
+}
+
+int eig_small_max(bool cplx) { return cplx ? EigMax<z64>::n : EigMax<double>::n; }
+
+size_t eig_job_bytes() { return sizeof(EigJob); }
+
+int eigh_batched_prepare(const EigBatchItem *items, int count, void *jobs) {
+  std::vector<EigJob> host(static_cast<size_t>(count));
+  for (int i = 0; i < count; ++i) {
+    const EigBatchItem &it = items[i];
+    const bool cplx = is_complex(it.s->dtype);
+    if (it.nb < 1 || it.nb > eig_small_max(cplx))
+      return fail(GPAW_ESHAPE, "batched eigensolver: nb outside [1, one-workgroup limit]");
+    EigJob &j = host[static_cast<size_t>(i)];
+    j.n = it.nb;
+    j.w = eig_layout(it.s->ws.eig, it.nb, cplx ? 2 : 1, false);
+    j.H = it.H;
+    j.S = it.S;
+    j.eps = it.eps;
+    j.C = it.C;
+    j.info = it.info;
+  }
+  if (count > 0) GFD_HIP(hipMemcpy(jobs, host.data(), host.size() * sizeof(EigJob), hipMemcpyHostToDevice));
+  return GPAW_OK;
+}
+
+int launch_eigh_batched(const EigBatchItem *items, int count, bool cplx, const void *jobs,
+                        hipStream_t st) {
+  if (count == 0) return GPAW_OK;
+  return cplx ? eigh_batched_t<z64>(items, count, jobs, st)
+              : eigh_batched_t<double>(items, count, jobs, st);
 }
 
 int launch_eigh(const gpaw_sys *s, const void *H, const void *S, int nb, double *eps, void *C,

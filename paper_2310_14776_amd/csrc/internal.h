@@ -269,6 +269,24 @@ int launch_apply_S(const gpaw_sys *s, const void *psi, int nb, const void *X, vo
 int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
                     int nb, void *H, void *S, hipStream_t st, double *part = nullptr,
                     size_t part_elems = 0);
+// Small subspace eigensolves (nb up to the one-workgroup limit) of several
+// systems of one scalar type in one chain of launches (eigh.hip). The job
+// table lives in device memory of at least eig_job_bytes() per item: filled
+// by eigh_batched_prepare (a synchronous copy, outside any stream capture),
+// read by the launches of launch_eigh_batched, which may be captured.
+struct EigBatchItem {
+  const gpaw_sys *s;
+  const void *H, *S;
+  int nb;
+  double *eps;
+  void *C;
+  int32_t *info;
+};
+int eig_small_max(bool cplx);
+size_t eig_job_bytes();
+int eigh_batched_prepare(const EigBatchItem *items, int count, void *jobs);
+int launch_eigh_batched(const EigBatchItem *items, int count, bool cplx, const void *jobs,
+                        hipStream_t st);
 size_t subspace_part_elems(const gpaw_sys *s, int nb);
 // Split-K planning (gemm.hip). A product whose K range is cut into ns
 // pieces launches units workgroups per piece (8 or more pieces are launched
