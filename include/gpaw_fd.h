@@ -312,6 +312,18 @@ GPAW_API int gpaw_batch_tune(gpaw_batch *b, const gpaw_batch_io *io, int32_t *in
  * 1 + 7 nsys int32 (host). */
 GPAW_API int gpaw_batch_tuning(const gpaw_batch *b, int32_t *out);
 
+/* Sets the launch shapes in the layout gpaw_batch_tuning returns (in holds
+ * 1 + 7 nsys int32, host; in[0] = graph branches 0..16, 0 = default), for
+ * a caller that kept an earlier autotuner result (a tuning cache) instead of
+ * running the autotuner again. Values are checked as the autotuner would
+ * choose them (points per lane 0/1/2; tile sides both 0 or both positive;
+ * x segments 0..n0; subspace workgroups 0..1024; rotation row tiles complex
+ * 2/4, real 4/8; projection bands complex 1/2, real 2/4/8; 0 = built-in),
+ * single-precision systems accept only 0s; on any bad value GPAW_EINVAL and
+ * nothing changes. The recorded graph is dropped; the next step records
+ * again. Results change only in the order of floating-point sums. */
+GPAW_API int gpaw_batch_set_tuning(gpaw_batch *b, const int32_t *in);
+
 /* Message for the calling host thread's last non-zero return ("" if none). */
 GPAW_API const char *gpaw_last_error(void);
 

@@ -6,6 +6,7 @@ include/gpaw_fd.h; all arithmetic runs in the library's kernels. There is
 no fallback: a missing library or a non-zero status raises.
 """
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -48,7 +49,7 @@ ENTRY_POINTS = ["gpaw_sys_create", "gpaw_sys_destroy", "gpaw_sys_info", "gpaw_pr
                 "gpaw_davidson_correction", "gpaw_davidson_step",
                 "gpaw_subspace_diag", "gpaw_rotate", "gpaw_orthonormalize",
                 "gpaw_batch_create", "gpaw_batch_destroy", "gpaw_batch_step",
-                "gpaw_batch_tune", "gpaw_batch_tuning",
+                "gpaw_batch_tune", "gpaw_batch_tuning", "gpaw_batch_set_tuning",
                 "gpaw_last_error", "gpaw_version", "gpaw_probe_copy", "gpaw_probe_mfma",
                 "gpaw_poisson_create", "gpaw_poisson_destroy", "gpaw_poisson_levels",
                 "gpaw_poisson_solve", "gpaw_laplacian_zero", "gpaw_grid_restrict",
@@ -99,6 +100,7 @@ def load():
     lib.gpaw_batch_step.argtypes = [vp, ctypes.POINTER(BatchIO), vp, vp]
     lib.gpaw_batch_tune.argtypes = [vp, ctypes.POINTER(BatchIO), vp]
     lib.gpaw_batch_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.gpaw_batch_set_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     i32p, f64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
     lib.gpaw_poisson_create.argtypes = [i32p, f64p, ctypes.POINTER(vp)]
     lib.gpaw_poisson_destroy.argtypes = [vp]
@@ -383,6 +385,10 @@ class System:
                     psi_rot=psi_rot, P_rot=P_rot)
 
 
+TUNING_KEYS = ("stencil_ppl", "stencil_ty", "stencil_tz", "stencil_xseg", "subspace_wgs",
+               "rotate_rb", "project_nbg")
+
+
 class Batch:
     """Many independent systems stepped by one graph launch (owns the
     library's gpaw_batch, not the systems)."""
@@ -432,9 +438,44 @@ class Batch:
         n = len(self.systems)
         out = (ctypes.c_int32 * (1 + 7 * n))()
         _check(load().gpaw_batch_tuning(self._h, out))
-        keys = ("stencil_ppl", "stencil_ty", "stencil_tz", "stencil_xseg", "subspace_wgs",
-                "rotate_rb", "project_nbg")
-        return int(out[0]), [dict(zip(keys, out[1 + 7 * i: 8 + 7 * i])) for i in range(n)]
+        return int(out[0]), [dict(zip(TUNING_KEYS, out[1 + 7 * i: 8 + 7 * i])) for i in range(n)]
+
+    def set_tuning(self, branches, shapes):
+        """gpaw_batch_set_tuning: shapes as tuning() returns them."""
+        n = len(self.systems)
+        if len(shapes) != n:
+            raise ValueError("one shape dict per system")
+        arr = (ctypes.c_int32 * (1 + 7 * n))()
+        arr[0] = int(branches)
+        for i, sh in enumerate(shapes):
+            for j, key in enumerate(TUNING_KEYS):
+                arr[1 + 7 * i + j] = int(sh[key])
+        _check(load().gpaw_batch_set_tuning(self._h, arr))
+
+    def signature(self):
+        """What a stored tuning is valid for: per system the grid, storage
+        type, boundary, band capacity and projector geometry."""
+        return [dict(n=list(g.n), dtype=str(g.dtype).replace("torch.", ""), boundary=g.boundary,
+                     max_bands=g.max_bands, natoms=g.natoms, np=g.np,
+                     entries=int(g.info["entries"])) for g in self.systems]
+
+    def save_tuning(self, path):
+        """Writes the current launch shapes and the batch's signature (JSON)."""
+        branches, shapes = self.tuning()
+        with open(path, "w") as fh:
+            json.dump(dict(format="gpaw-fd-tuning", version=1, signature=self.signature(),
+                           branches=branches, shapes=shapes), fh, indent=1)
+
+    def load_tuning(self, path):
+        """Applies shapes saved by save_tuning when they were made for the
+        same systems (same signature): returns True, else False and leaves
+        the batch unchanged."""
+        with open(path) as fh:
+            data = json.load(fh)
+        if data.get("format") != "gpaw-fd-tuning" or data.get("signature") != self.signature():
+            return False
+        self.set_tuning(data["branches"], data["shapes"])
+        return True
 
 
 def probe_copy(src, dst, stream=None):

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <array>
 #include <cstring>
+#include <initializer_list>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -494,6 +495,51 @@ int gpaw_batch_tune(gpaw_batch *b, const gpaw_batch_io *io, int32_t *info) {
   }
   b->nbranch = best;
   if ((rc = record(b, io, info, best)) != GPAW_OK) return rc;
+  return GPAW_OK;
+}
+
+int gpaw_batch_set_tuning(gpaw_batch *b, const int32_t *in) {
+  int rc;
+  if ((rc = check_batch(b)) != GPAW_OK) return rc;
+  if (!in) return fail(GPAW_EINVAL, "in must not be NULL");
+  if (in[0] < 0 || in[0] > kMaxBranches) return fail(GPAW_EINVAL, "graph branches outside [0, 16]");
+  // validate everything before changing anything
+  for (size_t i = 0; i < b->sys.size(); ++i) {
+    const gpaw_sys *s = b->sys[i];
+    const int32_t *v = in + 1 + 7 * i;
+    const std::string tag = "system " + std::to_string(i) + ": ";
+    const bool cplx = is_complex(s->dtype);
+    if (s->dtype == GPAW_F32 || s->dtype == GPAW_C64) {
+      for (int k = 0; k < 7; ++k)
+        if (v[k] != 0) return fail(GPAW_EINVAL, tag + "single-precision systems keep the built-in shapes");
+      continue;
+    }
+    auto one_of = [](int x, std::initializer_list<int> ok) {
+      return std::find(ok.begin(), ok.end(), x) != ok.end();
+    };
+    if (!one_of(v[0], {0, 1, 2})) return fail(GPAW_EINVAL, tag + "stencil points per lane: 0, 1 or 2");
+    if (v[1] < 0 || v[2] < 0 || (v[1] == 0) != (v[2] == 0))
+      return fail(GPAW_EINVAL, tag + "stencil tile: both sides positive, or both 0");
+    if (v[3] < 0 || v[3] > s->n[0]) return fail(GPAW_EINVAL, tag + "stencil x segments outside [0, n0]");
+    if (v[4] < 0 || v[4] > 1024) return fail(GPAW_EINVAL, tag + "subspace workgroups outside [0, 1024]");
+    if (!(cplx ? one_of(v[5], {0, 2, 4}) : one_of(v[5], {0, 4, 8})))
+      return fail(GPAW_EINVAL, tag + "rotation row tiles: complex 2 or 4, real 4 or 8 (or 0)");
+    if (!(cplx ? one_of(v[6], {0, 1, 2}) : one_of(v[6], {0, 2, 4, 8})))
+      return fail(GPAW_EINVAL, tag + "projection bands: complex 1 or 2, real 2, 4 or 8 (or 0)");
+  }
+  for (size_t i = 0; i < b->sys.size(); ++i) {
+    Tune &t = b->sys[i]->tune;
+    const int32_t *v = in + 1 + 7 * i;
+    t.st_ppl = v[0];
+    t.st_ty = v[1];
+    t.st_tz = v[2];
+    t.st_nseg = v[3];
+    t.sub_wgs = v[4];
+    t.rot_rb = v[5];
+    t.prj_nbg = v[6];
+  }
+  b->nbranch = in[0];
+  drop_graph(b);  // the next step records with the new shapes
   return GPAW_OK;
 }
 

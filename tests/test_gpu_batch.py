@@ -245,3 +245,43 @@ def test_batch_mixed_precision():
     batch.close()
     for g in gs:
         g.close()
+
+
+def test_batch_tuning_cache(tmp_path):
+    """Autotuned shapes saved to a file and applied to a new batch of the
+    same systems give that batch the same shapes and the same results, bit
+    for bit, without running the autotuner; a file made for other systems is
+    refused, and so are shapes the autotuner would never choose."""
+    systems = [synth.make_system(name=f"small{i}", **c) for i, c in enumerate(SMALL[:4])]
+    say("[batch] tuning cache")
+    r = Run(systems)
+    r.batch.tune(r.io, r.info)
+    r.step()
+    path = str(tmp_path / "tuning.json")
+    r.batch.save_tuning(path)
+    tuned = r.batch.tuning()
+    ref = [host(x).copy() for x in r.out]
+    ref_eps = [host(x).copy() for x in r.eps]
+    r.close()
+    r2 = Run(systems)
+    assert r2.batch.load_tuning(path)
+    assert r2.batch.tuning() == tuned
+    r2.step()
+    for i in range(len(systems)):
+        assert np.array_equal(host(r2.out[i]), ref[i]), i
+        assert np.array_equal(host(r2.eps[i]), ref_eps[i]), i
+    # a different set of systems: the file does not apply
+    r3 = Run(systems[:3])
+    before = r3.batch.tuning()
+    assert not r3.batch.load_tuning(path)
+    assert r3.batch.tuning() == before
+    # values outside the autotuner's choices are rejected, nothing changes
+    bad = [dict(s) for s in tuned[1][:3]]
+    bad[1]["rotate_rb"] = 3
+    with pytest.raises(gfd.GpawError) as e:
+        r3.batch.set_tuning(4, bad)
+    assert e.value.status == "GPAW_EINVAL"
+    assert r3.batch.tuning() == before
+    r3.step()
+    r3.close()
+    r2.close()
