@@ -955,6 +955,13 @@ int plane_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out
 template <typename T, int NB, int NI>
 int apply_S_t(const gpaw_sys *s, const void *psi, int nb, const void *X, void *out,
               hipStream_t st) {
+  // large blocks: S~psi = psi (a device copy), then the add-back pass over
+  // the covered points with the Delta S P rows (the same sums as below)
+  if (X && separate_addback(s, nb)) {
+    GFD_HIP(hipMemcpyAsync(out, psi, static_cast<size_t>(nb) * s->ng * sizeof(T),
+                           hipMemcpyDeviceToDevice, st));
+    return addback_t<T, NI>(s, nb, X, nullptr, out, nullptr, st);
+  }
   const AddArgs ab = make_add(s, X);
   dim3 grid(static_cast<unsigned>((s->ng + 256 * AS_CHUNKS - 1) / (256 * AS_CHUNKS)),
             (nb + NB - 1) / NB);
