@@ -426,18 +426,26 @@ __global__ __launch_bounds__(256) void k_trd_update(T *__restrict__ A, int n, in
     }
     return;
   }
-  // trailing block rows/cols >= k+2 in 16 x 16 tiles
+  // trailing block rows/cols >= k+2 in 32 x 32 tiles, four elements per
+  // lane (rows tid / 32 + 8 q of column tid % 32), so each workgroup's
+  // reduction above serves 1024 elements
   const int base = k + 2;
   const int m = n - base;
-  const int tiles = (m + 15) / 16;
+  const int tiles = (m + 31) / 32;
   const int tile = blockIdx.x - 1;
   const int ti = tile / tiles, tj = tile - (tile / tiles) * tiles;
-  const int r = base + ti * 16 + (threadIdx.x >> 4), c = base + tj * 16 + (threadIdx.x & 15);
-  if (r >= n || c >= n) return;
-  const T vr = vk[r], wr = p[r] + K * vk[r];
+  const int c = base + tj * 32 + (threadIdx.x & 31);
+  if (c >= n) return;
   const T vc = cj_l(vk[c]), wc = cj_l(p[c] + K * vk[c]);
-  T &a = A[static_cast<int64_t>(r) * n + c];
-  a = a - (vr * wc + wr * vc);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = base + ti * 32 + (threadIdx.x >> 5) + 8 * q;
+    if (r < n) {
+      const T vr = vk[r], wr = p[r] + K * vk[r];
+      T &a = A[static_cast<int64_t>(r) * n + c];
+      a = a - (vr * wc + wr * vc);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ vectors
@@ -644,7 +652,7 @@ int large_tridiag(T *A, int n, T *V, T *tau, double *d, double *e, T *p, int32_t
   for (int k = 0; k + 1 < n; ++k) {
     k_trd_symv<T><<<(n - k - 1 + 3) / 4, 256, 0, st>>>(A, n, k, V, tau, p, info);
     const int m = std::max(0, n - k - 2);
-    const int tiles = (m + 15) / 16;
+    const int tiles = (m + 31) / 32;
     k_trd_update<T><<<1 + tiles * tiles, 256, lds, st>>>(A, n, k, V, tau, p, d, e, info);
   }
   return GPAW_OK;
