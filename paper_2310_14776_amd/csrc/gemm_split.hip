@@ -358,10 +358,15 @@ __global__ __launch_bounds__(1024) void k_offid_small(const double *__restrict__
 // C (double / complex double, [nb][nb]) -> transposed BF16 planes
 // Ct[p][n][m] for p = hi, mid, lo (and the imaginary part in planes 3..5),
 // rows padded with zeros to nbp = nb rounded up to the 64-wide K step, so
-// that every 16-byte row fragment a rotation step reads is in bounds
+// that every 16-byte row fragment a rotation step reads is in bounds.
+// Cf (if set): the high parts once more, fragment-major for the column-panel
+// rotation: block (part c, rows 16 rb.., K step ks) is 512 values in lane
+// order, lane l = 16 fq + fr holding rows 16 rb + fr, values m = 32 ks +
+// 8 fq .. +7, so that a wavefront reads a fragment as one contiguous 1 KB.
 template <int NP>
 __global__ __launch_bounds__(256) void k_split_c(const double *__restrict__ C, __bf16 *__restrict__ Ct,
-                                                 int nb, int nbp, int minus_id) {
+                                                 int nb, int nbp, int minus_id,
+                                                 __bf16 *__restrict__ Cf) {
   const int64_t np = static_cast<int64_t>(nb) * nbp;
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (idx >= np) return;
@@ -382,6 +387,10 @@ __global__ __launch_bounds__(256) void k_split_c(const double *__restrict__ C, _
     Ct[(3 * c + 0) * np + t] = top_half(uh);
     Ct[(3 * c + 1) * np + t] = top_half(um);
     Ct[(3 * c + 2) * np + t] = top_half(ul);
+    if (Cf) {
+      const int64_t blk = (static_cast<int64_t>(c) * ((nb + 15) / 16) + (n >> 4)) * (nbp / 32) + (m >> 5);
+      Cf[blk * 512 + (((m >> 3) & 3) * 16 + (n & 15)) * 8 + (m & 7)] = top_half(uh);
+    }
   }
 }
 
@@ -613,6 +622,198 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
   }
   }  // output tiles
 }
+// The one-product rotation by an upper-triangular C = I + E (the case the
+// orthonormality correction produces: E = L^-H - I, max |E| <= 2^-21) as a
+// column-panel stream: each source value is read from HBM once and each
+// output value written once. A workgroup owns TN grid columns and all nb
+// output rows. It walks the rows in chunks of 8 wavefronts x 16 RB rows;
+// the source rows of a chunk are loaded in the accumulator layout, kept in
+// registers for the add-back, and their high BF16 parts appended to an LDS
+// panel (column-major, [part][column][m], rows padded by 8 values so that
+// the 16-byte fragment reads of 16 columns fall on distinct banks). Output
+// row n only needs source rows m <= n, so a chunk only needs the panel rows
+// written so far. E's fragments come from global memory through an NS-stage
+// register ring, from a fragment-major copy of E's high parts (one
+// contiguous 1 KB per fragment, so that each load touches the fewest cache
+// lines; E is shared by every workgroup and stays in L2). The next chunk's source rows are loaded during
+// the current chunk's products. Complex: re = Er sr - Ei si (the second
+// term in an accumulator of its own, so no fragment is negated),
+// im = Er si + Ei sr. The FP32 sums (terms of 2^-21 |src| and below) are
+// added to the source in FP64 and rounded once.
+constexpr int NEAR_PITCH_MAX = 1024 + 8;  // nb <= 1024
+
+template <typename T, int TN, int RB, int NS>
+__global__ __launch_bounds__(512) void k_rot_near(const __bf16 *__restrict__ Cf,
+                                                  const T *__restrict__ src, T *__restrict__ dst,
+                                                  int nb, int nbp, int64_t cols, int64_t gblocks,
+                                                  const int32_t *__restrict__ fewer) {
+  constexpr int NP = Parts<T>::n;
+  constexpr int CB = TN / 16;
+  constexpr int CHUNK = 128 * RB;  // rows per chunk: 8 wavefronts x RB blocks of 16
+  static_assert(RB == 1 || RB == 2, "one or two row blocks per wavefront");
+  static_assert((NS & (NS - 1)) == 0 && NS >= 2, "ring stages: a power of two");
+  __shared__ __attribute__((aligned(16))) __bf16 pan[NP * TN * NEAR_PITCH_MAX];
+  if (*fewer == 0) return;  // the six-product kernel's case
+  const int pitch = nbp + 8;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, fr = lane & 15, fq = lane >> 4;
+  const int nrb = (nb + 15) / 16, nks = nbp / 32;  // fragment blocks of Cf
+  const int nk_all = (nb + 31) / 32;  // 32-wide K steps over all rows
+  const int mrows = nk_all * 32;      // panel rows the products read
+  const int nchunks = (nb + CHUNK - 1) / CHUNK;
+  // each XCD a contiguous range of column blocks
+  const int x = blockIdx.x & 7;
+  const int64_t per = (gblocks + 7) / 8;
+  const int64_t blk_end = std::min<int64_t>(gblocks, (x + 1) * per);
+  const int64_t blk_step = gridDim.x >> 3;
+
+  // first row of row block rb of this wavefront in chunk ci: blocks w and
+  // 15 - w of the chunk's 16, so that every wavefront carries the same share
+  // of the triangle
+  auto rowblk = [&](int ci, int rb) { return ci * CHUNK + 16 * (rb == 0 ? wave : 15 - wave); };
+  T sc[RB][CB][4], sn[RB][CB][4];
+  auto load_src = [&](int64_t g0, int ci, T (&sv)[RB][CB][4]) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int n = std::min(rowblk(ci, rb) + 4 * fq + e, nb - 1);
+        const T *row = src + static_cast<int64_t>(n) * cols;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+          sv[rb][cb][e] = row[std::min<int64_t>(g0 + 16 * cb + fr, cols - 1)];
+      }
+  };
+
+  for (int64_t blk = x * per + (blockIdx.x >> 3); blk < blk_end; blk += blk_step) {
+    const int64_t g0 = blk * TN;
+    load_src(g0, 0, sc);
+    for (int ci = 0; ci < nchunks; ++ci) {
+      int r0[RB], nk[RB], nkmax = 0;
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        r0[rb] = rowblk(ci, rb);
+        // upper triangular: rows r0 .. r0 + 15 need m < r0 + 16
+        nk[rb] = r0[rb] < nb ? std::min(nk_all, (r0[rb] + 16 + 31) / 32) : 0;
+        nkmax = std::max(nkmax, nk[rb]);
+      }
+      // panel rows of this chunk: high parts, zero past nb
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const int nbase = r0[rb] + 4 * fq;
+        if (nbase < mrows) {
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int c = 0; c < NP; ++c) {
+              uint32_t w[2];
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                uint32_t hv[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                  const int e = 2 * h + q;
+                  const float v = c ? Parts<T>::im(sc[rb][cb][e]) : Parts<T>::re(sc[rb][cb][e]);
+                  hv[q] = nbase + e < nb ? bf16_rne(__float_as_uint(v)) >> 16 : 0u;
+                }
+                w[h] = hv[0] | (hv[1] << 16);
+              }
+              *reinterpret_cast<uint2 *>(pan + (c * TN + 16 * cb + fr) * pitch + nbase) =
+                  make_uint2(w[0], w[1]);
+            }
+        }
+      }
+      bf8 ring[NS][RB][NP];
+      auto load_a = [&](int slot, int k) {
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          if (k < nk[rb])  // then r0 < nb
+#pragma unroll
+            for (int c = 0; c < NP; ++c)
+              ring[slot][rb][c] = *reinterpret_cast<const bf8 *>(
+                  Cf + ((static_cast<int64_t>(c) * nrb + (r0[rb] >> 4)) * nks + k) * 512 + 8 * lane);
+      };
+#pragma unroll
+      for (int s = 0; s < NS - 1; ++s) load_a(s, s);
+      __syncthreads();  // the chunk's panel rows are written
+      if (ci + 1 < nchunks) load_src(g0, ci + 1, sn);
+
+      f4 acc[RB][CB][NP == 2 ? 3 : 1];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int q = 0; q < (NP == 2 ? 3 : 1); ++q) acc[rb][cb][q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int k0 = 0; k0 < nkmax; k0 += NS) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int k = k0 + s;
+          load_a((s + NS - 1) & (NS - 1), k + NS - 1);
+          if (k < nkmax) {
+            bf8 b[CB][NP];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+              for (int c = 0; c < NP; ++c)
+                b[cb][c] = *reinterpret_cast<const bf8 *>(pan + (c * TN + 16 * cb + fr) * pitch +
+                                                          32 * k + 8 * fq);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+              if (k < nk[rb])
+#pragma unroll
+              for (int cb = 0; cb < CB; ++cb) {
+                const bf8 ar = ring[s][rb][0];
+                acc[rb][cb][0] = mm(ar, b[cb][0], acc[rb][cb][0]);
+                if constexpr (NP == 2) {
+                  const bf8 ai = ring[s][rb][1];
+                  acc[rb][cb][1] = mm(ai, b[cb][1], acc[rb][cb][1]);
+                  acc[rb][cb][2] = mm(ar, b[cb][1], acc[rb][cb][2]);
+                  acc[rb][cb][2] = mm(ai, b[cb][0], acc[rb][cb][2]);
+                }
+              }
+          }
+        }
+      }
+      {
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            const int64_t g = g0 + 16 * cb + fr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int n = r0[rb] + 4 * fq + e;
+              if (n >= nb || g >= cols) continue;
+              const T v = sc[rb][cb][e];
+              T o;
+              if constexpr (NP == 2) {
+                const double re = static_cast<double>(Parts<T>::re(v)) +
+                                  (static_cast<double>(acc[rb][cb][0][e]) -
+                                   static_cast<double>(acc[rb][cb][1][e]));
+                const double im = static_cast<double>(Parts<T>::im(v)) +
+                                  static_cast<double>(acc[rb][cb][2][e]);
+                o = T{static_cast<float>(re), static_cast<float>(im)};
+              } else {
+                o = static_cast<float>(static_cast<double>(v) +
+                                       static_cast<double>(acc[rb][cb][0][e]));
+              }
+              dst[static_cast<int64_t>(n) * cols + g] = o;
+            }
+          }
+      }
+      if (ci + 1 < nchunks) {
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) sc[rb][cb][e] = sn[rb][cb][e];
+      }
+    }
+    __syncthreads();  // every wavefront is done with the panel
+  }
+}
+
 struct SplitPlanS {
   int tiles_n, tiles, nsplit;
   int64_t kchunk;
@@ -681,8 +882,12 @@ int rotate_split_t(const gpaw_sys *s, const void *C, const void *src, int nb, in
   // near the identity: rotate by C - I and add the source back, with one
   // BF16 product per pair when |C - I| is small enough (decided on the device)
   if (near_id) k_offid_small<NP><<<1, 1024, 0, st>>>(Cd, nb, s->ws.flag);
+  // the column-panel rotation (upper triangular, near the identity, nb <=
+  // 1024) reads a fragment-major copy of the high parts, stored after Ct
+  const bool panel = near_id && upper && nbp + 8 <= NEAR_PITCH_MAX;
+  __bf16 *Cf = panel ? Ct + 3 * NP * np : nullptr;
   k_split_c<NP><<<static_cast<unsigned>((np + 255) / 256), 256, 0, st>>>(Cd, Ct, nb, nbp,
-                                                                        near_id ? 1 : 0);
+                                                                        near_id ? 1 : 0, Cf);
   const int ntiles_n = (nb + TM - 1) / TM;
   const int64_t gtiles = (cols + TM - 1) / TM;
   const int64_t wgs = (gtiles + 7) / 8 * 8 * ntiles_n;
@@ -701,9 +906,20 @@ int rotate_split_t(const gpaw_sys *s, const void *C, const void *src, int nb, in
     const int64_t gt1 = (cols + TM1 - 1) / TM1;
     auto *k1 = &k_rot_lds<T, WT1, true, true>;
     auto *k6 = &k_rot_lds<T, WT, true, false>;
-    k1<<<grid_of(reinterpret_cast<const void *>(k1), gt1 * nt1), 256, 0, st>>>(
-        Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, nbp, cols, nt1, gt1,
-        upper ? 1 : 0, s->ws.flag);
+    if (panel) {
+      // upper triangular (the orthonormality correction): the column-panel
+      // stream, 32 complex or 64 real columns per workgroup
+      constexpr int TNP = NP == 2 ? 32 : 64, RBP = NP == 2 ? 1 : 2;
+      auto *kp = &k_rot_near<T, TNP, RBP, 4>;
+      const int64_t gb = (cols + TNP - 1) / TNP;
+      const int64_t r = std::max<int64_t>(8, resident_slots(reinterpret_cast<const void *>(kp), 512, 0) / 8 * 8);
+      kp<<<static_cast<unsigned>(std::min(r, (gb + 7) / 8 * 8)), 512, 0, st>>>(
+          Cf, static_cast<const T *>(src), static_cast<T *>(dst), nb, nbp, cols, gb, s->ws.flag);
+    } else {
+      k1<<<grid_of(reinterpret_cast<const void *>(k1), gt1 * nt1), 256, 0, st>>>(
+          Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, nbp, cols, nt1, gt1,
+          upper ? 1 : 0, s->ws.flag);
+    }
     k6<<<grid_of(reinterpret_cast<const void *>(k6), gtiles * ntiles_n), 256, 0, st>>>(
         Ct, static_cast<const T *>(src), static_cast<T *>(dst), nb, nbp, cols, ntiles_n, gtiles,
         upper ? 1 : 0, s->ws.flag);
@@ -728,8 +944,12 @@ size_t split_part_elems(int nb, bool cplx) {
 }
 
 size_t split_c_bytes(int nb, bool cplx) {
+  // three planes per part, then the fragment-major copy of the high parts
+  // (rows rounded up to 16)
   const size_t nbp = static_cast<size_t>((nb + KR - 1) / KR * KR);
-  return static_cast<size_t>(nb) * nbp * 3 * (cplx ? 2 : 1) * sizeof(__bf16);
+  const size_t parts = cplx ? 2 : 1;
+  return (static_cast<size_t>(nb) * 3 + static_cast<size_t>((nb + 15) / 16 * 16)) * nbp * parts *
+         sizeof(__bf16);
 }
 
 int launch_subspace_split(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,

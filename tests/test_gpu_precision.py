@@ -151,3 +151,48 @@ def test_orthonormalize_far_from_orthonormal(cplx):
     say(f"  max |S' - I| = {dev:.2e}")
     assert dev <= 1e-5
     g.close()
+
+
+@pytest.mark.parametrize("nb", [150, 1024])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_orthonormalize_one_product_ragged(cplx, nb):
+    """The one-product correction (L^-H = I + E, max |E| <= 2^-21) at a
+    ragged band count (150: a partial row chunk and a partial 32-wide K
+    step) and at the largest one the column-panel kernel takes (1024), on a
+    grid whose 3315 columns are no multiple of the 32 or 64 columns a
+    workgroup owns. The block is an S~-orthonormal one (oracle) mixed by
+    I + P with |P| ~ 1e-7, so that E is a few 1e-7 and the correction moves
+    the block by about 1e-6 relative: the device result must match the
+    oracle's Cholesky correction of the same FP32 values to FP32 resolution
+    and to a quarter of the size of the correction itself (a dropped or
+    mis-signed product term misses by the whole term)."""
+    cfg = dict(n=(15, 13, 17), h=0.2, nb=nb, natoms=3, rc=1.8, seed=57)
+    if cplx:
+        cfg["k"] = (0.25, 0.0, 0.5)
+    s = synth.make_system(**cfg)
+    say(f"[orthonormalize] one-product case complex={cplx} nb={nb}")
+    ops = oracle.Operators.from_system(s)
+    raw = s.psi.reshape(s.nb, -1)
+    x0 = oracle.orthonormalize(raw, ops.apply_S(raw), ops.dV)
+    rng = np.random.default_rng(5)
+    P = rng.uniform(-1, 1, (nb, nb)) * 1.2e-7
+    if cplx:
+        P = P + 1j * rng.uniform(-1, 1, (nb, nb)) * 1.2e-7
+    x = _round(x0 + P @ x0, cplx).astype(x0.dtype)
+    Sx = _round(ops.apply_S(x), cplx).astype(x0.dtype)
+    # precondition: the case is the one-product one, with a margin for the
+    # device's own rounding of S'
+    S1 = ops.dV * (x.conj() @ Sx.T)
+    S1 = 0.5 * (S1 + S1.conj().T)
+    Linv = np.linalg.inv(np.linalg.cholesky(S1))
+    offid = np.abs(Linv.conj().T - np.eye(nb)).max()
+    assert offid <= 0.8 * 2.0 ** -21, offid
+    want = oracle.orthonormalize(x, Sx, ops.dV)
+    corr = rel(x, want)
+    g = gfd.System.from_synth(s, precision="single")
+    got, _ = g.orthonormalize(to_dev(_round(x, cplx)), to_dev(_round(Sx, cplx)))
+    torch.cuda.synchronize()
+    err = rel(host(got).astype(want.dtype), want)
+    say(f"  max|E| = {offid:.2e}, correction {corr:.2e}, ||psi'' - oracle|| / ||oracle|| = {err:.2e}")
+    assert err <= 1e-6 and err <= 0.25 * corr
+    g.close()
