@@ -481,12 +481,22 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
               ca[ps][c][p][h] = *reinterpret_cast<const bf8 *>(
                   Ct + (3 * c + p) * np + static_cast<int64_t>(n) * nbp + m0 + sc + 32 * h);
     }
+    if (m0 + KR <= nb) {  // a whole step of rows: no clamping, one row offset per value
+      const T *rowp = srcg + static_cast<int64_t>(m0 + bm) * cols;
 #pragma unroll
-    for (int e = 0; e < MPT; ++e) {
-      const int m = std::min(m0 + bm + e, nb - 1);
-      const T v = srcg[static_cast<int64_t>(m) * cols];
-      rb[0][e] = Parts<T>::re(v);
-      if constexpr (NP == 2) rb[NP - 1][e] = Parts<T>::im(v);
+      for (int e = 0; e < MPT; ++e) {
+        const T v = rowp[static_cast<int64_t>(e) * cols];
+        rb[0][e] = Parts<T>::re(v);
+        if constexpr (NP == 2) rb[NP - 1][e] = Parts<T>::im(v);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < MPT; ++e) {
+        const int m = std::min(m0 + bm + e, nb - 1);
+        const T v = srcg[static_cast<int64_t>(m) * cols];
+        rb[0][e] = Parts<T>::re(v);
+        if constexpr (NP == 2) rb[NP - 1][e] = Parts<T>::im(v);
+      }
     }
   };
   auto stage = [&]() {
@@ -513,19 +523,23 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
 
   const int wr = wave >> 1, wc = wave & 1;
   const int fr = lane & 15, fk = (lane >> 4) * 8;
+  // complex: fx holds Ci pi, subtracted from the real part when the tile is
+  // promoted (so that no fragment is negated)
   d4 dacc[NP][WT][WT];
-  f4 facc[NP][WT][WT];
+  f4 facc[NP][WT][WT], fx[WT][WT];
 #pragma unroll
-  for (int c = 0; c < NP; ++c)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int i = 0; i < WT; ++i)
+    for (int j = 0; j < WT; ++j) {
 #pragma unroll
-      for (int j = 0; j < WT; ++j) {
+      for (int c = 0; c < NP; ++c) {
         dacc[c][i][j] = d4{0.0, 0.0, 0.0, 0.0};
         facc[c][i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
       }
+      fx[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
   fetch(0);
-  for (int step = 0; step < nsteps; ++step) {
+  auto run_step = [&](int step) {
     __syncthreads();
     stage();
     __syncthreads();
@@ -552,14 +566,14 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
           if (ADDSRC && one) {
             facc[0][i][j] = mm(fa[0][i].h, fb[0].h, facc[0][i][j]);
             if constexpr (NP == 2) {
-              facc[0][i][j] = mm(neg(fa[1][i]).h, fb[1].h, facc[0][i][j]);
+              fx[i][j] = mm(fa[1][i].h, fb[1].h, fx[i][j]);
               facc[1][i][j] = mm(fa[0][i].h, fb[1].h, facc[1][i][j]);
               facc[1][i][j] = mm(fa[1][i].h, fb[0].h, facc[1][i][j]);
             }
           } else {
             facc[0][i][j] = mm6(fa[0][i], fb[0], facc[0][i][j]);
             if constexpr (NP == 2) {
-              facc[0][i][j] = mm6(neg(fa[1][i]), fb[1], facc[0][i][j]);
+              fx[i][j] = mm6(fa[1][i], fb[1], fx[i][j]);
               facc[1][i][j] = mm6(fa[0][i], fb[1], facc[1][i][j]);
               facc[1][i][j] = mm6(fa[1][i], fb[0], facc[1][i][j]);
             }
@@ -567,21 +581,41 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
         }
       }
     }
-    // (the one-product rotation sums terms of size 2^-21 |psi| and keeps its
-    // FP32 tile: its rounding is far below that of the FP32 result)
-    if (!ONEP && ((step & 3) == 3 || step + 1 == nsteps)) {
+  };
+  // FP32 tiles into the FP64 accumulators after every 4 steps (the step loop
+  // is unrolled by 4 so that this needs no test per step). The one-product
+  // rotation sums terms of size 2^-21 |psi| and keeps its FP32 tile: its
+  // rounding is far below that of the FP32 result.
+  auto promote = [&]() {
 #pragma unroll
-      for (int c = 0; c < NP; ++c)
+    for (int i = 0; i < WT; ++i)
 #pragma unroll
-        for (int i = 0; i < WT; ++i)
+      for (int j = 0; j < WT; ++j) {
 #pragma unroll
-          for (int j = 0; j < WT; ++j) {
+        for (int c = 0; c < NP; ++c)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) dacc[c][i][j][e] += static_cast<double>(facc[c][i][j][e]);
-            facc[c][i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+          for (int e = 0; e < 4; ++e) {
+            double v = static_cast<double>(facc[c][i][j][e]);
+            if (NP == 2 && c == 0) v -= static_cast<double>(fx[i][j][e]);
+            dacc[c][i][j][e] += v;
           }
+#pragma unroll
+        for (int c = 0; c < NP; ++c) facc[c][i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+        fx[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+      }
+  };
+  int step = 0;
+  if constexpr (!ONEP) {
+    for (; step + 4 <= nsteps; step += 4) {
+      run_step(step);
+      run_step(step + 1);
+      run_step(step + 2);
+      run_step(step + 3);
+      promote();
     }
   }
+  for (; step < nsteps; ++step) run_step(step);
+  if constexpr (!ONEP) promote();
 #pragma unroll
   for (int i = 0; i < WT; ++i) {
     // ADDSRC: the source values of this row band are loaded together, from
@@ -607,7 +641,9 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
       for (int e = 0; e < 4; ++e) {
         const int n = n0 + wr * 16 * WT + i * 16 + 4 * (lane >> 4) + e;
         if (n >= nb) continue;
-        double vr = ONEP ? facc[0][i][j][e] : dacc[0][i][j][e];
+        double vr = ONEP ? static_cast<double>(facc[0][i][j][e]) -
+                               (NP == 2 ? static_cast<double>(fx[i][j][e]) : 0.0)
+                         : dacc[0][i][j][e];
         double vi = ONEP ? facc[NP - 1][i][j][e] : dacc[NP - 1][i][j][e];
         if constexpr (ADDSRC) {
           vr += Parts<T>::re(sv[j][e]);
