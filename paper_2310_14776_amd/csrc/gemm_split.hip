@@ -115,20 +115,36 @@ __device__ inline void split_to(float x, __bf16 &h, __bf16 &m, __bf16 &l) {
   l = top_half(__float_as_uint(r2));
 }
 
-// eight consecutive values (real or one part of complex) -> three planes
+// two FP32 values -> two BF16 values rounded to nearest even, the first in
+// the low half (the hardware pair conversion, written out so that the
+// operand order is explicit: the compiler's own vector form of it was found
+// to return the first element's result for both on this toolchain)
+__device__ inline uint32_t cvt2_bf16(float a, float b) {
+  uint32_t r;
+  asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// eight consecutive values (real or one part of complex) -> three planes,
+// the same exact split as split_to (hi = bf16(x), mid = bf16(x - hi),
+// lo = x - hi - mid, each remainder exact), two values per conversion
 __device__ inline void split_store8(const float *x, __bf16 *ph, __bf16 *pm, __bf16 *pl) {
-  bf8 h, m, l;
+  uint32_t h[4], m[4], l[4];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    __bf16 a, b, c;
-    split_to(x[e], a, b, c);
-    h[e] = a;
-    m[e] = b;
-    l[e] = c;
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t hq = cvt2_bf16(x[2 * q], x[2 * q + 1]);
+    const float r0 = x[2 * q] - __uint_as_float(hq << 16);
+    const float r1 = x[2 * q + 1] - __uint_as_float(hq & 0xFFFF0000u);
+    const uint32_t mq = cvt2_bf16(r0, r1);
+    const float s0 = r0 - __uint_as_float(mq << 16);
+    const float s1 = r1 - __uint_as_float(mq & 0xFFFF0000u);
+    h[q] = hq;
+    m[q] = mq;
+    l[q] = cvt2_bf16(s0, s1);  // exact: at most 8 significant bits
   }
-  *reinterpret_cast<bf8 *>(ph) = h;
-  *reinterpret_cast<bf8 *>(pm) = m;
-  *reinterpret_cast<bf8 *>(pl) = l;
+  *reinterpret_cast<uint4 *>(ph) = make_uint4(h[0], h[1], h[2], h[3]);
+  *reinterpret_cast<uint4 *>(pm) = make_uint4(m[0], m[1], m[2], m[3]);
+  *reinterpret_cast<uint4 *>(pl) = make_uint4(l[0], l[1], l[2], l[3]);
 }
 
 // eight consecutive values -> their high BF16 parts only (the one-product
@@ -167,13 +183,6 @@ __device__ inline Split8 frag(const __bf16 *plane0, int plane_stride, int off,
     f.l = *reinterpret_cast<const bf8 *>(plane0 + 2 * plane_stride + off);
   }
   return f;
-}
-
-__device__ inline Split8 neg(Split8 a) {
-  a.h = -a.h;
-  a.m = -a.m;
-  a.l = -a.l;
-  return a;
 }
 
 // part[(split*nmat + mat)][nb][nb] (double / complex double) =
@@ -275,14 +284,16 @@ __global__ __launch_bounds__(256) void k_sub_lds(const T *__restrict__ A, const 
 #pragma unroll
       for (int i = 0; i < WT; ++i) {
         const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-        // conj(a) b: re = ar br + ai bi, im = ar bi - ai br
+        // conj(a) b: re = ar br + ai bi, im = ar bi - ai br (the two parts of
+        // im in tiles of their own, subtracted in FP64: no fragment negated)
         f4 re = mm6(fa[0][i], fb[0], z);
         if constexpr (NP == 2) {
           re = mm6(fa[1][i], fb[1], re);
-          f4 im = mm6(fa[0][i], fb[1], z);
-          im = mm6(neg(fa[1][i]), fb[0], im);
+          const f4 im1 = mm6(fa[0][i], fb[1], z);
+          const f4 im2 = mm6(fa[1][i], fb[0], z);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) dacc[1][i][j][e] += static_cast<double>(im[e]);
+          for (int e = 0; e < 4; ++e)
+            dacc[1][i][j][e] += static_cast<double>(im1[e]) - static_cast<double>(im2[e]);
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) dacc[0][i][j][e] += static_cast<double>(re[e]);
