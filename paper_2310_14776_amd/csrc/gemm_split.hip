@@ -96,14 +96,26 @@ template <> struct Parts<z32> {
 // ---------------------------------------------------------------------------
 // LDS-staged split products. A workgroup stages 32-wide K slices of both
 // operands in LDS, splitting every element once into its three BF16 parts
-// (planes h, m, l, each row padded to LROW values so that the 16-byte
-// fragment reads of a wavefront spread over the banks); the next slice is
-// fetched from global memory while the matrix cores work on the current one.
+// (planes h, m, l); the next slice is fetched from global memory while the
+// matrix cores work on the current one. The planes are unpadded with their
+// 16-byte chunks XOR-swizzled per row (swz32, swz64), so that both the
+// staging stores (several chunks of a row, a pair of rows per 8 lanes) and
+// the fragment reads (one chunk of 8 consecutive rows per 8 lanes) fall on
+// distinct banks: the bank-conflict counter reads zero for them, against
+// about 5 conflict cycles per LDS instruction with rows padded by 16 bytes.
 // Workgroup ids are laid out so that the workgroups sharing an operand slice
 // (same K chunk for the subspace products, same grid columns for the
 // rotation) land on the same XCD and find it in that XCD's L2.
 constexpr int KS = 32;
-constexpr int LROW = 40;
+
+// offset (BF16 values) of 16-byte chunk c of row r: rows of 32 values (four
+// chunks), chunk c ^ ((r >> 1) & 3) (rows alternate between the two halves
+// of the banks; within 8 rows the swizzle separates the rest)
+__device__ inline int swz32(int r, int c) { return r * 32 + 8 * (c ^ ((r >> 1) & 3)); }
+// rows of 64 values (eight chunks), chunk c ^ s(r) with s(r) = 4 (r & 1) +
+// ((r >> 1) & 3): the pair of rows a staging store covers gets complementary
+// halves, eight consecutive rows distinct chunks
+__device__ inline int swz64(int r, int c) { return r * 64 + 8 * (c ^ (((r & 1) << 2) | ((r >> 1) & 3))); }
 
 __device__ inline void split_to(float x, __bf16 &h, __bf16 &m, __bf16 &l) {
   const uint32_t uh = bf16_rne(__float_as_uint(x));
@@ -197,7 +209,7 @@ __global__ __launch_bounds__(256) void k_sub_lds(const T *__restrict__ A, const 
                                                  int nmat, int nsplit, int sb) {
   constexpr int NP = Parts<T>::n;
   constexpr int TM = 32 * WT;
-  constexpr int PS = TM * LROW;  // plane stride (bf16)
+  constexpr int PS = TM * KS;  // plane stride (bf16): rows of KS values, unpadded
   constexpr int RPP = 256 / 4;   // rows staged per pass (4 threads x 8 values per row)
   __shared__ __attribute__((aligned(16))) __bf16 sA[3 * NP * PS];
   __shared__ __attribute__((aligned(16))) __bf16 sB[3 * NP * PS];
@@ -247,7 +259,8 @@ __global__ __launch_bounds__(256) void k_sub_lds(const T *__restrict__ A, const 
     for (int ps = 0; ps < PASSES; ++ps)
 #pragma unroll
       for (int c = 0; c < NP; ++c) {
-        const int o = (c * 3) * PS + (ps * RPP + sr) * LROW + sc;
+        const int row = ps * RPP + sr;
+        const int o = (c * 3) * PS + swz32(row, sc >> 3);
         split_store8(ra[ps][c], sA + o, sA + o + PS, sA + o + 2 * PS);
         split_store8(rbv[ps][c], sB + o, sB + o + PS, sB + o + 2 * PS);
       }
@@ -274,13 +287,13 @@ __global__ __launch_bounds__(256) void k_sub_lds(const T *__restrict__ A, const 
     for (int i = 0; i < WT; ++i)
 #pragma unroll
       for (int c = 0; c < NP; ++c)
-        fa[c][i] = frag(sA + (c * 3) * PS, PS, (wr * 16 * WT + i * 16 + fr) * LROW + fk);
+        fa[c][i] = frag(sA + (c * 3) * PS, PS, swz32(wr * 16 * WT + i * 16 + fr, fk >> 3));
 #pragma unroll
     for (int j = 0; j < WT; ++j) {
       Split8 fb[NP];
 #pragma unroll
       for (int c = 0; c < NP; ++c)
-        fb[c] = frag(sB + (c * 3) * PS, PS, (wc * 16 * WT + j * 16 + fr) * LROW + fk);
+        fb[c] = frag(sB + (c * 3) * PS, PS, swz32(wc * 16 * WT + j * 16 + fr, fk >> 3));
 #pragma unroll
       for (int i = 0; i < WT; ++i) {
         const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -423,7 +436,6 @@ __global__ __launch_bounds__(256) void k_split_c(const double *__restrict__ C, _
 // persistent (a resident-sized grid walks the output tiles, each XCD a
 // contiguous range of them), so the one that exits costs one launch.
 constexpr int KR = 64;     // K values per rotation step
-constexpr int LROWR = 72;  // LDS row pitch of the rotation tiles (BF16 values)
 
 template <typename T, int WT, bool ADDSRC, bool ONEP>
 __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
@@ -433,7 +445,7 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
                                                  const int32_t *__restrict__ fewer) {
   constexpr int NP = Parts<T>::n;
   constexpr int TM = 32 * WT;
-  constexpr int PS = TM * LROWR;
+  constexpr int PS = TM * KR;  // plane stride: rows of KR values, swizzled (swz64)
   constexpr int NPL = ONEP ? 1 : 3;  // BF16 planes staged per part
   static_assert(ADDSRC || !ONEP, "one product only near the identity");
   __shared__ __attribute__((aligned(16))) __bf16 sA[NPL * NP * PS];
@@ -520,13 +532,13 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
           if (p == 0 || !one)
 #pragma unroll
             for (int h = 0; h < 2; ++h)
-              *reinterpret_cast<bf8 *>(sA + (c * NPL + p) * PS + (ps * 64 + sr) * LROWR + sc +
-                                       32 * h) = ca[ps][c][p][h];
+              *reinterpret_cast<bf8 *>(sA + (c * NPL + p) * PS +
+                                       swz64(ps * 64 + sr, (sc >> 3) + 4 * h)) = ca[ps][c][p][h];
 #pragma unroll
     for (int c = 0; c < NP; ++c)
 #pragma unroll
       for (int h = 0; h < MPT / 8; ++h) {
-        const int o = (c * NPL) * PS + bg * LROWR + bm + 8 * h;
+        const int o = (c * NPL) * PS + swz64(bg, (bm >> 3) + h);
         if constexpr (ONEP) hi_store8(rb[c] + 8 * h, sB + o);
         else split_store8(rb[c] + 8 * h, sB + o, sB + o + PS, sB + o + 2 * PS);
       }
@@ -562,14 +574,14 @@ __global__ __launch_bounds__(256) void k_rot_lds(const __bf16 *__restrict__ Ct,
       for (int i = 0; i < WT; ++i)
 #pragma unroll
         for (int c = 0; c < NP; ++c)
-          fa[c][i] = frag(sA + (c * NPL) * PS, PS, (wr * 16 * WT + i * 16 + fr) * LROWR + 32 * kh + fk,
+          fa[c][i] = frag(sA + (c * NPL) * PS, PS, swz64(wr * 16 * WT + i * 16 + fr, 4 * kh + (fk >> 3)),
                           one);
 #pragma unroll
       for (int j = 0; j < WT; ++j) {
         Split8 fb[NP];
 #pragma unroll
         for (int c = 0; c < NP; ++c)
-          fb[c] = frag(sB + (c * NPL) * PS, PS, (wc * 16 * WT + j * 16 + fr) * LROWR + 32 * kh + fk,
+          fb[c] = frag(sB + (c * NPL) * PS, PS, swz64(wc * 16 * WT + j * 16 + fr, 4 * kh + (fk >> 3)),
                        one);
 #pragma unroll
         for (int i = 0; i < WT; ++i) {
