@@ -143,7 +143,6 @@ class Step:
         self.info = torch.zeros(1, dtype=torch.int32, device=dev)
         self.single = g.precision == "single"
         if self.single:
-            self.Spsi_rot = torch.empty_like(psi)
             self.psi_fin = torch.empty_like(psi)
             self.P_fin = torch.empty_like(self.P)
 
@@ -161,12 +160,11 @@ class Step:
                                         P_out=self.P_rot, stream=st)),
         ]
         if self.single:
-            # S~ of the stored rotated block (its projections are the rotated
-            # P), then the Cholesky orthonormality correction
-            out.append(("apply_S_rot", lambda: g.apply_S(self.psi_rot, self.P_rot,
-                                                         out=self.Spsi_rot, stream=st)))
+            # the Cholesky orthonormality correction of the stored rotated
+            # block, its overlap formed from the block and its (rotated)
+            # projections: S' = dV psi'^H psi' + P'^H Delta S P'
             out.append(("orthonormalize", lambda: g.orthonormalize(
-                self.psi_rot, self.Spsi_rot, out=self.psi_fin, P=self.P_rot, P_out=self.P_fin,
+                self.psi_rot, None, out=self.psi_fin, P=self.P_rot, P_out=self.P_fin,
                 info=self.info, stream=st)))
         return out
 

@@ -251,8 +251,12 @@ GPAW_API int gpaw_davidson_step(gpaw_sys *sys, int32_t nb, void *x, void *Hx, vo
  * sum_m (L^-H)_mn psi_m), so that psi_out^H S~ psi_out = I; P_out likewise
  * from P when both are non-NULL. Cholesky-based re-orthonormalisation (the
  * paper lists Cholesky decomposition among the subspace dense linear algebra,
- * Sec. "Parallelization"). info: as for gpaw_subspace_diag (j > 0 when the
- * leading j x j minor of S' is not positive definite). nb <= 1024. */
+ * Sec. "Parallelization"). Spsi may be NULL when P holds the projections of
+ * psi (or the system has no atoms): then S' = dV psi^H psi + P^H Delta S P,
+ * the same matrix by Eq. (dh) (S~ = 1 + sum_a p~ Delta S p~^H, so psi^H of
+ * the non-local part is conj(P) Delta S P), formed without S~psi. info: as
+ * for gpaw_subspace_diag (j > 0 when the leading j x j minor of S' is not
+ * positive definite). nb <= 1024. */
 GPAW_API int gpaw_orthonormalize(gpaw_sys *sys, const void *psi, const void *Spsi, int32_t nb,
                                  void *psi_out, const void *P, void *P_out, int32_t *info,
                                  void *stream);

@@ -521,13 +521,15 @@ int gpaw_orthonormalize(gpaw_sys *s, const void *psi, const void *Spsi, int32_t 
   if ((rc = check_sys(s)) != GPAW_OK) return rc;
   if ((rc = check_nb(s, nb)) != GPAW_OK) return rc;
   if (nb > 1024) return fail(GPAW_ESHAPE, "gpaw_orthonormalize supports nb <= 1024");
-  if (!psi || !Spsi || !psi_out) return fail(GPAW_EINVAL, "psi, Spsi and psi_out must not be NULL");
+  if (!psi || !psi_out) return fail(GPAW_EINVAL, "psi and psi_out must not be NULL");
   if ((P == nullptr) != (P_out == nullptr))
     return fail(GPAW_EINVAL, "P and P_out must be both NULL or both set");
+  if (!Spsi && !P && s->np > 0)
+    return fail(GPAW_EINVAL, "without Spsi the projections P of psi are needed");
   const size_t es = elem_size(s->dtype);
   const size_t bytes = static_cast<size_t>(nb) * s->ng * es;
   const size_t pbytes = static_cast<size_t>(nb) * s->np * es;
-  if (overlaps(psi_out, bytes, psi, bytes) || overlaps(psi_out, bytes, Spsi, bytes))
+  if (overlaps(psi_out, bytes, psi, bytes) || (Spsi && overlaps(psi_out, bytes, Spsi, bytes)))
     return fail(GPAW_EALIAS, "psi_out overlaps psi or Spsi");
   if (P && s->np > 0 && (overlaps(P_out, pbytes, P, pbytes) || overlaps(P_out, pbytes, psi_out, bytes)))
     return fail(GPAW_EALIAS, "P_out overlaps P or psi_out");
@@ -536,7 +538,26 @@ int gpaw_orthonormalize(gpaw_sys *s, const void *psi, const void *Spsi, int32_t 
   char *Sm = static_cast<char *>(s->ws.mat);
   char *Cm = Sm + mbytes;
   int32_t *dinfo = info ? info : s->ws.info;
-  if ((rc = launch_subspace(s, psi, Spsi, nullptr, nb, Sm, nullptr, st)) != GPAW_OK) return rc;
+  if (Spsi) {
+    if ((rc = launch_subspace(s, psi, Spsi, nullptr, nb, Sm, nullptr, st)) != GPAW_OK) return rc;
+  } else {
+    // S' = dV psi^H psi + P^H (Delta S P): the Gram matrix of the block, then
+    // the projector term as a product over the Np projector columns (a view
+    // of the system with Np "grid points" and unit volume element), added
+    if ((rc = launch_subspace(s, psi, psi, nullptr, nb, Sm, nullptr, st)) != GPAW_OK) return rc;
+    if (s->np > 0) {
+      if ((rc = launch_dmat(s, s->dS, P, nb, s->ws.X, st)) != GPAW_OK) return rc;
+      gpaw_sys pv = *s;
+      pv.ng = s->np;
+      pv.dV = 1.0;
+      if ((rc = launch_subspace(&pv, P, s->ws.X, nullptr, nb, Cm, nullptr, st)) != GPAW_OK)
+        return rc;
+      const int64_t nel = static_cast<int64_t>(nb) * nb * (is_complex(s->dtype) ? 2 : 1);
+      if ((rc = launch_add_mat(reinterpret_cast<const double *>(Cm), reinterpret_cast<double *>(Sm),
+                               nel, st)) != GPAW_OK)
+        return rc;
+    }
+  }
   if ((rc = launch_chol_inv(s, Sm, nb, Cm, dinfo, st)) != GPAW_OK) return rc;
   // L^-H is upper triangular (the rotations skip the zero half) and, for a
   // nearly orthonormal block, close to the identity

@@ -802,6 +802,20 @@ int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const 
   return subspace_t<double, 4, 0>(s, psi, Hpsi, Spsi, nb, H, S, st, part, part_elems);
 }
 
+namespace {
+__global__ __launch_bounds__(256) void k_add_mat(const double *__restrict__ a,
+                                                 double *__restrict__ acc, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) acc[i] += a[i];
+}
+}  // namespace
+
+int launch_add_mat(const double *a, double *acc, int64_t n, hipStream_t st) {
+  if (n <= 0) return GPAW_OK;
+  k_add_mat<<<static_cast<unsigned>((n + 255) / 256), 256, 0, st>>>(a, acc, n);
+  return GPAW_OK;
+}
+
 int launch_rotate(const gpaw_sys *s, const void *C, const void *src, int nb, int64_t cols,
                   void *dst, hipStream_t st, bool upper, bool near_id, int nout) {
   if (cols == 0) return GPAW_OK;

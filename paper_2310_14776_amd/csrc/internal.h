@@ -269,6 +269,8 @@ int launch_apply_S(const gpaw_sys *s, const void *psi, int nb, const void *X, vo
 int launch_subspace(const gpaw_sys *s, const void *psi, const void *Hpsi, const void *Spsi,
                     int nb, void *H, void *S, hipStream_t st, double *part = nullptr,
                     size_t part_elems = 0);
+// acc[i] += a[i] for n doubles (fixed order, one lane per element)
+int launch_add_mat(const double *a, double *acc, int64_t n, hipStream_t st);
 // Small subspace eigensolves (nb up to the one-workgroup limit) of several
 // systems of one scalar type in one chain of launches (eigh.hip). The job
 // table lives in device memory of at least eig_job_bytes() per item: filled

@@ -196,3 +196,43 @@ def test_orthonormalize_one_product_ragged(cplx, nb):
     say(f"  max|E| = {offid:.2e}, correction {corr:.2e}, ||psi'' - oracle|| / ||oracle|| = {err:.2e}")
     assert err <= 1e-6 and err <= 0.25 * corr
     g.close()
+
+
+@pytest.mark.parametrize("precision", ["double", "single"])
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("start", ["rotated", "raw"])
+def test_orthonormalize_from_projections(precision, cplx, start):
+    """gpaw_orthonormalize without S~psi: S' = dV psi^H psi + P^H Delta S P
+    from the block and its projections (Eq. (dh): the non-local part of
+    S~ seen from psi is conj(P) Delta S P) against the oracle's correction
+    through S~psi on the same values, with the same bounds as the S~psi form
+    (1e-12 relative in FP64, FP32 resolution in single precision; the
+    projections are rounded too, which moves S' by about 1e-8). The rotated
+    projections P_out must be the projections of the corrected block. Without
+    S~psi the call needs P: GPAW_EINVAL otherwise."""
+    cfg = dict(n=(16, 14, 18), h=0.2, nb=24, natoms=3, rc=1.8, seed=54)
+    if cplx:
+        cfg["k"] = (0.25, 0.0, 0.5)
+    s = synth.make_system(**cfg)
+    say(f"[orthonormalize-P] precision={precision} complex={cplx} start={start}")
+    ref = oracle.fd_step(s)
+    ops = ref["ops"]
+    x = ref["psi_rot"] if start == "rotated" else s.psi.reshape(s.nb, -1)
+    single = precision == "single"
+    if single:
+        x = _round(x, cplx).astype(np.complex128 if cplx else np.float64)
+    Px = ops.project(x)
+    want = oracle.orthonormalize(x, ops.apply_S(x, Px), ops.dV)
+    g = gfd.System.from_synth(s, precision=precision)
+    up = (lambda a: to_dev(_round(a, cplx))) if single else to_dev
+    got, Pgot = g.orthonormalize(up(x), None, P=up(Px))
+    torch.cuda.synchronize()
+    err = rel(host(got).astype(want.dtype), want)
+    perr = rel(host(Pgot).astype(want.dtype), ops.project(want))
+    say(f"  ||psi'' - oracle|| / ||oracle|| = {err:.2e}, projections {perr:.2e}")
+    tol = 1e-6 if single else 1e-12
+    assert err <= tol and perr <= tol
+    with pytest.raises(gfd.GpawError) as e:
+        g.orthonormalize(up(x), None)
+    assert e.value.status == "GPAW_EINVAL"
+    g.close()
