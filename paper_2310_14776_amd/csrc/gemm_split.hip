@@ -13,7 +13,7 @@
 // accumulators after every 32-term step: the rounding error of an FP32
 // partial sum is 2^-24 of that sum, so long FP32 runs over positive terms
 // (the diagonal of S_nm) would dominate the error. The rotation, whose output
-// is FP32, promotes every 8 steps (256 terms).
+// is FP32, promotes every 256 terms (4 steps of 64).
 //
 // MFMA layout (16x16x32, BF16 in, FP32 out): lane l supplies A[i = l%16]
 // [8 values of k] and B[8 values of k][j = l%16] from the same k set, and
